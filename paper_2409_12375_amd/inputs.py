@@ -1,0 +1,257 @@
+"""Seeded synthetic inputs: triangle surface meshes and panel densities.
+
+This module holds only input generation (geometry and random numbers).  It
+contains none of the operator's arithmetic, so both the GPU path and the CPU
+oracle can be fed from it.
+
+The paper's structures (a wire, two square coils, a BGA package and an HBPOP
+package, Sec. III) are proprietary or not given; these generators stand in for
+them with the same kind of geometry: conductor surfaces meshed into flat
+triangles (Sec. II-A), with quasi-uniform panel size.
+
+Every generator returns ``(V, T)``: vertices [nv][3] float64 and triangles
+[N][3] int32 (indexed, conforming where the surface is connected).
+Geometry seed 2409 (+ mesh index), density seed 12375, numpy PCG64.
+"""
+import numpy as np
+
+GEOM_SEED = 2409
+DENS_SEED = 12375
+
+
+class _Welder:
+    """Collects vertices, merging coincident ones (quantised coordinates)."""
+
+    def __init__(self, tol=1e-9):
+        self.tol = tol
+        self.map = {}
+        self.pts = []
+
+    def add(self, p):
+        key = tuple(int(round(c / self.tol)) for c in p)
+        idx = self.map.get(key)
+        if idx is None:
+            idx = len(self.pts)
+            self.map[key] = idx
+            self.pts.append(np.asarray(p, dtype=np.float64))
+        return idx
+
+    def add_many(self, P):
+        return np.array([self.add(p) for p in P], dtype=np.int64)
+
+    def vertices(self):
+        return np.array(self.pts, dtype=np.float64).reshape(-1, 3)
+
+
+def _grid_tris(idx, flip=False):
+    """Split every quad of an index grid idx[i][j] into two triangles."""
+    a = idx[:-1, :-1].ravel()
+    b = idx[1:, :-1].ravel()
+    c = idx[1:, 1:].ravel()
+    d = idx[:-1, 1:].ravel()
+    if flip:
+        t1 = np.stack([a, c, b], 1)
+        t2 = np.stack([a, d, c], 1)
+    else:
+        t1 = np.stack([a, b, c], 1)
+        t2 = np.stack([a, c, d], 1)
+    return np.concatenate([t1, t2])
+
+
+def densities(n_panels, n_cols, dtype=np.complex128, seed=DENS_SEED):
+    """iid N(0,1) real and imaginary parts, shape [N][n_cols] (panel-major)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    re = rng.standard_normal((n_panels, n_cols))
+    im = rng.standard_normal((n_panels, n_cols))
+    return (re + 1j * im).astype(dtype)
+
+
+# --------------------------------------------------------------------------
+# straight bar
+# --------------------------------------------------------------------------
+def bar(nx=4, ny=4, nz=126, size=(1.0, 1.0, 20.0), jitter=0.05, seed=GEOM_SEED):
+    """Surface of the box [0,sx]x[0,sy]x[0,sz] with nx*ny*nz surface cells per
+    direction, every quad split in two.  N = 4*(nx*nz + ny*nz + nx*ny).
+    Defaults: 1 x 1 x 20 bar, 4096 triangles.
+
+    Vertex jitter is uniform in +-jitter of the local cell size, only along
+    the directions in which the vertex is free to move without leaving its
+    face (vertices on bar edges slide along the edge, corners stay fixed), so
+    the mesh stays flat and conforming."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sx, sy, sz = size
+    n = (nx, ny, nz)
+    h = (sx / nx, sy / ny, sz / nz)
+    index = {}
+    pts = []
+
+    def vid(i, j, k):
+        key = (i, j, k)
+        v = index.get(key)
+        if v is None:
+            v = len(pts)
+            index[key] = v
+            p = [i * h[0], j * h[1], k * h[2]]
+            for d, q in enumerate((i, j, k)):
+                if 0 < q < n[d]:
+                    p[d] += rng.uniform(-jitter, jitter) * h[d]
+            pts.append(p)
+        return v
+
+    tris = []
+
+    def face(axis, side):
+        a1, a2 = [d for d in range(3) if d != axis]
+        fixed = 0 if side == 0 else n[axis]
+        idx = np.empty((n[a1] + 1, n[a2] + 1), dtype=np.int64)
+        for u in range(n[a1] + 1):
+            for v in range(n[a2] + 1):
+                c = [0, 0, 0]
+                c[axis] = fixed
+                c[a1] = u
+                c[a2] = v
+                idx[u, v] = vid(*c)
+        # outward normal: e_a1 x e_a2 = +e_axis for (axis,a1,a2) cyclic
+        cyc = (a1 - axis) % 3 == 1
+        flip = (side == 0) == cyc
+        tris.append(_grid_tris(idx, flip=flip))
+
+    for axis in range(3):
+        for side in (0, 1):
+            face(axis, side)
+    T = np.concatenate(tris).astype(np.int32)
+    return np.array(pts, dtype=np.float64), T
+
+
+# --------------------------------------------------------------------------
+# icosphere
+# --------------------------------------------------------------------------
+def icosphere(level, radius=1.0, center=(0.0, 0.0, 0.0)):
+    """Regular icosahedron, each face split into 4 `level` times, vertices
+    projected onto the sphere.  N = 20 * 4**level."""
+    t = (1.0 + 5 ** 0.5) / 2.0
+    V = [[-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0], [0, -1, t], [0, 1, t],
+         [0, -1, -t], [0, 1, -t], [t, 0, -1], [t, 0, 1], [-t, 0, -1], [-t, 0, 1]]
+    V = [np.array(v, dtype=np.float64) / np.linalg.norm(v) for v in V]
+    F = [[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11], [1, 5, 9], [5, 11, 4],
+         [11, 10, 2], [10, 7, 6], [7, 1, 8], [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8],
+         [3, 8, 9], [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]]
+    for _ in range(level):
+        cache = {}
+
+        def mid(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in cache:
+                m = V[a] + V[b]
+                V.append(m / np.linalg.norm(m))
+                cache[key] = len(V) - 1
+            return cache[key]
+
+        nF = []
+        for a, b, c in F:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nF += [[a, ab, ca], [b, bc, ab], [c, ca, bc], [ab, bc, ca]]
+        F = nF
+    Vout = np.array(V) * radius + np.asarray(center, dtype=np.float64)
+    return Vout, np.array(F, dtype=np.int32)
+
+
+# --------------------------------------------------------------------------
+# swept rectangular tube along a planar polyline (square spiral coils)
+# --------------------------------------------------------------------------
+def _rect_ring(nw, nt):
+    """Boundary of the unit cross-section [-1,1]x[-1,1] (u in-plane, v along z)
+    with nw cells along u and nt along v, counter-clockwise.  Returns [M][2]."""
+    pts = []
+    for i in range(nw):
+        pts.append((-1 + 2 * i / nw, -1))
+    for j in range(nt):
+        pts.append((1, -1 + 2 * j / nt))
+    for i in range(nw):
+        pts.append((1 - 2 * i / nw, 1))
+    for j in range(nt):
+        pts.append((-1, 1 - 2 * j / nt))
+    return np.array(pts)
+
+
+def swept_trace(poly, width, thick, z0, nw, nt, ds, welder):
+    """Mesh the surface of a trace of rectangular cross-section width x thick
+    whose centre line is the planar polyline `poly` [M][2] at height z0.
+    Mitred corners, flat end caps.  Returns triangles (vertex ids in welder)."""
+    poly = np.asarray(poly, dtype=np.float64)
+    ring = _rect_ring(nw, nt)
+    M = len(ring)
+    segs = poly[1:] - poly[:-1]
+    lens = np.linalg.norm(segs, axis=1)
+    dirs = segs / lens[:, None]
+    nrm = np.stack([-dirs[:, 1], dirs[:, 0]], 1)
+    # corner rings: perpendicular at the two ends, mitred at interior corners
+    offs = [nrm[0]]
+    for s in range(1, len(segs)):
+        n1, n2 = nrm[s - 1], nrm[s]
+        offs.append((n1 + n2) / (1.0 + n1 @ n2))
+    offs.append(nrm[-1])
+
+    def ring_at(p, off):
+        P3 = np.empty((M, 3))
+        P3[:, 0:2] = p[None, :] + ring[:, 0:1] * (0.5 * width) * off[None, :]
+        P3[:, 2] = z0 + ring[:, 1] * 0.5 * thick
+        return P3
+
+    corner = [ring_at(poly[i], offs[i]) for i in range(len(poly))]
+    stations = []
+    for s in range(len(segs)):
+        ns = max(1, int(round(lens[s] / ds)))
+        for q in range(ns):
+            f = q / ns
+            # interpolating the two corner rings keeps every quad of the
+            # segment between its two mitre planes (no fold-over at corners)
+            stations.append((1.0 - f) * corner[s] + f * corner[s + 1])
+    stations.append(corner[-1])
+    rings = [welder.add_many(P3) for P3 in stations]
+    rings = np.array(rings)  # [S][M]
+    idx = np.concatenate([rings, rings[:, :1]], 1)  # close the ring
+    tris = [_grid_tris(idx)]
+    # end caps: structured grid over the cross-section, boundary shared with ring
+    for end, (p, off) in ((0, (poly[0], offs[0])), (1, (poly[-1], offs[-1]))):
+        g = np.empty((nw + 1, nt + 1), dtype=np.int64)
+        for i in range(nw + 1):
+            for j in range(nt + 1):
+                u = -1 + 2 * i / nw
+                v = -1 + 2 * j / nt
+                q = np.array([p[0] + u * 0.5 * width * off[0], p[1] + u * 0.5 * width * off[1],
+                              z0 + v * 0.5 * thick])
+                g[i, j] = welder.add(q)
+        tris.append(_grid_tris(g, flip=(end == 1)))
+    return np.concatenate(tris)
+
+
+def square_spiral(turns, outer, pitch):
+    """Centre line of a square spiral: side lengths shrink by `pitch` every
+    second side, starting at the outer corner."""
+    a = outer / 2.0
+    p = np.array([-a, -a])
+    pts = [p.copy()]
+    dirs = [(1, 0), (0, 1), (-1, 0), (0, -1)]
+    for k in range(4 * turns):
+        L = outer - (k // 2) * pitch
+        p = p + L * np.array(dirs[k % 4], dtype=np.float64)
+        pts.append(p.copy())
+    return np.array(pts)
+
+
+def coils(target_n=200_000, turns=5, width=0.1, thick=0.035, spacing=0.1, gap=0.5,
+          outer=3.0, nw=8, nt=3):
+    """Two identical 5-turn square planar spiral coils stacked along z with
+    `gap` between their facing surfaces.  Trace width 0.1, thickness 0.035,
+    spacing 0.1 (pitch 0.2).  The along-trace step is chosen so the total panel
+    count is close to target_n."""
+    pitch = width + spacing
+    poly = square_spiral(turns, outer - width, pitch)
+    length = np.linalg.norm(poly[1:] - poly[:-1], axis=1).sum()
+    per_step = 2 * 2 * (nw + nt)  # triangles per station step per coil
+    ds = length / max(1.0, (target_n / 2 - 2 * 2 * nw * nt) / per_step)
+    W = _Welder()
+    T1 = swept_trace(poly, width, thick, 0.0, nw, nt, ds, W)
+    T2 = swept_trace(poly, width, thick, thick + gap, nw, nt, ds, W)
+    return W.vertices(), np.concatenate([T1, T2]).astype(np.int32)
