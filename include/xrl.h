@@ -1,0 +1,275 @@
+/*
+ * xrl.h -- C-ABI of the MI355X (gfx950) FMM-accelerated panel operator of the
+ * XRL method (arXiv 2409.12375).
+ *
+ * The operator.  After the centroid-midpoint basis transformation (Sec. II-A,
+ * Fig. 2, Algorithm 1) the surface current is carried by pulse functions on
+ * flat triangle panels, one scalar density per Cartesian component
+ * (eq. (4)), and the expensive part of every iteration of the solve is the
+ * product of the panel matrix P with those densities (eq. (9), Sec. II-C):
+ *
+ *     (P x)_k = sum_l P_kl x_l,   P_kl = int_{S_k} int_{S_l} 1/|r - r'| dS' dS
+ *
+ * (eq. (6), second term, with the factor j*omega*mu0/(4*pi) taken outside the
+ * integral as Sec. II-D describes, so P is frequency independent and shared by
+ * every port and frequency).  P is real, symmetric and positive definite
+ * (Sec. II-D); densities are complex.  The library applies P with a fast
+ * multipole method on the panel centroids (Sec. II-C) and stores the
+ * near-field entries on panels (Sec. II-C, last paragraph).
+ *
+ * Conventions (all entry points):
+ *  - Every function returns xrl_status; 0 is success, negative is an error.
+ *    Nothing throws across the ABI.  xrl_last_error() returns a thread-local
+ *    message describing the last failure on the calling thread.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued on it; functions that must read results back to the host
+ *    synchronise that stream before returning.
+ *  - Handles are opaque and owned by the library; each create has a matching
+ *    destroy.  Device memory for handles is allocated with hipMalloc by the
+ *    library.  Caller buffers (x, y, b) are never freed by the library.
+ *  - On error the outputs are unspecified and the handles stay valid.
+ *    Asynchronous kernel faults surface as XRL_E_HIP at the next call that
+ *    synchronises.
+ */
+#ifndef XRL_H
+#define XRL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t xrl_status;
+#define XRL_OK 0
+#define XRL_E_INVALID_ARG (-1)      /* bad pointer, size, option or layout */
+#define XRL_E_DEGENERATE_PANEL (-2) /* a panel with (near) zero area or a NaN vertex */
+#define XRL_E_OOM (-3)              /* device or host allocation failed */
+#define XRL_E_HIP (-4)              /* a HIP runtime call failed */
+#define XRL_E_NOT_CONVERGED (-5)    /* GMRES stopped before reaching rtol */
+#define XRL_E_UNSUPPORTED (-6)      /* option combination not implemented */
+#define XRL_E_STATE (-7)            /* call out of order (e.g. matvec before assemble) */
+
+/* Data types of densities and potentials (complex, interleaved re/im). */
+#define XRL_C64 1  /* complex64: pairs of float  */
+#define XRL_C128 2 /* complex128: pairs of double */
+
+/* Arithmetic of the operator application. */
+#define XRL_PREC_FP64 0  /* every phase in FP64 (M2L on FP64 MFMA)                      */
+#define XRL_PREC_FP32 1  /* "plain FP32": every phase FP32, M2L on the vector ALUs,
+                            near field by quadrature in FP32                             */
+#define XRL_PREC_MIXED 2 /* FP32 M2L on MFMA with FP32 accumulation; self and touching
+                            near-field integrals in FP64, stored FP32                   */
+
+/* M2L engine. */
+#define XRL_M2L_AUTO 0   /* MFMA for FP64 and MIXED, vector ALU for FP32 */
+#define XRL_M2L_MFMA 1
+#define XRL_M2L_VALU 2
+
+const char *xrl_last_error(void);
+/* Library version string (static storage). */
+const char *xrl_version(void);
+
+/* ------------------------------------------------------------------ */
+/* Mesh and tree                                                       */
+/* ------------------------------------------------------------------ */
+/* An indexed triangle mesh.  vertices: [n_vertices][3] float64;
+ * tris: [n_panels][3] int32 vertex indices (0-based).  Both arrays live on
+ * the host (on_device = 0) or on the current HIP device (on_device = 1); they
+ * are copied during xrl_tree_build and not referenced afterwards.
+ * Vertex order only fixes the sign of the panel normal, which P does not use. */
+typedef struct {
+    int64_t n_vertices;
+    int64_t n_panels;
+    const double *vertices;
+    const int32_t *tris;
+    int32_t on_device;
+} xrl_mesh_desc;
+
+typedef struct xrl_tree xrl_tree;
+typedef struct xrl_plan xrl_plan;
+
+/* Panel geometry (centroid, area, normal, diameter), a cube around all
+ * centroids, 63-bit Morton codes of the centroids, a radix sort and a
+ * level-by-level split of every box holding more than max_leaf centroids,
+ * all on the device (the octree of the FMM of Sec. II-C, built on panel
+ * centroids).  A panel belongs to the box that holds its centroid.
+ *   max_leaf  : 1..64 (64 recommended)
+ *   max_depth : 1..21; a box at max_depth is a leaf whatever its count
+ *               (flagged in xrl_tree_info.n_overfull_leaves).
+ * Errors: XRL_E_INVALID_ARG (sizes, indices out of range),
+ *         XRL_E_DEGENERATE_PANEL (area <= 1e-14 * diameter^2, or non-finite),
+ *         XRL_E_OOM, XRL_E_HIP. */
+xrl_status xrl_tree_build(const xrl_mesh_desc *mesh, int32_t max_leaf, int32_t max_depth,
+                          void *stream, xrl_tree **out);
+void xrl_tree_destroy(xrl_tree *tree);
+
+typedef struct {
+    int64_t n_panels;
+    int64_t n_boxes;
+    int64_t n_leaves;
+    int32_t depth;             /* deepest level present (root = 0) */
+    int32_t n_overfull_leaves; /* leaves at max_depth with more than max_leaf panels */
+    double root_center[3];
+    double root_size;          /* side of the root cube */
+} xrl_tree_info;
+xrl_status xrl_tree_get_info(const xrl_tree *tree, xrl_tree_info *info);
+
+/* ------------------------------------------------------------------ */
+/* Plan                                                                */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t order;     /* expansion order p (1..12); (p+1)^2 real coefficients per column */
+    int32_t precision; /* XRL_PREC_* */
+    int32_t m2l_engine;/* XRL_M2L_* */
+    int32_t max_cols;  /* largest number of complex columns one matvec will carry */
+} xrl_plan_opts;
+
+/* Interaction lists of the adaptive octree (U: adjacent leaves, V: same-level
+ * well-separated boxes, W and X: the adaptive lists), translated into a
+ * near-field list per target leaf (U, W and X, applied directly) and M2L
+ * pairs (V), plus the translation operators (M2M, L2L: 8 each; M2L: one per
+ * integer offset in [-3,3]^3 outside [-1,1]^3) and the per-panel moment table
+ * of the regular solid harmonics integrated exactly over each panel.
+ * Several trees make one batched plan: the meshes are stacked in the order
+ * given, densities are concatenated along the panel axis.  The trees must
+ * outlive the plan.
+ * Errors: XRL_E_INVALID_ARG, XRL_E_UNSUPPORTED (order or engine), XRL_E_OOM,
+ *         XRL_E_HIP. */
+xrl_status xrl_fmm_plan(xrl_tree *const *trees, int32_t n_trees, const xrl_plan_opts *opts,
+                        void *stream, xrl_plan **out);
+void xrl_plan_destroy(xrl_plan *plan);
+
+typedef struct {
+    int64_t n_panels;
+    int64_t n_boxes;
+    int64_t n_leaves;
+    int64_t n_m2l_pairs;  /* V-list pairs over all levels */
+    int64_t n_near_rows;  /* source rows over all target leaves */
+    int64_t n_near_entries; /* stored near-field values (with target padding) */
+    int64_t n_near_pairs; /* unpadded target-source panel pairs */
+    int32_t order;
+    int32_t precision;
+    double max_sep_ratio; /* max over M2L pairs of (rad_t + rad_s) / |c_t - c_s| */
+} xrl_plan_info;
+xrl_status xrl_plan_get_info(const xrl_plan *plan, xrl_plan_info *info);
+
+/* ------------------------------------------------------------------ */
+/* Near field                                                          */
+/* ------------------------------------------------------------------ */
+/* Optional learned surrogate for near-singular pairs: a 18 -> H -> H -> 2
+ * multilayer perceptron with SiLU activations whose first output predicts
+ * P_kl / P_kl^(3x3 Gauss) - 1 and whose second predicts log10 of the absolute
+ * error of the first.  Weights are FP32, row-major [out][in], on the host. */
+typedef struct {
+    int32_t hidden;          /* H (128) */
+    const float *w1, *b1;    /* [H][18], [H] */
+    const float *w2, *b2;    /* [H][H],  [H] */
+    const float *w3, *b3;    /* [2][H],  [2] */
+    const float *feat_lo, *feat_hi; /* [18] input range seen in training */
+    float log10_err_bound;   /* fall back to quadrature when out[1] exceeds it */
+} xrl_mlp;
+
+typedef struct {
+    double r_near;      /* non-touching pairs with |c_k-c_l|/max(diam) < r_near use the
+                           semi-analytic rule (default 2.0) */
+    double r_mid;       /* regular pairs below r_mid use 4x4 product Gauss, above 3x3
+                           (default 6.0) */
+    const xrl_mlp *surrogate; /* NULL: quadrature everywhere */
+    int32_t audit_every;      /* with a surrogate: every k-th accepted pair is also
+                                 integrated by quadrature for the error report (0: off) */
+} xrl_nf_opts;
+
+typedef struct {
+    int64_t n_entries;     /* stored values (padding included) */
+    int64_t n_self, n_touching, n_near_singular, n_regular;
+    int64_t n_mlp_accepted, n_mlp_fallback;
+    double audit_max_rel_err, audit_rms_rel_err; /* surrogate audit, if any */
+    double ms;             /* wall time of the assembly */
+} xrl_nf_stats;
+
+/* Fill the near-field panel-panel entries P_kl (frequency independent, done
+ * once and reused by every matvec, Sec. II-C and II-D).  Pair classes: self
+ * (closed form), touching (shared vertex index: exact inner integral, graded
+ * outer rule), near-singular (exact inner integral, subdivided outer rule, or
+ * the surrogate), regular (product Gauss).  stats may be NULL.
+ * Errors: XRL_E_INVALID_ARG, XRL_E_OOM, XRL_E_HIP. */
+xrl_status xrl_nearfield_assemble(xrl_plan *plan, const xrl_nf_opts *opts, void *stream,
+                                  xrl_nf_stats *stats);
+
+/* ------------------------------------------------------------------ */
+/* Operator application                                                */
+/* ------------------------------------------------------------------ */
+/* Per-column complex scalars for y = alpha_c * (P x)_c + beta_c * A .* x_c
+ * (A = panel areas, i.e. the Galerkin mass term of eq. (6) first term with
+ * beta = Z_s).  alpha, beta: host arrays of n_cols (re, im) double pairs;
+ * either may be NULL (alpha = 1, beta = 0). */
+typedef struct {
+    const double *alpha;
+    const double *beta;
+} xrl_epilogue;
+
+/* y = P x (plus the optional epilogue) for n_cols complex columns.
+ *   x : device, [n_panels][ldx] complex (XRL_C64 or XRL_C128), user panel
+ *       order, columns 0..n_cols-1 used; ldx >= n_cols (in complex elements).
+ *   y : device, [n_panels][ldy] same dtype; only columns 0..n_cols-1 written.
+ * n_cols <= max_cols of the plan.  Requires xrl_nearfield_assemble first.
+ * x and y must not overlap.
+ * Errors: XRL_E_INVALID_ARG, XRL_E_STATE, XRL_E_HIP. */
+xrl_status xrl_fmm_matvec(const xrl_plan *plan, const void *x, int64_t ldx, int32_t n_cols,
+                          int32_t dtype, void *y, int64_t ldy, const xrl_epilogue *ep,
+                          void *stream);
+
+/* Per-phase device times (milliseconds) of the last matvec, recorded with
+ * HIP events on the matvec stream when profiling is on:
+ * [0] gather [1] P2P [2] P2M [3] M2M [4] M2L [5] L2L [6] L2P [7] scatter. */
+#define XRL_N_PHASES 8
+xrl_status xrl_plan_set_profiling(xrl_plan *plan, int32_t on);
+xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHASES] */);
+
+/* Debug export of plan internals to host memory (tests):
+ *   item 0: perm        int32 [n_panels]   sorted position -> global panel
+ *   item 1: box_range   int32 [n_boxes][2] panel range [begin, end) per box
+ *   item 2: box_level   int32 [n_boxes]
+ *   item 3: near_rows   int32 [n_leaves+1] CSR over leaves into item 4
+ *   item 4: near_src    int32 [n_near_rows] sorted source panel per row
+ *   item 5: m2l_pairs   int32 [n_m2l_pairs][2] (target box, source box)
+ *   item 6: leaf_box    int32 [n_leaves]   box index of each leaf
+ *   item 7: box_parent  int32 [n_boxes]
+ *   item 8: near_values float64 [n_near_entries] (per leaf [rows][tpad])
+ *   item 9: leaf_tpad   int32 [n_leaves]   padded target count of each leaf block
+ * With buf == NULL only *nbytes is set. */
+xrl_status xrl_plan_export(const xrl_plan *plan, int32_t item, void *buf, int64_t *nbytes);
+
+/* Self-test of the 16x16x4 MFMA operand layout used by the M2L kernel:
+ * D[16][16] = A[16][4] * B[4][16], row-major host arrays of float
+ * (elem_bytes = 4) or double (8).  Runs one wave on the current device. */
+xrl_status xrl_selftest_mfma(int32_t elem_bytes, const void *A, const void *B, void *D);
+
+/* ------------------------------------------------------------------ */
+/* Iterative solve                                                     */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t iterations;  /* total inner iterations (max over right-hand sides) */
+    int32_t restarts;
+    int32_t converged;   /* number of right-hand sides that reached rtol */
+    double max_rel_residual; /* max over right-hand sides of ||b - A x|| / ||b|| */
+} xrl_gmres_stats;
+
+/* Solve (beta_c * diag(A) + alpha_c * P) x_c = b_c for n_rhs complex columns
+ * together (multiple right-hand sides share every FMM matvec; Sec. III:
+ * restarted GMRES, restart 50, relative residual 1e-4 or 1e-6).  Arnoldi
+ * orthogonalisation (classical Gram-Schmidt, twice) and the least-squares
+ * update are FP64 whatever the plan's precision.
+ *   b, x : device, [n_panels][n_rhs] complex128, user panel order; x holds
+ *          the initial guess on entry and the solution on exit.
+ * Errors: XRL_E_INVALID_ARG, XRL_E_STATE, XRL_E_NOT_CONVERGED (stats filled),
+ *         XRL_E_HIP. */
+xrl_status xrl_gmres_solve(const xrl_plan *plan, const xrl_epilogue *op, const void *b, void *x,
+                           int32_t n_rhs, int32_t restart, double rtol, int32_t max_iter,
+                           void *stream, xrl_gmres_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XRL_H */

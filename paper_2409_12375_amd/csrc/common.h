@@ -1,0 +1,242 @@
+// Internal helpers shared by the library's translation units: status
+// plumbing, device buffers, and the tree / plan structures.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/xrl.h"
+
+namespace xrl {
+
+void set_error(const char *fmt, ...);
+
+// Exception used internally; converted to a status at the ABI boundary.
+struct Error {
+    xrl_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(xrl_status code, const char *fmt, ...);
+
+#define XRL_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            ::xrl::fail(e_ == hipErrorOutOfMemory ? XRL_E_OOM : XRL_E_HIP, "%s: %s (%s:%d)", \
+                        #call, hipGetErrorString(e_), __FILE__, __LINE__);                \
+    } while (0)
+
+#define XRL_CHECK(cond, code, ...)                   \
+    do {                                             \
+        if (!(cond)) ::xrl::fail(code, __VA_ARGS__); \
+    } while (0)
+
+// Run `body` and convert any xrl::Error to a status (the ABI never throws).
+template <class F>
+xrl_status guarded(F &&body)
+{
+    try {
+        body();
+        return XRL_OK;
+    } catch (const Error &e) {
+        set_error("%s", e.msg.c_str());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return XRL_E_OOM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return XRL_E_HIP;
+    }
+}
+
+// Owning device buffer.
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t count) { alloc(count); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept
+    {
+        if (this != &o) {
+            release();
+            p = o.p;
+            n = o.n;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t count)
+    {
+        release();
+        n = count;
+        if (count) XRL_HIP(hipMalloc((void **)&p, count * sizeof(T)));
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void upload(const T *h, size_t count, hipStream_t s)
+    {
+        if (count > n) alloc(count);
+        if (count) XRL_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    void upload(const std::vector<T> &h, hipStream_t s) { upload(h.data(), h.size(), s); }
+    std::vector<T> download(hipStream_t s, size_t count = (size_t)-1) const
+    {
+        if (count == (size_t)-1) count = n;
+        std::vector<T> h(count);
+        if (count) {
+            XRL_HIP(hipMemcpyAsync(h.data(), p, count * sizeof(T), hipMemcpyDeviceToHost, s));
+            XRL_HIP(hipStreamSynchronize(s));
+        }
+        return h;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Morton helpers (21 bits per axis, 63-bit codes).
+__host__ __device__ inline uint64_t spread3(uint32_t v)
+{
+    uint64_t x = v & 0x1fffffull;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+__host__ __device__ inline uint32_t compact3(uint64_t x)
+{
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+    x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+    x = (x ^ (x >> 32)) & 0x1fffffull;
+    return (uint32_t)x;
+}
+__host__ __device__ inline uint64_t morton3(uint32_t ix, uint32_t iy, uint32_t iz)
+{
+    return spread3(ix) | (spread3(iy) << 1) | (spread3(iz) << 2);
+}
+
+constexpr int kMaxDepth = 21;
+constexpr int kMaxLeaf = 64;
+
+}  // namespace xrl
+
+// --------------------------------------------------------------------------
+// Tree: one mesh, panels sorted in Morton order of their centroids.
+// --------------------------------------------------------------------------
+struct xrl_tree {
+    int64_t N = 0, nv = 0;
+    int max_leaf = 64, max_depth = 21;
+    double root_c[3] = {0, 0, 0};
+    double root_size = 0;
+    int depth = 0;
+    int n_overfull = 0;
+    // sorted panel data (device)
+    xrl::DevBuf<int32_t> perm;    // sorted position -> original panel index
+    xrl::DevBuf<double> pv;       // [N][9] vertices of each panel
+    xrl::DevBuf<int32_t> pvid;    // [N][3] vertex ids of each panel
+    xrl::DevBuf<double> cen;      // [N][3] centroids
+    xrl::DevBuf<double> area;     // [N]
+    xrl::DevBuf<double> diam;     // [N] longest edge
+    xrl::DevBuf<uint64_t> code;   // [N] sorted Morton codes
+    // boxes, level-major, sorted by key within a level (host copies; small)
+    std::vector<int64_t> level_off;  // [depth+2]
+    std::vector<uint64_t> box_key;   // key at its own level
+    std::vector<int32_t> box_level, box_parent, box_child0, box_nchild, box_beg, box_end;
+};
+
+// --------------------------------------------------------------------------
+// Plan: one or more trees, interaction lists, operators, near field.
+// --------------------------------------------------------------------------
+struct xrl_plan {
+    int p = 8, K = 81;
+    int precision = XRL_PREC_MIXED;
+    int m2l_engine = XRL_M2L_MFMA;
+    int max_cols = 1;  // complex columns
+    std::vector<xrl_tree *> trees;
+    std::vector<int64_t> panel_off;  // [ntrees+1] global panel offsets (user order == sorted blocks)
+    int64_t N = 0;
+    // global boxes (level-major across trees)
+    int64_t B = 0;
+    int depth = 0;
+    std::vector<int64_t> level_off;  // [depth+2]
+    std::vector<int32_t> h_box_beg, h_box_end, h_box_parent, h_box_child0, h_box_nchild, h_box_level,
+        h_box_tree;
+    std::vector<int32_t> h_leaf_box;
+    xrl::DevBuf<int32_t> box_beg, box_end, box_parent, box_child0, box_nchild, box_level, box_octant;
+    xrl::DevBuf<double> box_center;  // [B][3]
+    xrl::DevBuf<double> box_h;       // [B] side length
+    xrl::DevBuf<double> box_rad;     // [B] panel-inclusive radius
+    xrl::DevBuf<int32_t> leaf_box;   // [n_leaves]
+    int64_t n_leaves = 0;
+    // global sorted panels
+    xrl::DevBuf<int32_t> perm;   // global sorted pos -> global user panel index
+    xrl::DevBuf<int32_t> iperm;  // user -> sorted
+    xrl::DevBuf<double> pv;      // [N][9]
+    xrl::DevBuf<int32_t> pvid;   // [N][3] (vertex ids offset per tree)
+    xrl::DevBuf<double> cen, area, diam;
+    xrl::DevBuf<int32_t> panel_leaf;  // [N] leaf index (into leaf_box) of each sorted panel
+    // M2L pairs grouped by slab and offset
+    int64_t n_m2l = 0;
+    int slab_targets = 0;
+    int m2l_ct = 0;  // column tile width used for slab sizing
+    std::vector<int32_t> h_m2l_pairs;  // [n][2] (t, s) for export
+    xrl::DevBuf<int32_t> m2l_tgt_list;   // [n_targets] target boxes in slab order
+    xrl::DevBuf<int32_t> slab_tbeg;      // [n_slabs+1] into m2l_tgt_list
+    xrl::DevBuf<int32_t> slab_gbeg;      // [n_slabs+1] into groups
+    xrl::DevBuf<int32_t> grp_off;        // [n_groups] operator offset code
+    xrl::DevBuf<int32_t> grp_pbeg;       // [n_groups+1] into pair arrays
+    xrl::DevBuf<int32_t> pair_tloc;      // [n_pairs] target slot within slab
+    xrl::DevBuf<int32_t> pair_src;       // [n_pairs] source box
+    int64_t n_slabs = 0, n_groups = 0, n_targets = 0;
+    double max_sep_ratio = 0;
+    // operators (FP64 master + FP32 copy), real (p+1)^2 x (p+1)^2, row = output
+    xrl::DevBuf<double> op_m2m64, op_l2l64, op_m2l64;  // [8][K][K], [8][K][K], [343][KP][KK]
+    xrl::DevBuf<float> op_m2m32, op_l2l32, op_m2l32;
+    // M2L operators in MFMA fragment order [343][KP/16][KK/4][64]
+    xrl::DevBuf<double> op_m2l64f;
+    xrl::DevBuf<float> op_m2l32f;
+    int KP = 96, KK = 84;  // padded row / k dims of the M2L operator tiles
+    // moment table per sorted panel, scaled to its leaf: [N][K]
+    xrl::DevBuf<double> mom64;
+    xrl::DevBuf<float> mom32;
+    // near field: per leaf a list of source rows; block [rows][tpad]
+    std::vector<int32_t> h_near_rows;  // [n_leaves+1]
+    xrl::DevBuf<int32_t> near_rows;    // [n_leaves+1]
+    xrl::DevBuf<int32_t> near_src;     // [n_rows]
+    xrl::DevBuf<int64_t> near_val_off; // [n_leaves+1] value offsets
+    xrl::DevBuf<int32_t> leaf_tpad;    // [n_leaves]
+    int64_t n_near_rows = 0, n_near_entries = 0, n_near_pairs = 0;
+    xrl::DevBuf<double> near64;
+    xrl::DevBuf<float> near32;
+    bool assembled = false;
+    // work buffers for the matvec (sorted order, real columns)
+    mutable xrl::DevBuf<double> xs64, ys64, M64, L64;
+    mutable xrl::DevBuf<float> xs32, ys32, M32, L32;
+    mutable int64_t work_cols = 0;
+    // profiling
+    bool profiling = false;
+    mutable double phase_ms[XRL_N_PHASES] = {0};
+    mutable hipEvent_t ev[XRL_N_PHASES + 1] = {};
+    bool events_made = false;
+};

@@ -1,0 +1,572 @@
+// The FMM-accelerated panel matvec y = P x (eq. (9): FMM applies P to the
+// panel densities I_pt, Sec. II-C).  Densities and potentials are complex;
+// P is real, so a complex column is carried as two real columns.
+//
+// Phases (all on the caller's stream):
+//   gather   user order, complex -> Morton order, real columns   xs[N][C]
+//   P2P      y  = P_near x (stored near-field blocks)             ys[N][C]
+//   P2M      M_leaf = sum_k Q_k x_k (exact panel moments)         M[B][K][C]
+//   M2M      parents from children, deepest level first
+//   M2L      L_t = sum_{s in V(t)} T_{o(t,s)} M_s (MFMA or vector ALU)
+//   L2L      children from parents, top level first
+//   L2P      y += (1/h) sum_i w_i Q_k[i] L_leaf[i]  (Galerkin-tested local)
+//   scatter  y_user = alpha_c y + beta_c A .* x_user
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+
+#include "common.h"
+
+namespace xrl {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- gather / scatter
+template <typename TI, typename TW>
+__global__ void k_gather_x(int64_t N, const int32_t *__restrict__ perm, const TI *__restrict__ x, int64_t ldx,
+                           int ncols, TW *__restrict__ xs)
+{
+    const int C = 2 * ncols;
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= N * C) return;
+    const int64_t i = e / C;
+    const int c = (int)(e - i * C);
+    const int64_t u = perm[i];
+    xs[e] = (TW)x[2 * (u * ldx + (c >> 1)) + (c & 1)];
+}
+
+template <typename TO, typename TW>
+__global__ void k_scatter_y(int64_t N, const int32_t *__restrict__ perm, const TW *__restrict__ ys,
+                            const double *__restrict__ area, const TO *__restrict__ x, int64_t ldx,
+                            TO *__restrict__ y, int64_t ldy, int ncols, const double *__restrict__ alpha,
+                            const double *__restrict__ beta)
+{
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= N * ncols) return;
+    const int64_t i = e / ncols;
+    const int c = (int)(e - i * ncols);
+    const int64_t u = perm[i];
+    const double pr = (double)ys[i * 2 * ncols + 2 * c], pi = (double)ys[i * 2 * ncols + 2 * c + 1];
+    double ar = 1, ai = 0, br = 0, bi = 0;
+    if (alpha) {
+        ar = alpha[2 * c];
+        ai = alpha[2 * c + 1];
+    }
+    double yr = ar * pr - ai * pi, yi = ar * pi + ai * pr;
+    if (beta) {
+        br = beta[2 * c];
+        bi = beta[2 * c + 1];
+        const double xr = (double)x[2 * (u * ldx + c)], xi = (double)x[2 * (u * ldx + c) + 1];
+        const double A = area[i];
+        yr += A * (br * xr - bi * xi);
+        yi += A * (br * xi + bi * xr);
+    }
+    y[2 * (u * ldy + c)] = (TO)yr;
+    y[2 * (u * ldy + c) + 1] = (TO)yi;
+}
+
+// ---------------------------------------------------------------- P2P
+// One workgroup per (target leaf, column tile).  Lane j of a group of tpad
+// lanes owns target panel j; the 256/tpad groups stride over the source rows
+// of the leaf; block values are read coalesced ([row][tpad]).
+template <typename T, int CT>
+__global__ __launch_bounds__(256) void k_p2p(const int32_t *__restrict__ leaf_box, const int32_t *__restrict__ box_beg,
+                                             const int32_t *__restrict__ box_end, const int32_t *__restrict__ near_rows,
+                                             const int32_t *__restrict__ near_src, const int32_t *__restrict__ leaf_tpad,
+                                             const int64_t *__restrict__ val_off, const T *__restrict__ val,
+                                             const T *__restrict__ xs, T *__restrict__ ys, int C)
+{
+    __shared__ T red[256 * CT];
+    const int64_t li = blockIdx.x;
+    const int c0 = blockIdx.y * CT;
+    const int32_t tb = leaf_box[li];
+    const int32_t kb = box_beg[tb], nt = box_end[tb] - kb;
+    const int32_t r0 = near_rows[li], nr = near_rows[li + 1] - r0;
+    const int G = leaf_tpad[li];
+    const int slots = 256 / G;
+    const int j = threadIdx.x % G, slot = threadIdx.x / G;
+    const T *vb = val + val_off[li];
+    T acc[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[c] = 0;
+    const bool full = c0 + CT <= C;
+    for (int32_t r = slot; r < nr; r += slots) {
+        const T v = vb[(int64_t)r * G + j];
+        const T *xr = xs + (int64_t)near_src[r0 + r] * C + c0;
+        if (full) {
+#pragma unroll
+            for (int c = 0; c < CT; ++c) acc[c] += v * xr[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                if (c0 + c < C) acc[c] += v * xr[c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) red[(slot * G + j) * CT + c] = acc[c];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nt * CT; idx += 256) {
+        const int jj = idx / CT, c = idx - jj * CT;
+        if (c0 + c >= C) continue;
+        T sum = 0;
+        for (int sl = 0; sl < slots; ++sl) sum += red[(sl * G + jj) * CT + c];
+        ys[(int64_t)(kb + jj) * C + c0 + c] = sum;
+    }
+}
+
+// ---------------------------------------------------------------- P2M
+template <typename T, int CT>
+__global__ __launch_bounds__(256) void k_p2m(const int32_t *__restrict__ leaf_box, const int32_t *__restrict__ box_beg,
+                                             const int32_t *__restrict__ box_end, const T *__restrict__ mom,
+                                             const T *__restrict__ xs, T *__restrict__ M, int C, int K)
+{
+    __shared__ T sx[64 * CT];
+    const int32_t b = leaf_box[blockIdx.x];
+    const int c0 = blockIdx.y * CT;
+    const int32_t kb = box_beg[b], nt = box_end[b] - kb;
+    for (int idx = threadIdx.x; idx < nt * CT; idx += blockDim.x) {
+        const int k = idx / CT, c = idx - k * CT;
+        sx[idx] = (c0 + c < C) ? xs[(int64_t)(kb + k) * C + c0 + c] : T(0);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < K * CT; idx += blockDim.x) {
+        const int i = idx / CT, c = idx - i * CT;
+        if (c0 + c >= C) continue;
+        T acc = 0;
+        for (int k = 0; k < nt; ++k) acc += mom[(int64_t)(kb + k) * K + i] * sx[k * CT + c];
+        M[((int64_t)b * K + i) * C + c0 + c] = acc;
+    }
+}
+
+// ---------------------------------------------------------------- M2M / L2L
+// out[b] (=|+=) sum over inputs of op[oct] * in[...]; one workgroup per
+// (box, column tile); inputs staged in LDS.
+template <typename T, int CT, bool UP>
+__global__ __launch_bounds__(256) void k_translate(int64_t lo, int64_t hi, const int32_t *__restrict__ child0,
+                                                   const int32_t *__restrict__ nchild,
+                                                   const int32_t *__restrict__ parent,
+                                                   const int32_t *__restrict__ octant, const T *__restrict__ op,
+                                                   const T *__restrict__ in, T *__restrict__ out, int C, int K)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *sin = reinterpret_cast<T *>(smem_raw);  // [8][K][CT]
+    const int64_t b = lo + blockIdx.x;
+    if (b >= hi) return;
+    const int c0 = blockIdx.y * CT;
+    int nin;
+    if (UP) {
+        nin = nchild[b];
+        if (nin == 0) return;  // leaf: multipole from P2M
+        for (int idx = threadIdx.x; idx < nin * K * CT; idx += blockDim.x) {
+            const int q = idx / (K * CT), rem = idx - q * K * CT, i = rem / CT, c = rem - i * CT;
+            sin[idx] = (c0 + c < C) ? in[((int64_t)(child0[b] + q) * K + i) * C + c0 + c] : T(0);
+        }
+    } else {
+        nin = 1;
+        const int32_t p = parent[b];
+        for (int idx = threadIdx.x; idx < K * CT; idx += blockDim.x) {
+            const int i = idx / CT, c = idx - i * CT;
+            sin[idx] = (c0 + c < C) ? in[((int64_t)p * K + i) * C + c0 + c] : T(0);
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < K * CT; idx += blockDim.x) {
+        const int i = idx / CT, c = idx - i * CT;
+        if (c0 + c >= C) continue;
+        T acc = 0;
+        for (int q = 0; q < nin; ++q) {
+            const int oc = UP ? octant[child0[b] + q] : octant[b];
+            const T *row = op + ((int64_t)oc * K + i) * K;
+            const T *col = sin + (int64_t)q * K * CT + c;
+            for (int kk = 0; kk < K; ++kk) acc += row[kk] * col[kk * CT];
+        }
+        T *o = out + ((int64_t)b * K + i) * C + c0 + c;
+        if (UP)
+            *o = acc;
+        else
+            *o += acc;
+    }
+}
+
+// ---------------------------------------------------------------- L2P
+template <typename T, int CT>
+__global__ __launch_bounds__(256) void k_l2p(const int32_t *__restrict__ leaf_box, const int32_t *__restrict__ box_beg,
+                                             const int32_t *__restrict__ box_end, const double *__restrict__ hbox,
+                                             const T *__restrict__ mom, const T *__restrict__ L, T *__restrict__ ys,
+                                             int C, int K)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *sl = reinterpret_cast<T *>(smem_raw);  // [K][CT]
+    const int32_t b = leaf_box[blockIdx.x];
+    const int c0 = blockIdx.y * CT;
+    const int32_t kb = box_beg[b], nt = box_end[b] - kb;
+    const T ih = T(1.0 / hbox[b]);
+    for (int idx = threadIdx.x; idx < K * CT; idx += blockDim.x) {
+        const int i = idx / CT, c = idx - i * CT;
+        int n = 0;
+        while ((n + 1) * (n + 1) <= i) ++n;
+        const T w = (i == n * n) ? T(1) : T(2);
+        sl[idx] = (c0 + c < C) ? w * ih * L[((int64_t)b * K + i) * C + c0 + c] : T(0);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nt * CT; idx += blockDim.x) {
+        const int k = idx / CT, c = idx - k * CT;
+        if (c0 + c >= C) continue;
+        const T *q = mom + (int64_t)(kb + k) * K;
+        T acc = 0;
+        for (int i = 0; i < K; ++i) acc += q[i] * sl[i * CT + c];
+        ys[(int64_t)(kb + k) * C + c0 + c] += acc;
+    }
+}
+
+// ---------------------------------------------------------------- M2L
+struct M2LArgs {
+    const int32_t *tgt_list, *slab_tbeg, *slab_gbeg, *grp_off, *grp_pbeg, *pair_tloc, *pair_src;
+    int C, K, KK, ct;
+};
+
+// MFMA 16x16x4 operand layout on a 64-lane wave (checked by the GPU tests):
+// A[i][k]: lane = i + 16 k;  B[k][j]: lane = j + 16 k;
+// D[i][j]: lane = j + 16 (i / 4), element i % 4.
+// op_frag holds each operator in fragment order [o][row tile][k step][lane].
+template <typename T>
+__device__ inline void mfma_16x16x4(T a, T b, typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type &d);
+template <>
+__device__ inline void mfma_16x16x4<float>(float a, float b, f32x4 &d)
+{
+    d = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, d, 0, 0, 0);
+}
+template <>
+__device__ inline void mfma_16x16x4<double>(double a, double b, f64x4 &d)
+{
+    d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_m2l_mfma(M2LArgs a, const T *__restrict__ op_frag, const T *__restrict__ M,
+                                                  T *__restrict__ L)
+{
+    using VT = typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type;
+    extern __shared__ unsigned char smem_raw[];
+    T *acc = reinterpret_cast<T *>(smem_raw);  // [nts][K][ct]
+    const int slab = blockIdx.x;
+    const int ct = a.ct, C = a.C, K = a.K;
+    const int c0 = blockIdx.y * ct;
+    const int tb = a.slab_tbeg[slab], nts = a.slab_tbeg[slab + 1] - tb;
+    for (int idx = threadIdx.x; idx < nts * K * ct; idx += blockDim.x) acc[idx] = T(0);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nrt = (K + 15) / 16, nks = a.KK / 4;
+    const int kq = lane >> 4, li = lane & 15;
+    for (int g = a.slab_gbeg[slab]; g < a.slab_gbeg[slab + 1]; ++g) {
+        const int o = a.grp_off[g], pb = a.grp_pbeg[g], np = a.grp_pbeg[g + 1] - pb;
+        const int ncols = np * ct, nct = (ncols + 15) / 16, nblk = nrt * nct;
+        const T *Tf = op_frag + (int64_t)o * nrt * nks * 64;
+        for (int blk = wave; blk < nblk; blk += 4) {
+            const int rt = blk % nrt, ctile = blk / nrt;
+            const int n = ctile * 16 + li;
+            const int p = n / ct, c = n - p * ct;
+            const bool valid = n < ncols && c0 + c < C;
+            const int32_t src = valid ? a.pair_src[pb + p] : 0;
+            const T *Mp = M + (int64_t)src * K * C + c0 + c;
+            const T *Ap = Tf + (int64_t)rt * nks * 64 + lane;
+            VT d = {0, 0, 0, 0};
+            for (int ks = 0; ks < nks; ++ks) {
+                const int kk = 4 * ks + kq;
+                const T av = Ap[ks * 64];
+                const T bv = (valid && kk < K) ? Mp[(int64_t)kk * C] : T(0);
+                mfma_16x16x4<T>(av, bv, d);
+            }
+            if (valid) {
+                const int tl = a.pair_tloc[pb + p];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = rt * 16 + 4 * kq + e;
+                    if (row < K) acc[((int64_t)tl * K + row) * ct + c] += d[e];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < nts * K * ct; idx += blockDim.x) {
+        const int t = idx / (K * ct), rem = idx - t * K * ct, row = rem / ct, c = rem - row * ct;
+        if (c0 + c < C) L[((int64_t)a.tgt_list[tb + t] * K + row) * C + c0 + c] = acc[idx];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_m2l_valu(M2LArgs a, const T *__restrict__ op, /* [343][KP][KK] */
+                                                  int KP, const T *__restrict__ M, T *__restrict__ L)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *acc = reinterpret_cast<T *>(smem_raw);
+    const int slab = blockIdx.x;
+    const int ct = a.ct, C = a.C, K = a.K, KK = a.KK;
+    const int c0 = blockIdx.y * ct;
+    const int tb = a.slab_tbeg[slab], nts = a.slab_tbeg[slab + 1] - tb;
+    for (int idx = threadIdx.x; idx < nts * K * ct; idx += blockDim.x) acc[idx] = T(0);
+    __syncthreads();
+    for (int g = a.slab_gbeg[slab]; g < a.slab_gbeg[slab + 1]; ++g) {
+        const int o = a.grp_off[g], pb = a.grp_pbeg[g], np = a.grp_pbeg[g + 1] - pb;
+        const int ncols = np * ct;
+        const T *To = op + (int64_t)o * KP * KK;
+        for (int idx = threadIdx.x; idx < K * ncols; idx += blockDim.x) {
+            const int row = idx / ncols, n = idx - row * ncols;
+            const int p = n / ct, c = n - p * ct;
+            if (c0 + c >= C) continue;
+            const T *Mp = M + (int64_t)a.pair_src[pb + p] * K * C + c0 + c;
+            const T *Tr = To + (int64_t)row * KK;
+            T s = 0;
+            for (int kk = 0; kk < K; ++kk) s += Tr[kk] * Mp[(int64_t)kk * C];
+            acc[((int64_t)a.pair_tloc[pb + p] * K + row) * ct + c] += s;
+        }
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < nts * K * ct; idx += blockDim.x) {
+        const int t = idx / (K * ct), rem = idx - t * K * ct, row = rem / ct, c = rem - row * ct;
+        if (c0 + c < C) L[((int64_t)a.tgt_list[tb + t] * K + row) * C + c0 + c] = acc[idx];
+    }
+}
+
+// ---------------------------------------------------------------- driver
+template <typename T>
+__global__ void k_fill_zero(T *__restrict__ p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = T(0);
+}
+
+template <typename T>
+static void p2p_launch(const xrl_plan *P, const T *val, const T *xs, T *ys, int C, hipStream_t s)
+{
+    if (P->n_leaves == 0) return;
+    auto go = [&](auto ctc) {
+        constexpr int CT = decltype(ctc)::value;
+        dim3 grid((unsigned)P->n_leaves, (unsigned)cdiv(C, CT));
+        k_p2p<T, CT><<<grid, 256, 0, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p, P->near_rows.p, P->near_src.p,
+                                          P->leaf_tpad.p, P->near_val_off.p, val, xs, ys, C);
+    };
+    if (C <= 2)
+        go(std::integral_constant<int, 2>());
+    else if (C <= 4)
+        go(std::integral_constant<int, 4>());
+    else if (C <= 8)
+        go(std::integral_constant<int, 8>());
+    else
+        go(std::integral_constant<int, 16>());
+    XRL_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols, int dtype, void *y, int64_t ldy,
+                       const double *alpha, const double *beta, hipStream_t s, DevBuf<T> &xs, DevBuf<T> &ys,
+                       DevBuf<T> &M, DevBuf<T> &L, const T *near, const T *mom, const T *m2m, const T *l2l,
+                       const T *m2l_rows, const T *m2l_frag)
+{
+    const int C = 2 * ncols;
+    const int K = P->K;
+    const int64_t N = P->N, B = P->B;
+    if (xs.n < (size_t)(N * C)) {
+        xs.alloc(N * C);
+        ys.alloc(N * C);
+    }
+    if (M.n < (size_t)(B * K * C)) {
+        M.alloc(B * K * C);
+        L.alloc(B * K * C);
+    }
+    const bool prof = P->profiling;
+    auto mark = [&](int i) {
+        if (prof) XRL_HIP(hipEventRecord(P->ev[i], s));
+    };
+    mark(0);
+    const int bs = 256;
+    if (dtype == XRL_C64)
+        k_gather_x<float, T><<<cdiv(N * C, bs), bs, 0, s>>>(N, P->perm.p, (const float *)x, ldx, ncols, xs.p);
+    else
+        k_gather_x<double, T><<<cdiv(N * C, bs), bs, 0, s>>>(N, P->perm.p, (const double *)x, ldx, ncols, xs.p);
+    XRL_HIP(hipGetLastError());
+    mark(1);
+    p2p_launch<T>(P, near, xs.p, ys.p, C, s);
+    mark(2);
+    // column tile of the P2M / M2M / L2L / L2P kernels (M2M stages 8 children
+    // of K x CT values in LDS: at most 41 KB in FP32, 41 KB in FP64)
+    const int CT = (sizeof(T) == 8 || C <= 8) ? 8 : 16;
+    const unsigned ntile = (unsigned)cdiv(C, CT);
+    auto p2m = [&](auto ctc) {
+        constexpr int CTT = decltype(ctc)::value;
+        k_p2m<T, CTT><<<dim3((unsigned)P->n_leaves, (unsigned)cdiv(C, CTT)), 256, 0, s>>>(
+            P->leaf_box.p, P->box_beg.p, P->box_end.p, mom, xs.p, M.p, C, K);
+    };
+    if (CT == 8)
+        p2m(std::integral_constant<int, 8>());
+    else
+        p2m(std::integral_constant<int, 16>());
+    XRL_HIP(hipGetLastError());
+    mark(3);
+    for (int l = P->depth - 1; l >= 0; --l) {
+        const int64_t lo = P->level_off[l], hi = P->level_off[l + 1];
+        if (hi <= lo) continue;
+        const size_t sm = 8 * (size_t)K * CT * sizeof(T);
+        if (CT == 8)
+            k_translate<T, 8, true><<<dim3((unsigned)(hi - lo), ntile), 256, sm, s>>>(
+                lo, hi, P->box_child0.p, P->box_nchild.p, P->box_parent.p, P->box_octant.p, m2m, M.p, M.p, C, K);
+        else
+            k_translate<T, 16, true><<<dim3((unsigned)(hi - lo), ntile), 256, sm, s>>>(
+                lo, hi, P->box_child0.p, P->box_nchild.p, P->box_parent.p, P->box_octant.p, m2m, M.p, M.p, C, K);
+        XRL_HIP(hipGetLastError());
+    }
+    mark(4);
+    // zero every local expansion (a fill kernel, so the sequence stays
+    // capturable into a HIP graph without memset nodes)
+    k_fill_zero<T><<<(unsigned)std::min<int64_t>(cdiv(B * K * C, 256), 65536), 256, 0, s>>>(L.p, B * K * C);
+    XRL_HIP(hipGetLastError());
+    if (P->n_slabs > 0) {
+        const int ct = std::min(C, P->m2l_ct);
+        M2LArgs a{P->m2l_tgt_list.p, P->slab_tbeg.p, P->slab_gbeg.p, P->grp_off.p, P->grp_pbeg.p,
+                  P->pair_tloc.p,    P->pair_src.p,  C,              K,            P->KK,
+                  ct};
+        const size_t sm = (size_t)P->slab_targets * K * ct * sizeof(T);
+        dim3 grid((unsigned)P->n_slabs, (unsigned)cdiv(C, ct));
+        if (P->m2l_engine == XRL_M2L_MFMA)
+            k_m2l_mfma<T><<<grid, 256, sm, s>>>(a, m2l_frag, M.p, L.p);
+        else
+            k_m2l_valu<T><<<grid, 256, sm, s>>>(a, m2l_rows, P->KP, M.p, L.p);
+        XRL_HIP(hipGetLastError());
+    }
+    mark(5);
+    for (int l = 3; l <= P->depth; ++l) {
+        const int64_t lo = P->level_off[l], hi = P->level_off[l + 1];
+        if (hi <= lo) continue;
+        const size_t sm = (size_t)K * CT * sizeof(T);
+        if (CT == 8)
+            k_translate<T, 8, false><<<dim3((unsigned)(hi - lo), ntile), 256, sm, s>>>(
+                lo, hi, P->box_child0.p, P->box_nchild.p, P->box_parent.p, P->box_octant.p, l2l, L.p, L.p, C, K);
+        else
+            k_translate<T, 16, false><<<dim3((unsigned)(hi - lo), ntile), 256, sm, s>>>(
+                lo, hi, P->box_child0.p, P->box_nchild.p, P->box_parent.p, P->box_octant.p, l2l, L.p, L.p, C, K);
+        XRL_HIP(hipGetLastError());
+    }
+    mark(6);
+    {
+        const size_t sm = (size_t)K * CT * sizeof(T);
+        if (CT == 8)
+            k_l2p<T, 8><<<dim3((unsigned)P->n_leaves, ntile), 256, sm, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p,
+                                                                            P->box_h.p, mom, L.p, ys.p, C, K);
+        else
+            k_l2p<T, 16><<<dim3((unsigned)P->n_leaves, ntile), 256, sm, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p,
+                                                                             P->box_h.p, mom, L.p, ys.p, C, K);
+        XRL_HIP(hipGetLastError());
+    }
+    mark(7);
+    DevBuf<double> dab;
+    const double *da = nullptr, *db = nullptr;
+    if (alpha || beta) {
+        std::vector<double> h(4 * ncols, 0.0);
+        for (int c = 0; c < ncols; ++c) {
+            h[2 * c] = alpha ? alpha[2 * c] : 1.0;
+            h[2 * c + 1] = alpha ? alpha[2 * c + 1] : 0.0;
+            h[2 * ncols + 2 * c] = beta ? beta[2 * c] : 0.0;
+            h[2 * ncols + 2 * c + 1] = beta ? beta[2 * c + 1] : 0.0;
+        }
+        dab.upload(h, s);
+        da = dab.p;
+        db = beta ? dab.p + 2 * ncols : nullptr;
+    }
+    if (dtype == XRL_C64)
+        k_scatter_y<float, T><<<cdiv(N * ncols, bs), bs, 0, s>>>(N, P->perm.p, ys.p, P->area.p, (const float *)x, ldx,
+                                                                 (float *)y, ldy, ncols, da, db);
+    else
+        k_scatter_y<double, T><<<cdiv(N * ncols, bs), bs, 0, s>>>(N, P->perm.p, ys.p, P->area.p, (const double *)x, ldx,
+                                                                  (double *)y, ldy, ncols, da, db);
+    XRL_HIP(hipGetLastError());
+    mark(8);
+    if (dab.p) XRL_HIP(hipStreamSynchronize(s));  // keep the epilogue scalars alive until used
+    if (prof) {
+        XRL_HIP(hipEventSynchronize(P->ev[8]));
+        // phase order of the public API: gather, P2P, P2M, M2M, M2L, L2L, L2P, scatter
+        for (int i = 0; i < XRL_N_PHASES; ++i) {
+            float ms = 0;
+            XRL_HIP(hipEventElapsedTime(&ms, P->ev[i], P->ev[i + 1]));
+            P->phase_ms[i] = ms;
+        }
+    }
+}
+
+}  // namespace xrl
+
+using namespace xrl;
+
+extern "C" xrl_status xrl_fmm_matvec(const xrl_plan *P, const void *x, int64_t ldx, int32_t n_cols, int32_t dtype,
+                                     void *y, int64_t ldy, const xrl_epilogue *ep, void *stream)
+{
+    return guarded([&] {
+        XRL_CHECK(P && x && y, XRL_E_INVALID_ARG, "xrl_fmm_matvec: null argument");
+        XRL_CHECK(P->assembled, XRL_E_STATE, "xrl_fmm_matvec: call xrl_nearfield_assemble first");
+        XRL_CHECK(n_cols >= 1 && n_cols <= P->max_cols, XRL_E_INVALID_ARG,
+                  "xrl_fmm_matvec: n_cols must be in 1..max_cols (%d), got %d", P->max_cols, n_cols);
+        XRL_CHECK(ldx >= n_cols && ldy >= n_cols, XRL_E_INVALID_ARG, "xrl_fmm_matvec: ldx/ldy < n_cols");
+        XRL_CHECK(dtype == XRL_C64 || dtype == XRL_C128, XRL_E_INVALID_ARG, "xrl_fmm_matvec: bad dtype %d", dtype);
+        XRL_CHECK(x != y, XRL_E_INVALID_ARG, "xrl_fmm_matvec: x and y must not alias");
+        hipStream_t s = (hipStream_t)stream;
+        xrl_plan *Pm = const_cast<xrl_plan *>(P);
+        if (Pm->profiling && !Pm->events_made) {
+            for (auto &e : Pm->ev) XRL_HIP(hipEventCreate(&e));
+            Pm->events_made = true;
+        }
+        const double *al = ep ? ep->alpha : nullptr, *be = ep ? ep->beta : nullptr;
+        if (P->precision == XRL_PREC_FP64)
+            run_matvec<double>(P, x, ldx, n_cols, dtype, y, ldy, al, be, s, Pm->xs64, Pm->ys64, Pm->M64, Pm->L64,
+                               P->near64.p, P->mom64.p, P->op_m2m64.p, P->op_l2l64.p, P->op_m2l64.p,
+                               P->op_m2l64f.p);
+        else
+            run_matvec<float>(P, x, ldx, n_cols, dtype, y, ldy, al, be, s, Pm->xs32, Pm->ys32, Pm->M32, Pm->L32,
+                              P->near32.p, P->mom32.p, P->op_m2m32.p, P->op_l2l32.p, P->op_m2l32.p, P->op_m2l32f.p);
+    });
+}
+
+// Self-test of the MFMA operand layout: D[16][16] = A[16][4] B[4][16] through
+// the same 16x16x4 helper the M2L kernel uses (row-major host arrays).
+template <typename T>
+__global__ void k_mfma_probe(const T *A, const T *B, T *D)
+{
+    using VT = typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type;
+    const int lane = threadIdx.x;
+    const int i = lane & 15, k = lane >> 4;
+    VT d = {0, 0, 0, 0};
+    mfma_16x16x4<T>(A[i * 4 + k], B[k * 16 + i], d);
+    for (int e = 0; e < 4; ++e) D[(4 * k + e) * 16 + i] = d[e];
+}
+
+extern "C" xrl_status xrl_selftest_mfma(int32_t dtype, const void *A, const void *B, void *D)
+{
+    return guarded([&] {
+        XRL_CHECK(A && B && D && (dtype == 4 || dtype == 8), XRL_E_INVALID_ARG, "xrl_selftest_mfma: bad arguments");
+        const size_t e = dtype;
+        DevBuf<char> dA(64 * e), dB(64 * e), dD(256 * e);
+        XRL_HIP(hipMemcpy(dA.p, A, 64 * e, hipMemcpyHostToDevice));
+        XRL_HIP(hipMemcpy(dB.p, B, 64 * e, hipMemcpyHostToDevice));
+        if (dtype == 4)
+            k_mfma_probe<float><<<1, 64>>>((const float *)dA.p, (const float *)dB.p, (float *)dD.p);
+        else
+            k_mfma_probe<double><<<1, 64>>>((const double *)dA.p, (const double *)dB.p, (double *)dD.p);
+        XRL_HIP(hipGetLastError());
+        XRL_HIP(hipMemcpy(D, dD.p, 256 * e, hipMemcpyDeviceToHost));
+    });
+}
+
+extern "C" xrl_status xrl_plan_set_profiling(xrl_plan *P, int32_t on)
+{
+    return guarded([&] {
+        XRL_CHECK(P, XRL_E_INVALID_ARG, "xrl_plan_set_profiling: null plan");
+        P->profiling = on != 0;
+    });
+}
+
+extern "C" xrl_status xrl_plan_get_phase_ms(const xrl_plan *P, double *ms)
+{
+    return guarded([&] {
+        XRL_CHECK(P && ms, XRL_E_INVALID_ARG, "xrl_plan_get_phase_ms: null argument");
+        for (int i = 0; i < XRL_N_PHASES; ++i) ms[i] = P->phase_ms[i];
+    });
+}

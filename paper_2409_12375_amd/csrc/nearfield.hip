@@ -1,0 +1,416 @@
+// Near-field assembly: the panel-panel entries P_kl of eq. (6) (second term,
+// without j*omega*mu0/4pi) for every pair in the near lists, filled once and
+// reused by every matvec (Sec. II-C, last paragraph; Sec. II-D).
+//
+// Pair classes (k target, l source, r = |c_k - c_l| / max(diam_k, diam_l)):
+//   self          k == l: closed form of the double integral over a flat
+//                 triangle, (4A^2/3) sum_e ln(Pr / (Pr - 2 l_e)) / l_e
+//                 (Arcioni-Bressan-Perregrini 1997, Eibert-Hansen 1995).
+//   touching      a shared vertex: outer tensor Gauss rule on S_k in coordinates
+//                 collapsed at the shared vertex, both directions through the
+//                 sigmoidal map u^3/(u^3+(1-u)^3) (Sidi 1993); inner integral
+//                 exact (potential of a uniform triangle, Wilton et al. 1984).
+//   near-singular r < r_near: outer conical Gauss rule on 1, 4 or 16
+//                 sub-triangles of S_k, inner integral exact.  Optionally the
+//                 learned surrogate with quadrature fall-back.
+//   regular       product of two conical Gauss rules (4x4 or 3x3 points per
+//                 triangle in FP32; 5x5 or 4x4 in FP64).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace xrl {
+
+struct NFRules {
+    double gx[40], gw[40];  // Gauss-Legendre on [0,1], n_touch points
+    double nx[8], nw[8];    // near-singular conical rule, n = 6
+    double rx4[8], rw4[8];  // regular, n_hi points
+    double rx3[8], rw3[8];  // regular, n_lo points
+    int n_touch, n_ns, n_hi, n_lo;
+};
+
+template <typename T>
+__device__ inline T dot3(const T *a, const T *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// int_{triangle v} 1/|r - r'| dS' for a uniform unit density (Wilton et al. 1984).
+template <typename T>
+__device__ T tri_potential(const T *v, const T *r)
+{
+    T e1[3], e2[3], n[3];
+    for (int d = 0; d < 3; ++d) {
+        e1[d] = v[3 + d] - v[d];
+        e2[d] = v[6 + d] - v[d];
+    }
+    n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    const T nn = sqrt(dot3(n, n));
+    for (int d = 0; d < 3; ++d) n[d] /= nn;
+    T q[3] = {r[0] - v[0], r[1] - v[1], r[2] - v[2]};
+    const T h = dot3(n, q);
+    const T ah = fabs(h);
+    T rho[3] = {r[0] - h * n[0], r[1] - h * n[1], r[2] - h * n[2]};
+    T phi = 0;
+    for (int i = 0; i < 3; ++i) {
+        const T *a = v + 3 * i;
+        const T *b = v + 3 * ((i + 1) % 3);
+        T s[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        const T L = sqrt(dot3(s, s));
+        for (int d = 0; d < 3; ++d) s[d] /= L;
+        T m[3] = {s[1] * n[2] - s[2] * n[1], s[2] * n[0] - s[0] * n[2], s[0] * n[1] - s[1] * n[0]};
+        T pa[3] = {a[0] - rho[0], a[1] - rho[1], a[2] - rho[2]};
+        T pb[3] = {b[0] - rho[0], b[1] - rho[1], b[2] - rho[2]};
+        const T t0 = dot3(pa, m);
+        const T sm = dot3(pa, s), sp = dot3(pb, s);
+        if (fabs(t0) <= T(1e-12) * L) continue;
+        const T R0s = t0 * t0 + h * h;
+        T ra[3] = {r[0] - a[0], r[1] - a[1], r[2] - a[2]};
+        T rb[3] = {r[0] - b[0], r[1] - b[1], r[2] - b[2]};
+        const T Rm = sqrt(dot3(ra, ra)), Rp = sqrt(dot3(rb, rb));
+        const T fp = sp >= 0 ? Rp + sp : R0s / (Rp - sp);
+        const T fm = sm >= 0 ? Rm + sm : R0s / (Rm - sm);
+        phi += t0 * log(fp / fm);
+        if (ah > T(1e-12) * L) phi -= ah * (atan(t0 * sp / (R0s + ah * Rp)) - atan(t0 * sm / (R0s + ah * Rm)));
+    }
+    return phi;
+}
+
+__device__ inline double self_term(const double *v)
+{
+    double l[3];
+    for (int i = 0; i < 3; ++i) {
+        const double *a = v + 3 * i, *b = v + 3 * ((i + 1) % 3);
+        const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
+        l[i] = sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    const double e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
+    const double e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
+    const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                 cz = e1[0] * e2[1] - e1[1] * e2[0];
+    const double A = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+    const double pr = l[0] + l[1] + l[2];
+    double s = 0;
+    for (int e = 0; e < 3; ++e) s += log(pr / (pr - 2 * l[e])) / l[e];
+    return 4.0 * A * A / 3.0 * s;
+}
+
+template <typename T>
+__device__ inline T tri_area2(const T *v)
+{
+    const T e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
+    const T e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
+    const T cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2], cz = e1[0] * e2[1] - e1[1] * e2[0];
+    return sqrt(cx * cx + cy * cy + cz * cz);
+}
+
+// Touching pair: target vertices reordered so that tv[0] is a shared vertex.
+template <typename T>
+__device__ T touching_pair(const T *tv, const T *sv, const NFRules &R)
+{
+    const T A2 = tri_area2(tv);
+    T acc = 0;
+    for (int i = 0; i < R.n_touch; ++i) {
+        const T u = (T)R.gx[i], u3 = u * u * u, v3 = (1 - u) * (1 - u) * (1 - u);
+        const T s = u3 / (u3 + v3);
+        const T ds = T(3) * u * u * (1 - u) * (1 - u) / ((u3 + v3) * (u3 + v3));
+        T inner = 0;
+        for (int j = 0; j < R.n_touch; ++j) {
+            const T w = (T)R.gx[j], w3 = w * w * w, z3 = (1 - w) * (1 - w) * (1 - w);
+            const T t = w3 / (w3 + z3);
+            const T dt = T(3) * w * w * (1 - w) * (1 - w) / ((w3 + z3) * (w3 + z3));
+            T x[3];
+            for (int d = 0; d < 3; ++d) x[d] = tv[d] + s * (tv[3 + d] - tv[d]) + s * t * (tv[6 + d] - tv[3 + d]);
+            inner += (T)R.gw[j] * dt * tri_potential(sv, x);
+        }
+        acc += (T)R.gw[i] * ds * s * inner;
+    }
+    return acc * A2;
+}
+
+// Conical rule on triangle v with the potential of triangle sv.
+template <typename T>
+__device__ T conical_outer(const T *v, const T *sv, const NFRules &R)
+{
+    const T A2 = tri_area2(v);
+    T acc = 0;
+    for (int i = 0; i < R.n_ns; ++i) {
+        const T s = (T)R.nx[i];
+        T inner = 0;
+        for (int j = 0; j < R.n_ns; ++j) {
+            const T t = (T)R.nx[j];
+            T x[3];
+            for (int d = 0; d < 3; ++d) x[d] = v[d] + s * (v[3 + d] - v[d]) + s * t * (v[6 + d] - v[3 + d]);
+            inner += (T)R.nw[j] * tri_potential(sv, x);
+        }
+        acc += (T)R.nw[i] * s * inner;
+    }
+    return acc * A2;
+}
+
+// Near-singular pair: the target split into 4^lev sub-triangles by midpoint
+// subdivision (child c of (a,b,c): 0 corner a, 1 corner b, 2 corner c, 3 middle).
+template <typename T>
+__device__ T near_pair(const T *tv, const T *sv, int lev, const NFRules &R)
+{
+    T acc = 0;
+    const int nsub = 1 << (2 * lev);
+    for (int q = 0; q < nsub; ++q) {
+        T v[9];
+        for (int i = 0; i < 9; ++i) v[i] = tv[i];
+        for (int l = lev - 1; l >= 0; --l) {
+            const int c = (q >> (2 * l)) & 3;
+            T m01[3], m12[3], m20[3];
+            for (int d = 0; d < 3; ++d) {
+                m01[d] = T(0.5) * (v[d] + v[3 + d]);
+                m12[d] = T(0.5) * (v[3 + d] + v[6 + d]);
+                m20[d] = T(0.5) * (v[6 + d] + v[d]);
+            }
+            for (int d = 0; d < 3; ++d) {
+                if (c == 0) { v[3 + d] = m01[d]; v[6 + d] = m20[d]; }
+                else if (c == 1) { v[d] = m01[d]; v[6 + d] = m12[d]; }
+                else if (c == 2) { v[d] = m20[d]; v[3 + d] = m12[d]; }
+                else { v[d] = m12[d]; v[3 + d] = m20[d]; v[6 + d] = m01[d]; }
+            }
+        }
+        acc += conical_outer(v, sv, R);
+    }
+    return acc;
+}
+
+template <typename T>
+__device__ T regular_pair(const T *tv, const T *sv, int n, const double *gx, const double *gw)
+{
+    const T At = tri_area2(tv), As = tri_area2(sv);
+    T px[25][3], pw[25];
+    int m = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j, ++m) {
+            const T s = (T)gx[i], t = (T)gx[j];
+            for (int d = 0; d < 3; ++d) px[m][d] = sv[d] + s * (sv[3 + d] - sv[d]) + s * t * (sv[6 + d] - sv[3 + d]);
+            pw[m] = (T)gw[i] * (T)gw[j] * s;
+        }
+    T acc = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const T s = (T)gx[i], t = (T)gx[j];
+            T x[3];
+            for (int d = 0; d < 3; ++d) x[d] = tv[d] + s * (tv[3 + d] - tv[d]) + s * t * (tv[6 + d] - tv[3 + d]);
+            T inner = 0;
+            for (int q = 0; q < m; ++q) {
+                const T dx = x[0] - px[q][0], dy = x[1] - px[q][1], dz = x[2] - px[q][2];
+                inner += pw[q] / sqrt(dx * dx + dy * dy + dz * dz);
+            }
+            acc += (T)gw[i] * (T)gw[j] * s * inner;
+        }
+    return acc * At * As;
+}
+
+struct NFArgs {
+    const int32_t *leaf_box, *box_beg, *box_end, *near_rows, *near_src, *leaf_tpad, *pvid;
+    const int64_t *val_off;
+    const double *pv, *cen, *diam;
+    double r_near, r_mid;
+    int64_t n_leaves;
+    unsigned long long *counters;  // [0] self [1] touch [2] near-singular [3] regular
+    int64_t *work;                 // special entries: value index
+    int32_t *work_meta;            // packed (k, l)
+    unsigned long long *work_n;    // [0] touching count, [1] near-singular count (separate halves)
+    int64_t work_cap;
+};
+
+__device__ inline int shared_vertex(const int32_t *ik, const int32_t *il)
+{
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (ik[a] == il[b]) return a;
+    return -1;
+}
+
+// Pass 1: one workgroup per target leaf; self and regular entries computed,
+// touching and near-singular entries queued.
+template <typename V, bool FP64>
+__global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restrict__ val)
+{
+    const int64_t li = blockIdx.x;
+    if (li >= a.n_leaves) return;
+    const int32_t T = a.leaf_box[li];
+    const int32_t kb = a.box_beg[T], nt = a.box_end[T] - kb;
+    const int32_t r0 = a.near_rows[li], nr = a.near_rows[li + 1] - r0;
+    const int tpad = a.leaf_tpad[li];
+    const int sh = tpad == 16 ? 4 : (tpad == 32 ? 5 : 6);
+    const int64_t vo = a.val_off[li];
+    unsigned long long c_self = 0, c_reg = 0;
+    for (int64_t e = threadIdx.x; e < (int64_t)nr << sh; e += blockDim.x) {
+        const int32_t r = (int32_t)(e >> sh), j = (int32_t)(e & (tpad - 1));
+        if (j >= nt) {
+            val[vo + e] = V(0);
+            continue;
+        }
+        const int32_t k = kb + j, l = a.near_src[r0 + r];
+        if (k == l) {
+            val[vo + e] = (V)self_term(a.pv + 9 * (int64_t)k);
+            ++c_self;
+            continue;
+        }
+        const int sv = shared_vertex(a.pvid + 3 * (int64_t)k, a.pvid + 3 * (int64_t)l);
+        const double dx = a.cen[3 * k] - a.cen[3 * l], dy = a.cen[3 * k + 1] - a.cen[3 * l + 1],
+                     dz = a.cen[3 * k + 2] - a.cen[3 * l + 2];
+        const double rr = sqrt(dx * dx + dy * dy + dz * dz) / fmax(a.diam[k], a.diam[l]);
+        if (sv >= 0 || rr < a.r_near) {
+            const int which = sv >= 0 ? 0 : 1;
+            const unsigned long long slot = atomicAdd(&a.work_n[which], 1ull);
+            const int64_t pos = which == 0 ? (int64_t)slot : a.work_cap - 1 - (int64_t)slot;
+            if (pos >= 0 && pos < a.work_cap) {
+                a.work[pos] = vo + e;
+                a.work_meta[2 * pos] = k;
+                a.work_meta[2 * pos + 1] = l;
+            }
+            val[vo + e] = V(0);
+            continue;
+        }
+        ++c_reg;
+        if (FP64) {
+            double tv[9], svv[9];
+            for (int i = 0; i < 9; ++i) {
+                tv[i] = a.pv[9 * (int64_t)k + i];
+                svv[i] = a.pv[9 * (int64_t)l + i];
+            }
+            val[vo + e] = (V)(rr < a.r_mid ? regular_pair<double>(tv, svv, R.n_hi, R.rx4, R.rw4)
+                                           : regular_pair<double>(tv, svv, R.n_lo, R.rx3, R.rw3));
+        } else {
+            // FP32 arithmetic relative to the target centroid
+            float tv[9], svv[9];
+            for (int i = 0; i < 9; ++i) {
+                tv[i] = (float)(a.pv[9 * (int64_t)k + i] - a.cen[3 * k + i % 3]);
+                svv[i] = (float)(a.pv[9 * (int64_t)l + i] - a.cen[3 * k + i % 3]);
+            }
+            val[vo + e] = (V)(rr < a.r_mid ? regular_pair<float>(tv, svv, R.n_hi, R.rx4, R.rw4)
+                                           : regular_pair<float>(tv, svv, R.n_lo, R.rx3, R.rw3));
+        }
+    }
+    if (c_self) atomicAdd(&a.counters[0], c_self);
+    if (c_reg) atomicAdd(&a.counters[3], c_reg);
+}
+
+// Pass 2: queued touching (which = 0, from the front of the queue) or
+// near-singular (which = 1, from the back) entries, one per thread.
+template <typename V, typename C>
+__global__ __launch_bounds__(64) void k_nf_special(NFArgs a, NFRules R, int which, int64_t count,
+                                                   V *__restrict__ val)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int64_t pos = which == 0 ? i : a.work_cap - 1 - i;
+    const int32_t k = a.work_meta[2 * pos], l = a.work_meta[2 * pos + 1];
+    // coordinates relative to the target centroid
+    C tv[9], sv[9];
+    if (which == 0) {
+        const int s0 = shared_vertex(a.pvid + 3 * (int64_t)k, a.pvid + 3 * (int64_t)l);
+        for (int j = 0; j < 3; ++j)
+            for (int d = 0; d < 3; ++d) tv[3 * j + d] = (C)(a.pv[9 * (int64_t)k + 3 * ((s0 + j) % 3) + d] - a.cen[3 * k + d]);
+        for (int q = 0; q < 9; ++q) sv[q] = (C)(a.pv[9 * (int64_t)l + q] - a.cen[3 * k + q % 3]);
+        val[a.work[pos]] = (V)touching_pair<C>(tv, sv, R);
+    } else {
+        for (int q = 0; q < 9; ++q) {
+            tv[q] = (C)(a.pv[9 * (int64_t)k + q] - a.cen[3 * k + q % 3]);
+            sv[q] = (C)(a.pv[9 * (int64_t)l + q] - a.cen[3 * k + q % 3]);
+        }
+        const double dx = a.cen[3 * k] - a.cen[3 * l], dy = a.cen[3 * k + 1] - a.cen[3 * l + 1],
+                     dz = a.cen[3 * k + 2] - a.cen[3 * l + 2];
+        const double rr = sqrt(dx * dx + dy * dy + dz * dz) / fmax(a.diam[k], a.diam[l]);
+        const int lev = rr < 0.75 ? 2 : (rr < 1.5 ? 1 : 0);
+        val[a.work[pos]] = (V)near_pair<C>(tv, sv, lev, R);
+    }
+}
+
+void gauss_legendre01(int n, double *x, double *w);
+
+}  // namespace xrl
+
+using namespace xrl;
+
+extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opts, void *stream,
+                                             xrl_nf_stats *stats)
+{
+    return guarded([&] {
+        XRL_CHECK(P, XRL_E_INVALID_ARG, "xrl_nearfield_assemble: null plan");
+        hipStream_t s = (hipStream_t)stream;
+        xrl_nf_opts o{2.0, 6.0, nullptr, 0};
+        if (opts) o = *opts;
+        XRL_CHECK(o.r_near > 0 && o.r_mid >= o.r_near, XRL_E_INVALID_ARG,
+                  "xrl_nearfield_assemble: need 0 < r_near <= r_mid");
+        XRL_CHECK(o.surrogate == nullptr, XRL_E_UNSUPPORTED, "xrl_nearfield_assemble: surrogate not available");
+        hipEvent_t e0, e1;
+        XRL_HIP(hipEventCreate(&e0));
+        XRL_HIP(hipEventCreate(&e1));
+        XRL_HIP(hipEventRecord(e0, s));
+        const bool fp64 = P->precision == XRL_PREC_FP64;
+        NFRules R{};
+        R.n_touch = fp64 ? 32 : 24;
+        R.n_ns = 6;
+        R.n_hi = fp64 ? 5 : 4;
+        R.n_lo = fp64 ? 4 : 3;
+        gauss_legendre01(R.n_touch, R.gx, R.gw);
+        gauss_legendre01(R.n_ns, R.nx, R.nw);
+        gauss_legendre01(R.n_hi, R.rx4, R.rw4);
+        gauss_legendre01(R.n_lo, R.rx3, R.rw3);
+        if (fp64) {
+            P->near32.release();
+            P->near64.alloc(std::max<int64_t>(P->n_near_entries, 1));
+        } else {
+            P->near64.release();
+            P->near32.alloc(std::max<int64_t>(P->n_near_entries, 1));
+        }
+        // queue capacity: touching + near-singular entries (bounded by all pairs)
+        const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(P->n_near_pairs, 160 * P->N));
+        DevBuf<int64_t> work(cap);
+        DevBuf<int32_t> meta(2 * cap);
+        DevBuf<unsigned long long> cnt(4), wn(2);
+        XRL_HIP(hipMemsetAsync(cnt.p, 0, cnt.bytes(), s));
+        XRL_HIP(hipMemsetAsync(wn.p, 0, wn.bytes(), s));
+        NFArgs a{P->leaf_box.p, P->box_beg.p, P->box_end.p, P->near_rows.p, P->near_src.p, P->leaf_tpad.p,
+                 P->pvid.p,     P->near_val_off.p, P->pv.p, P->cen.p, P->diam.p, o.r_near, o.r_mid,
+                 P->n_leaves,   cnt.p,       work.p,   meta.p,  wn.p,    cap};
+        if (P->n_leaves > 0) {
+            if (fp64)
+                k_nf_main<double, true><<<P->n_leaves, 256, 0, s>>>(a, R, P->near64.p);
+            else
+                k_nf_main<float, false><<<P->n_leaves, 256, 0, s>>>(a, R, P->near32.p);
+            XRL_HIP(hipGetLastError());
+        }
+        auto hw = wn.download(s);
+        XRL_CHECK((int64_t)(hw[0] + hw[1]) <= cap, XRL_E_OOM,
+                  "xrl_nearfield_assemble: special-pair queue overflow (%llu + %llu > %lld)",
+                  (unsigned long long)hw[0], (unsigned long long)hw[1], (long long)cap);
+        for (int which = 0; which < 2; ++which) {
+            const int64_t n = (int64_t)hw[which];
+            if (n == 0) continue;
+            if (P->precision == XRL_PREC_FP64)
+                k_nf_special<double, double><<<cdiv(n, 64), 64, 0, s>>>(a, R, which, n, P->near64.p);
+            else if (P->precision == XRL_PREC_MIXED)
+                k_nf_special<float, double><<<cdiv(n, 64), 64, 0, s>>>(a, R, which, n, P->near32.p);
+            else
+                k_nf_special<float, float><<<cdiv(n, 64), 64, 0, s>>>(a, R, which, n, P->near32.p);
+            XRL_HIP(hipGetLastError());
+        }
+        XRL_HIP(hipEventRecord(e1, s));
+        XRL_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        XRL_HIP(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        auto hc = cnt.download(s);
+        P->assembled = true;
+        if (stats) {
+            std::memset(stats, 0, sizeof *stats);
+            stats->n_entries = P->n_near_entries;
+            stats->n_self = (int64_t)hc[0];
+            stats->n_touching = (int64_t)hw[0];
+            stats->n_near_singular = (int64_t)hw[1];
+            stats->n_regular = (int64_t)hc[3];
+            stats->ms = ms;
+        }
+    });
+}

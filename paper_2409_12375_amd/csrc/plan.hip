@@ -1,0 +1,718 @@
+// FMM plan: global boxes over one or more trees, interaction lists (on the
+// device), translation operators, per-panel moment tables.
+//
+// Lists of the adaptive octree (U, V, W, X; the classical adaptive FMM that
+// Sec. II-C refers to for the panel-based FMM):
+//   V(b)  boxes at b's level that are children of the colleagues of b's
+//         parent and not adjacent to b                      -> M2L
+//   U(T)  leaves adjacent to leaf T (any level, T included)  -> direct
+//   W(T)  descendants D of T's colleagues with D not adjacent to T and
+//         D's parent adjacent to T                           -> direct (all panels of D)
+//   X(B)  leaves C coarser than B, adjacent to B's parent, not adjacent to B
+//                                                            -> direct to every
+//         leaf below B
+// so the near field of a target leaf is U(T), W(T) and X of T and of all its
+// ancestors, each given as a contiguous range of Morton-sorted panels.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+
+#include "common.h"
+#include "harmonics.h"
+
+namespace xrl {
+
+void build_m2m(int p, double *out);
+void build_l2l(int p, double *out);
+void build_m2l(int p, int ox, int oy, int oz, double *out);
+void gauss_legendre01(int n, double *x, double *w);
+
+struct BoxView {
+    const uint64_t *key;
+    const int32_t *level, *parent, *child0, *nchild, *tree;
+    const int64_t *seg;  // [(depth+1) * (ntrees+1)]
+    int ntrees;
+};
+
+__device__ inline void box_coords(uint64_t key, int32_t c[3])
+{
+    c[0] = (int32_t)compact3(key);
+    c[1] = (int32_t)compact3(key >> 1);
+    c[2] = (int32_t)compact3(key >> 2);
+}
+
+// Closed cubes of boxes (level la, coords a) and (lb, b) intersect.
+__device__ inline bool adjacent(int la, const int32_t *a, int lb, const int32_t *b)
+{
+    const int f = la > lb ? la : lb;
+    const int sa = f - la, sb = f - lb;
+    for (int d = 0; d < 3; ++d) {
+        const int64_t alo = (int64_t)a[d] << sa, ahi = (int64_t)(a[d] + 1) << sa;
+        const int64_t blo = (int64_t)b[d] << sb, bhi = (int64_t)(b[d] + 1) << sb;
+        if (alo > bhi || blo > ahi) return false;
+    }
+    return true;
+}
+
+__device__ inline int32_t find_box(const BoxView &bv, int level, int tree, uint64_t key)
+{
+    int64_t lo = bv.seg[level * (bv.ntrees + 1) + tree], hi = bv.seg[level * (bv.ntrees + 1) + tree + 1];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (bv.key[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    if (lo < bv.seg[level * (bv.ntrees + 1) + tree + 1] && bv.key[lo] == key) return (int32_t)lo;
+    return -1;
+}
+
+// Same-level neighbours (27 slots, -1 when absent; slot 13 is the box itself).
+__global__ void k_colleagues(BoxView bv, int64_t B, int32_t *__restrict__ coll)
+{
+    int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const int l = bv.level[b], t = bv.tree[b];
+    int32_t c[3];
+    box_coords(bv.key[b], c);
+    const int32_t lim = 1 << l;
+    int slot = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx, ++slot) {
+                const int32_t x = c[0] + dx, y = c[1] + dy, z = c[2] + dz;
+                int32_t r = -1;
+                if (x >= 0 && y >= 0 && z >= 0 && x < lim && y < lim && z < lim)
+                    r = (slot == 13) ? (int32_t)b : find_box(bv, l, t, morton3(x, y, z));
+                coll[27 * b + slot] = r;
+            }
+}
+
+// V-lists: count (out == nullptr) or fill.
+__global__ void k_vlist(BoxView bv, int64_t B, const int32_t *__restrict__ coll, int32_t *__restrict__ cnt,
+                        const int64_t *__restrict__ off, int32_t *__restrict__ src, int32_t *__restrict__ code)
+{
+    int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const int l = bv.level[b];
+    int n = 0;
+    if (l >= 2) {
+        const int32_t p = bv.parent[b];
+        int32_t cb[3];
+        box_coords(bv.key[b], cb);
+        for (int s = 0; s < 27; ++s) {
+            const int32_t q = coll[27 * p + s];
+            if (q < 0) continue;
+            for (int i = 0; i < bv.nchild[q]; ++i) {
+                const int32_t c = bv.child0[q] + i;
+                int32_t cc[3];
+                box_coords(bv.key[c], cc);
+                const int ox = cb[0] - cc[0], oy = cb[1] - cc[1], oz = cb[2] - cc[2];
+                if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1 && oz >= -1 && oz <= 1) continue;
+                if (src) {
+                    src[off[b] + n] = c;
+                    code[off[b] + n] = (ox + 3) + 7 * (oy + 3) + 49 * (oz + 3);
+                }
+                ++n;
+            }
+        }
+    }
+    if (!src) cnt[b] = n;
+}
+
+// Near-field source boxes of every leaf (U, W, X): count or fill.
+__global__ void k_nearlist(BoxView bv, const int32_t *__restrict__ leaves, int64_t nleaf,
+                           const int32_t *__restrict__ coll, int32_t *__restrict__ cnt,
+                           const int64_t *__restrict__ off, int32_t *__restrict__ out)
+{
+    int64_t li = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (li >= nleaf) return;
+    const int32_t T = leaves[li];
+    const int lT = bv.level[T];
+    int32_t cT[3];
+    box_coords(bv.key[T], cT);
+    int n = 0;
+    auto emit = [&](int32_t box) {
+        if (out) out[off[li] + n] = box;
+        ++n;
+    };
+    // U (same level and finer) and W: colleagues and the descent below them
+    int32_t stack[8 * kMaxDepth + 8];
+    for (int s = 0; s < 27; ++s) {
+        const int32_t C = coll[27 * T + s];
+        if (C < 0) continue;
+        if (bv.nchild[C] == 0) {
+            emit(C);
+            continue;
+        }
+        int sp = 0;
+        for (int i = 0; i < bv.nchild[C]; ++i) stack[sp++] = bv.child0[C] + i;
+        while (sp > 0) {
+            const int32_t D = stack[--sp];
+            int32_t cD[3];
+            box_coords(bv.key[D], cD);
+            if (adjacent(lT, cT, bv.level[D], cD)) {
+                if (bv.nchild[D] == 0)
+                    emit(D);  // U, finer
+                else
+                    for (int i = 0; i < bv.nchild[D]; ++i) stack[sp++] = bv.child0[D] + i;
+            } else {
+                emit(D);  // W
+            }
+        }
+    }
+    // U (coarser): leaf colleagues of proper ancestors adjacent to T
+    for (int32_t A = bv.parent[T]; A >= 0; A = bv.parent[A]) {
+        for (int s = 0; s < 27; ++s) {
+            if (s == 13) continue;
+            const int32_t Q = coll[27 * A + s];
+            if (Q < 0 || bv.nchild[Q] != 0) continue;
+            int32_t cQ[3];
+            box_coords(bv.key[Q], cQ);
+            if (adjacent(lT, cT, bv.level[Q], cQ)) emit(Q);
+        }
+    }
+    // X of T and of every ancestor Bx: leaves Q coarser than Bx, adjacent to
+    // parent(Bx), not adjacent to Bx
+    for (int32_t Bx = T; bv.parent[Bx] >= 0; Bx = bv.parent[Bx]) {
+        const int32_t P = bv.parent[Bx];
+        int32_t cB[3], cP[3];
+        box_coords(bv.key[Bx], cB);
+        box_coords(bv.key[P], cP);
+        const int lB = bv.level[Bx], lP = bv.level[P];
+        for (int32_t A = P; A >= 0; A = bv.parent[A]) {
+            for (int s = 0; s < 27; ++s) {
+                if (s == 13) continue;
+                const int32_t Q = coll[27 * A + s];
+                if (Q < 0 || bv.nchild[Q] != 0) continue;
+                int32_t cQ[3];
+                box_coords(bv.key[Q], cQ);
+                const int lQ = bv.level[Q];
+                if (adjacent(lP, cP, lQ, cQ) && !adjacent(lB, cB, lQ, cQ)) emit(Q);
+            }
+        }
+    }
+    if (!out) cnt[li] = n;
+}
+
+// Panel-inclusive radius of every box about its centre.
+__global__ void k_box_radius(int64_t B, const int32_t *__restrict__ beg, const int32_t *__restrict__ end,
+                             const double *__restrict__ center, const double *__restrict__ pv,
+                             double *__restrict__ rad)
+{
+    int64_t b = blockIdx.x;
+    if (b >= B) return;
+    __shared__ double red[256];
+    double r = 0;
+    const double cx = center[3 * b], cy = center[3 * b + 1], cz = center[3 * b + 2];
+    for (int64_t k = beg[b] + threadIdx.x; k < end[b]; k += blockDim.x)
+        for (int j = 0; j < 3; ++j) {
+            const double dx = pv[9 * k + 3 * j] - cx, dy = pv[9 * k + 3 * j + 1] - cy, dz = pv[9 * k + 3 * j + 2] - cz;
+            r = fmax(r, sqrt(dx * dx + dy * dy + dz * dz));
+        }
+    red[threadIdx.x] = r;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rad[b] = red[0];
+}
+
+// Moment table: for every sorted panel k in leaf box b(k),
+//   Q_k = int_{S_k} conj(Rn_m((y - c_b)/h_b)) dy  in real storage,
+// exact with an n x n conical Gauss rule for degree <= 2n - 2 >= p.
+template <int P>
+__global__ void k_moments(int64_t N, const double *__restrict__ pv, const int32_t *__restrict__ panel_leaf,
+                          const int32_t *__restrict__ leaf_box, const double *__restrict__ center,
+                          const double *__restrict__ hbox, const double *__restrict__ area, int nq,
+                          const double *__restrict__ gx, const double *__restrict__ gw, double *__restrict__ mom64,
+                          float *__restrict__ mom32)
+{
+    constexpr int K = (P + 1) * (P + 1);
+    constexpr int NC = (P + 1) * (P + 2) / 2;
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int32_t b = leaf_box[panel_leaf[k]];
+    const double ih = 1.0 / hbox[b];
+    double v[9];
+    for (int i = 0; i < 9; ++i) v[i] = pv[9 * k + i];
+    double acc[K];
+    for (int i = 0; i < K; ++i) acc[i] = 0;
+    const double A2 = 2.0 * area[k];
+    double re[NC], im[NC];
+    for (int i = 0; i < nq; ++i)
+        for (int j = 0; j < nq; ++j) {
+            const double s = gx[i], t = gx[j];
+            const double w = gw[i] * gw[j] * A2 * s;
+            double u[3];
+            for (int d = 0; d < 3; ++d)
+                u[d] = (v[d] + s * (v[3 + d] - v[d]) + s * t * (v[6 + d] - v[3 + d]) - center[3 * b + d]) * ih;
+            regular_harmonics<P, double>(u[0], u[1], u[2], re, im);
+            for (int n = 0; n <= P; ++n) {
+                acc[ridx(n, 0, 0)] += w * re[n * (n + 1) / 2];
+                for (int m = 1; m <= n; ++m) {
+                    acc[ridx(n, m, 0)] += w * re[n * (n + 1) / 2 + m];
+                    acc[ridx(n, m, 1)] -= w * im[n * (n + 1) / 2 + m];
+                }
+            }
+        }
+    for (int i = 0; i < K; ++i) {
+        mom64[(size_t)k * K + i] = acc[i];
+        mom32[(size_t)k * K + i] = (float)acc[i];
+    }
+}
+
+__global__ void k_concat_panels(int64_t n, int64_t off, int32_t user_off, int32_t vid_off,
+                                const int32_t *__restrict__ perm_t, const double *__restrict__ pv_t,
+                                const int32_t *__restrict__ pvid_t, const double *__restrict__ cen_t,
+                                const double *__restrict__ area_t, const double *__restrict__ diam_t,
+                                int32_t *__restrict__ perm, int32_t *__restrict__ iperm, double *__restrict__ pv,
+                                int32_t *__restrict__ pvid, double *__restrict__ cen, double *__restrict__ area,
+                                double *__restrict__ diam)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t g = off + i;
+    const int32_t u = user_off + perm_t[i];
+    perm[g] = u;
+    iperm[u] = (int32_t)g;
+    for (int j = 0; j < 9; ++j) pv[9 * g + j] = pv_t[9 * i + j];
+    for (int j = 0; j < 3; ++j) {
+        pvid[3 * g + j] = vid_off + pvid_t[3 * i + j];
+        cen[3 * g + j] = cen_t[3 * i + j];
+    }
+    area[g] = area_t[i];
+    diam[g] = diam_t[i];
+}
+
+__global__ void k_panel_leaf(int64_t nleaf, const int32_t *__restrict__ leaf_box, const int32_t *__restrict__ beg,
+                             const int32_t *__restrict__ end, int32_t *__restrict__ panel_leaf)
+{
+    int64_t li = blockIdx.x;
+    if (li >= nleaf) return;
+    const int32_t b = leaf_box[li];
+    for (int32_t k = beg[b] + threadIdx.x; k < end[b]; k += blockDim.x) panel_leaf[k] = (int32_t)li;
+}
+
+}  // namespace xrl
+
+using namespace xrl;
+
+static void build_plan(xrl_plan *P, hipStream_t s)
+{
+    const int ntrees = (int)P->trees.size();
+    // ---------------- global panels
+    P->panel_off.assign(ntrees + 1, 0);
+    std::vector<int64_t> vid_off(ntrees + 1, 0);
+    for (int t = 0; t < ntrees; ++t) {
+        P->panel_off[t + 1] = P->panel_off[t] + P->trees[t]->N;
+        vid_off[t + 1] = vid_off[t] + P->trees[t]->nv;
+    }
+    XRL_CHECK(P->panel_off[ntrees] < (int64_t(1) << 31) && vid_off[ntrees] < (int64_t(1) << 31), XRL_E_UNSUPPORTED,
+              "xrl_fmm_plan: more than 2^31 panels or vertices in one plan");
+    const int64_t N = P->N = P->panel_off[ntrees];
+    P->perm.alloc(N);
+    P->iperm.alloc(N);
+    P->pv.alloc(9 * N);
+    P->pvid.alloc(3 * N);
+    P->cen.alloc(3 * N);
+    P->area.alloc(N);
+    P->diam.alloc(N);
+    for (int t = 0; t < ntrees; ++t) {
+        const xrl_tree *T = P->trees[t];
+        k_concat_panels<<<cdiv(T->N, 256), 256, 0, s>>>(T->N, P->panel_off[t], (int32_t)P->panel_off[t],
+                                                        (int32_t)vid_off[t], T->perm.p, T->pv.p, T->pvid.p, T->cen.p,
+                                                        T->area.p, T->diam.p, P->perm.p, P->iperm.p, P->pv.p,
+                                                        P->pvid.p, P->cen.p, P->area.p, P->diam.p);
+        XRL_HIP(hipGetLastError());
+    }
+    // ---------------- global boxes, level-major across trees
+    int depth = 0;
+    for (auto *T : P->trees) depth = std::max(depth, T->depth);
+    P->depth = depth;
+    std::vector<std::vector<int32_t>> newid(ntrees);
+    std::vector<int64_t> seg((depth + 1) * (ntrees + 1), 0);
+    int64_t B = 0;
+    P->level_off.assign(depth + 2, 0);
+    for (int l = 0; l <= depth; ++l) {
+        P->level_off[l] = B;
+        for (int t = 0; t < ntrees; ++t) {
+            const xrl_tree *T = P->trees[t];
+            if (newid[t].empty()) newid[t].assign(T->box_key.size(), -1);
+            seg[l * (ntrees + 1) + t] = B;
+            if (l <= T->depth)
+                for (int64_t b = T->level_off[l]; b < T->level_off[l + 1]; ++b) newid[t][b] = (int32_t)B++;
+        }
+        seg[l * (ntrees + 1) + ntrees] = B;
+    }
+    P->level_off[depth + 1] = B;
+    P->B = B;
+    std::vector<uint64_t> key(B);
+    std::vector<int32_t> level(B), parent(B), child0(B), nchild(B), beg(B), end(B), tree(B);
+    std::vector<double> center(3 * B), hsz(B);
+    for (int t = 0; t < ntrees; ++t) {
+        const xrl_tree *T = P->trees[t];
+        for (size_t b = 0; b < T->box_key.size(); ++b) {
+            const int32_t g = newid[t][b];
+            key[g] = T->box_key[b];
+            level[g] = T->box_level[b];
+            parent[g] = T->box_parent[b] >= 0 ? newid[t][T->box_parent[b]] : -1;
+            child0[g] = T->box_child0[b] >= 0 ? newid[t][T->box_child0[b]] : -1;
+            nchild[g] = T->box_nchild[b];
+            beg[g] = (int32_t)(P->panel_off[t] + T->box_beg[b]);
+            end[g] = (int32_t)(P->panel_off[t] + T->box_end[b]);
+            tree[g] = t;
+            const double h = T->root_size / double(1 << level[g]);
+            hsz[g] = h;
+            const uint64_t k = key[g];
+            const uint32_t c[3] = {compact3(k), compact3(k >> 1), compact3(k >> 2)};
+            for (int d = 0; d < 3; ++d) center[3 * g + d] = T->root_c[d] - 0.5 * T->root_size + (c[d] + 0.5) * h;
+        }
+    }
+    P->h_box_beg = beg;
+    P->h_box_end = end;
+    P->h_box_parent = parent;
+    P->h_box_child0 = child0;
+    P->h_box_nchild = nchild;
+    P->h_box_level = level;
+    P->h_box_tree = tree;
+    std::vector<int32_t> leaves, octant(B);
+    for (int64_t b = 0; b < B; ++b) {
+        octant[b] = (int32_t)(key[b] & 7);
+        if (nchild[b] == 0) {
+            leaves.push_back((int32_t)b);
+            XRL_CHECK(end[b] - beg[b] <= kMaxLeaf, XRL_E_UNSUPPORTED,
+                      "xrl_fmm_plan: a leaf holds %d > 64 panels (coincident centroids at max depth)",
+                      end[b] - beg[b]);
+        }
+    }
+    P->h_leaf_box = leaves;
+    P->n_leaves = (int64_t)leaves.size();
+    DevBuf<uint64_t> dkey;
+    dkey.upload(key, s);
+    DevBuf<int32_t> dtree;
+    dtree.upload(tree, s);
+    DevBuf<int64_t> dseg;
+    dseg.upload(seg, s);
+    P->box_level.upload(level, s);
+    P->box_parent.upload(parent, s);
+    P->box_child0.upload(child0, s);
+    P->box_nchild.upload(nchild, s);
+    P->box_beg.upload(beg, s);
+    P->box_end.upload(end, s);
+    P->box_octant.upload(octant, s);
+    P->box_center.upload(center, s);
+    P->box_h.upload(hsz, s);
+    P->leaf_box.upload(leaves, s);
+    P->box_rad.alloc(B);
+    k_box_radius<<<B, 256, 0, s>>>(B, P->box_beg.p, P->box_end.p, P->box_center.p, P->pv.p, P->box_rad.p);
+    XRL_HIP(hipGetLastError());
+    P->panel_leaf.alloc(N);
+    k_panel_leaf<<<P->n_leaves, 64, 0, s>>>(P->n_leaves, P->leaf_box.p, P->box_beg.p, P->box_end.p,
+                                             P->panel_leaf.p);
+    XRL_HIP(hipGetLastError());
+    BoxView bv{dkey.p, P->box_level.p, P->box_parent.p, P->box_child0.p, P->box_nchild.p, dtree.p, dseg.p, ntrees};
+    // ---------------- colleagues
+    DevBuf<int32_t> coll(27 * (size_t)B);
+    k_colleagues<<<cdiv(B, 128), 128, 0, s>>>(bv, B, coll.p);
+    XRL_HIP(hipGetLastError());
+    // ---------------- V lists
+    DevBuf<int32_t> vcnt(B);
+    k_vlist<<<cdiv(B, 128), 128, 0, s>>>(bv, B, coll.p, vcnt.p, nullptr, nullptr, nullptr);
+    XRL_HIP(hipGetLastError());
+    auto hv = vcnt.download(s);
+    std::vector<int64_t> voff(B + 1, 0);
+    for (int64_t b = 0; b < B; ++b) voff[b + 1] = voff[b] + hv[b];
+    const int64_t nV = voff[B];
+    P->n_m2l = nV;
+    DevBuf<int64_t> dvoff;
+    dvoff.upload(voff, s);
+    DevBuf<int32_t> vsrc(std::max<int64_t>(nV, 1)), vcode(std::max<int64_t>(nV, 1));
+    k_vlist<<<cdiv(B, 128), 128, 0, s>>>(bv, B, coll.p, vcnt.p, dvoff.p, vsrc.p, vcode.p);
+    XRL_HIP(hipGetLastError());
+    auto hsrc = vsrc.download(s, nV);
+    auto hcode = vcode.download(s, nV);
+    // ---------------- near lists (source boxes), then rows
+    DevBuf<int32_t> ncnt(P->n_leaves);
+    k_nearlist<<<cdiv(P->n_leaves, 64), 64, 0, s>>>(bv, P->leaf_box.p, P->n_leaves, coll.p, ncnt.p, nullptr,
+                                                     nullptr);
+    XRL_HIP(hipGetLastError());
+    auto hn = ncnt.download(s);
+    std::vector<int64_t> noff(P->n_leaves + 1, 0);
+    for (int64_t i = 0; i < P->n_leaves; ++i) noff[i + 1] = noff[i] + hn[i];
+    DevBuf<int64_t> dnoff;
+    dnoff.upload(noff, s);
+    DevBuf<int32_t> nbox(std::max<int64_t>(noff.back(), 1));
+    k_nearlist<<<cdiv(P->n_leaves, 64), 64, 0, s>>>(bv, P->leaf_box.p, P->n_leaves, coll.p, ncnt.p, dnoff.p,
+                                                     nbox.p);
+    XRL_HIP(hipGetLastError());
+    auto hnbox = nbox.download(s, noff.back());
+    // rows
+    std::vector<int32_t> rows_ptr(P->n_leaves + 1, 0), src_rows;
+    std::vector<int64_t> val_off(P->n_leaves + 1, 0);
+    std::vector<int32_t> tpad(P->n_leaves);
+    int64_t pairs = 0;
+    for (int64_t li = 0; li < P->n_leaves; ++li) {
+        const int32_t T = leaves[li];
+        const int nt = end[T] - beg[T];
+        tpad[li] = nt <= 16 ? 16 : (nt <= 32 ? 32 : 64);
+        // sort source boxes by their panel range so the rows are in Morton order
+        std::vector<std::pair<int32_t, int32_t>> rg;
+        for (int64_t j = noff[li]; j < noff[li + 1]; ++j) rg.push_back({beg[hnbox[j]], end[hnbox[j]]});
+        std::sort(rg.begin(), rg.end());
+        int64_t nrow = 0;
+        for (auto &r : rg) {
+            for (int32_t k = r.first; k < r.second; ++k) src_rows.push_back(k);
+            nrow += r.second - r.first;
+        }
+        XRL_CHECK((int64_t)src_rows.size() < (int64_t(1) << 31), XRL_E_UNSUPPORTED,
+                  "xrl_fmm_plan: near-field row count overflows int32");
+        rows_ptr[li + 1] = (int32_t)src_rows.size();
+        val_off[li + 1] = val_off[li] + nrow * tpad[li];
+        pairs += nrow * nt;
+    }
+    P->h_near_rows = rows_ptr;
+    P->n_near_rows = (int64_t)src_rows.size();
+    P->n_near_entries = val_off.back();
+    P->n_near_pairs = pairs;
+    P->near_rows.upload(rows_ptr, s);
+    P->near_src.upload(src_rows, s);
+    P->near_val_off.upload(val_off, s);
+    P->leaf_tpad.upload(tpad, s);
+    // ---------------- M2L slabs and offset groups
+    const int creal = 2 * P->max_cols;
+    const size_t elt = P->precision == XRL_PREC_FP64 ? 8 : 4;
+    P->m2l_ct = std::min(creal, P->precision == XRL_PREC_FP64 ? 8 : 16);
+    const int budget = 64 * 1024;
+    P->slab_targets = (int)std::max<int64_t>(1, std::min<int64_t>(64, budget / (P->K * P->m2l_ct * (int64_t)elt)));
+    std::vector<int32_t> tlist, slab_tbeg{0}, slab_gbeg{0}, grp_off, grp_pbeg{0}, pair_tloc, pair_src;
+    P->h_m2l_pairs.resize(2 * nV);
+    std::vector<double> hrad = P->box_rad.download(s);
+    double maxsep = 0;
+    {
+        std::vector<int32_t> targets;
+        for (int64_t b = 0; b < B; ++b)
+            if (voff[b + 1] > voff[b]) targets.push_back((int32_t)b);
+        const int ST = P->slab_targets;
+        for (size_t t0 = 0; t0 < targets.size(); t0 += ST) {
+            const size_t t1 = std::min(targets.size(), t0 + ST);
+            std::vector<std::array<int32_t, 3>> pr;  // (code, tloc, src)
+            for (size_t ti = t0; ti < t1; ++ti) {
+                const int32_t b = targets[ti];
+                tlist.push_back(b);
+                for (int64_t j = voff[b]; j < voff[b + 1]; ++j) pr.push_back({hcode[j], (int32_t)(ti - t0), hsrc[j]});
+            }
+            std::stable_sort(pr.begin(), pr.end(),
+                             [](const std::array<int32_t, 3> &a, const std::array<int32_t, 3> &b) { return a[0] < b[0]; });
+            for (size_t i = 0; i < pr.size(); ++i) {
+                if (i == 0 || pr[i][0] != pr[i - 1][0]) {
+                    if (i > 0) grp_pbeg.push_back((int32_t)pair_tloc.size());
+                    grp_off.push_back(pr[i][0]);
+                }
+                pair_tloc.push_back(pr[i][1]);
+                pair_src.push_back(pr[i][2]);
+            }
+            if (!pr.empty()) grp_pbeg.push_back((int32_t)pair_tloc.size());
+            slab_tbeg.push_back((int32_t)tlist.size());
+            slab_gbeg.push_back((int32_t)grp_off.size());
+        }
+        // grp_pbeg currently has a leading 0 and one end per group
+        for (int64_t b = 0, q = 0; b < B; ++b)
+            for (int64_t j = voff[b]; j < voff[b + 1]; ++j, ++q) {
+                P->h_m2l_pairs[2 * q] = (int32_t)b;
+                P->h_m2l_pairs[2 * q + 1] = hsrc[j];
+                const int32_t sb = hsrc[j];
+                double d2 = 0;
+                for (int d = 0; d < 3; ++d) {
+                    const double dd = center[3 * b + d] - center[3 * sb + d];
+                    d2 += dd * dd;
+                }
+                maxsep = std::max(maxsep, (hrad[b] + hrad[sb]) / std::sqrt(d2));
+            }
+        P->n_targets = (int64_t)tlist.size();
+        P->n_slabs = (int64_t)slab_tbeg.size() - 1;
+        P->n_groups = (int64_t)grp_off.size();
+    }
+    P->max_sep_ratio = maxsep;
+    P->m2l_tgt_list.upload(tlist, s);
+    P->slab_tbeg.upload(slab_tbeg, s);
+    P->slab_gbeg.upload(slab_gbeg, s);
+    P->grp_off.upload(grp_off, s);
+    P->grp_pbeg.upload(grp_pbeg, s);
+    P->pair_tloc.upload(pair_tloc, s);
+    P->pair_src.upload(pair_src, s);
+    // ---------------- operators
+    const int p = P->p, K = P->K;
+    std::vector<double> m2m(8 * (size_t)K * K), l2l(8 * (size_t)K * K);
+    build_m2m(p, m2m.data());
+    build_l2l(p, l2l.data());
+    P->KP = (int)cdiv(K, 16) * 16;
+    P->KK = (int)cdiv(K, 4) * 4;
+    std::vector<double> m2l(343 * (size_t)P->KP * P->KK, 0.0), tmp((size_t)K * K);
+    std::vector<char> used(343, 0);
+    for (int c : grp_off) used[c] = 1;
+    for (int c = 0; c < 343; ++c) {
+        if (!used[c]) continue;
+        const int ox = c % 7 - 3, oy = (c / 7) % 7 - 3, oz = c / 49 - 3;
+        build_m2l(p, ox, oy, oz, tmp.data());
+        for (int r = 0; r < K; ++r)
+            for (int k = 0; k < K; ++k) m2l[((size_t)c * P->KP + r) * P->KK + k] = tmp[(size_t)r * K + k];
+    }
+    auto to32 = [](const std::vector<double> &v) {
+        std::vector<float> f(v.size());
+        for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+        return f;
+    };
+    // fragment order for the 16x16x4 MFMA A operand: lane = row % 16 + 16 (k % 4)
+    const int nrt = P->KP / 16, nks = P->KK / 4;
+    std::vector<double> frag(m2l.size(), 0.0);
+    for (int c = 0; c < 343; ++c)
+        for (int rt = 0; rt < nrt; ++rt)
+            for (int ks = 0; ks < nks; ++ks)
+                for (int lane = 0; lane < 64; ++lane)
+                    frag[(((size_t)c * nrt + rt) * nks + ks) * 64 + lane] =
+                        m2l[((size_t)c * P->KP + rt * 16 + (lane & 15)) * P->KK + 4 * ks + (lane >> 4)];
+    P->op_m2l64f.upload(frag, s);
+    P->op_m2l32f.upload(to32(frag), s);
+    P->op_m2m64.upload(m2m, s);
+    P->op_l2l64.upload(l2l, s);
+    P->op_m2l64.upload(m2l, s);
+    P->op_m2m32.upload(to32(m2m), s);
+    P->op_l2l32.upload(to32(l2l), s);
+    P->op_m2l32.upload(to32(m2l), s);
+    // ---------------- moments
+    const int nq = (p + 3) / 2;  // 2 nq - 2 >= p
+    std::vector<double> gx(nq), gw(nq);
+    gauss_legendre01(nq, gx.data(), gw.data());
+    DevBuf<double> dgx, dgw;
+    dgx.upload(gx, s);
+    dgw.upload(gw, s);
+    P->mom64.alloc((size_t)N * K);
+    P->mom32.alloc((size_t)N * K);
+#define XRL_MOM(PP)                                                                                          \
+    case PP:                                                                                                 \
+        k_moments<PP><<<cdiv(N, 64), 64, 0, s>>>(N, P->pv.p, P->panel_leaf.p, P->leaf_box.p, P->box_center.p, \
+                                                 P->box_h.p, P->area.p, nq, dgx.p, dgw.p, P->mom64.p,      \
+                                                 P->mom32.p);                                              \
+        break;
+    switch (p) {
+        XRL_MOM(2)
+        XRL_MOM(4)
+        XRL_MOM(6)
+        XRL_MOM(8)
+        XRL_MOM(10)
+        XRL_MOM(12)
+        default: fail(XRL_E_UNSUPPORTED, "xrl_fmm_plan: order %d not compiled (2,4,6,8,10,12)", p);
+    }
+#undef XRL_MOM
+    XRL_HIP(hipGetLastError());
+    XRL_HIP(hipStreamSynchronize(s));
+}
+
+extern "C" xrl_status xrl_fmm_plan(xrl_tree *const *trees, int32_t n_trees, const xrl_plan_opts *opts,
+                                   void *stream, xrl_plan **out)
+{
+    return guarded([&] {
+        XRL_CHECK(trees && opts && out && n_trees >= 1, XRL_E_INVALID_ARG, "xrl_fmm_plan: bad arguments");
+        *out = nullptr;
+        for (int t = 0; t < n_trees; ++t) XRL_CHECK(trees[t], XRL_E_INVALID_ARG, "xrl_fmm_plan: null tree %d", t);
+        XRL_CHECK(opts->order >= 2 && opts->order <= 12 && opts->order % 2 == 0, XRL_E_UNSUPPORTED,
+                  "xrl_fmm_plan: order must be even in 2..12 (got %d)", opts->order);
+        XRL_CHECK(opts->precision >= 0 && opts->precision <= 2, XRL_E_INVALID_ARG, "xrl_fmm_plan: bad precision");
+        XRL_CHECK(opts->m2l_engine >= 0 && opts->m2l_engine <= 2, XRL_E_INVALID_ARG, "xrl_fmm_plan: bad engine");
+        XRL_CHECK(opts->max_cols >= 1 && opts->max_cols <= 4096, XRL_E_INVALID_ARG,
+                  "xrl_fmm_plan: max_cols must be in 1..4096");
+        auto P = std::make_unique<xrl_plan>();
+        P->p = opts->order;
+        P->K = (P->p + 1) * (P->p + 1);
+        P->precision = opts->precision;
+        P->m2l_engine = opts->m2l_engine == XRL_M2L_AUTO
+                            ? (opts->precision == XRL_PREC_FP32 ? XRL_M2L_VALU : XRL_M2L_MFMA)
+                            : opts->m2l_engine;
+        P->max_cols = opts->max_cols;
+        P->trees.assign(trees, trees + n_trees);
+        build_plan(P.get(), (hipStream_t)stream);
+        *out = P.release();
+    });
+}
+
+extern "C" void xrl_plan_destroy(xrl_plan *plan)
+{
+    if (!plan) return;
+    if (plan->events_made)
+        for (auto &e : plan->ev) (void)hipEventDestroy(e);
+    delete plan;
+}
+
+extern "C" xrl_status xrl_plan_get_info(const xrl_plan *P, xrl_plan_info *info)
+{
+    return guarded([&] {
+        XRL_CHECK(P && info, XRL_E_INVALID_ARG, "xrl_plan_get_info: null argument");
+        info->n_panels = P->N;
+        info->n_boxes = P->B;
+        info->n_leaves = P->n_leaves;
+        info->n_m2l_pairs = P->n_m2l;
+        info->n_near_rows = P->n_near_rows;
+        info->n_near_entries = P->n_near_entries;
+        info->n_near_pairs = P->n_near_pairs;
+        info->order = P->p;
+        info->precision = P->precision;
+        info->max_sep_ratio = P->max_sep_ratio;
+    });
+}
+
+extern "C" xrl_status xrl_plan_export(const xrl_plan *P, int32_t item, void *buf, int64_t *nbytes)
+{
+    return guarded([&] {
+        XRL_CHECK(P && nbytes, XRL_E_INVALID_ARG, "xrl_plan_export: null argument");
+        std::vector<int32_t> v;
+        switch (item) {
+            case 0: v = const_cast<xrl_plan *>(P)->perm.download(0); break;
+            case 1:
+                v.resize(2 * P->B);
+                for (int64_t b = 0; b < P->B; ++b) {
+                    v[2 * b] = P->h_box_beg[b];
+                    v[2 * b + 1] = P->h_box_end[b];
+                }
+                break;
+            case 2: v = P->h_box_level; break;
+            case 3: v = P->h_near_rows; break;
+            case 4: v = const_cast<xrl_plan *>(P)->near_src.download(0); break;
+            case 5: v = P->h_m2l_pairs; break;
+            case 6: v = P->h_leaf_box; break;
+            case 7: v = P->h_box_parent; break;
+            case 9: v = const_cast<xrl_plan *>(P)->leaf_tpad.download(0); break;
+            case 8: {
+                // near-field values as float64 (layout: items 3, 4, 9)
+                std::vector<double> d;
+                if (P->near64.p)
+                    d = const_cast<xrl_plan *>(P)->near64.download(0, P->n_near_entries);
+                else {
+                    auto f = const_cast<xrl_plan *>(P)->near32.download(0, P->n_near_entries);
+                    d.assign(f.begin(), f.end());
+                }
+                const int64_t nb = (int64_t)(d.size() * sizeof(double));
+                if (buf) {
+                    XRL_CHECK(*nbytes >= nb, XRL_E_INVALID_ARG, "xrl_plan_export: buffer too small");
+                    std::memcpy(buf, d.data(), nb);
+                }
+                *nbytes = nb;
+                return;
+            }
+            default: fail(XRL_E_INVALID_ARG, "xrl_plan_export: unknown item %d", item);
+        }
+        const int64_t nb = (int64_t)(v.size() * sizeof(int32_t));
+        if (buf) {
+            XRL_CHECK(*nbytes >= nb, XRL_E_INVALID_ARG, "xrl_plan_export: buffer too small");
+            std::memcpy(buf, v.data(), nb);
+        }
+        *nbytes = nb;
+    });
+}

@@ -1,0 +1,337 @@
+// Octree on panel centroids (the FMM of Sec. II-C runs on panel centroids):
+// panel geometry, Morton codes, radix sort and level-by-level splitting, on
+// the device.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <memory>
+
+#include "common.h"
+
+namespace xrl {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+void fail(xrl_status code, const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw Error{code, std::string(buf)};
+}
+
+// Per panel (input order): vertices, centroid, area, longest edge; error
+// flags: bit 0 vertex index out of range, bit 1 degenerate or non-finite.
+__global__ void k_panel_geometry(const double *__restrict__ V, int64_t nv, const int32_t *__restrict__ T,
+                                 int64_t N, double *__restrict__ cen, double *__restrict__ area,
+                                 double *__restrict__ diam, int *__restrict__ flags)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    int32_t i0 = T[3 * k], i1 = T[3 * k + 1], i2 = T[3 * k + 2];
+    if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
+        atomicOr(flags, 1);
+        cen[3 * k] = cen[3 * k + 1] = cen[3 * k + 2] = 0.0;
+        area[k] = 0.0;
+        diam[k] = 0.0;
+        return;
+    }
+    double a[3], b[3], c[3];
+    for (int d = 0; d < 3; ++d) {
+        a[d] = V[3 * (int64_t)i0 + d];
+        b[d] = V[3 * (int64_t)i1 + d];
+        c[d] = V[3 * (int64_t)i2 + d];
+    }
+    double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    double e3[3] = {c[0] - b[0], c[1] - b[1], c[2] - b[2]};
+    double cx = e1[1] * e2[2] - e1[2] * e2[1];
+    double cy = e1[2] * e2[0] - e1[0] * e2[2];
+    double cz = e1[0] * e2[1] - e1[1] * e2[0];
+    double A = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+    double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    double l2 = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+    double l3 = sqrt(e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2]);
+    double D = fmax(l1, fmax(l2, l3));
+    for (int d = 0; d < 3; ++d) cen[3 * k + d] = (a[d] + b[d] + c[d]) / 3.0;
+    area[k] = A;
+    diam[k] = D;
+    if (!(A > 1e-14 * D * D) || !isfinite(A) || !isfinite(D)) atomicOr(flags, 2);
+}
+
+// Partial bounding box of centroids: out[block][6] = (min xyz, max xyz).
+__global__ void k_bbox(const double *__restrict__ cen, int64_t N, double *__restrict__ out)
+{
+    __shared__ double s[256][6];
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < N;
+         k += (int64_t)gridDim.x * blockDim.x)
+        for (int d = 0; d < 3; ++d) {
+            mn[d] = fmin(mn[d], cen[3 * k + d]);
+            mx[d] = fmax(mx[d], cen[3 * k + d]);
+        }
+    for (int d = 0; d < 3; ++d) {
+        s[threadIdx.x][d] = mn[d];
+        s[threadIdx.x][3 + d] = mx[d];
+    }
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int d = 0; d < 3; ++d) {
+                s[threadIdx.x][d] = fmin(s[threadIdx.x][d], s[threadIdx.x + w][d]);
+                s[threadIdx.x][3 + d] = fmax(s[threadIdx.x][3 + d], s[threadIdx.x + w][3 + d]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 6; ++d) out[6 * blockIdx.x + d] = s[0][d];
+}
+
+__global__ void k_morton(const double *__restrict__ cen, int64_t N, double x0, double y0, double z0,
+                         double inv_h, uint64_t *__restrict__ code, int32_t *__restrict__ idx)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const double o[3] = {x0, y0, z0};
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) {
+        double f = (cen[3 * k + d] - o[d]) * inv_h;  // in [0, 2^21)
+        long long v = (long long)floor(f);
+        v = v < 0 ? 0 : (v > 2097151 ? 2097151 : v);
+        q[d] = (uint32_t)v;
+    }
+    code[k] = morton3(q[0], q[1], q[2]);
+    idx[k] = (int32_t)k;
+}
+
+__global__ void k_gather_panels(const int32_t *__restrict__ perm, int64_t N, const double *__restrict__ V,
+                                const int32_t *__restrict__ T, const double *__restrict__ cen_in,
+                                const double *__restrict__ area_in, const double *__restrict__ diam_in,
+                                double *__restrict__ pv, int32_t *__restrict__ pvid, double *__restrict__ cen,
+                                double *__restrict__ area, double *__restrict__ diam)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int64_t k = perm[i];
+    for (int j = 0; j < 3; ++j) {
+        int32_t v = T[3 * k + j];
+        pvid[3 * i + j] = v;
+        for (int d = 0; d < 3; ++d) pv[9 * i + 3 * j + d] = V[3 * (int64_t)v + d];
+        cen[3 * i + j] = cen_in[3 * k + j];
+    }
+    area[i] = area_in[k];
+    diam[i] = diam_in[k];
+}
+
+// For every box of one level that must split: the 9 boundaries of its child
+// ranges in the sorted code array (lower bounds of the 8 child digits + end).
+__global__ void k_child_bounds(const uint64_t *__restrict__ code, const int32_t *__restrict__ beg,
+                               const int32_t *__restrict__ end, const uint64_t *__restrict__ key, int nbox,
+                               int level, int32_t *__restrict__ bounds)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    const int shift_child = 3 * (kMaxDepth - level - 1);
+    for (int d = 0; d <= 8; ++d) {
+        int32_t lo = beg[b], hi = end[b];
+        if (d < 8) {
+            const uint64_t target = ((key[b] << 3) | (uint64_t)d) << shift_child;
+            while (lo < hi) {
+                int32_t mid = lo + (hi - lo) / 2;
+                if (code[mid] < target)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+        }
+        bounds[9 * b + d] = lo;
+    }
+}
+
+}  // namespace xrl
+
+using namespace xrl;
+
+extern "C" const char *xrl_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *xrl_version(void) { return "xrl-mi355x 0.1 (gfx950)"; }
+
+extern "C" xrl_status xrl_tree_build(const xrl_mesh_desc *mesh, int32_t max_leaf, int32_t max_depth,
+                                     void *stream, xrl_tree **out)
+{
+    return guarded([&] {
+        XRL_CHECK(mesh && out, XRL_E_INVALID_ARG, "xrl_tree_build: null mesh or out");
+        *out = nullptr;
+        XRL_CHECK(mesh->vertices && mesh->tris, XRL_E_INVALID_ARG, "xrl_tree_build: null arrays");
+        XRL_CHECK(mesh->n_panels >= 1 && mesh->n_panels < (int64_t(1) << 31) && mesh->n_vertices >= 3 &&
+                      mesh->n_vertices < (int64_t(1) << 31),
+                  XRL_E_INVALID_ARG, "xrl_tree_build: bad sizes (n_panels=%lld, n_vertices=%lld)",
+                  (long long)mesh->n_panels, (long long)mesh->n_vertices);
+        XRL_CHECK(max_leaf >= 1 && max_leaf <= kMaxLeaf, XRL_E_INVALID_ARG,
+                  "xrl_tree_build: max_leaf must be in 1..64 (got %d)", max_leaf);
+        XRL_CHECK(max_depth >= 1 && max_depth <= kMaxDepth, XRL_E_INVALID_ARG,
+                  "xrl_tree_build: max_depth must be in 1..21 (got %d)", max_depth);
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t N = mesh->n_panels, nv = mesh->n_vertices;
+        auto t = std::make_unique<xrl_tree>();
+        t->N = N;
+        t->nv = nv;
+        t->max_leaf = max_leaf;
+        t->max_depth = max_depth;
+        DevBuf<double> V(3 * nv);
+        DevBuf<int32_t> T(3 * N);
+        hipMemcpyKind kind = mesh->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        XRL_HIP(hipMemcpyAsync(V.p, mesh->vertices, V.bytes(), kind, s));
+        XRL_HIP(hipMemcpyAsync(T.p, mesh->tris, T.bytes(), kind, s));
+        DevBuf<double> cen0(3 * N), area0(N), diam0(N);
+        DevBuf<int> flags(1);
+        XRL_HIP(hipMemsetAsync(flags.p, 0, sizeof(int), s));
+        const int bs = 256;
+        k_panel_geometry<<<cdiv(N, bs), bs, 0, s>>>(V.p, nv, T.p, N, cen0.p, area0.p, diam0.p, flags.p);
+        XRL_HIP(hipGetLastError());
+        int hflag = flags.download(s)[0];
+        XRL_CHECK(!(hflag & 1), XRL_E_INVALID_ARG, "xrl_tree_build: vertex index out of range");
+        XRL_CHECK(!(hflag & 2), XRL_E_DEGENERATE_PANEL,
+                  "xrl_tree_build: degenerate or non-finite panel (area <= 1e-14 diam^2)");
+        // bounding cube of the centroids
+        int nb = (int)std::min<int64_t>(1024, cdiv(N, bs));
+        DevBuf<double> part(6 * nb);
+        k_bbox<<<nb, bs, 0, s>>>(cen0.p, N, part.p);
+        XRL_HIP(hipGetLastError());
+        auto hp = part.download(s);
+        double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+        for (int b = 0; b < nb; ++b)
+            for (int d = 0; d < 3; ++d) {
+                mn[d] = std::min(mn[d], hp[6 * b + d]);
+                mx[d] = std::max(mx[d], hp[6 * b + 3 + d]);
+            }
+        double ext = std::max({mx[0] - mn[0], mx[1] - mn[1], mx[2] - mn[2]});
+        double scale = std::max({std::fabs(mn[0]), std::fabs(mn[1]), std::fabs(mn[2]), std::fabs(mx[0]),
+                                 std::fabs(mx[1]), std::fabs(mx[2]), 1e-300});
+        double side = ext * (1.0 + 1e-6) + 1e-9 * scale;
+        if (!(side > 0)) side = 1.0;
+        for (int d = 0; d < 3; ++d) t->root_c[d] = 0.5 * (mn[d] + mx[d]);
+        t->root_size = side;
+        // Morton codes and sort
+        DevBuf<uint64_t> code_in(N), code(N);
+        DevBuf<int32_t> idx_in(N);
+        t->perm.alloc(N);
+        const double inv_h = double(1 << kMaxDepth) / side;
+        k_morton<<<cdiv(N, bs), bs, 0, s>>>(cen0.p, N, t->root_c[0] - 0.5 * side, t->root_c[1] - 0.5 * side,
+                                            t->root_c[2] - 0.5 * side, inv_h, code_in.p, idx_in.p);
+        XRL_HIP(hipGetLastError());
+        size_t tmp_bytes = 0;
+        XRL_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, code_in.p, code.p, idx_in.p, t->perm.p,
+                                                   (int)N, 0, 63, s));
+        DevBuf<char> tmp(tmp_bytes);
+        XRL_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp_bytes, code_in.p, code.p, idx_in.p, t->perm.p,
+                                                   (int)N, 0, 63, s));
+        t->pv.alloc(9 * N);
+        t->pvid.alloc(3 * N);
+        t->cen.alloc(3 * N);
+        t->area.alloc(N);
+        t->diam.alloc(N);
+        k_gather_panels<<<cdiv(N, bs), bs, 0, s>>>(t->perm.p, N, V.p, T.p, cen0.p, area0.p, diam0.p, t->pv.p,
+                                                   t->pvid.p, t->cen.p, t->area.p, t->diam.p);
+        XRL_HIP(hipGetLastError());
+        // level-by-level split
+        t->level_off = {0};
+        t->box_key = {0};
+        t->box_level = {0};
+        t->box_parent = {-1};
+        t->box_beg = {0};
+        t->box_end = {(int32_t)N};
+        t->box_child0 = {-1};
+        t->box_nchild = {0};
+        int level = 0;
+        DevBuf<int32_t> dbeg, dend, dbounds;
+        DevBuf<uint64_t> dkey;
+        while (true) {
+            const int64_t lo = t->level_off.back();
+            const int64_t hi = (int64_t)t->box_key.size();
+            t->level_off.push_back(hi);
+            // boxes of this level that split
+            std::vector<int32_t> sb, se, sidx;
+            std::vector<uint64_t> sk;
+            for (int64_t b = lo; b < hi; ++b) {
+                int32_t cnt = t->box_end[b] - t->box_beg[b];
+                if (cnt > max_leaf) {
+                    if (level < max_depth) {
+                        sb.push_back(t->box_beg[b]);
+                        se.push_back(t->box_end[b]);
+                        sk.push_back(t->box_key[b]);
+                        sidx.push_back((int32_t)b);
+                    } else {
+                        t->n_overfull++;
+                    }
+                }
+            }
+            if (sb.empty()) break;
+            const int ns = (int)sb.size();
+            dbeg.upload(sb, s);
+            dend.upload(se, s);
+            dkey.upload(sk, s);
+            dbounds.alloc(9 * (size_t)ns);
+            k_child_bounds<<<cdiv(ns, 128), 128, 0, s>>>(code.p, dbeg.p, dend.p, dkey.p, ns, level, dbounds.p);
+            XRL_HIP(hipGetLastError());
+            auto bd = dbounds.download(s);
+            for (int i = 0; i < ns; ++i) {
+                const int32_t b = sidx[i];
+                t->box_child0[b] = (int32_t)t->box_key.size();
+                int nch = 0;
+                for (int d = 0; d < 8; ++d) {
+                    int32_t cb = bd[9 * i + d], ce = bd[9 * i + d + 1];
+                    if (ce > cb) {
+                        t->box_key.push_back((sk[i] << 3) | (uint64_t)d);
+                        t->box_level.push_back(level + 1);
+                        t->box_parent.push_back(b);
+                        t->box_beg.push_back(cb);
+                        t->box_end.push_back(ce);
+                        t->box_child0.push_back(-1);
+                        t->box_nchild.push_back(0);
+                        ++nch;
+                    }
+                }
+                t->box_nchild[b] = nch;
+            }
+            ++level;
+        }
+        // level_off holds [depth + 2] entries: the start of every level and the total
+        t->depth = (int)t->level_off.size() - 2;
+        t->code = std::move(code);
+        XRL_HIP(hipStreamSynchronize(s));
+        *out = t.release();
+    });
+}
+
+extern "C" void xrl_tree_destroy(xrl_tree *tree) { delete tree; }
+
+extern "C" xrl_status xrl_tree_get_info(const xrl_tree *t, xrl_tree_info *info)
+{
+    return guarded([&] {
+        XRL_CHECK(t && info, XRL_E_INVALID_ARG, "xrl_tree_get_info: null argument");
+        info->n_panels = t->N;
+        info->n_boxes = (int64_t)t->box_key.size();
+        int64_t nl = 0;
+        for (size_t b = 0; b < t->box_nchild.size(); ++b) nl += t->box_nchild[b] == 0;
+        info->n_leaves = nl;
+        info->depth = t->depth;
+        info->n_overfull_leaves = t->n_overfull;
+        for (int d = 0; d < 3; ++d) info->root_center[d] = t->root_c[d];
+        info->root_size = t->root_size;
+    });
+}

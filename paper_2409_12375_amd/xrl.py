@@ -1,0 +1,266 @@
+"""Thin ctypes binding of libxrl.so (include/xrl.h).
+
+Argument marshalling only: every step of the operator runs in the HIP
+library.  PyTorch provides device memory and the stream.  There is no CPU
+fallback: if the library is missing, `lib()` raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxrl.so")
+_lib = None
+
+C64, C128 = 1, 2
+PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
+ENGINE = {"auto": 0, "mfma": 1, "valu": 2}
+N_PHASES = 8
+PHASES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "l2p", "scatter"]
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+class XrlError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("xrl error %d: %s" % (code, msg))
+        self.code = code
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_vertices", _i64), ("n_panels", _i64), ("vertices", _vp), ("tris", _vp), ("on_device", _i32)]
+
+
+class TreeInfo(ctypes.Structure):
+    _fields_ = [("n_panels", _i64), ("n_boxes", _i64), ("n_leaves", _i64), ("depth", _i32),
+                ("n_overfull_leaves", _i32), ("root_center", ctypes.c_double * 3), ("root_size", ctypes.c_double)]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("order", _i32), ("precision", _i32), ("m2l_engine", _i32), ("max_cols", _i32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_panels", _i64), ("n_boxes", _i64), ("n_leaves", _i64), ("n_m2l_pairs", _i64),
+                ("n_near_rows", _i64), ("n_near_entries", _i64), ("n_near_pairs", _i64), ("order", _i32),
+                ("precision", _i32), ("max_sep_ratio", ctypes.c_double)]
+
+
+class Mlp(ctypes.Structure):
+    _fields_ = [("hidden", _i32), ("w1", _vp), ("b1", _vp), ("w2", _vp), ("b2", _vp), ("w3", _vp), ("b3", _vp),
+                ("feat_lo", _vp), ("feat_hi", _vp), ("log10_err_bound", ctypes.c_float)]
+
+
+class NfOpts(ctypes.Structure):
+    _fields_ = [("r_near", ctypes.c_double), ("r_mid", ctypes.c_double), ("surrogate", ctypes.POINTER(Mlp)),
+                ("audit_every", _i32)]
+
+
+class NfStats(ctypes.Structure):
+    _fields_ = [("n_entries", _i64), ("n_self", _i64), ("n_touching", _i64), ("n_near_singular", _i64),
+                ("n_regular", _i64), ("n_mlp_accepted", _i64), ("n_mlp_fallback", _i64),
+                ("audit_max_rel_err", ctypes.c_double), ("audit_rms_rel_err", ctypes.c_double),
+                ("ms", ctypes.c_double)]
+
+
+class Epilogue(ctypes.Structure):
+    _fields_ = [("alpha", _vp), ("beta", _vp)]
+
+
+class GmresStats(ctypes.Structure):
+    _fields_ = [("iterations", _i32), ("restarts", _i32), ("converged", _i32),
+                ("max_rel_residual", ctypes.c_double)]
+
+
+def lib():
+    """Load libxrl.so (built in-tree by paper_2409_12375_amd/build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libxrl.so is not built (run paper_2409_12375_amd/build.py or "
+                               "__graft_entry__.build()); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        L.xrl_last_error.restype = ctypes.c_char_p
+        L.xrl_version.restype = ctypes.c_char_p
+        L.xrl_tree_build.argtypes = [ctypes.POINTER(MeshDesc), _i32, _i32, _vp, ctypes.POINTER(_vp)]
+        L.xrl_tree_destroy.argtypes = [_vp]
+        L.xrl_tree_destroy.restype = None
+        L.xrl_tree_get_info.argtypes = [_vp, ctypes.POINTER(TreeInfo)]
+        L.xrl_fmm_plan.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(PlanOpts), _vp, ctypes.POINTER(_vp)]
+        L.xrl_plan_destroy.argtypes = [_vp]
+        L.xrl_plan_destroy.restype = None
+        L.xrl_plan_get_info.argtypes = [_vp, ctypes.POINTER(PlanInfo)]
+        L.xrl_nearfield_assemble.argtypes = [_vp, ctypes.POINTER(NfOpts), _vp, ctypes.POINTER(NfStats)]
+        L.xrl_fmm_matvec.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _i64, ctypes.POINTER(Epilogue), _vp]
+        L.xrl_plan_set_profiling.argtypes = [_vp, _i32]
+        L.xrl_plan_get_phase_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
+        L.xrl_plan_export.argtypes = [_vp, _i32, _vp, ctypes.POINTER(_i64)]
+        if hasattr(L, "xrl_gmres_solve"):
+            L.xrl_gmres_solve.argtypes = [_vp, ctypes.POINTER(Epilogue), _vp, _vp, _i32, _i32, ctypes.c_double, _i32,
+                                          _vp, ctypes.POINTER(GmresStats)]
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise XrlError(code, lib().xrl_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return _vp(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return _vp(stream)
+    return _vp(stream.cuda_stream)
+
+
+class Tree:
+    """Octree over one mesh (xrl_tree_build)."""
+
+    def __init__(self, V, T, max_leaf=64, max_depth=21, stream=None):
+        self._V = np.ascontiguousarray(V, dtype=np.float64)
+        self._T = np.ascontiguousarray(T, dtype=np.int32)
+        d = MeshDesc(self._V.shape[0], self._T.shape[0], self._V.ctypes.data, self._T.ctypes.data, 0)
+        h = _vp()
+        _check(lib().xrl_tree_build(ctypes.byref(d), max_leaf, max_depth, _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.n_panels = self._T.shape[0]
+
+    def info(self):
+        i = TreeInfo()
+        _check(lib().xrl_tree_get_info(self.h, ctypes.byref(i)))
+        return {f: getattr(i, f) if f not in ("root_center",) else list(i.root_center) for f, _ in TreeInfo._fields_}
+
+    def close(self):
+        if self.h:
+            lib().xrl_tree_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """FMM plan over one or more trees (xrl_fmm_plan)."""
+
+    def __init__(self, trees, order=8, precision="mixed", engine="auto", max_cols=3, stream=None):
+        if isinstance(trees, Tree):
+            trees = [trees]
+        self.trees = list(trees)  # keep the trees alive
+        arr = (_vp * len(trees))(*[t.h for t in trees])
+        o = PlanOpts(order, PREC[precision], ENGINE[engine], max_cols)
+        h = _vp()
+        _check(lib().xrl_fmm_plan(arr, len(trees), ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.precision = precision
+        self.n_panels = sum(t.n_panels for t in trees)
+
+    def info(self):
+        i = PlanInfo()
+        _check(lib().xrl_plan_get_info(self.h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in PlanInfo._fields_}
+
+    def assemble(self, r_near=2.0, r_mid=6.0, surrogate=None, audit_every=0, stream=None):
+        o = NfOpts(r_near, r_mid, None, audit_every)
+        keep = None
+        if surrogate is not None:
+            keep = surrogate.as_struct()
+            o.surrogate = ctypes.pointer(keep[0])
+        st = NfStats()
+        _check(lib().xrl_nearfield_assemble(self.h, ctypes.byref(o), _stream(stream), ctypes.byref(st)))
+        del keep
+        return {f: getattr(st, f) for f, _ in NfStats._fields_}
+
+    def matvec(self, x, y=None, alpha=None, beta=None, stream=None):
+        """y = alpha_c * (P x)_c + beta_c * area * x_c for a complex CUDA tensor x
+        of shape [N] or [N][C] (user panel order)."""
+        import torch
+        if x.dtype not in (torch.complex64, torch.complex128) or not x.is_cuda:
+            raise ValueError("x must be a complex64/complex128 CUDA tensor")
+        squeeze = x.dim() == 1
+        X = x.reshape(x.shape[0], -1)
+        if X.stride(1) != 1:
+            X = X.contiguous()
+        ncols = X.shape[1]
+        if y is None:
+            y = torch.empty_like(X)
+        Y = y.reshape(y.shape[0], -1)
+        if Y.stride(1) != 1 or Y.dtype != X.dtype or Y.shape != X.shape:
+            raise ValueError("y must match x in shape and dtype with unit column stride")
+        ep = None
+        keep = []
+        if alpha is not None or beta is not None:
+            ep = Epilogue()
+            for name in ("alpha", "beta"):
+                v = alpha if name == "alpha" else beta
+                if v is not None:
+                    a = np.empty(2 * ncols)
+                    vv = np.broadcast_to(np.asarray(v, dtype=np.complex128), (ncols,))
+                    a[0::2] = vv.real
+                    a[1::2] = vv.imag
+                    keep.append(a)
+                    setattr(ep, name, a.ctypes.data)
+        dt = C64 if X.dtype == torch.complex64 else C128
+        _check(lib().xrl_fmm_matvec(self.h, _vp(X.data_ptr()), X.stride(0), ncols, dt, _vp(Y.data_ptr()), Y.stride(0),
+                                    ctypes.byref(ep) if ep is not None else None, _stream(stream)))
+        return Y[:, 0] if squeeze else Y
+
+    def set_profiling(self, on=True):
+        _check(lib().xrl_plan_set_profiling(self.h, 1 if on else 0))
+
+    def phase_ms(self):
+        a = (ctypes.c_double * N_PHASES)()
+        _check(lib().xrl_plan_get_phase_ms(self.h, a))
+        return dict(zip(PHASES, list(a)))
+
+    def export(self, item):
+        n = _i64(0)
+        _check(lib().xrl_plan_export(self.h, item, None, ctypes.byref(n)))
+        out = np.zeros(n.value // 4, dtype=np.int32)
+        _check(lib().xrl_plan_export(self.h, item, _vp(out.ctypes.data), ctypes.byref(n)))
+        return out
+
+    def gmres(self, b, x0=None, alpha=1.0, beta=0.0, restart=50, rtol=1e-6, max_iter=500, stream=None):
+        """Solve (beta_c A + alpha_c P) x_c = b_c; b is a complex128 CUDA tensor
+        [N] or [N][R].  Returns (x, stats)."""
+        import torch
+        squeeze = b.dim() == 1
+        Bm = b.reshape(b.shape[0], -1).to(torch.complex128).contiguous()
+        R = Bm.shape[1]
+        X = torch.zeros_like(Bm) if x0 is None else x0.reshape(Bm.shape).to(torch.complex128).contiguous().clone()
+        ep = Epilogue()
+        keep = []
+        for name, v in (("alpha", alpha), ("beta", beta)):
+            a = np.empty(2 * R)
+            vv = np.broadcast_to(np.asarray(v, dtype=np.complex128), (R,))
+            a[0::2] = vv.real
+            a[1::2] = vv.imag
+            keep.append(a)
+            setattr(ep, name, a.ctypes.data)
+        st = GmresStats()
+        code = lib().xrl_gmres_solve(self.h, ctypes.byref(ep), _vp(Bm.data_ptr()), _vp(X.data_ptr()), R, restart,
+                                     rtol, max_iter, _stream(stream), ctypes.byref(st))
+        stats = {f: getattr(st, f) for f, _ in GmresStats._fields_}
+        if code not in (0, -5):
+            _check(code)
+        stats["status"] = code
+        return (X[:, 0] if squeeze else X), stats
+
+    def close(self):
+        if self.h:
+            lib().xrl_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
