@@ -151,6 +151,8 @@ typedef struct {
     int32_t order;
     int32_t precision;
     double max_sep_ratio; /* max over M2L pairs of (rad_t + rad_s) / |c_t - c_s| */
+    int64_t n_demoted_pairs; /* V-list candidates whose panel-inclusive radii do not
+                                separate them; applied directly as near field */
 } xrl_plan_info;
 xrl_status xrl_plan_get_info(const xrl_plan *plan, xrl_plan_info *info);
 

@@ -198,6 +198,7 @@ struct xrl_plan {
     xrl::DevBuf<int32_t> panel_leaf;  // [N] leaf index (into leaf_box) of each sorted panel
     // M2L pairs grouped by slab and offset
     int64_t n_m2l = 0;
+    int64_t n_demoted = 0;  // V candidates applied directly (radii do not separate)
     int slab_targets = 0;
     int m2l_ct = 0;  // column tile width used for slab sizing
     std::vector<int32_t> h_m2l_pairs;  // [n][2] (t, s) for export

@@ -228,7 +228,8 @@ struct M2LArgs {
 
 // MFMA 16x16x4 operand layout on a 64-lane wave (checked by the GPU tests):
 // A[i][k]: lane = i + 16 k;  B[k][j]: lane = j + 16 k;
-// D[i][j]: lane = j + 16 (i / 4), element i % 4.
+// D[i][j]: lane = j + 16 q, element e, with i = 4 q + e for f32 and
+//          i = q + 4 e for f64.
 // op_frag holds each operator in fragment order [o][row tile][k step][lane].
 template <typename T>
 __device__ inline void mfma_16x16x4(T a, T b, typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type &d);
@@ -241,6 +242,12 @@ template <>
 __device__ inline void mfma_16x16x4<double>(double a, double b, f64x4 &d)
 {
     d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+}
+
+template <typename T>
+__device__ inline int mfma_row(int q, int e)
+{
+    return sizeof(T) == 4 ? 4 * q + e : q + 4 * e;
 }
 
 template <typename T>
@@ -282,7 +289,7 @@ __global__ __launch_bounds__(256) void k_m2l_mfma(M2LArgs a, const T *__restrict
                 const int tl = a.pair_tloc[pb + p];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int row = rt * 16 + 4 * kq + e;
+                    const int row = rt * 16 + mfma_row<T>(kq, e);
                     if (row < K) acc[((int64_t)tl * K + row) * ct + c] += d[e];
                 }
             }
@@ -535,7 +542,7 @@ __global__ void k_mfma_probe(const T *A, const T *B, T *D)
     const int i = lane & 15, k = lane >> 4;
     VT d = {0, 0, 0, 0};
     mfma_16x16x4<T>(A[i * 4 + k], B[k * 16 + i], d);
-    for (int e = 0; e < 4; ++e) D[(4 * k + e) * 16 + i] = d[e];
+    for (int e = 0; e < 4; ++e) D[mfma_row<T>(k, e) * 16 + i] = d[e];
 }
 
 extern "C" xrl_status xrl_selftest_mfma(int32_t dtype, const void *A, const void *B, void *D)

@@ -64,7 +64,8 @@ __device__ T tri_potential(const T *v, const T *r)
         T pb[3] = {b[0] - rho[0], b[1] - rho[1], b[2] - rho[2]};
         const T t0 = dot3(pa, m);
         const T sm = dot3(pa, s), sp = dot3(pb, s);
-        if (fabs(t0) <= T(1e-12) * L) continue;
+        const T eps = sizeof(T) == 4 ? T(1e-5) : T(1e-12);
+        if (fabs(t0) <= eps * L) continue;
         const T R0s = t0 * t0 + h * h;
         T ra[3] = {r[0] - a[0], r[1] - a[1], r[2] - a[2]};
         T rb[3] = {r[0] - b[0], r[1] - b[1], r[2] - b[2]};
@@ -72,7 +73,7 @@ __device__ T tri_potential(const T *v, const T *r)
         const T fp = sp >= 0 ? Rp + sp : R0s / (Rp - sp);
         const T fm = sm >= 0 ? Rm + sm : R0s / (Rm - sm);
         phi += t0 * log(fp / fm);
-        if (ah > T(1e-12) * L) phi -= ah * (atan(t0 * sp / (R0s + ah * Rp)) - atan(t0 * sm / (R0s + ah * Rm)));
+        if (ah > eps * L) phi -= ah * (atan(t0 * sp / (R0s + ah * Rp)) - atan(t0 * sm / (R0s + ah * Rm)));
     }
     return phi;
 }

@@ -94,14 +94,19 @@ __global__ void k_colleagues(BoxView bv, int64_t B, int32_t *__restrict__ coll)
             }
 }
 
-// V-lists: count (out == nullptr) or fill.
-__global__ void k_vlist(BoxView bv, int64_t B, const int32_t *__restrict__ coll, int32_t *__restrict__ cnt,
-                        const int64_t *__restrict__ off, int32_t *__restrict__ src, int32_t *__restrict__ code)
+// V-lists: count (src == nullptr) or fill.  A candidate pair whose
+// panel-inclusive radii do not separate (rad_t + rad_s >= theta |c_t - c_s|)
+// cannot be translated with a convergent expansion; it is emitted to the
+// demoted list instead and applied directly as near field.
+__global__ void k_vlist(BoxView bv, int64_t B, const int32_t *__restrict__ coll, const double *__restrict__ center,
+                        const double *__restrict__ rad, double theta, int32_t *__restrict__ cnt,
+                        int32_t *__restrict__ dcnt, const int64_t *__restrict__ off, const int64_t *__restrict__ doff,
+                        int32_t *__restrict__ src, int32_t *__restrict__ code, int32_t *__restrict__ dsrc)
 {
     int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= B) return;
     const int l = bv.level[b];
-    int n = 0;
+    int n = 0, nd = 0;
     if (l >= 2) {
         const int32_t p = bv.parent[b];
         int32_t cb[3];
@@ -115,6 +120,13 @@ __global__ void k_vlist(BoxView bv, int64_t B, const int32_t *__restrict__ coll,
                 box_coords(bv.key[c], cc);
                 const int ox = cb[0] - cc[0], oy = cb[1] - cc[1], oz = cb[2] - cc[2];
                 if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1 && oz >= -1 && oz <= 1) continue;
+                const double dx = center[3 * b] - center[3 * c], dy = center[3 * b + 1] - center[3 * c + 1],
+                             dz = center[3 * b + 2] - center[3 * c + 2];
+                if (rad[b] + rad[c] >= theta * sqrt(dx * dx + dy * dy + dz * dz)) {
+                    if (src) dsrc[doff[b] + nd] = c;
+                    ++nd;
+                    continue;
+                }
                 if (src) {
                     src[off[b] + n] = c;
                     code[off[b] + n] = (ox + 3) + 7 * (oy + 3) + 49 * (oz + 3);
@@ -123,7 +135,10 @@ __global__ void k_vlist(BoxView bv, int64_t B, const int32_t *__restrict__ coll,
             }
         }
     }
-    if (!src) cnt[b] = n;
+    if (!src) {
+        cnt[b] = n;
+        dcnt[b] = nd;
+    }
 }
 
 // Near-field source boxes of every leaf (U, W, X): count or fill.
@@ -423,22 +438,45 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     DevBuf<int32_t> coll(27 * (size_t)B);
     k_colleagues<<<cdiv(B, 128), 128, 0, s>>>(bv, B, coll.p);
     XRL_HIP(hipGetLastError());
-    // ---------------- V lists
-    DevBuf<int32_t> vcnt(B);
-    k_vlist<<<cdiv(B, 128), 128, 0, s>>>(bv, B, coll.p, vcnt.p, nullptr, nullptr, nullptr);
+    // ---------------- V lists (and pairs demoted to the near field)
+    DevBuf<int32_t> vcnt(B), dcnt(B);
+    const double theta = 1.0;
+    k_vlist<<<cdiv(B, 128), 128, 0, s>>>(bv, B, coll.p, P->box_center.p, P->box_rad.p, theta, vcnt.p, dcnt.p,
+                                         nullptr, nullptr, nullptr, nullptr, nullptr);
     XRL_HIP(hipGetLastError());
     auto hv = vcnt.download(s);
-    std::vector<int64_t> voff(B + 1, 0);
-    for (int64_t b = 0; b < B; ++b) voff[b + 1] = voff[b] + hv[b];
+    auto hd = dcnt.download(s);
+    std::vector<int64_t> voff(B + 1, 0), doff(B + 1, 0);
+    for (int64_t b = 0; b < B; ++b) {
+        voff[b + 1] = voff[b] + hv[b];
+        doff[b + 1] = doff[b] + hd[b];
+    }
     const int64_t nV = voff[B];
     P->n_m2l = nV;
-    DevBuf<int64_t> dvoff;
+    P->n_demoted = doff[B];
+    DevBuf<int64_t> dvoff, ddoff;
     dvoff.upload(voff, s);
-    DevBuf<int32_t> vsrc(std::max<int64_t>(nV, 1)), vcode(std::max<int64_t>(nV, 1));
-    k_vlist<<<cdiv(B, 128), 128, 0, s>>>(bv, B, coll.p, vcnt.p, dvoff.p, vsrc.p, vcode.p);
+    ddoff.upload(doff, s);
+    DevBuf<int32_t> vsrc(std::max<int64_t>(nV, 1)), vcode(std::max<int64_t>(nV, 1)),
+        dsrc(std::max<int64_t>(doff[B], 1));
+    k_vlist<<<cdiv(B, 128), 128, 0, s>>>(bv, B, coll.p, P->box_center.p, P->box_rad.p, theta, vcnt.p, dcnt.p,
+                                         dvoff.p, ddoff.p, vsrc.p, vcode.p, dsrc.p);
     XRL_HIP(hipGetLastError());
     auto hsrc = vsrc.download(s, nV);
     auto hcode = vcode.download(s, nV);
+    auto hdsrc = dsrc.download(s, doff[B]);
+    // demoted pairs (t, s): every leaf below t gets the panels of s as near sources
+    std::vector<int32_t> leaf_of_panel(N, -1);
+    for (size_t li = 0; li < leaves.size(); ++li)
+        for (int32_t k = beg[leaves[li]]; k < end[leaves[li]]; ++k) leaf_of_panel[k] = (int32_t)li;
+    std::vector<std::vector<int32_t>> extra(leaves.size());
+    for (int64_t b = 0; b < B; ++b)
+        for (int64_t j = doff[b]; j < doff[b + 1]; ++j)
+            for (int32_t k = beg[b]; k < end[b];) {
+                const int32_t li = leaf_of_panel[k];
+                extra[li].push_back(hdsrc[j]);
+                k = end[leaves[li]];
+            }
     // ---------------- near lists (source boxes), then rows
     DevBuf<int32_t> ncnt(P->n_leaves);
     k_nearlist<<<cdiv(P->n_leaves, 64), 64, 0, s>>>(bv, P->leaf_box.p, P->n_leaves, coll.p, ncnt.p, nullptr,
@@ -466,6 +504,7 @@ static void build_plan(xrl_plan *P, hipStream_t s)
         // sort source boxes by their panel range so the rows are in Morton order
         std::vector<std::pair<int32_t, int32_t>> rg;
         for (int64_t j = noff[li]; j < noff[li + 1]; ++j) rg.push_back({beg[hnbox[j]], end[hnbox[j]]});
+        for (int32_t sb : extra[li]) rg.push_back({beg[sb], end[sb]});
         std::sort(rg.begin(), rg.end());
         int64_t nrow = 0;
         for (auto &r : rg) {
@@ -665,6 +704,7 @@ extern "C" xrl_status xrl_plan_get_info(const xrl_plan *P, xrl_plan_info *info)
         info->order = P->p;
         info->precision = P->precision;
         info->max_sep_ratio = P->max_sep_ratio;
+        info->n_demoted_pairs = P->n_demoted;
     });
 }
 

@@ -147,20 +147,19 @@ __global__ void k_child_bounds(const uint64_t *__restrict__ code, const int32_t 
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nbox) return;
     const int shift_child = 3 * (kMaxDepth - level - 1);
-    for (int d = 0; d <= 8; ++d) {
+    for (int d = 0; d < 8; ++d) {
         int32_t lo = beg[b], hi = end[b];
-        if (d < 8) {
-            const uint64_t target = ((key[b] << 3) | (uint64_t)d) << shift_child;
-            while (lo < hi) {
-                int32_t mid = lo + (hi - lo) / 2;
-                if (code[mid] < target)
-                    lo = mid + 1;
-                else
-                    hi = mid;
-            }
+        const uint64_t target = ((key[b] << 3) | (uint64_t)d) << shift_child;
+        while (lo < hi) {
+            int32_t mid = lo + (hi - lo) / 2;
+            if (code[mid] < target)
+                lo = mid + 1;
+            else
+                hi = mid;
         }
         bounds[9 * b + d] = lo;
     }
+    bounds[9 * b + 8] = end[b];
 }
 
 }  // namespace xrl

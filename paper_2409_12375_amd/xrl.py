@@ -46,7 +46,7 @@ class PlanOpts(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n_panels", _i64), ("n_boxes", _i64), ("n_leaves", _i64), ("n_m2l_pairs", _i64),
                 ("n_near_rows", _i64), ("n_near_entries", _i64), ("n_near_pairs", _i64), ("order", _i32),
-                ("precision", _i32), ("max_sep_ratio", ctypes.c_double)]
+                ("precision", _i32), ("max_sep_ratio", ctypes.c_double), ("n_demoted_pairs", _i64)]
 
 
 class Mlp(ctypes.Structure):
