@@ -423,11 +423,11 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
                 lo, hi, P->box_child0.p, P->box_nchild.p, P->box_parent.p, P->box_octant.p, m2m, M.p, M.p, C, K);
         XRL_HIP(hipGetLastError());
     }
-    mark(4);
     // zero every local expansion (a fill kernel, so the sequence stays
     // capturable into a HIP graph without memset nodes)
     k_fill_zero<T><<<(unsigned)std::min<int64_t>(cdiv(B * K * C, 256), 65536), 256, 0, s>>>(L.p, B * K * C);
     XRL_HIP(hipGetLastError());
+    mark(4);
     if (P->n_slabs > 0) {
         const int ct = std::min(C, P->m2l_ct);
         M2LArgs a{P->m2l_tgt_list.p, P->slab_tbeg.p, P->slab_gbeg.p, P->grp_off.p, P->grp_pbeg.p,
