@@ -196,24 +196,30 @@ struct xrl_plan {
     xrl::DevBuf<int32_t> pvid;   // [N][3] (vertex ids offset per tree)
     xrl::DevBuf<double> cen, area, diam;
     xrl::DevBuf<int32_t> panel_leaf;  // [N] leaf index (into leaf_box) of each sorted panel
-    // M2L pairs grouped by slab and offset
+    // M2L pairs sorted by translation offset (one operator per group), the
+    // per-target reduction lists over the sorted positions, and per column
+    // count work-item lists (cached)
     int64_t n_m2l = 0;
     int64_t n_demoted = 0;  // V candidates applied directly (radii do not separate)
-    int slab_targets = 0;
-    int m2l_ct = 0;  // column tile width used for slab sizing
-    std::vector<int32_t> h_m2l_pairs;  // [n][2] (t, s) for export
-    xrl::DevBuf<int32_t> m2l_tgt_list;   // [n_targets] target boxes in slab order
-    xrl::DevBuf<int32_t> slab_tbeg;      // [n_slabs+1] into m2l_tgt_list
-    xrl::DevBuf<int32_t> slab_gbeg;      // [n_slabs+1] into groups
-    xrl::DevBuf<int32_t> grp_off;        // [n_groups] operator offset code
-    xrl::DevBuf<int32_t> grp_pbeg;       // [n_groups+1] into pair arrays
-    xrl::DevBuf<int32_t> pair_tloc;      // [n_pairs] target slot within slab
-    xrl::DevBuf<int32_t> pair_src;       // [n_pairs] source box
-    int64_t n_slabs = 0, n_groups = 0, n_targets = 0;
+    std::vector<int32_t> h_m2l_pairs;   // [n][2] (t, s), per-target order, for export
+    std::vector<int32_t> h_os_gbeg;     // [n_groups+1]
+    xrl::DevBuf<int32_t> os_src;        // [n_pairs] source box, offset-sorted
+    xrl::DevBuf<int32_t> os_goff;       // [n_groups] operator offset code
+    xrl::DevBuf<int32_t> os_gbeg;       // [n_groups+1]
+    xrl::DevBuf<int32_t> red_tgt;       // [n_red] target boxes with V pairs
+    xrl::DevBuf<int32_t> red_ptr;       // [n_red+1]
+    xrl::DevBuf<int32_t> red_slot;      // [n_pairs] offset-sorted position of each pair
+    int64_t n_groups = 0, n_red = 0;
+    mutable std::vector<std::pair<int64_t, xrl::DevBuf<int32_t>>> item_cache;  // key: (engine, cols)
+    mutable xrl::DevBuf<float> os_tmp32;
+    mutable xrl::DevBuf<double> os_tmp64;
     double max_sep_ratio = 0;
     // operators (FP64 master + FP32 copy), real (p+1)^2 x (p+1)^2, row = output
     xrl::DevBuf<double> op_m2m64, op_l2l64, op_m2l64;  // [8][K][K], [8][K][K], [343][KP][KK]
     xrl::DevBuf<float> op_m2m32, op_l2l32, op_m2l32;
+    // M2L operators k-major for the vector-ALU GEMM [343][KK][KP]
+    xrl::DevBuf<float> op_m2l32k;
+    xrl::DevBuf<double> op_m2l64k;
     // M2L operators in MFMA fragment order [343][KP/16][KK/4][64]
     xrl::DevBuf<double> op_m2l64f;
     xrl::DevBuf<float> op_m2l32f;

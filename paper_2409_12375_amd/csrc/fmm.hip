@@ -221,11 +221,15 @@ __global__ __launch_bounds__(256) void k_l2p(const int32_t *__restrict__ leaf_bo
 }
 
 // ---------------------------------------------------------------- M2L
-struct M2LArgs {
-    const int32_t *tgt_list, *slab_tbeg, *slab_gbeg, *grp_off, *grp_pbeg, *pair_tloc, *pair_src;
-    int C, K, KK, ct;
-};
-
+// Offset-stationary batched GEMM.  All V-list pairs with the same integer
+// offset share one operator T_o, so for every offset group
+//     D_g[KP][pairs x cols] = T_o[KP][KK] * [M_s1 | M_s2 | ...]
+// is one dense product with the operator held in registers (MFMA) or LDS
+// (vector ALU).  Column n of a group is (pair n / Cc, column n % Cc).  D is
+// written per pair to a scratch array tmp[pair][Cc][KP] and a second kernel
+// sums the pairs of every target in a fixed order (deterministic, no
+// atomics).
+//
 // MFMA 16x16x4 operand layout on a 64-lane wave (checked by the GPU tests):
 // A[i][k]: lane = i + 16 k;  B[k][j]: lane = j + 16 k;
 // D[i][j]: lane = j + 16 q, element e, with i = 4 q + e for f32 and
@@ -250,89 +254,199 @@ __device__ inline int mfma_row(int q, int e)
     return sizeof(T) == 4 ? 4 * q + e : q + 4 * e;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_m2l_mfma(M2LArgs a, const T *__restrict__ op_frag, const T *__restrict__ M,
-                                                  T *__restrict__ L)
+template <int ORD>
+struct M2LDims {
+    static constexpr int K = (ORD + 1) * (ORD + 1);
+    static constexpr int NRT = (K + 15) / 16;  // 16-row tiles
+    static constexpr int NKS = (K + 3) / 4;    // 4-deep k steps
+    static constexpr int KP = NRT * 16;
+    static constexpr int KK = NKS * 4;
+};
+
+// One wave per work item (group g, column tiles [ct0, ct1)).
+template <typename T, int ORD>
+__global__ __launch_bounds__(256) void k_m2l_os_mfma(const int32_t *__restrict__ items, int n_items,
+                                                     const int32_t *__restrict__ gbeg, const int32_t *__restrict__ goff,
+                                                     const int32_t *__restrict__ src, const T *__restrict__ op_frag,
+                                                     const T *__restrict__ M, int C, int c0, int Cc,
+                                                     T *__restrict__ tmp)
 {
+    using D = M2LDims<ORD>;
     using VT = typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type;
-    extern __shared__ unsigned char smem_raw[];
-    T *acc = reinterpret_cast<T *>(smem_raw);  // [nts][K][ct]
-    const int slab = blockIdx.x;
-    const int ct = a.ct, C = a.C, K = a.K;
-    const int c0 = blockIdx.y * ct;
-    const int tb = a.slab_tbeg[slab], nts = a.slab_tbeg[slab + 1] - tb;
-    for (int idx = threadIdx.x; idx < nts * K * ct; idx += blockDim.x) acc[idx] = T(0);
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nrt = (K + 15) / 16, nks = a.KK / 4;
-    const int kq = lane >> 4, li = lane & 15;
-    for (int g = a.slab_gbeg[slab]; g < a.slab_gbeg[slab + 1]; ++g) {
-        const int o = a.grp_off[g], pb = a.grp_pbeg[g], np = a.grp_pbeg[g + 1] - pb;
-        const int ncols = np * ct, nct = (ncols + 15) / 16, nblk = nrt * nct;
-        const T *Tf = op_frag + (int64_t)o * nrt * nks * 64;
-        for (int blk = wave; blk < nblk; blk += 4) {
-            const int rt = blk % nrt, ctile = blk / nrt;
-            const int n = ctile * 16 + li;
-            const int p = n / ct, c = n - p * ct;
-            const bool valid = n < ncols && c0 + c < C;
-            const int32_t src = valid ? a.pair_src[pb + p] : 0;
-            const T *Mp = M + (int64_t)src * K * C + c0 + c;
-            const T *Ap = Tf + (int64_t)rt * nks * 64 + lane;
-            VT d = {0, 0, 0, 0};
-            for (int ks = 0; ks < nks; ++ks) {
-                const int kk = 4 * ks + kq;
-                const T av = Ap[ks * 64];
-                const T bv = (valid && kk < K) ? Mp[(int64_t)kk * C] : T(0);
-                mfma_16x16x4<T>(av, bv, d);
-            }
-            if (valid) {
-                const int tl = a.pair_tloc[pb + p];
+    constexpr int RB = sizeof(T) == 4 ? D::NRT : 2;  // row tiles of the operator held in registers
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= n_items) return;
+    const int lane = threadIdx.x & 63, li = lane & 15, kq = lane >> 4;
+    const int g = items[3 * w], ct0 = items[3 * w + 1], ct1 = items[3 * w + 2];
+    const int pb = gbeg[g], ncols = (gbeg[g + 1] - pb) * Cc;
+    const T *Tf = op_frag + (int64_t)goff[g] * D::NRT * D::NKS * 64 + lane;
+    for (int r0 = 0; r0 < D::NRT; r0 += RB) {
+        T a[RB][D::NKS];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = rt * 16 + mfma_row<T>(kq, e);
-                    if (row < K) acc[((int64_t)tl * K + row) * ct + c] += d[e];
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int ks = 0; ks < D::NKS; ++ks) a[rb][ks] = (r0 + rb < D::NRT) ? Tf[((r0 + rb) * D::NKS + ks) * 64] : T(0);
+        for (int ct = ct0; ct < ct1; ++ct) {
+            const int n = ct * 16 + li;
+            const int p = n / Cc, c = n - p * Cc;
+            const bool valid = n < ncols;
+            const T *Mp = M + (int64_t)(valid ? src[pb + p] : 0) * D::K * C + c0 + c;
+            T b[D::NKS];
+#pragma unroll
+            for (int ks = 0; ks < D::NKS; ++ks) {
+                const int kk = 4 * ks + kq;
+                b[ks] = (valid && kk < D::K) ? Mp[(int64_t)kk * C] : T(0);
+            }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                if (r0 + rb >= D::NRT) break;
+                VT d = {0, 0, 0, 0};
+#pragma unroll
+                for (int ks = 0; ks < D::NKS; ++ks) mfma_16x16x4<T>(a[rb][ks], b[ks], d);
+                if (valid) {
+                    T *out = tmp + ((int64_t)(pb + p) * Cc + c) * D::KP + (r0 + rb) * 16;
+                    if (sizeof(T) == 4) {
+                        *reinterpret_cast<VT *>(out + 4 * kq) = d;
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) out[mfma_row<T>(kq, e)] = d[e];
+                    }
                 }
             }
         }
-        __syncthreads();
-    }
-    for (int idx = threadIdx.x; idx < nts * K * ct; idx += blockDim.x) {
-        const int t = idx / (K * ct), rem = idx - t * K * ct, row = rem / ct, c = rem - row * ct;
-        if (c0 + c < C) L[((int64_t)a.tgt_list[tb + t] * K + row) * C + c0 + c] = acc[idx];
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_m2l_valu(M2LArgs a, const T *__restrict__ op, /* [343][KP][KK] */
-                                                  int KP, const T *__restrict__ M, T *__restrict__ L)
+// One workgroup per work item (group g, columns [n0, n1), at most 64):
+// operator (k-major) and the gathered multipoles staged in LDS, every thread
+// owns NRT rows x 4 columns of the product.
+template <typename T, int ORD>
+__global__ __launch_bounds__(256) void k_m2l_os_valu(const int32_t *__restrict__ items,
+                                                     const int32_t *__restrict__ gbeg, const int32_t *__restrict__ goff,
+                                                     const int32_t *__restrict__ src, const T *__restrict__ op_k,
+                                                     const T *__restrict__ M, int C, int c0, int Cc,
+                                                     T *__restrict__ tmp)
 {
-    extern __shared__ unsigned char smem_raw[];
-    T *acc = reinterpret_cast<T *>(smem_raw);
-    const int slab = blockIdx.x;
-    const int ct = a.ct, C = a.C, K = a.K, KK = a.KK;
-    const int c0 = blockIdx.y * ct;
-    const int tb = a.slab_tbeg[slab], nts = a.slab_tbeg[slab + 1] - tb;
-    for (int idx = threadIdx.x; idx < nts * K * ct; idx += blockDim.x) acc[idx] = T(0);
-    __syncthreads();
-    for (int g = a.slab_gbeg[slab]; g < a.slab_gbeg[slab + 1]; ++g) {
-        const int o = a.grp_off[g], pb = a.grp_pbeg[g], np = a.grp_pbeg[g + 1] - pb;
-        const int ncols = np * ct;
-        const T *To = op + (int64_t)o * KP * KK;
-        for (int idx = threadIdx.x; idx < K * ncols; idx += blockDim.x) {
-            const int row = idx / ncols, n = idx - row * ncols;
-            const int p = n / ct, c = n - p * ct;
-            if (c0 + c >= C) continue;
-            const T *Mp = M + (int64_t)a.pair_src[pb + p] * K * C + c0 + c;
-            const T *Tr = To + (int64_t)row * KK;
-            T s = 0;
-            for (int kk = 0; kk < K; ++kk) s += Tr[kk] * Mp[(int64_t)kk * C];
-            acc[((int64_t)a.pair_tloc[pb + p] * K + row) * ct + c] += s;
+    using D = M2LDims<ORD>;
+    __shared__ T sA[D::KK * D::KP];
+    __shared__ T sB[D::KK * 64];
+    const int g = items[3 * blockIdx.x], n0 = items[3 * blockIdx.x + 1], n1 = items[3 * blockIdx.x + 2];
+    const int pb = gbeg[g];
+    const T *Ao = op_k + (int64_t)goff[g] * D::KK * D::KP;
+    for (int i = threadIdx.x; i < D::KK * D::KP; i += 256) sA[i] = Ao[i];
+    for (int i = threadIdx.x; i < D::KK * 64; i += 256) {
+        const int k = i >> 6, j = i & 63, n = n0 + j;
+        T v = T(0);
+        if (n < n1 && k < D::K) {
+            const int p = n / Cc, c = n - p * Cc;
+            v = M[((int64_t)src[pb + p] * D::K + k) * C + c0 + c];
         }
-        __syncthreads();
+        sB[i] = v;
     }
-    for (int idx = threadIdx.x; idx < nts * K * ct; idx += blockDim.x) {
-        const int t = idx / (K * ct), rem = idx - t * K * ct, row = rem / ct, c = rem - row * ct;
-        if (c0 + c < C) L[((int64_t)a.tgt_list[tb + t] * K + row) * C + c0 + c] = acc[idx];
+    __syncthreads();
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+    T acc[D::NRT][4];
+#pragma unroll
+    for (int i = 0; i < D::NRT; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+    for (int k = 0; k < D::K; ++k) {
+        T a[D::NRT], b[4];
+#pragma unroll
+        for (int i = 0; i < D::NRT; ++i) a[i] = sA[k * D::KP + tr * D::NRT + i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = sB[k * 64 + tc * 4 + j];
+#pragma unroll
+        for (int i = 0; i < D::NRT; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int n = n0 + tc * 4 + j;
+        if (n >= n1) continue;
+        const int p = n / Cc, c = n - p * Cc;
+        T *out = tmp + ((int64_t)(pb + p) * Cc + c) * D::KP + tr * D::NRT;
+#pragma unroll
+        for (int i = 0; i < D::NRT; ++i) out[i] = acc[i][j];
+    }
+}
+
+// L[t][row][c0 + c] = sum over the pairs of t (fixed order) of tmp[slot][c][row].
+template <typename T, int ORD>
+__global__ __launch_bounds__(256) void k_m2l_reduce(const int32_t *__restrict__ red_tgt,
+                                                    const int32_t *__restrict__ red_ptr,
+                                                    const int32_t *__restrict__ red_slot, const T *__restrict__ tmp,
+                                                    int C, int c0, int Cc, T *__restrict__ L)
+{
+    using D = M2LDims<ORD>;
+    const int ti = blockIdx.x;
+    const int32_t t = red_tgt[ti], j0 = red_ptr[ti], j1 = red_ptr[ti + 1];
+    for (int idx = threadIdx.x; idx < Cc * D::K; idx += 256) {
+        const int c = idx / D::K, row = idx - c * D::K;
+        T s = 0;
+        for (int j = j0; j < j1; ++j) s += tmp[((int64_t)red_slot[j] * Cc + c) * D::KP + row];
+        L[((int64_t)t * D::K + row) * C + c0 + c] = s;
+    }
+}
+
+// Work items of one column chunk width Cc (cached per engine and width).
+static const int32_t *m2l_items(const xrl_plan *P, bool mfma, int Cc, int *n_items, hipStream_t s)
+{
+    const int64_t key = (mfma ? 1000000 : 0) + Cc;
+    for (auto &kv : P->item_cache)
+        if (kv.first == key) {
+            *n_items = (int)(kv.second.n / 3);
+            return kv.second.p;
+        }
+    std::vector<int32_t> it;
+    for (int64_t g = 0; g < P->n_groups; ++g) {
+        const int64_t ncols = (int64_t)(P->h_os_gbeg[g + 1] - P->h_os_gbeg[g]) * Cc;
+        if (mfma) {
+            const int64_t nct = cdiv(ncols, 16), WT = 8;
+            for (int64_t c = 0; c < nct; c += WT) it.insert(it.end(), {(int32_t)g, (int32_t)c, (int32_t)std::min(nct, c + WT)});
+        } else {
+            for (int64_t c = 0; c < ncols; c += 64) it.insert(it.end(), {(int32_t)g, (int32_t)c, (int32_t)std::min(ncols, c + 64)});
+        }
+    }
+    P->item_cache.emplace_back(key, DevBuf<int32_t>());
+    auto &buf = P->item_cache.back().second;
+    buf.upload(it, s);
+    XRL_HIP(hipStreamSynchronize(s));
+    *n_items = (int)(it.size() / 3);
+    return buf.p;
+}
+
+template <typename T, int ORD>
+static void m2l_launch(const xrl_plan *P, const T *op_frag, const T *op_k, const T *M, T *L, DevBuf<T> &tmp, int C,
+                       hipStream_t s)
+{
+    using D = M2LDims<ORD>;
+    if (P->n_m2l == 0) return;
+    const bool mfma = P->m2l_engine == XRL_M2L_MFMA;
+    // column chunk so that the per-pair scratch stays within 4 GiB
+    const int64_t per_col = P->n_m2l * (int64_t)D::KP * (int64_t)sizeof(T);
+    const int Cc = (int)std::max<int64_t>(1, std::min<int64_t>(C, (int64_t(4) << 30) / per_col));
+    if (tmp.n < (size_t)(P->n_m2l * (int64_t)Cc * D::KP)) tmp.alloc(P->n_m2l * (int64_t)Cc * D::KP);
+    for (int c0 = 0; c0 < C; c0 += Cc) {
+        const int cc = std::min(Cc, C - c0);
+        int n_items = 0;
+        const int32_t *items = m2l_items(P, mfma, cc, &n_items, s);
+        if (mfma) {
+            k_m2l_os_mfma<T, ORD><<<(unsigned)cdiv(n_items, 4), 256, 0, s>>>(
+                items, n_items, P->os_gbeg.p, P->os_goff.p, P->os_src.p, op_frag, M, C, c0, cc, tmp.p);
+        } else {
+            // the LDS-staged operator of the vector-ALU kernel fits up to order 8
+            if constexpr (ORD <= 8)
+                k_m2l_os_valu<T, ORD><<<(unsigned)n_items, 256, 0, s>>>(items, P->os_gbeg.p, P->os_goff.p,
+                                                                        P->os_src.p, op_k, M, C, c0, cc, tmp.p);
+            else
+                fail(XRL_E_UNSUPPORTED, "xrl_fmm_matvec: the vector-ALU M2L supports order <= 8");
+        }
+        XRL_HIP(hipGetLastError());
+        k_m2l_reduce<T, ORD><<<(unsigned)P->n_red, 256, 0, s>>>(P->red_tgt.p, P->red_ptr.p, P->red_slot.p, tmp.p, C,
+                                                                c0, cc, L);
+        XRL_HIP(hipGetLastError());
     }
 }
 
@@ -368,8 +482,8 @@ static void p2p_launch(const xrl_plan *P, const T *val, const T *xs, T *ys, int 
 template <typename T>
 static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols, int dtype, void *y, int64_t ldy,
                        const double *alpha, const double *beta, hipStream_t s, DevBuf<T> &xs, DevBuf<T> &ys,
-                       DevBuf<T> &M, DevBuf<T> &L, const T *near, const T *mom, const T *m2m, const T *l2l,
-                       const T *m2l_rows, const T *m2l_frag)
+                       DevBuf<T> &M, DevBuf<T> &L, DevBuf<T> &tmp, const T *near, const T *mom, const T *m2m,
+                       const T *l2l, const T *m2l_k, const T *m2l_frag)
 {
     const int C = 2 * ncols;
     const int K = P->K;
@@ -428,18 +542,13 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
     k_fill_zero<T><<<(unsigned)std::min<int64_t>(cdiv(B * K * C, 256), 65536), 256, 0, s>>>(L.p, B * K * C);
     XRL_HIP(hipGetLastError());
     mark(4);
-    if (P->n_slabs > 0) {
-        const int ct = std::min(C, P->m2l_ct);
-        M2LArgs a{P->m2l_tgt_list.p, P->slab_tbeg.p, P->slab_gbeg.p, P->grp_off.p, P->grp_pbeg.p,
-                  P->pair_tloc.p,    P->pair_src.p,  C,              K,            P->KK,
-                  ct};
-        const size_t sm = (size_t)P->slab_targets * K * ct * sizeof(T);
-        dim3 grid((unsigned)P->n_slabs, (unsigned)cdiv(C, ct));
-        if (P->m2l_engine == XRL_M2L_MFMA)
-            k_m2l_mfma<T><<<grid, 256, sm, s>>>(a, m2l_frag, M.p, L.p);
-        else
-            k_m2l_valu<T><<<grid, 256, sm, s>>>(a, m2l_rows, P->KP, M.p, L.p);
-        XRL_HIP(hipGetLastError());
+    switch (P->p) {
+        case 2: m2l_launch<T, 2>(P, m2l_frag, m2l_k, M.p, L.p, tmp, C, s); break;
+        case 4: m2l_launch<T, 4>(P, m2l_frag, m2l_k, M.p, L.p, tmp, C, s); break;
+        case 6: m2l_launch<T, 6>(P, m2l_frag, m2l_k, M.p, L.p, tmp, C, s); break;
+        case 8: m2l_launch<T, 8>(P, m2l_frag, m2l_k, M.p, L.p, tmp, C, s); break;
+        case 10: m2l_launch<T, 10>(P, m2l_frag, m2l_k, M.p, L.p, tmp, C, s); break;
+        default: m2l_launch<T, 12>(P, m2l_frag, m2l_k, M.p, L.p, tmp, C, s); break;
     }
     mark(5);
     for (int l = 3; l <= P->depth; ++l) {
@@ -524,11 +633,12 @@ extern "C" xrl_status xrl_fmm_matvec(const xrl_plan *P, const void *x, int64_t l
         const double *al = ep ? ep->alpha : nullptr, *be = ep ? ep->beta : nullptr;
         if (P->precision == XRL_PREC_FP64)
             run_matvec<double>(P, x, ldx, n_cols, dtype, y, ldy, al, be, s, Pm->xs64, Pm->ys64, Pm->M64, Pm->L64,
-                               P->near64.p, P->mom64.p, P->op_m2m64.p, P->op_l2l64.p, P->op_m2l64.p,
+                               Pm->os_tmp64, P->near64.p, P->mom64.p, P->op_m2m64.p, P->op_l2l64.p, P->op_m2l64k.p,
                                P->op_m2l64f.p);
         else
             run_matvec<float>(P, x, ldx, n_cols, dtype, y, ldy, al, be, s, Pm->xs32, Pm->ys32, Pm->M32, Pm->L32,
-                              P->near32.p, P->mom32.p, P->op_m2m32.p, P->op_l2l32.p, P->op_m2l32.p, P->op_m2l32f.p);
+                              Pm->os_tmp32, P->near32.p, P->mom32.p, P->op_m2m32.p, P->op_l2l32.p, P->op_m2l32k.p,
+                              P->op_m2l32f.p);
     });
 }
 

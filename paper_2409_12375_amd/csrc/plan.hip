@@ -525,68 +525,51 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     P->near_src.upload(src_rows, s);
     P->near_val_off.upload(val_off, s);
     P->leaf_tpad.upload(tpad, s);
-    // ---------------- M2L slabs and offset groups
-    const int creal = 2 * P->max_cols;
-    const size_t elt = P->precision == XRL_PREC_FP64 ? 8 : 4;
-    P->m2l_ct = std::min(creal, P->precision == XRL_PREC_FP64 ? 8 : 16);
-    const int budget = 64 * 1024;
-    P->slab_targets = (int)std::max<int64_t>(1, std::min<int64_t>(64, budget / (P->K * P->m2l_ct * (int64_t)elt)));
-    std::vector<int32_t> tlist, slab_tbeg{0}, slab_gbeg{0}, grp_off, grp_pbeg{0}, pair_tloc, pair_src;
+    // ---------------- M2L pairs sorted by offset, per-target reduction lists
+    std::vector<int32_t> ord(nV);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return hcode[a] < hcode[b]; });
+    std::vector<int32_t> os_src(nV), slot(nV), grp_off, gbeg;
+    for (int64_t j = 0; j < nV; ++j) {
+        os_src[j] = hsrc[ord[j]];
+        slot[ord[j]] = (int32_t)j;
+        if (j == 0 || hcode[ord[j]] != hcode[ord[j - 1]]) {
+            grp_off.push_back(hcode[ord[j]]);
+            gbeg.push_back((int32_t)j);
+        }
+    }
+    gbeg.push_back((int32_t)nV);
+    std::vector<int32_t> red_tgt, red_ptr{0};
     P->h_m2l_pairs.resize(2 * nV);
     std::vector<double> hrad = P->box_rad.download(s);
     double maxsep = 0;
-    {
-        std::vector<int32_t> targets;
-        for (int64_t b = 0; b < B; ++b)
-            if (voff[b + 1] > voff[b]) targets.push_back((int32_t)b);
-        const int ST = P->slab_targets;
-        for (size_t t0 = 0; t0 < targets.size(); t0 += ST) {
-            const size_t t1 = std::min(targets.size(), t0 + ST);
-            std::vector<std::array<int32_t, 3>> pr;  // (code, tloc, src)
-            for (size_t ti = t0; ti < t1; ++ti) {
-                const int32_t b = targets[ti];
-                tlist.push_back(b);
-                for (int64_t j = voff[b]; j < voff[b + 1]; ++j) pr.push_back({hcode[j], (int32_t)(ti - t0), hsrc[j]});
-            }
-            std::stable_sort(pr.begin(), pr.end(),
-                             [](const std::array<int32_t, 3> &a, const std::array<int32_t, 3> &b) { return a[0] < b[0]; });
-            for (size_t i = 0; i < pr.size(); ++i) {
-                if (i == 0 || pr[i][0] != pr[i - 1][0]) {
-                    if (i > 0) grp_pbeg.push_back((int32_t)pair_tloc.size());
-                    grp_off.push_back(pr[i][0]);
-                }
-                pair_tloc.push_back(pr[i][1]);
-                pair_src.push_back(pr[i][2]);
-            }
-            if (!pr.empty()) grp_pbeg.push_back((int32_t)pair_tloc.size());
-            slab_tbeg.push_back((int32_t)tlist.size());
-            slab_gbeg.push_back((int32_t)grp_off.size());
+    for (int64_t b = 0, q = 0; b < B; ++b) {
+        if (voff[b + 1] > voff[b]) {
+            red_tgt.push_back((int32_t)b);
+            red_ptr.push_back((int32_t)voff[b + 1]);
         }
-        // grp_pbeg currently has a leading 0 and one end per group
-        for (int64_t b = 0, q = 0; b < B; ++b)
-            for (int64_t j = voff[b]; j < voff[b + 1]; ++j, ++q) {
-                P->h_m2l_pairs[2 * q] = (int32_t)b;
-                P->h_m2l_pairs[2 * q + 1] = hsrc[j];
-                const int32_t sb = hsrc[j];
-                double d2 = 0;
-                for (int d = 0; d < 3; ++d) {
-                    const double dd = center[3 * b + d] - center[3 * sb + d];
-                    d2 += dd * dd;
-                }
-                maxsep = std::max(maxsep, (hrad[b] + hrad[sb]) / std::sqrt(d2));
+        for (int64_t j = voff[b]; j < voff[b + 1]; ++j, ++q) {
+            P->h_m2l_pairs[2 * q] = (int32_t)b;
+            P->h_m2l_pairs[2 * q + 1] = hsrc[j];
+            const int32_t sb = hsrc[j];
+            double d2 = 0;
+            for (int d = 0; d < 3; ++d) {
+                const double dd = center[3 * b + d] - center[3 * sb + d];
+                d2 += dd * dd;
             }
-        P->n_targets = (int64_t)tlist.size();
-        P->n_slabs = (int64_t)slab_tbeg.size() - 1;
-        P->n_groups = (int64_t)grp_off.size();
+            maxsep = std::max(maxsep, (hrad[b] + hrad[sb]) / std::sqrt(d2));
+        }
     }
     P->max_sep_ratio = maxsep;
-    P->m2l_tgt_list.upload(tlist, s);
-    P->slab_tbeg.upload(slab_tbeg, s);
-    P->slab_gbeg.upload(slab_gbeg, s);
-    P->grp_off.upload(grp_off, s);
-    P->grp_pbeg.upload(grp_pbeg, s);
-    P->pair_tloc.upload(pair_tloc, s);
-    P->pair_src.upload(pair_src, s);
+    P->n_groups = (int64_t)grp_off.size();
+    P->n_red = (int64_t)red_tgt.size();
+    P->h_os_gbeg = gbeg;
+    P->os_src.upload(os_src, s);
+    P->os_goff.upload(grp_off, s);
+    P->os_gbeg.upload(gbeg, s);
+    P->red_tgt.upload(red_tgt, s);
+    P->red_ptr.upload(red_ptr, s);
+    P->red_slot.upload(slot, s);
     // ---------------- operators
     const int p = P->p, K = P->K;
     std::vector<double> m2m(8 * (size_t)K * K), l2l(8 * (size_t)K * K);
@@ -620,6 +603,13 @@ static void build_plan(xrl_plan *P, hipStream_t s)
                         m2l[((size_t)c * P->KP + rt * 16 + (lane & 15)) * P->KK + 4 * ks + (lane >> 4)];
     P->op_m2l64f.upload(frag, s);
     P->op_m2l32f.upload(to32(frag), s);
+    std::vector<double> kmaj(m2l.size(), 0.0);
+    for (int c = 0; c < 343; ++c)
+        for (int r = 0; r < P->KP; ++r)
+            for (int k = 0; k < P->KK; ++k)
+                kmaj[((size_t)c * P->KK + k) * P->KP + r] = m2l[((size_t)c * P->KP + r) * P->KK + k];
+    P->op_m2l64k.upload(kmaj, s);
+    P->op_m2l32k.upload(to32(kmaj), s);
     P->op_m2m64.upload(m2m, s);
     P->op_l2l64.upload(l2l, s);
     P->op_m2l64.upload(m2l, s);
