@@ -166,6 +166,23 @@ struct xrl_tree {
 };
 
 // --------------------------------------------------------------------------
+// One translation pass (M2L over all levels, or M2M / L2L at one level):
+// (target box, source box, operator) triples sorted by operator, plus the
+// per-target reduction lists over the sorted positions.
+// --------------------------------------------------------------------------
+struct TransPass {
+    int64_t n_pairs = 0, n_groups = 0, n_red = 0;
+    std::vector<int32_t> h_gbeg;      // [n_groups+1]
+    xrl::DevBuf<int32_t> src;         // [n_pairs] source box, operator-sorted
+    xrl::DevBuf<int32_t> goff;        // [n_groups] operator index
+    xrl::DevBuf<int32_t> gbeg;        // [n_groups+1]
+    xrl::DevBuf<int32_t> red_tgt;     // [n_red] target boxes
+    xrl::DevBuf<int32_t> red_ptr;     // [n_red+1]
+    xrl::DevBuf<int32_t> red_slot;    // [n_pairs] sorted position of each pair, target order
+    mutable std::vector<std::pair<int64_t, xrl::DevBuf<int32_t>>> item_cache;  // key: (engine, cols)
+};
+
+// --------------------------------------------------------------------------
 // Plan: one or more trees, interaction lists, operators, near field.
 // --------------------------------------------------------------------------
 struct xrl_plan {
@@ -196,21 +213,12 @@ struct xrl_plan {
     xrl::DevBuf<int32_t> pvid;   // [N][3] (vertex ids offset per tree)
     xrl::DevBuf<double> cen, area, diam;
     xrl::DevBuf<int32_t> panel_leaf;  // [N] leaf index (into leaf_box) of each sorted panel
-    // M2L pairs sorted by translation offset (one operator per group), the
-    // per-target reduction lists over the sorted positions, and per column
-    // count work-item lists (cached)
+    // translation passes
     int64_t n_m2l = 0;
     int64_t n_demoted = 0;  // V candidates applied directly (radii do not separate)
-    std::vector<int32_t> h_m2l_pairs;   // [n][2] (t, s), per-target order, for export
-    std::vector<int32_t> h_os_gbeg;     // [n_groups+1]
-    xrl::DevBuf<int32_t> os_src;        // [n_pairs] source box, offset-sorted
-    xrl::DevBuf<int32_t> os_goff;       // [n_groups] operator offset code
-    xrl::DevBuf<int32_t> os_gbeg;       // [n_groups+1]
-    xrl::DevBuf<int32_t> red_tgt;       // [n_red] target boxes with V pairs
-    xrl::DevBuf<int32_t> red_ptr;       // [n_red+1]
-    xrl::DevBuf<int32_t> red_slot;      // [n_pairs] offset-sorted position of each pair
-    int64_t n_groups = 0, n_red = 0;
-    mutable std::vector<std::pair<int64_t, xrl::DevBuf<int32_t>>> item_cache;  // key: (engine, cols)
+    std::vector<int32_t> h_m2l_pairs;  // [n][2] (t, s), per-target order, for export
+    TransPass m2l;
+    std::vector<TransPass> m2m, l2l;   // per level
     mutable xrl::DevBuf<float> os_tmp32;
     mutable xrl::DevBuf<double> os_tmp64;
     double max_sep_ratio = 0;
@@ -220,9 +228,10 @@ struct xrl_plan {
     // M2L operators k-major for the vector-ALU GEMM [343][KK][KP]
     xrl::DevBuf<float> op_m2l32k;
     xrl::DevBuf<double> op_m2l64k;
-    // M2L operators in MFMA fragment order [343][KP/16][KK/4][64]
-    xrl::DevBuf<double> op_m2l64f;
-    xrl::DevBuf<float> op_m2l32f;
+    // operators in MFMA fragment order [n_op][KP/16][KK/4][64] and k-major
+    // [n_op][KK][KP] for the vector-ALU GEMM (M2L: 343 slots, M2M/L2L: 8)
+    xrl::DevBuf<double> op_m2l64f, op_m2m64f, op_l2l64f, op_m2m64k, op_l2l64k;
+    xrl::DevBuf<float> op_m2l32f, op_m2m32f, op_l2l32f, op_m2m32k, op_l2l32k;
     int KP = 96, KK = 84;  // padded row / k dims of the M2L operator tiles
     // moment table per sorted panel, scaled to its leaf: [N][K]
     xrl::DevBuf<double> mom64;

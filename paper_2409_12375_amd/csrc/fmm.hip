@@ -6,13 +6,14 @@
 //   gather   user order, complex -> Morton order, real columns   xs[N][C]
 //   P2P      y  = P_near x (stored near-field blocks)             ys[N][C]
 //   P2M      M_leaf = sum_k Q_k x_k (exact panel moments)         M[B][K][C]
-//   M2M      parents from children, deepest level first
-//   M2L      L_t = sum_{s in V(t)} T_{o(t,s)} M_s (MFMA or vector ALU)
-//   L2L      children from parents, top level first
+//   M2M      parents from children, deepest level first  } grouped GEMMs, one
+//   M2L      L_t = sum_{s in V(t)} T_{o(t,s)} M_s         } operator per group,
+//   L2L      children from parents, top level first      } MFMA or vector ALU
 //   L2P      y += (1/h) sum_i w_i Q_k[i] L_leaf[i]  (Galerkin-tested local)
 //   scatter  y_user = alpha_c y + beta_c A .* x_user
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <type_traits>
 
 #include "common.h"
@@ -28,12 +29,12 @@ __global__ void k_gather_x(int64_t N, const int32_t *__restrict__ perm, const TI
                            int ncols, TW *__restrict__ xs)
 {
     const int C = 2 * ncols;
-    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= N * C) return;
-    const int64_t i = e / C;
-    const int c = (int)(e - i * C);
-    const int64_t u = perm[i];
-    xs[e] = (TW)x[2 * (u * ldx + (c >> 1)) + (c & 1)];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N * C; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / C;
+        const int c = (int)(e - i * C);
+        const int64_t u = perm[i];
+        xs[e] = (TW)x[2 * (u * ldx + (c >> 1)) + (c & 1)];
+    }
 }
 
 template <typename TO, typename TW>
@@ -42,8 +43,8 @@ __global__ void k_scatter_y(int64_t N, const int32_t *__restrict__ perm, const T
                             TO *__restrict__ y, int64_t ldy, int ncols, const double *__restrict__ alpha,
                             const double *__restrict__ beta)
 {
-    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= N * ncols) return;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N * ncols;
+         e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e / ncols;
     const int c = (int)(e - i * ncols);
     const int64_t u = perm[i];
@@ -64,12 +65,16 @@ __global__ void k_scatter_y(int64_t N, const int32_t *__restrict__ perm, const T
     }
     y[2 * (u * ldy + c)] = (TO)yr;
     y[2 * (u * ldy + c) + 1] = (TO)yi;
+    }
 }
 
 // ---------------------------------------------------------------- P2P
-// One workgroup per (target leaf, column tile).  Lane j of a group of tpad
-// lanes owns target panel j; the 256/tpad groups stride over the source rows
-// of the leaf; block values are read coalesced ([row][tpad]).
+// One workgroup per (target leaf, column tile).  The stored block of a leaf
+// is [rows][tpad]; a thread owns VEC consecutive targets of one row (one
+// 16-byte load) and the tpad/VEC threads of a row group stride over the rows.
+// Source indices and the source densities of a chunk of 256 rows are staged
+// in LDS first, so the value stream is the only global load in the inner
+// loop.  The row groups are summed in a fixed order at the end.
 template <typename T, int CT>
 __global__ __launch_bounds__(256) void k_p2p(const int32_t *__restrict__ leaf_box, const int32_t *__restrict__ box_beg,
                                              const int32_t *__restrict__ box_end, const int32_t *__restrict__ near_rows,
@@ -77,40 +82,56 @@ __global__ __launch_bounds__(256) void k_p2p(const int32_t *__restrict__ leaf_bo
                                              const int64_t *__restrict__ val_off, const T *__restrict__ val,
                                              const T *__restrict__ xs, T *__restrict__ ys, int C)
 {
-    __shared__ T red[256 * CT];
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int ROWS = 256;
+    using V4 = typename std::conditional<sizeof(T) == 4, f32x4, double __attribute__((ext_vector_type(2)))>::type;
+    __shared__ T sx[ROWS * CT];
+    __shared__ T red[256 * VEC * CT];
     const int64_t li = blockIdx.x;
     const int c0 = blockIdx.y * CT;
     const int32_t tb = leaf_box[li];
     const int32_t kb = box_beg[tb], nt = box_end[tb] - kb;
     const int32_t r0 = near_rows[li], nr = near_rows[li + 1] - r0;
     const int G = leaf_tpad[li];
-    const int slots = 256 / G;
-    const int j = threadIdx.x % G, slot = threadIdx.x / G;
+    const int tpr = G / VEC;          // threads per row
+    const int groups = 256 / tpr;     // rows in flight per pass
+    const int jv = (threadIdx.x % tpr) * VEC, grp = threadIdx.x / tpr;
     const T *vb = val + val_off[li];
-    T acc[CT];
+    T acc[VEC][CT];
 #pragma unroll
-    for (int c = 0; c < CT; ++c) acc[c] = 0;
-    const bool full = c0 + CT <= C;
-    for (int32_t r = slot; r < nr; r += slots) {
-        const T v = vb[(int64_t)r * G + j];
-        const T *xr = xs + (int64_t)near_src[r0 + r] * C + c0;
-        if (full) {
+    for (int v = 0; v < VEC; ++v)
 #pragma unroll
-            for (int c = 0; c < CT; ++c) acc[c] += v * xr[c];
-        } else {
+        for (int c = 0; c < CT; ++c) acc[v][c] = 0;
+    for (int32_t rc = 0; rc < nr; rc += ROWS) {
+        const int nrc = min(ROWS, nr - rc);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nrc * CT; i += 256) {
+            const int r = i / CT, c = i - r * CT;
+            sx[i] = (c0 + c < C) ? xs[(int64_t)near_src[r0 + rc + r] * C + c0 + c] : T(0);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int r = grp; r < nrc; r += groups) {
+            const V4 v = *reinterpret_cast<const V4 *>(vb + (int64_t)(rc + r) * G + jv);
+            const T *xr = sx + r * CT;
 #pragma unroll
-            for (int c = 0; c < CT; ++c)
-                if (c0 + c < C) acc[c] += v * xr[c];
+            for (int c = 0; c < CT; ++c) {
+                const T xv = xr[c];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc[e][c] += v[e] * xv;
+            }
         }
     }
 #pragma unroll
-    for (int c = 0; c < CT; ++c) red[(slot * G + j) * CT + c] = acc[c];
+    for (int e = 0; e < VEC; ++e)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) red[(grp * G + jv + e) * CT + c] = acc[e][c];
     __syncthreads();
     for (int idx = threadIdx.x; idx < nt * CT; idx += 256) {
         const int jj = idx / CT, c = idx - jj * CT;
         if (c0 + c >= C) continue;
         T sum = 0;
-        for (int sl = 0; sl < slots; ++sl) sum += red[(sl * G + jj) * CT + c];
+        for (int g = 0; g < groups; ++g) sum += red[(g * G + jj) * CT + c];
         ys[(int64_t)(kb + jj) * C + c0 + c] = sum;
     }
 }
@@ -136,56 +157,6 @@ __global__ __launch_bounds__(256) void k_p2m(const int32_t *__restrict__ leaf_bo
         T acc = 0;
         for (int k = 0; k < nt; ++k) acc += mom[(int64_t)(kb + k) * K + i] * sx[k * CT + c];
         M[((int64_t)b * K + i) * C + c0 + c] = acc;
-    }
-}
-
-// ---------------------------------------------------------------- M2M / L2L
-// out[b] (=|+=) sum over inputs of op[oct] * in[...]; one workgroup per
-// (box, column tile); inputs staged in LDS.
-template <typename T, int CT, bool UP>
-__global__ __launch_bounds__(256) void k_translate(int64_t lo, int64_t hi, const int32_t *__restrict__ child0,
-                                                   const int32_t *__restrict__ nchild,
-                                                   const int32_t *__restrict__ parent,
-                                                   const int32_t *__restrict__ octant, const T *__restrict__ op,
-                                                   const T *__restrict__ in, T *__restrict__ out, int C, int K)
-{
-    extern __shared__ unsigned char smem_raw[];
-    T *sin = reinterpret_cast<T *>(smem_raw);  // [8][K][CT]
-    const int64_t b = lo + blockIdx.x;
-    if (b >= hi) return;
-    const int c0 = blockIdx.y * CT;
-    int nin;
-    if (UP) {
-        nin = nchild[b];
-        if (nin == 0) return;  // leaf: multipole from P2M
-        for (int idx = threadIdx.x; idx < nin * K * CT; idx += blockDim.x) {
-            const int q = idx / (K * CT), rem = idx - q * K * CT, i = rem / CT, c = rem - i * CT;
-            sin[idx] = (c0 + c < C) ? in[((int64_t)(child0[b] + q) * K + i) * C + c0 + c] : T(0);
-        }
-    } else {
-        nin = 1;
-        const int32_t p = parent[b];
-        for (int idx = threadIdx.x; idx < K * CT; idx += blockDim.x) {
-            const int i = idx / CT, c = idx - i * CT;
-            sin[idx] = (c0 + c < C) ? in[((int64_t)p * K + i) * C + c0 + c] : T(0);
-        }
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < K * CT; idx += blockDim.x) {
-        const int i = idx / CT, c = idx - i * CT;
-        if (c0 + c >= C) continue;
-        T acc = 0;
-        for (int q = 0; q < nin; ++q) {
-            const int oc = UP ? octant[child0[b] + q] : octant[b];
-            const T *row = op + ((int64_t)oc * K + i) * K;
-            const T *col = sin + (int64_t)q * K * CT + c;
-            for (int kk = 0; kk < K; ++kk) acc += row[kk] * col[kk * CT];
-        }
-        T *o = out + ((int64_t)b * K + i) * C + c0 + c;
-        if (UP)
-            *o = acc;
-        else
-            *o += acc;
     }
 }
 
@@ -372,12 +343,13 @@ __global__ __launch_bounds__(256) void k_m2l_os_valu(const int32_t *__restrict__
     }
 }
 
-// L[t][row][c0 + c] = sum over the pairs of t (fixed order) of tmp[slot][c][row].
+// out[t][row][c0 + c] (=|+=) sum over the pairs of t (fixed order) of
+// tmp[slot][c][row].
 template <typename T, int ORD>
-__global__ __launch_bounds__(256) void k_m2l_reduce(const int32_t *__restrict__ red_tgt,
-                                                    const int32_t *__restrict__ red_ptr,
-                                                    const int32_t *__restrict__ red_slot, const T *__restrict__ tmp,
-                                                    int C, int c0, int Cc, T *__restrict__ L)
+__global__ __launch_bounds__(256) void k_pass_reduce(const int32_t *__restrict__ red_tgt,
+                                                     const int32_t *__restrict__ red_ptr,
+                                                     const int32_t *__restrict__ red_slot, const T *__restrict__ tmp,
+                                                     int C, int c0, int Cc, int accumulate, T *__restrict__ out)
 {
     using D = M2LDims<ORD>;
     const int ti = blockIdx.x;
@@ -386,22 +358,23 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(const int32_t *__restrict__ 
         const int c = idx / D::K, row = idx - c * D::K;
         T s = 0;
         for (int j = j0; j < j1; ++j) s += tmp[((int64_t)red_slot[j] * Cc + c) * D::KP + row];
-        L[((int64_t)t * D::K + row) * C + c0 + c] = s;
+        T *o = out + ((int64_t)t * D::K + row) * C + c0 + c;
+        *o = accumulate ? *o + s : s;
     }
 }
 
 // Work items of one column chunk width Cc (cached per engine and width).
-static const int32_t *m2l_items(const xrl_plan *P, bool mfma, int Cc, int *n_items, hipStream_t s)
+static const int32_t *pass_items(const TransPass &T, bool mfma, int Cc, int *n_items, hipStream_t s)
 {
     const int64_t key = (mfma ? 1000000 : 0) + Cc;
-    for (auto &kv : P->item_cache)
+    for (auto &kv : T.item_cache)
         if (kv.first == key) {
             *n_items = (int)(kv.second.n / 3);
             return kv.second.p;
         }
     std::vector<int32_t> it;
-    for (int64_t g = 0; g < P->n_groups; ++g) {
-        const int64_t ncols = (int64_t)(P->h_os_gbeg[g + 1] - P->h_os_gbeg[g]) * Cc;
+    for (int64_t g = 0; g < T.n_groups; ++g) {
+        const int64_t ncols = (int64_t)(T.h_gbeg[g + 1] - T.h_gbeg[g]) * Cc;
         if (mfma) {
             const int64_t nct = cdiv(ncols, 16), WT = 8;
             for (int64_t c = 0; c < nct; c += WT) it.insert(it.end(), {(int32_t)g, (int32_t)c, (int32_t)std::min(nct, c + WT)});
@@ -409,43 +382,45 @@ static const int32_t *m2l_items(const xrl_plan *P, bool mfma, int Cc, int *n_ite
             for (int64_t c = 0; c < ncols; c += 64) it.insert(it.end(), {(int32_t)g, (int32_t)c, (int32_t)std::min(ncols, c + 64)});
         }
     }
-    P->item_cache.emplace_back(key, DevBuf<int32_t>());
-    auto &buf = P->item_cache.back().second;
+    T.item_cache.emplace_back(key, DevBuf<int32_t>());
+    auto &buf = T.item_cache.back().second;
     buf.upload(it, s);
     XRL_HIP(hipStreamSynchronize(s));
     *n_items = (int)(it.size() / 3);
     return buf.p;
 }
 
+// One translation pass: grouped GEMM into the scratch array, then the
+// per-target reduction into `out` (overwrite or accumulate).
 template <typename T, int ORD>
-static void m2l_launch(const xrl_plan *P, const T *op_frag, const T *op_k, const T *M, T *L, DevBuf<T> &tmp, int C,
-                       hipStream_t s)
+static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag, const T *op_k, const T *in, T *out,
+                        int accumulate, DevBuf<T> &tmp, int C, hipStream_t s)
 {
     using D = M2LDims<ORD>;
-    if (P->n_m2l == 0) return;
+    if (TP.n_pairs == 0) return;
     const bool mfma = P->m2l_engine == XRL_M2L_MFMA;
     // column chunk so that the per-pair scratch stays within 4 GiB
-    const int64_t per_col = P->n_m2l * (int64_t)D::KP * (int64_t)sizeof(T);
+    const int64_t per_col = TP.n_pairs * (int64_t)D::KP * (int64_t)sizeof(T);
     const int Cc = (int)std::max<int64_t>(1, std::min<int64_t>(C, (int64_t(4) << 30) / per_col));
-    if (tmp.n < (size_t)(P->n_m2l * (int64_t)Cc * D::KP)) tmp.alloc(P->n_m2l * (int64_t)Cc * D::KP);
+    if (tmp.n < (size_t)(TP.n_pairs * (int64_t)Cc * D::KP)) tmp.alloc(TP.n_pairs * (int64_t)Cc * D::KP);
     for (int c0 = 0; c0 < C; c0 += Cc) {
         const int cc = std::min(Cc, C - c0);
         int n_items = 0;
-        const int32_t *items = m2l_items(P, mfma, cc, &n_items, s);
+        const int32_t *items = pass_items(TP, mfma, cc, &n_items, s);
         if (mfma) {
             k_m2l_os_mfma<T, ORD><<<(unsigned)cdiv(n_items, 4), 256, 0, s>>>(
-                items, n_items, P->os_gbeg.p, P->os_goff.p, P->os_src.p, op_frag, M, C, c0, cc, tmp.p);
+                items, n_items, TP.gbeg.p, TP.goff.p, TP.src.p, op_frag, in, C, c0, cc, tmp.p);
         } else {
             // the LDS-staged operator of the vector-ALU kernel fits up to order 8
             if constexpr (ORD <= 8)
-                k_m2l_os_valu<T, ORD><<<(unsigned)n_items, 256, 0, s>>>(items, P->os_gbeg.p, P->os_goff.p,
-                                                                        P->os_src.p, op_k, M, C, c0, cc, tmp.p);
+                k_m2l_os_valu<T, ORD><<<(unsigned)n_items, 256, 0, s>>>(items, TP.gbeg.p, TP.goff.p, TP.src.p, op_k,
+                                                                        in, C, c0, cc, tmp.p);
             else
-                fail(XRL_E_UNSUPPORTED, "xrl_fmm_matvec: the vector-ALU M2L supports order <= 8");
+                fail(XRL_E_UNSUPPORTED, "xrl_fmm_matvec: the vector-ALU translations support order <= 8");
         }
         XRL_HIP(hipGetLastError());
-        k_m2l_reduce<T, ORD><<<(unsigned)P->n_red, 256, 0, s>>>(P->red_tgt.p, P->red_ptr.p, P->red_slot.p, tmp.p, C,
-                                                                c0, cc, L);
+        k_pass_reduce<T, ORD><<<(unsigned)TP.n_red, 256, 0, s>>>(TP.red_tgt.p, TP.red_ptr.p, TP.red_slot.p, tmp.p, C,
+                                                                 c0, cc, accumulate, out);
         XRL_HIP(hipGetLastError());
     }
 }
@@ -480,10 +455,34 @@ static void p2p_launch(const xrl_plan *P, const T *val, const T *xs, T *ys, int 
 }
 
 template <typename T>
+struct Ops {
+    const T *near, *mom, *m2m_f, *m2m_k, *l2l_f, *l2l_k, *m2l_f, *m2l_k;
+};
+
+template <typename T, int ORD>
+static void translations(const xrl_plan *P, const Ops<T> &op, T *M, T *L, DevBuf<T> &tmp, int C, hipStream_t s,
+                         const std::function<void(int)> &mark)
+{
+    using D = M2LDims<ORD>;
+    mark(3);
+    for (int l = P->depth - 1; l >= 0; --l)
+        pass_launch<T, ORD>(P, P->m2m[l], op.m2m_f, op.m2m_k, M, M, 0, tmp, C, s);
+    // zero every local expansion (a fill kernel, so the sequence stays
+    // capturable into a HIP graph without memset nodes)
+    const int64_t nL = P->B * (int64_t)D::K * C;
+    k_fill_zero<T><<<(unsigned)std::min<int64_t>(cdiv(nL, 256), 65536), 256, 0, s>>>(L, nL);
+    XRL_HIP(hipGetLastError());
+    mark(4);
+    pass_launch<T, ORD>(P, P->m2l, op.m2l_f, op.m2l_k, M, L, 0, tmp, C, s);
+    mark(5);
+    for (int l = 3; l <= P->depth; ++l) pass_launch<T, ORD>(P, P->l2l[l], op.l2l_f, op.l2l_k, L, L, 1, tmp, C, s);
+    mark(6);
+}
+
+template <typename T>
 static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols, int dtype, void *y, int64_t ldy,
                        const double *alpha, const double *beta, hipStream_t s, DevBuf<T> &xs, DevBuf<T> &ys,
-                       DevBuf<T> &M, DevBuf<T> &L, DevBuf<T> &tmp, const T *near, const T *mom, const T *m2m,
-                       const T *l2l, const T *m2l_k, const T *m2l_frag)
+                       DevBuf<T> &M, DevBuf<T> &L, DevBuf<T> &tmp, const Ops<T> &op)
 {
     const int C = 2 * ncols;
     const int K = P->K;
@@ -497,81 +496,47 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
         L.alloc(B * K * C);
     }
     const bool prof = P->profiling;
-    auto mark = [&](int i) {
+    std::function<void(int)> mark = [&](int i) {
         if (prof) XRL_HIP(hipEventRecord(P->ev[i], s));
     };
     mark(0);
     const int bs = 256;
+    const unsigned gx = (unsigned)std::min<int64_t>(cdiv(N * C, bs), 1 << 20);
     if (dtype == XRL_C64)
-        k_gather_x<float, T><<<cdiv(N * C, bs), bs, 0, s>>>(N, P->perm.p, (const float *)x, ldx, ncols, xs.p);
+        k_gather_x<float, T><<<gx, bs, 0, s>>>(N, P->perm.p, (const float *)x, ldx, ncols, xs.p);
     else
-        k_gather_x<double, T><<<cdiv(N * C, bs), bs, 0, s>>>(N, P->perm.p, (const double *)x, ldx, ncols, xs.p);
+        k_gather_x<double, T><<<gx, bs, 0, s>>>(N, P->perm.p, (const double *)x, ldx, ncols, xs.p);
     XRL_HIP(hipGetLastError());
     mark(1);
-    p2p_launch<T>(P, near, xs.p, ys.p, C, s);
+    p2p_launch<T>(P, op.near, xs.p, ys.p, C, s);
     mark(2);
-    // column tile of the P2M / M2M / L2L / L2P kernels (M2M stages 8 children
-    // of K x CT values in LDS: at most 41 KB in FP32, 41 KB in FP64)
     const int CT = (sizeof(T) == 8 || C <= 8) ? 8 : 16;
     const unsigned ntile = (unsigned)cdiv(C, CT);
-    auto p2m = [&](auto ctc) {
-        constexpr int CTT = decltype(ctc)::value;
-        k_p2m<T, CTT><<<dim3((unsigned)P->n_leaves, (unsigned)cdiv(C, CTT)), 256, 0, s>>>(
-            P->leaf_box.p, P->box_beg.p, P->box_end.p, mom, xs.p, M.p, C, K);
-    };
-    if (CT == 8)
-        p2m(std::integral_constant<int, 8>());
-    else
-        p2m(std::integral_constant<int, 16>());
-    XRL_HIP(hipGetLastError());
-    mark(3);
-    for (int l = P->depth - 1; l >= 0; --l) {
-        const int64_t lo = P->level_off[l], hi = P->level_off[l + 1];
-        if (hi <= lo) continue;
-        const size_t sm = 8 * (size_t)K * CT * sizeof(T);
+    if (P->n_leaves > 0) {
         if (CT == 8)
-            k_translate<T, 8, true><<<dim3((unsigned)(hi - lo), ntile), 256, sm, s>>>(
-                lo, hi, P->box_child0.p, P->box_nchild.p, P->box_parent.p, P->box_octant.p, m2m, M.p, M.p, C, K);
+            k_p2m<T, 8><<<dim3((unsigned)P->n_leaves, ntile), 256, 0, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p,
+                                                                           op.mom, xs.p, M.p, C, K);
         else
-            k_translate<T, 16, true><<<dim3((unsigned)(hi - lo), ntile), 256, sm, s>>>(
-                lo, hi, P->box_child0.p, P->box_nchild.p, P->box_parent.p, P->box_octant.p, m2m, M.p, M.p, C, K);
+            k_p2m<T, 16><<<dim3((unsigned)P->n_leaves, ntile), 256, 0, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p,
+                                                                            op.mom, xs.p, M.p, C, K);
         XRL_HIP(hipGetLastError());
     }
-    // zero every local expansion (a fill kernel, so the sequence stays
-    // capturable into a HIP graph without memset nodes)
-    k_fill_zero<T><<<(unsigned)std::min<int64_t>(cdiv(B * K * C, 256), 65536), 256, 0, s>>>(L.p, B * K * C);
-    XRL_HIP(hipGetLastError());
-    mark(4);
     switch (P->p) {
-        case 2: m2l_launch<T, 2>(P, m2l_frag, m2l_k, M.p, L.p, tmp, C, s); break;
-        case 4: m2l_launch<T, 4>(P, m2l_frag, m2l_k, M.p, L.p, tmp, C, s); break;
-        case 6: m2l_launch<T, 6>(P, m2l_frag, m2l_k, M.p, L.p, tmp, C, s); break;
-        case 8: m2l_launch<T, 8>(P, m2l_frag, m2l_k, M.p, L.p, tmp, C, s); break;
-        case 10: m2l_launch<T, 10>(P, m2l_frag, m2l_k, M.p, L.p, tmp, C, s); break;
-        default: m2l_launch<T, 12>(P, m2l_frag, m2l_k, M.p, L.p, tmp, C, s); break;
+        case 2: translations<T, 2>(P, op, M.p, L.p, tmp, C, s, mark); break;
+        case 4: translations<T, 4>(P, op, M.p, L.p, tmp, C, s, mark); break;
+        case 6: translations<T, 6>(P, op, M.p, L.p, tmp, C, s, mark); break;
+        case 8: translations<T, 8>(P, op, M.p, L.p, tmp, C, s, mark); break;
+        case 10: translations<T, 10>(P, op, M.p, L.p, tmp, C, s, mark); break;
+        default: translations<T, 12>(P, op, M.p, L.p, tmp, C, s, mark); break;
     }
-    mark(5);
-    for (int l = 3; l <= P->depth; ++l) {
-        const int64_t lo = P->level_off[l], hi = P->level_off[l + 1];
-        if (hi <= lo) continue;
-        const size_t sm = (size_t)K * CT * sizeof(T);
-        if (CT == 8)
-            k_translate<T, 8, false><<<dim3((unsigned)(hi - lo), ntile), 256, sm, s>>>(
-                lo, hi, P->box_child0.p, P->box_nchild.p, P->box_parent.p, P->box_octant.p, l2l, L.p, L.p, C, K);
-        else
-            k_translate<T, 16, false><<<dim3((unsigned)(hi - lo), ntile), 256, sm, s>>>(
-                lo, hi, P->box_child0.p, P->box_nchild.p, P->box_parent.p, P->box_octant.p, l2l, L.p, L.p, C, K);
-        XRL_HIP(hipGetLastError());
-    }
-    mark(6);
-    {
+    if (P->n_leaves > 0) {
         const size_t sm = (size_t)K * CT * sizeof(T);
         if (CT == 8)
             k_l2p<T, 8><<<dim3((unsigned)P->n_leaves, ntile), 256, sm, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p,
-                                                                            P->box_h.p, mom, L.p, ys.p, C, K);
+                                                                            P->box_h.p, op.mom, L.p, ys.p, C, K);
         else
             k_l2p<T, 16><<<dim3((unsigned)P->n_leaves, ntile), 256, sm, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p,
-                                                                             P->box_h.p, mom, L.p, ys.p, C, K);
+                                                                             P->box_h.p, op.mom, L.p, ys.p, C, K);
         XRL_HIP(hipGetLastError());
     }
     mark(7);
@@ -589,18 +554,19 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
         da = dab.p;
         db = beta ? dab.p + 2 * ncols : nullptr;
     }
+    const unsigned gy = (unsigned)std::min<int64_t>(cdiv(N * ncols, bs), 1 << 20);
     if (dtype == XRL_C64)
-        k_scatter_y<float, T><<<cdiv(N * ncols, bs), bs, 0, s>>>(N, P->perm.p, ys.p, P->area.p, (const float *)x, ldx,
-                                                                 (float *)y, ldy, ncols, da, db);
+        k_scatter_y<float, T><<<gy, bs, 0, s>>>(N, P->perm.p, ys.p, P->area.p, (const float *)x, ldx, (float *)y, ldy,
+                                                ncols, da, db);
     else
-        k_scatter_y<double, T><<<cdiv(N * ncols, bs), bs, 0, s>>>(N, P->perm.p, ys.p, P->area.p, (const double *)x, ldx,
-                                                                  (double *)y, ldy, ncols, da, db);
+        k_scatter_y<double, T><<<gy, bs, 0, s>>>(N, P->perm.p, ys.p, P->area.p, (const double *)x, ldx, (double *)y,
+                                                 ldy, ncols, da, db);
     XRL_HIP(hipGetLastError());
     mark(8);
     if (dab.p) XRL_HIP(hipStreamSynchronize(s));  // keep the epilogue scalars alive until used
     if (prof) {
         XRL_HIP(hipEventSynchronize(P->ev[8]));
-        // phase order of the public API: gather, P2P, P2M, M2M, M2L, L2L, L2P, scatter
+        // public phase order: gather, P2P, P2M, M2M, M2L, L2L, L2P, scatter
         for (int i = 0; i < XRL_N_PHASES; ++i) {
             float ms = 0;
             XRL_HIP(hipEventElapsedTime(&ms, P->ev[i], P->ev[i + 1]));
@@ -631,14 +597,17 @@ extern "C" xrl_status xrl_fmm_matvec(const xrl_plan *P, const void *x, int64_t l
             Pm->events_made = true;
         }
         const double *al = ep ? ep->alpha : nullptr, *be = ep ? ep->beta : nullptr;
-        if (P->precision == XRL_PREC_FP64)
+        if (P->precision == XRL_PREC_FP64) {
+            Ops<double> op{P->near64.p, P->mom64.p, P->op_m2m64f.p, P->op_m2m64k.p, P->op_l2l64f.p, P->op_l2l64k.p,
+                           P->op_m2l64f.p, P->op_m2l64k.p};
             run_matvec<double>(P, x, ldx, n_cols, dtype, y, ldy, al, be, s, Pm->xs64, Pm->ys64, Pm->M64, Pm->L64,
-                               Pm->os_tmp64, P->near64.p, P->mom64.p, P->op_m2m64.p, P->op_l2l64.p, P->op_m2l64k.p,
-                               P->op_m2l64f.p);
-        else
+                               Pm->os_tmp64, op);
+        } else {
+            Ops<float> op{P->near32.p, P->mom32.p, P->op_m2m32f.p, P->op_m2m32k.p, P->op_l2l32f.p, P->op_l2l32k.p,
+                          P->op_m2l32f.p, P->op_m2l32k.p};
             run_matvec<float>(P, x, ldx, n_cols, dtype, y, ldy, al, be, s, Pm->xs32, Pm->ys32, Pm->M32, Pm->L32,
-                              Pm->os_tmp32, P->near32.p, P->mom32.p, P->op_m2m32.p, P->op_l2l32.p, P->op_m2l32k.p,
-                              P->op_m2l32f.p);
+                              Pm->os_tmp32, op);
+        }
     });
 }
 

@@ -316,6 +316,46 @@ __global__ void k_panel_leaf(int64_t nleaf, const int32_t *__restrict__ leaf_box
     for (int32_t k = beg[b] + threadIdx.x; k < end[b]; k += blockDim.x) panel_leaf[k] = (int32_t)li;
 }
 
+// Sort the (target, source, operator) triples of one pass by operator; the
+// input is grouped by target (targets ascending, pairs of a target
+// contiguous).
+static void build_pass(TransPass &T, const std::vector<int32_t> &tgt, const std::vector<int32_t> &src,
+                       const std::vector<int32_t> &code, hipStream_t s)
+{
+    const int64_t n = (int64_t)tgt.size();
+    T.n_pairs = n;
+    std::vector<int32_t> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+    std::vector<int32_t> osrc(n), slot(n), goff, gbeg;
+    for (int64_t j = 0; j < n; ++j) {
+        osrc[j] = src[ord[j]];
+        slot[ord[j]] = (int32_t)j;
+        if (j == 0 || code[ord[j]] != code[ord[j - 1]]) {
+            goff.push_back(code[ord[j]]);
+            gbeg.push_back((int32_t)j);
+        }
+    }
+    gbeg.push_back((int32_t)n);
+    std::vector<int32_t> rt, rp{0};
+    for (int64_t q = 0; q < n; ++q) {
+        if (q == 0 || tgt[q] != tgt[q - 1]) {
+            if (q > 0) rp.push_back((int32_t)q);
+            rt.push_back(tgt[q]);
+        }
+    }
+    if (n > 0) rp.push_back((int32_t)n);
+    T.n_groups = (int64_t)goff.size();
+    T.n_red = (int64_t)rt.size();
+    T.h_gbeg = gbeg;
+    T.src.upload(osrc, s);
+    T.goff.upload(goff, s);
+    T.gbeg.upload(gbeg, s);
+    T.red_tgt.upload(rt, s);
+    T.red_ptr.upload(rp, s);
+    T.red_slot.upload(slot, s);
+}
+
 }  // namespace xrl
 
 using namespace xrl;
@@ -525,29 +565,42 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     P->near_src.upload(src_rows, s);
     P->near_val_off.upload(val_off, s);
     P->leaf_tpad.upload(tpad, s);
-    // ---------------- M2L pairs sorted by offset, per-target reduction lists
-    std::vector<int32_t> ord(nV);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return hcode[a] < hcode[b]; });
-    std::vector<int32_t> os_src(nV), slot(nV), grp_off, gbeg;
-    for (int64_t j = 0; j < nV; ++j) {
-        os_src[j] = hsrc[ord[j]];
-        slot[ord[j]] = (int32_t)j;
-        if (j == 0 || hcode[ord[j]] != hcode[ord[j - 1]]) {
-            grp_off.push_back(hcode[ord[j]]);
-            gbeg.push_back((int32_t)j);
+    // ---------------- translation passes: M2L (all levels), M2M and L2L per level
+    {
+        std::vector<int32_t> tg, sr, cd;
+        for (int64_t b = 0; b < B; ++b)
+            for (int64_t j = voff[b]; j < voff[b + 1]; ++j) {
+                tg.push_back((int32_t)b);
+                sr.push_back(hsrc[j]);
+                cd.push_back(hcode[j]);
+            }
+        build_pass(P->m2l, tg, sr, cd, s);
+        P->m2m.clear();
+        P->l2l.clear();
+        P->m2m.resize(depth + 1);
+        P->l2l.resize(depth + 1);
+        for (int l = 0; l <= depth; ++l) {
+            std::vector<int32_t> t1, s1, c1, t2, s2, c2;
+            for (int64_t b = P->level_off[l]; b < P->level_off[l + 1]; ++b) {
+                for (int i = 0; i < nchild[b]; ++i) {  // M2M: parent b <- child
+                    t1.push_back((int32_t)b);
+                    s1.push_back(child0[b] + i);
+                    c1.push_back(octant[child0[b] + i]);
+                }
+                if (l >= 3) {  // L2L: child b <- parent (locals are zero above level 2)
+                    t2.push_back((int32_t)b);
+                    s2.push_back(parent[b]);
+                    c2.push_back(octant[b]);
+                }
+            }
+            build_pass(P->m2m[l], t1, s1, c1, s);
+            build_pass(P->l2l[l], t2, s2, c2, s);
         }
     }
-    gbeg.push_back((int32_t)nV);
-    std::vector<int32_t> red_tgt, red_ptr{0};
     P->h_m2l_pairs.resize(2 * nV);
     std::vector<double> hrad = P->box_rad.download(s);
     double maxsep = 0;
-    for (int64_t b = 0, q = 0; b < B; ++b) {
-        if (voff[b + 1] > voff[b]) {
-            red_tgt.push_back((int32_t)b);
-            red_ptr.push_back((int32_t)voff[b + 1]);
-        }
+    for (int64_t b = 0, q = 0; b < B; ++b)
         for (int64_t j = voff[b]; j < voff[b + 1]; ++j, ++q) {
             P->h_m2l_pairs[2 * q] = (int32_t)b;
             P->h_m2l_pairs[2 * q + 1] = hsrc[j];
@@ -559,17 +612,16 @@ static void build_plan(xrl_plan *P, hipStream_t s)
             }
             maxsep = std::max(maxsep, (hrad[b] + hrad[sb]) / std::sqrt(d2));
         }
-    }
     P->max_sep_ratio = maxsep;
-    P->n_groups = (int64_t)grp_off.size();
-    P->n_red = (int64_t)red_tgt.size();
-    P->h_os_gbeg = gbeg;
-    P->os_src.upload(os_src, s);
-    P->os_goff.upload(grp_off, s);
-    P->os_gbeg.upload(gbeg, s);
-    P->red_tgt.upload(red_tgt, s);
-    P->red_ptr.upload(red_ptr, s);
-    P->red_slot.upload(slot, s);
+    std::vector<int32_t> grp_off;
+    {
+        std::vector<char> seen(343, 0);
+        for (int64_t j = 0; j < nV; ++j)
+            if (!seen[hcode[j]]) {
+                seen[hcode[j]] = 1;
+                grp_off.push_back(hcode[j]);
+            }
+    }
     // ---------------- operators
     const int p = P->p, K = P->K;
     std::vector<double> m2m(8 * (size_t)K * K), l2l(8 * (size_t)K * K);
@@ -592,24 +644,38 @@ static void build_plan(xrl_plan *P, hipStream_t s)
         for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
         return f;
     };
-    // fragment order for the 16x16x4 MFMA A operand: lane = row % 16 + 16 (k % 4)
+    // fragment order for the 16x16x4 MFMA A operand (lane = row % 16 + 16 (k % 4))
+    // and k-major order for the vector-ALU GEMM, from padded [n_op][KP][KK]
     const int nrt = P->KP / 16, nks = P->KK / 4;
-    std::vector<double> frag(m2l.size(), 0.0);
-    for (int c = 0; c < 343; ++c)
-        for (int rt = 0; rt < nrt; ++rt)
-            for (int ks = 0; ks < nks; ++ks)
-                for (int lane = 0; lane < 64; ++lane)
-                    frag[(((size_t)c * nrt + rt) * nks + ks) * 64 + lane] =
-                        m2l[((size_t)c * P->KP + rt * 16 + (lane & 15)) * P->KK + 4 * ks + (lane >> 4)];
-    P->op_m2l64f.upload(frag, s);
-    P->op_m2l32f.upload(to32(frag), s);
-    std::vector<double> kmaj(m2l.size(), 0.0);
-    for (int c = 0; c < 343; ++c)
-        for (int r = 0; r < P->KP; ++r)
-            for (int k = 0; k < P->KK; ++k)
-                kmaj[((size_t)c * P->KK + k) * P->KP + r] = m2l[((size_t)c * P->KP + r) * P->KK + k];
-    P->op_m2l64k.upload(kmaj, s);
-    P->op_m2l32k.upload(to32(kmaj), s);
+    auto layouts = [&](const std::vector<double> &pad, int nop, DevBuf<double> &f64, DevBuf<float> &f32,
+                       DevBuf<double> &k64, DevBuf<float> &k32) {
+        std::vector<double> frag(pad.size(), 0.0), kmaj(pad.size(), 0.0);
+        for (int c = 0; c < nop; ++c) {
+            for (int rt = 0; rt < nrt; ++rt)
+                for (int ks = 0; ks < nks; ++ks)
+                    for (int lane = 0; lane < 64; ++lane)
+                        frag[(((size_t)c * nrt + rt) * nks + ks) * 64 + lane] =
+                            pad[((size_t)c * P->KP + rt * 16 + (lane & 15)) * P->KK + 4 * ks + (lane >> 4)];
+            for (int r = 0; r < P->KP; ++r)
+                for (int k = 0; k < P->KK; ++k)
+                    kmaj[((size_t)c * P->KK + k) * P->KP + r] = pad[((size_t)c * P->KP + r) * P->KK + k];
+        }
+        f64.upload(frag, s);
+        f32.upload(to32(frag), s);
+        k64.upload(kmaj, s);
+        k32.upload(to32(kmaj), s);
+    };
+    auto padded = [&](const std::vector<double> &dense, int nop) {
+        std::vector<double> out((size_t)nop * P->KP * P->KK, 0.0);
+        for (int c = 0; c < nop; ++c)
+            for (int r = 0; r < K; ++r)
+                for (int k = 0; k < K; ++k)
+                    out[((size_t)c * P->KP + r) * P->KK + k] = dense[((size_t)c * K + r) * K + k];
+        return out;
+    };
+    layouts(m2l, 343, P->op_m2l64f, P->op_m2l32f, P->op_m2l64k, P->op_m2l32k);
+    layouts(padded(m2m, 8), 8, P->op_m2m64f, P->op_m2m32f, P->op_m2m64k, P->op_m2m32k);
+    layouts(padded(l2l, 8), 8, P->op_l2l64f, P->op_l2l32f, P->op_l2l64k, P->op_l2l32k);
     P->op_m2m64.upload(m2m, s);
     P->op_l2l64.upload(l2l, s);
     P->op_m2l64.upload(m2l, s);
