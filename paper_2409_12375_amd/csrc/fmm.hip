@@ -257,17 +257,26 @@ __global__ __launch_bounds__(256) void k_m2l_os_mfma(const int32_t *__restrict__
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int ks = 0; ks < D::NKS; ++ks) a[rb][ks] = (r0 + rb < D::NRT) ? Tf[((r0 + rb) * D::NKS + ks) * 64] : T(0);
-        for (int ct = ct0; ct < ct1; ++ct) {
+        // B fragments of the first column tile; the next tile's loads are
+        // issued before the current tile's MFMAs
+        T b[D::NKS], bn[D::NKS];
+        auto load_b = [&](int ct, T *dst) {
             const int n = ct * 16 + li;
             const int p = n / Cc, c = n - p * Cc;
-            const bool valid = n < ncols;
+            const bool valid = n < ncols && ct < ct1;
             const T *Mp = M + (int64_t)(valid ? src[pb + p] : 0) * D::K * C + c0 + c;
-            T b[D::NKS];
 #pragma unroll
             for (int ks = 0; ks < D::NKS; ++ks) {
                 const int kk = 4 * ks + kq;
-                b[ks] = (valid && kk < D::K) ? Mp[(int64_t)kk * C] : T(0);
+                dst[ks] = (valid && kk < D::K) ? Mp[(int64_t)kk * C] : T(0);
             }
+        };
+        load_b(ct0, b);
+        for (int ct = ct0; ct < ct1; ++ct) {
+            load_b(ct + 1, bn);
+            const int n = ct * 16 + li;
+            const int p = n / Cc, c = n - p * Cc;
+            const bool valid = n < ncols;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
                 if (r0 + rb >= D::NRT) break;
@@ -284,6 +293,8 @@ __global__ __launch_bounds__(256) void k_m2l_os_mfma(const int32_t *__restrict__
                     }
                 }
             }
+#pragma unroll
+            for (int ks = 0; ks < D::NKS; ++ks) b[ks] = bn[ks];
         }
     }
 }
@@ -299,14 +310,15 @@ __global__ __launch_bounds__(256) void k_m2l_os_valu(const int32_t *__restrict__
                                                      T *__restrict__ tmp)
 {
     using D = M2LDims<ORD>;
+    constexpr int NC = 64, TC = 4;
     __shared__ T sA[D::KK * D::KP];
-    __shared__ T sB[D::KK * 64];
+    __shared__ T sB[D::KK * NC];
     const int g = items[3 * blockIdx.x], n0 = items[3 * blockIdx.x + 1], n1 = items[3 * blockIdx.x + 2];
     const int pb = gbeg[g];
     const T *Ao = op_k + (int64_t)goff[g] * D::KK * D::KP;
     for (int i = threadIdx.x; i < D::KK * D::KP; i += 256) sA[i] = Ao[i];
-    for (int i = threadIdx.x; i < D::KK * 64; i += 256) {
-        const int k = i >> 6, j = i & 63, n = n0 + j;
+    for (int i = threadIdx.x; i < D::KK * NC; i += 256) {
+        const int k = i / NC, j = i - k * NC, n = n0 + j;
         T v = T(0);
         if (n < n1 && k < D::K) {
             const int p = n / Cc, c = n - p * Cc;
@@ -316,25 +328,25 @@ __global__ __launch_bounds__(256) void k_m2l_os_valu(const int32_t *__restrict__
     }
     __syncthreads();
     const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
-    T acc[D::NRT][4];
+    T acc[D::NRT][TC];
 #pragma unroll
     for (int i = 0; i < D::NRT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+        for (int j = 0; j < TC; ++j) acc[i][j] = 0;
     for (int k = 0; k < D::K; ++k) {
-        T a[D::NRT], b[4];
+        T a[D::NRT], b[TC];
 #pragma unroll
         for (int i = 0; i < D::NRT; ++i) a[i] = sA[k * D::KP + tr * D::NRT + i];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = sB[k * 64 + tc * 4 + j];
+        for (int j = 0; j < TC; ++j) b[j] = sB[k * NC + tc * TC + j];
 #pragma unroll
         for (int i = 0; i < D::NRT; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+            for (int j = 0; j < TC; ++j) acc[i][j] += a[i] * b[j];
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int n = n0 + tc * 4 + j;
+    for (int j = 0; j < TC; ++j) {
+        const int n = n0 + tc * TC + j;
         if (n >= n1) continue;
         const int p = n / Cc, c = n - p * Cc;
         T *out = tmp + ((int64_t)(pb + p) * Cc + c) * D::KP + tr * D::NRT;
@@ -352,12 +364,26 @@ __global__ __launch_bounds__(256) void k_pass_reduce(const int32_t *__restrict__
                                                      int C, int c0, int Cc, int accumulate, T *__restrict__ out)
 {
     using D = M2LDims<ORD>;
+    __shared__ int64_t sbase[512];
     const int ti = blockIdx.x;
-    const int32_t t = red_tgt[ti], j0 = red_ptr[ti], j1 = red_ptr[ti + 1];
+    const int32_t t = red_tgt[ti], j0 = red_ptr[ti], np = red_ptr[ti + 1] - j0;
+    for (int j = threadIdx.x; j < np && j < 512; j += 256) sbase[j] = (int64_t)red_slot[j0 + j] * Cc * D::KP;
+    __syncthreads();
     for (int idx = threadIdx.x; idx < Cc * D::K; idx += 256) {
         const int c = idx / D::K, row = idx - c * D::K;
-        T s = 0;
-        for (int j = j0; j < j1; ++j) s += tmp[((int64_t)red_slot[j] * Cc + c) * D::KP + row];
+        const T *tp = tmp + (int64_t)c * D::KP + row;
+        T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        int j = 0;
+        const int nl = np < 512 ? np : 512;
+        for (; j + 4 <= nl; j += 4) {
+            s0 += tp[sbase[j]];
+            s1 += tp[sbase[j + 1]];
+            s2 += tp[sbase[j + 2]];
+            s3 += tp[sbase[j + 3]];
+        }
+        for (; j < nl; ++j) s0 += tp[sbase[j]];
+        for (; j < np; ++j) s0 += tp[(int64_t)red_slot[j0 + j] * Cc * D::KP];
+        const T s = (s0 + s1) + (s2 + s3);
         T *o = out + ((int64_t)t * D::K + row) * C + c0 + c;
         *o = accumulate ? *o + s : s;
     }
@@ -412,11 +438,12 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
                 items, n_items, TP.gbeg.p, TP.goff.p, TP.src.p, op_frag, in, C, c0, cc, tmp.p);
         } else {
             // the LDS-staged operator of the vector-ALU kernel fits up to order 8
-            if constexpr (ORD <= 8)
+            if constexpr (ORD <= 8 && (sizeof(T) == 4 || ORD <= 6))
                 k_m2l_os_valu<T, ORD><<<(unsigned)n_items, 256, 0, s>>>(items, TP.gbeg.p, TP.goff.p, TP.src.p, op_k,
                                                                         in, C, c0, cc, tmp.p);
             else
-                fail(XRL_E_UNSUPPORTED, "xrl_fmm_matvec: the vector-ALU translations support order <= 8");
+                fail(XRL_E_UNSUPPORTED, "xrl_fmm_matvec: the vector-ALU translations support order <= 8 "
+                                        "(<= 6 in FP64)");
         }
         XRL_HIP(hipGetLastError());
         k_pass_reduce<T, ORD><<<(unsigned)TP.n_red, 256, 0, s>>>(TP.red_tgt.p, TP.red_ptr.p, TP.red_slot.p, tmp.p, C,

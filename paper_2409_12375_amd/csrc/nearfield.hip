@@ -180,28 +180,36 @@ __device__ T near_pair(const T *tv, const T *sv, int lev, const NFRules &R)
     return acc;
 }
 
-template <typename T>
-__device__ T regular_pair(const T *tv, const T *sv, int n, const double *gx, const double *gw)
+// Product of two NQ x NQ conical rules (compile-time size: the source points
+// stay in registers).
+template <typename T, int NQ>
+__device__ T regular_pair(const T *tv, const T *sv, const double *gx, const double *gw)
 {
     const T At = tri_area2(tv), As = tri_area2(sv);
-    T px[25][3], pw[25];
-    int m = 0;
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j, ++m) {
+    T py[NQ * NQ][3], pw[NQ * NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
             const T s = (T)gx[i], t = (T)gx[j];
-            for (int d = 0; d < 3; ++d) px[m][d] = sv[d] + s * (sv[3 + d] - sv[d]) + s * t * (sv[6 + d] - sv[3 + d]);
-            pw[m] = (T)gw[i] * (T)gw[j] * s;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) py[i * NQ + j][d] = sv[d] + s * (sv[3 + d] - sv[d]) + s * t * (sv[6 + d] - sv[3 + d]);
+            pw[i * NQ + j] = (T)gw[i] * (T)gw[j] * s;
         }
     T acc = 0;
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
             const T s = (T)gx[i], t = (T)gx[j];
             T x[3];
+#pragma unroll
             for (int d = 0; d < 3; ++d) x[d] = tv[d] + s * (tv[3 + d] - tv[d]) + s * t * (tv[6 + d] - tv[3 + d]);
             T inner = 0;
-            for (int q = 0; q < m; ++q) {
-                const T dx = x[0] - px[q][0], dy = x[1] - px[q][1], dz = x[2] - px[q][2];
-                inner += pw[q] / sqrt(dx * dx + dy * dy + dz * dz);
+#pragma unroll
+            for (int q = 0; q < NQ * NQ; ++q) {
+                const T dx = x[0] - py[q][0], dy = x[1] - py[q][1], dz = x[2] - py[q][2];
+                inner += pw[q] * rsqrt(dx * dx + dy * dy + dz * dz);
             }
             acc += (T)gw[i] * (T)gw[j] * s * inner;
         }
@@ -220,6 +228,28 @@ struct NFArgs {
     unsigned long long *work_n;    // [0] touching count, [1] near-singular count (separate halves)
     int64_t work_cap;
 };
+
+// Queue slot for a special entry: touching pairs fill the queue from the
+// front (which = 0), near-singular pairs from the back (which = 1).  One
+// atomic per wave and queue (lanes counted with a ballot), not one per entry.
+__device__ inline int64_t queue_slot(const NFArgs &a, int which)
+{
+    int64_t pos = -1;
+    for (int q = 0; q < 2; ++q) {
+        const unsigned long long mask = __ballot(which == q);
+        if (mask == 0) continue;
+        const int lane = __lane_id();
+        const int leader = __ffsll((long long)mask) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(&a.work_n[q], (unsigned long long)__popcll(mask));
+        base = __shfl(base, leader);
+        if (which == q) {
+            const unsigned long long rank = __popcll(mask & ((1ull << lane) - 1ull));
+            pos = q == 0 ? (int64_t)(base + rank) : a.work_cap - 1 - (int64_t)(base + rank);
+        }
+    }
+    return pos;
+}
 
 __device__ inline int shared_vertex(const int32_t *ik, const int32_t *il)
 {
@@ -261,8 +291,7 @@ __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restr
         const double rr = sqrt(dx * dx + dy * dy + dz * dz) / fmax(a.diam[k], a.diam[l]);
         if (sv >= 0 || rr < a.r_near) {
             const int which = sv >= 0 ? 0 : 1;
-            const unsigned long long slot = atomicAdd(&a.work_n[which], 1ull);
-            const int64_t pos = which == 0 ? (int64_t)slot : a.work_cap - 1 - (int64_t)slot;
+            const int64_t pos = queue_slot(a, which);
             if (pos >= 0 && pos < a.work_cap) {
                 a.work[pos] = vo + e;
                 a.work_meta[2 * pos] = k;
@@ -278,8 +307,8 @@ __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restr
                 tv[i] = a.pv[9 * (int64_t)k + i];
                 svv[i] = a.pv[9 * (int64_t)l + i];
             }
-            val[vo + e] = (V)(rr < a.r_mid ? regular_pair<double>(tv, svv, R.n_hi, R.rx4, R.rw4)
-                                           : regular_pair<double>(tv, svv, R.n_lo, R.rx3, R.rw3));
+            val[vo + e] = (V)(rr < a.r_mid ? regular_pair<double, 5>(tv, svv, R.rx4, R.rw4)
+                                           : regular_pair<double, 4>(tv, svv, R.rx3, R.rw3));
         } else {
             // FP32 arithmetic relative to the target centroid
             float tv[9], svv[9];
@@ -287,12 +316,21 @@ __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restr
                 tv[i] = (float)(a.pv[9 * (int64_t)k + i] - a.cen[3 * k + i % 3]);
                 svv[i] = (float)(a.pv[9 * (int64_t)l + i] - a.cen[3 * k + i % 3]);
             }
-            val[vo + e] = (V)(rr < a.r_mid ? regular_pair<float>(tv, svv, R.n_hi, R.rx4, R.rw4)
-                                           : regular_pair<float>(tv, svv, R.n_lo, R.rx3, R.rw3));
+            val[vo + e] = (V)(rr < a.r_mid ? regular_pair<float, 4>(tv, svv, R.rx4, R.rw4)
+                                           : regular_pair<float, 3>(tv, svv, R.rx3, R.rw3));
         }
     }
-    if (c_self) atomicAdd(&a.counters[0], c_self);
-    if (c_reg) atomicAdd(&a.counters[3], c_reg);
+    // class counters: LDS first, one global atomic per workgroup
+    __shared__ unsigned long long s_cnt[2];
+    if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0;
+    __syncthreads();
+    if (c_self) atomicAdd(&s_cnt[0], c_self);
+    if (c_reg) atomicAdd(&s_cnt[1], c_reg);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&a.counters[0], s_cnt[0]);
+        atomicAdd(&a.counters[3], s_cnt[1]);
+    }
 }
 
 // Pass 2: queued touching (which = 0, from the front of the queue) or
