@@ -160,9 +160,12 @@ xrl_status xrl_plan_get_info(const xrl_plan *plan, xrl_plan_info *info);
 /* Near field                                                          */
 /* ------------------------------------------------------------------ */
 /* Optional learned surrogate for near-singular pairs: a 18 -> H -> H -> 2
- * multilayer perceptron with SiLU activations whose first output predicts
- * P_kl / P_kl^(3x3 Gauss) - 1 and whose second predicts log10 of the absolute
- * error of the first.  Weights are FP32, row-major [out][in], on the host. */
+ * multilayer perceptron with SiLU activations (H = 64 or 128).  Its first
+ * output divided by rho^4 (rho: distance of the target centroid from the
+ * source centroid in source diameters, from the features) predicts
+ * P_kl / P_kl^(3x3 Gauss) - 1; its second output predicts log10 of the
+ * absolute error of that prediction.  Weights are FP32, row-major [out][in],
+ * on the host. */
 typedef struct {
     int32_t hidden;          /* H (128) */
     const float *w1, *b1;    /* [H][18], [H] */
@@ -198,6 +201,47 @@ typedef struct {
  * Errors: XRL_E_INVALID_ARG, XRL_E_OOM, XRL_E_HIP. */
 xrl_status xrl_nearfield_assemble(xrl_plan *plan, const xrl_nf_opts *opts, void *stream,
                                   xrl_nf_stats *stats);
+
+/* Self-test of the 16x16x16 bf16 MFMA layout used by the surrogate's
+ * inference: D[16][16] = bf16(A[16][16]) * bf16(B[16][16]), float host arrays. */
+xrl_status xrl_selftest_mfma_bf16(const float *A, const float *B, float *D);
+
+/* Surrogate support (the learned near-singular model above).
+ * Features and cheap values of explicit triangle pairs, on the device:
+ *   tri_k, tri_l : [n][9] float64 (target, source vertices)
+ *   feat         : [n][18] float32 (canonical frame of the source, see the
+ *                  surrogate source file), cheap: [n] float64 3x3 Gauss value
+ *                  (may be NULL). */
+xrl_status xrl_surrogate_features(const double *tri_k, const double *tri_l, int64_t n, float *feat,
+                                  double *cheap, void *stream);
+
+/* Training of the surrogate on the device with the library's own FP32
+ * forward, backward and Adam kernels.  Weights w (device, packed
+ * W1 b1 W2 b2 W3 b3, H*H + 22*H + 2 floats) hold the initial values on entry
+ * and the trained values on exit.  Loss: mean (y0 - t)^2 +
+ * calib_weight * mean (y1 - (log10(target_scale |y0 - t| / rho^4) - log_mu) / log_sigma)^2,
+ * the second target taken as a constant (no gradient through y0).
+ * X: [n][18] device features, t: [n] device targets.  loss_hist: host
+ * [epochs] (mean first loss term over each epoch) or NULL. */
+typedef struct {
+    int32_t hidden, batch, epochs;
+    float lr, lr_decay, beta1, beta2, eps;
+    float calib_weight, log_mu, log_sigma, target_scale;
+    uint64_t seed;
+} xrl_mlp_train_opts;
+xrl_status xrl_mlp_train(const float *X, const float *t, int64_t n, const xrl_mlp_train_opts *opts,
+                         float *w, float *loss_hist, void *stream);
+
+/* Loss (host [2]: the two terms) and gradient (device, packed like w) of one
+ * batch; loss_args (host [4]) = calib_weight, log_mu, log_sigma, target_scale. */
+xrl_status xrl_mlp_loss_grad(const float *w, int32_t hidden, const float *X, const float *t, int64_t n,
+                             const float *loss_args, float *loss, float *grad, void *stream);
+
+/* Forward pass, out: [n][2] device, first output already divided by rho^4.
+ * bf16 = 0: FP32 kernels (training path); bf16 = 1: the BF16 MFMA inference
+ * kernel used by the assembly. */
+xrl_status xrl_mlp_forward(const float *w, int32_t hidden, const float *X, int64_t n, int32_t bf16,
+                           float *out, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Operator application                                                */

@@ -62,6 +62,7 @@ def lib():
                                       ctypes.c_int64, _d, ctypes.c_int]
         L.orc_matvec_rows.restype = ctypes.c_int
         L.orc_dense.argtypes = [_d, _i32, _i64, ctypes.c_int64, _i64, ctypes.c_int64, _d, ctypes.c_int]
+        L.orc_pairs.argtypes = [_d, _i32, _i64, _i64, ctypes.c_int64, _d, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -141,6 +142,18 @@ def dense(V, T, rows=None, cols=None, nthreads=0):
     lib().orc_dense(_pd(V), T.ctypes.data_as(_i32), rows.ctypes.data_as(_i64), len(rows),
                     cols.ctypes.data_as(_i64), len(cols), _pd(P), nthreads)
     return P
+
+
+def pairs(V, T, ks, ls, nthreads=0):
+    """P_kl for explicit index pairs (k, l)."""
+    V = _f64(V)
+    T = np.ascontiguousarray(T, dtype=np.int32)
+    ks = np.ascontiguousarray(ks, dtype=np.int64)
+    ls = np.ascontiguousarray(ls, dtype=np.int64)
+    out = np.zeros(len(ks))
+    lib().orc_pairs(_pd(V), T.ctypes.data_as(_i32), ks.ctypes.data_as(_i64), ls.ctypes.data_as(_i64), len(ks),
+                    _pd(out), nthreads)
+    return out
 
 
 def matvec(V, T, x, rows=None, nthreads=0):

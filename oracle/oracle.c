@@ -456,6 +456,18 @@ int orc_matvec_rows(const double *V, const int32_t *T, int64_t N,
     return used;
 }
 
+/* P_kl for an explicit list of (k, l) index pairs (training labels). */
+void orc_pairs(const double *V, const int32_t *T, const int64_t *ks, const int64_t *ls, int64_t n, double *out,
+               int nthreads)
+{
+    orc_init();
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_entry_idx(V, T, ks[i], ls[i]);
+}
+
 /* Dense operator block P[rows][cols] (tests on small meshes). */
 void orc_dense(const double *V, const int32_t *T, const int64_t *rows, int64_t nr,
                const int64_t *cols, int64_t nc, double *P, int nthreads)

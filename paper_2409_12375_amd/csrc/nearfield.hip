@@ -19,17 +19,11 @@
 #include <cmath>
 #include <cstring>
 
-#include "common.h"
+#include "nfcommon.h"
 
 namespace xrl {
 
-struct NFRules {
-    double gx[40], gw[40];  // Gauss-Legendre on [0,1], n_touch points
-    double nx[8], nw[8];    // near-singular conical rule, n = 6
-    double rx4[8], rw4[8];  // regular, n_hi points
-    double rx3[8], rw3[8];  // regular, n_lo points
-    int n_touch, n_ns, n_hi, n_lo;
-};
+
 
 template <typename T>
 __device__ inline T dot3(const T *a, const T *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -216,18 +210,7 @@ __device__ T regular_pair(const T *tv, const T *sv, const double *gx, const doub
     return acc * At * As;
 }
 
-struct NFArgs {
-    const int32_t *leaf_box, *box_beg, *box_end, *near_rows, *near_src, *leaf_tpad, *pvid;
-    const int64_t *val_off;
-    const double *pv, *cen, *diam;
-    double r_near, r_mid;
-    int64_t n_leaves;
-    unsigned long long *counters;  // [0] self [1] touch [2] near-singular [3] regular
-    int64_t *work;                 // special entries: value index
-    int32_t *work_meta;            // packed (k, l)
-    unsigned long long *work_n;    // [0] touching count, [1] near-singular count (separate halves)
-    int64_t work_cap;
-};
+
 
 // Queue slot for a special entry: touching pairs fill the queue from the
 // front (which = 0), near-singular pairs from the back (which = 1).  One
@@ -337,11 +320,12 @@ __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restr
 // near-singular (which = 1, from the back) entries, one per thread.
 template <typename V, typename C>
 __global__ __launch_bounds__(64) void k_nf_special(NFArgs a, NFRules R, int which, int64_t count,
-                                                   V *__restrict__ val)
+                                                   V *__restrict__ val, const int64_t *__restrict__ list,
+                                                   double *__restrict__ alt_out)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const int64_t pos = which == 0 ? i : a.work_cap - 1 - i;
+    const int64_t pos = list ? list[i] : (which == 0 ? i : a.work_cap - 1 - i);
     const int32_t k = a.work_meta[2 * pos], l = a.work_meta[2 * pos + 1];
     // coordinates relative to the target centroid
     C tv[9], sv[9];
@@ -350,7 +334,11 @@ __global__ __launch_bounds__(64) void k_nf_special(NFArgs a, NFRules R, int whic
         for (int j = 0; j < 3; ++j)
             for (int d = 0; d < 3; ++d) tv[3 * j + d] = (C)(a.pv[9 * (int64_t)k + 3 * ((s0 + j) % 3) + d] - a.cen[3 * k + d]);
         for (int q = 0; q < 9; ++q) sv[q] = (C)(a.pv[9 * (int64_t)l + q] - a.cen[3 * k + q % 3]);
-        val[a.work[pos]] = (V)touching_pair<C>(tv, sv, R);
+        const C v = touching_pair<C>(tv, sv, R);
+        if (alt_out)
+            alt_out[i] = (double)v;
+        else
+            val[a.work[pos]] = (V)v;
     } else {
         for (int q = 0; q < 9; ++q) {
             tv[q] = (C)(a.pv[9 * (int64_t)k + q] - a.cen[3 * k + q % 3]);
@@ -360,11 +348,50 @@ __global__ __launch_bounds__(64) void k_nf_special(NFArgs a, NFRules R, int whic
                      dz = a.cen[3 * k + 2] - a.cen[3 * l + 2];
         const double rr = sqrt(dx * dx + dy * dy + dz * dz) / fmax(a.diam[k], a.diam[l]);
         const int lev = rr < 0.75 ? 2 : (rr < 1.5 ? 1 : 0);
-        val[a.work[pos]] = (V)near_pair<C>(tv, sv, lev, R);
+        const C v = near_pair<C>(tv, sv, lev, R);
+        if (alt_out)
+            alt_out[i] = (double)v;
+        else
+            val[a.work[pos]] = (V)v;
     }
 }
 
-void gauss_legendre01(int n, double *x, double *w);
+// Surrogate decision for queued near-singular entry i (queue position
+// cap - 1 - i): accept P = cheap (1 + out0) when every feature lies in the
+// training range and out1 <= bound, else queue the entry for quadrature.
+// Every audit_every-th accepted entry is also queued for an audit.
+template <typename V>
+__global__ void k_ns_accept(NFArgs a, int64_t n, const float *__restrict__ feat, const double *__restrict__ cheap,
+                            const float *__restrict__ out, const float *__restrict__ lo, const float *__restrict__ hi,
+                            float bound, int audit_every, V *__restrict__ val, int64_t *__restrict__ fb,
+                            unsigned long long *__restrict__ fbn, int64_t *__restrict__ aud,
+                            double *__restrict__ aud_val, unsigned long long *__restrict__ audn)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t pos = a.work_cap - 1 - i;
+    bool ok = out[2 * i + 1] <= bound && isfinite(out[2 * i]);
+    for (int q = 0; q < 18 && ok; ++q) ok = feat[18 * i + q] >= lo[q] && feat[18 * i + q] <= hi[q];
+    if (ok) {
+        const double v = cheap[i] * (1.0 + (double)out[2 * i]);
+        val[a.work[pos]] = (V)v;
+        if (audit_every > 0 && i % audit_every == 0) {
+            const unsigned long long j = atomicAdd(audn, 1ull);
+            aud[j] = pos;
+            aud_val[j] = v;
+        }
+    } else {
+        const unsigned long long j = atomicAdd(fbn, 1ull);
+        fb[j] = pos;
+    }
+}
+
+__global__ void k_audit_err(const double *__restrict__ ref, const double *__restrict__ got, int64_t n,
+                            double *__restrict__ rel)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) rel[i] = fabs(got[i] - ref[i]) / fabs(ref[i]);
+}
 
 }  // namespace xrl
 
@@ -380,7 +407,9 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
         if (opts) o = *opts;
         XRL_CHECK(o.r_near > 0 && o.r_mid >= o.r_near, XRL_E_INVALID_ARG,
                   "xrl_nearfield_assemble: need 0 < r_near <= r_mid");
-        XRL_CHECK(o.surrogate == nullptr, XRL_E_UNSUPPORTED, "xrl_nearfield_assemble: surrogate not available");
+        if (o.surrogate)
+            XRL_CHECK(o.surrogate->hidden == 64 || o.surrogate->hidden == 128, XRL_E_UNSUPPORTED,
+                      "xrl_nearfield_assemble: surrogate hidden width must be 64 or 128");
         hipEvent_t e0, e1;
         XRL_HIP(hipEventCreate(&e0));
         XRL_HIP(hipEventCreate(&e1));
@@ -423,16 +452,61 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
         XRL_CHECK((int64_t)(hw[0] + hw[1]) <= cap, XRL_E_OOM,
                   "xrl_nearfield_assemble: special-pair queue overflow (%llu + %llu > %lld)",
                   (unsigned long long)hw[0], (unsigned long long)hw[1], (long long)cap);
-        for (int which = 0; which < 2; ++which) {
-            const int64_t n = (int64_t)hw[which];
-            if (n == 0) continue;
+        auto special = [&](int which, int64_t count, const int64_t *list, double *alt) {
+            if (count == 0) return;
             if (P->precision == XRL_PREC_FP64)
-                k_nf_special<double, double><<<cdiv(n, 64), 64, 0, s>>>(a, R, which, n, P->near64.p);
+                k_nf_special<double, double><<<cdiv(count, 64), 64, 0, s>>>(a, R, which, count, P->near64.p, list, alt);
             else if (P->precision == XRL_PREC_MIXED)
-                k_nf_special<float, double><<<cdiv(n, 64), 64, 0, s>>>(a, R, which, n, P->near32.p);
+                k_nf_special<float, double><<<cdiv(count, 64), 64, 0, s>>>(a, R, which, count, P->near32.p, list, alt);
             else
-                k_nf_special<float, float><<<cdiv(n, 64), 64, 0, s>>>(a, R, which, n, P->near32.p);
+                k_nf_special<float, float><<<cdiv(count, 64), 64, 0, s>>>(a, R, which, count, P->near32.p, list, alt);
             XRL_HIP(hipGetLastError());
+        };
+        special(0, (int64_t)hw[0], nullptr, nullptr);
+        int64_t n_acc = 0, n_fb = (int64_t)hw[1];
+        double aud_max = 0, aud_rms = 0;
+        if (o.surrogate && hw[1] > 0) {
+            const int64_t nns = (int64_t)hw[1];
+            MlpDevice mlp;
+            mlp_prepare_host(mlp, o.surrogate, s);
+            DevBuf<float> feat(18 * nns), out(2 * nns), lo, hi;
+            DevBuf<double> cheap(nns), aud_val(nns), aud_ref(nns), rel(nns);
+            DevBuf<int64_t> fb(nns), aud(nns);
+            DevBuf<unsigned long long> fbn(2);
+            lo.upload(o.surrogate->feat_lo, 18, s);
+            hi.upload(o.surrogate->feat_hi, 18, s);
+            XRL_HIP(hipMemsetAsync(fbn.p, 0, fbn.bytes(), s));
+            ns_features(a, nns, feat.p, cheap.p, s);
+            mlp_infer(mlp, feat.p, nns, out.p, s);
+            if (fp64)
+                k_ns_accept<double><<<cdiv(nns, 256), 256, 0, s>>>(a, nns, feat.p, cheap.p, out.p, lo.p, hi.p,
+                                                                  o.surrogate->log10_err_bound, o.audit_every,
+                                                                  P->near64.p, fb.p, fbn.p, aud.p, aud_val.p,
+                                                                  fbn.p + 1);
+            else
+                k_ns_accept<float><<<cdiv(nns, 256), 256, 0, s>>>(a, nns, feat.p, cheap.p, out.p, lo.p, hi.p,
+                                                                 o.surrogate->log10_err_bound, o.audit_every,
+                                                                 P->near32.p, fb.p, fbn.p, aud.p, aud_val.p,
+                                                                 fbn.p + 1);
+            XRL_HIP(hipGetLastError());
+            auto hn = fbn.download(s);
+            n_fb = (int64_t)hn[0];
+            n_acc = nns - n_fb;
+            special(1, n_fb, fb.p, nullptr);
+            const int64_t na = (int64_t)hn[1];
+            if (na > 0) {
+                special(1, na, aud.p, aud_ref.p);
+                k_audit_err<<<cdiv(na, 256), 256, 0, s>>>(aud_ref.p, aud_val.p, na, rel.p);
+                auto hr = rel.download(s, na);
+                double ss = 0;
+                for (double r : hr) {
+                    aud_max = std::max(aud_max, r);
+                    ss += r * r;
+                }
+                aud_rms = std::sqrt(ss / na);
+            }
+        } else {
+            special(1, (int64_t)hw[1], nullptr, nullptr);
         }
         XRL_HIP(hipEventRecord(e1, s));
         XRL_HIP(hipEventSynchronize(e1));
@@ -449,6 +523,10 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
             stats->n_touching = (int64_t)hw[0];
             stats->n_near_singular = (int64_t)hw[1];
             stats->n_regular = (int64_t)hc[3];
+            stats->n_mlp_accepted = n_acc;
+            stats->n_mlp_fallback = o.surrogate ? n_fb : 0;
+            stats->audit_max_rel_err = aud_max;
+            stats->audit_rms_rel_err = aud_rms;
             stats->ms = ms;
         }
     });

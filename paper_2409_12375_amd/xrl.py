@@ -70,6 +70,13 @@ class Epilogue(ctypes.Structure):
     _fields_ = [("alpha", _vp), ("beta", _vp)]
 
 
+class MlpTrainOpts(ctypes.Structure):
+    _fields_ = [("hidden", _i32), ("batch", _i32), ("epochs", _i32), ("lr", ctypes.c_float),
+                ("lr_decay", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("calib_weight", ctypes.c_float), ("log_mu", ctypes.c_float),
+                ("log_sigma", ctypes.c_float), ("target_scale", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
 class GmresStats(ctypes.Structure):
     _fields_ = [("iterations", _i32), ("restarts", _i32), ("converged", _i32),
                 ("max_rel_residual", ctypes.c_double)]
@@ -98,6 +105,12 @@ def lib():
         L.xrl_plan_set_profiling.argtypes = [_vp, _i32]
         L.xrl_plan_get_phase_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
         L.xrl_plan_export.argtypes = [_vp, _i32, _vp, ctypes.POINTER(_i64)]
+        L.xrl_surrogate_features.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
+        L.xrl_mlp_train.argtypes = [_vp, _vp, _i64, ctypes.POINTER(MlpTrainOpts), _vp, _vp, _vp]
+        L.xrl_mlp_loss_grad.argtypes = [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _vp]
+        L.xrl_mlp_forward.argtypes = [_vp, _i32, _vp, _i64, _i32, _vp, _vp]
+        L.xrl_selftest_mfma.argtypes = [_i32, _vp, _vp, _vp]
+        L.xrl_selftest_mfma_bf16.argtypes = [_vp, _vp, _vp]
         if hasattr(L, "xrl_gmres_solve"):
             L.xrl_gmres_solve.argtypes = [_vp, ctypes.POINTER(Epilogue), _vp, _vp, _i32, _i32, ctypes.c_double, _i32,
                                           _vp, ctypes.POINTER(GmresStats)]
@@ -264,3 +277,82 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Surrogate of near-singular pairs
+# ---------------------------------------------------------------------------
+def mlp_size(H):
+    return H * H + 22 * H + 2
+
+
+def surrogate_features(tri_k, tri_l, stream=None):
+    """Features [n][18] and cheap 3x3 values [n] of explicit triangle pairs
+    (CUDA float64 tensors [n][9]), computed by the library."""
+    import torch
+    n = tri_k.shape[0]
+    feat = torch.empty((n, 18), dtype=torch.float32, device=tri_k.device)
+    cheap = torch.empty(n, dtype=torch.float64, device=tri_k.device)
+    _check(lib().xrl_surrogate_features(_vp(tri_k.data_ptr()), _vp(tri_l.data_ptr()), n, _vp(feat.data_ptr()),
+                                        _vp(cheap.data_ptr()), _stream(stream)))
+    return feat, cheap
+
+
+def mlp_loss_grad(w, H, X, t, lam, mu, sig, scale, stream=None):
+    import torch
+    g = torch.empty_like(w)
+    la = np.array([lam, mu, sig, scale], dtype=np.float32)
+    loss = np.zeros(2, dtype=np.float32)
+    _check(lib().xrl_mlp_loss_grad(_vp(w.data_ptr()), H, _vp(X.data_ptr()), _vp(t.data_ptr()), X.shape[0],
+                                   _vp(la.ctypes.data), _vp(loss.ctypes.data), _vp(g.data_ptr()), _stream(stream)))
+    return loss, g
+
+
+def mlp_forward(w, H, X, bf16=False, stream=None):
+    import torch
+    out = torch.empty((X.shape[0], 2), dtype=torch.float32, device=X.device)
+    _check(lib().xrl_mlp_forward(_vp(w.data_ptr()), H, _vp(X.data_ptr()), X.shape[0], 1 if bf16 else 0,
+                                 _vp(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def mlp_train(w, X, t, hidden=128, batch=4096, epochs=10, lr=2e-3, lr_decay=0.85, calib_weight=0.2, log_mu=-5.0,
+              log_sigma=2.0, target_scale=1.0, seed=12375, stream=None):
+    """Train in place on the device; returns the per-epoch loss history."""
+    o = MlpTrainOpts(hidden, batch, epochs, lr, lr_decay, 0.9, 0.999, 1e-8, calib_weight, log_mu, log_sigma,
+                     target_scale, seed)
+    hist = np.zeros(epochs, dtype=np.float32)
+    _check(lib().xrl_mlp_train(_vp(X.data_ptr()), _vp(t.data_ptr()), X.shape[0], ctypes.byref(o), _vp(w.data_ptr()),
+                               _vp(hist.ctypes.data), _stream(stream)))
+    return hist
+
+
+class Surrogate:
+    """Trained weights (packed FP32, output scaling folded in), feature range
+    and the log10 error bound used for the fall-back decision."""
+
+    def __init__(self, w, hidden, feat_lo, feat_hi, bound):
+        self.w = np.ascontiguousarray(w, dtype=np.float32)
+        self.hidden = int(hidden)
+        self.feat_lo = np.ascontiguousarray(feat_lo, dtype=np.float32)
+        self.feat_hi = np.ascontiguousarray(feat_hi, dtype=np.float32)
+        self.bound = float(bound)
+
+    @classmethod
+    def load(cls, path):
+        d = np.load(path, allow_pickle=False)
+        return cls(d["w"], int(d["hidden"]), d["feat_lo"], d["feat_hi"], float(d["bound"]))
+
+    def save(self, path, **extra):
+        np.savez(path, w=self.w, hidden=self.hidden, feat_lo=self.feat_lo, feat_hi=self.feat_hi, bound=self.bound,
+                 **extra)
+
+    def as_struct(self):
+        H = self.hidden
+        o = 0
+        ptrs = []
+        for size in (18 * H, H, H * H, H, 2 * H, 2):
+            ptrs.append(self.w.ctypes.data + 4 * o)
+            o += size
+        s = Mlp(H, *ptrs, self.feat_lo.ctypes.data, self.feat_hi.ctypes.data, self.bound)
+        return (s, self)  # keep the arrays alive with the struct
