@@ -255,3 +255,111 @@ def coils(target_n=200_000, turns=5, width=0.1, thick=0.035, spacing=0.1, gap=0.
     T1 = swept_trace(poly, width, thick, 0.0, nw, nt, ds, W)
     T2 = swept_trace(poly, width, thick, thick + gap, nw, nt, ds, W)
     return W.vertices(), np.concatenate([T1, T2]).astype(np.int32)
+
+
+# --------------------------------------------------------------------------
+# plane with holes, vias and solder balls (BGA-like package)
+# --------------------------------------------------------------------------
+def _square_ring_cell(cx, cy, half, rh, n_theta, nr, z, welder, flip):
+    """Top or bottom face of one square cell of side 2*half with a centred hole
+    of radius rh: n_theta points on the circle, the same angles projected onto
+    the square, nr quad layers in between (split in two)."""
+    th = 2 * np.pi * np.arange(n_theta) / n_theta
+    c, s = np.cos(th), np.sin(th)
+    m = np.maximum(np.abs(c), np.abs(s))
+    circ = np.stack([cx + rh * c, cy + rh * s], 1)
+    sq = np.stack([cx + half * c / m, cy + half * s / m], 1)
+    idx = np.empty((nr + 1, n_theta + 1), dtype=np.int64)
+    for k in range(nr + 1):
+        f = k / nr
+        P = (1 - f) * circ + f * sq
+        ids = welder.add_many(np.column_stack([P, np.full(n_theta, z)]))
+        idx[k, :n_theta] = ids
+        idx[k, n_theta] = ids[0]
+    return _grid_tris(idx, flip=flip)
+
+
+def _cylinder(cx, cy, r, z0, z1, nfac, nz, welder, caps, flip=False):
+    th = 2 * np.pi * np.arange(nfac) / nfac
+    ring = np.stack([cx + r * np.cos(th), cy + r * np.sin(th)], 1)
+    idx = np.empty((nz + 1, nfac + 1), dtype=np.int64)
+    for k in range(nz + 1):
+        z = z0 + (z1 - z0) * k / nz
+        ids = welder.add_many(np.column_stack([ring, np.full(nfac, z)]))
+        idx[k, :nfac] = ids
+        idx[k, nfac] = ids[0]
+    tris = [_grid_tris(idx, flip=flip)]
+    if caps:
+        for k, z, fl in ((0, z0, True), (nz, z1, False)):
+            ctr = welder.add((cx, cy, z))
+            ring_ids = idx[k, :nfac]
+            fan = np.stack([np.full(nfac, ctr), ring_ids, np.roll(ring_ids, -1)], 1)
+            tris.append(fan[:, [0, 2, 1]] if fl else fan)
+    return np.concatenate(tris)
+
+
+def bga(n_grid=20, pitch=0.5, hole_r=0.2, thick=0.035, n_theta=64, nr=6, wall_nz=3, n_via=10, via_r=0.15,
+        via_len=0.5, via_fac=16, via_nz=40, ball_r=0.2, ball_gap=0.1, ball_level=3):
+    """BGA-like package: a square plane (n_grid x n_grid cells of side pitch,
+    thickness thick) with a circular hole in every cell, cylindrical vias
+    (16 facets, capped) through the central n_via x n_via holes without
+    contact, and a solder-ball sphere ball_gap below the lower end of every via.
+    Defaults: 10 x 10 plane, 400 holes of radius 0.2, 100 vias of radius 0.15
+    and length 0.5, 100 balls of radius 0.2; about 1.03M triangles."""
+    W = _Welder(tol=1e-10)
+    half = 0.5 * pitch
+    L = n_grid * pitch
+    x0 = -0.5 * L
+    tris = []
+    for i in range(n_grid):
+        for j in range(n_grid):
+            cx, cy = x0 + (i + 0.5) * pitch, x0 + (j + 0.5) * pitch
+            tris.append(_square_ring_cell(cx, cy, half, hole_r, n_theta, nr, thick, W, flip=False))
+            tris.append(_square_ring_cell(cx, cy, half, hole_r, n_theta, nr, 0.0, W, flip=True))
+            tris.append(_cylinder(cx, cy, hole_r, 0.0, thick, n_theta, wall_nz, W, caps=False, flip=True))
+    # outer rim: the square-boundary points of the border cells, top to bottom
+    nside = n_theta // 8  # boundary points per half side of a cell
+    for side in range(4):
+        pts = []
+        for k in range(n_grid):
+            for q in range(2 * nside):
+                # angles of the projected square points on one cell side
+                t = -np.pi / 4 + (np.pi / 2) * q / (2 * nside)
+                u = x0 + (k + 0.5) * pitch + half * np.tan(t)
+                pts.append(u)
+        pts.append(-x0)
+        pts = np.array(pts)
+        if side == 0:
+            P = np.stack([np.full_like(pts, -x0), pts], 1)
+        elif side == 1:
+            P = np.stack([pts[::-1], np.full_like(pts, -x0)], 1)
+        elif side == 2:
+            P = np.stack([np.full_like(pts, x0), pts[::-1]], 1)
+        else:
+            P = np.stack([pts, np.full_like(pts, x0)], 1)
+        idx = np.empty((wall_nz + 1, len(P)), dtype=np.int64)
+        for k in range(wall_nz + 1):
+            z = thick * k / wall_nz
+            idx[k] = W.add_many(np.column_stack([P, np.full(len(P), z)]))
+        tris.append(_grid_tris(idx, flip=True))
+    # vias through the central holes and balls below them
+    first = (n_grid - n_via) // 2
+    zmid = 0.5 * thick
+    V_off = []
+    for i in range(first, first + n_via):
+        for j in range(first, first + n_via):
+            cx, cy = x0 + (i + 0.5) * pitch, x0 + (j + 0.5) * pitch
+            z0, z1 = zmid - 0.5 * via_len, zmid + 0.5 * via_len
+            tris.append(_cylinder(cx, cy, via_r, z0, z1, via_fac, via_nz, W, caps=True))
+            V_off.append((cx, cy, z0 - ball_gap - ball_r))
+    Vs, Ts = icosphere(ball_level, radius=ball_r)
+    Vbase = W.vertices()
+    T = np.concatenate(tris)
+    Vlist = [Vbase]
+    Tlist = [T]
+    nv = len(Vbase)
+    for (cx, cy, cz) in V_off:
+        Vlist.append(Vs + np.array([cx, cy, cz]))
+        Tlist.append(Ts + nv)
+        nv += len(Vs)
+    return np.concatenate(Vlist), np.concatenate(Tlist).astype(np.int32)
