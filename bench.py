@@ -34,9 +34,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_variant(xrl, torch, tree, x, precision, steps, warmup, order=8, surrogate=None):
+def run_variant(xrl, torch, tree, x, precision, steps, warmup, order=8, surrogate=None, engine="auto"):
     n_cols = x.shape[1]
-    plan = xrl.Plan(tree, order=order, precision=precision, max_cols=n_cols)
+    plan = xrl.Plan(tree, order=order, precision=precision, engine=engine, max_cols=n_cols)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = plan.assemble(surrogate=surrogate, audit_every=100 if surrogate is not None else 0)
@@ -73,7 +73,8 @@ def main():
     ap.add_argument("--n", type=int, default=200_000, help="target panel count of the coil mesh")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--variants", default=None, help="comma list of fp32, mixed, surrogate (first = headline)")
+    ap.add_argument("--variants", default=None, help="comma list of fp32, mixed, surrogate (first = headline); "
+                    "name@engine overrides the translation engine (auto, mfma, valu, mfma_os, mfma_ts)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -106,14 +107,16 @@ def main():
     results = {}
     ys = {}
     for name in variants.split(","):
-        prec = "mixed" if name == "surrogate" else name
+        base, _, engine = name.partition("@")
+        prec = "mixed" if base == "surrogate" else base
         sur = None
-        if name == "surrogate":
+        if base == "surrogate":
             if not os.path.exists(sur_path):
                 log("no trained surrogate weights, skipping the surrogate variant")
                 continue
             sur = xrl.Surrogate.load(sur_path)
-        plan, y, t, t_asm, st, ph = run_variant(xrl, torch, tree, x, prec, args.steps, args.warmup, surrogate=sur)
+        plan, y, t, t_asm, st, ph = run_variant(xrl, torch, tree, x, prec, args.steps, args.warmup, surrogate=sur,
+                                                    engine=engine or "auto")
         info = plan.info()
         K = (8 + 1) ** 2
         C = 2 * n_c

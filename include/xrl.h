@@ -61,10 +61,16 @@ typedef int32_t xrl_status;
 #define XRL_PREC_MIXED 2 /* FP32 M2L on MFMA with FP32 accumulation; self and touching
                             near-field integrals in FP64, stored FP32                   */
 
-/* M2L engine. */
-#define XRL_M2L_AUTO 0   /* MFMA for FP64 and MIXED, vector ALU for FP32 */
-#define XRL_M2L_MFMA 1
-#define XRL_M2L_VALU 2
+/* Translation engine (M2L, and M2M/L2L with it). */
+#define XRL_M2L_AUTO 0    /* MFMA for FP64 and MIXED, vector ALU for FP32 */
+#define XRL_M2L_MFMA 1    /* MFMA; the kernel shape follows the column count of each
+                             call: offset-stationary below 16 real columns,
+                             target-stationary from 16 on                              */
+#define XRL_M2L_VALU 2    /* vector ALU, offset-stationary                             */
+#define XRL_M2L_MFMA_OS 3 /* MFMA, always offset-stationary (pairs that share an
+                             operator batched into one GEMM, per-target reduction)    */
+#define XRL_M2L_MFMA_TS 4 /* MFMA, always target-stationary (one wave per target
+                             accumulates its pairs in registers)                      */
 
 const char *xrl_last_error(void);
 /* Library version string (static storage). */
@@ -273,6 +279,49 @@ xrl_status xrl_fmm_matvec(const xrl_plan *plan, const void *x, int64_t ldx, int3
 xrl_status xrl_plan_set_profiling(xrl_plan *plan, int32_t on);
 xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHASES] */);
 
+/* Kernel-shape knobs of a plan (results agree to rounding for every
+ * setting; only speed changes).  Takes effect at the next matvec.
+ *   XRL_TUNE_TS_KERNEL   (0..2, default 0): form of the target-stationary M2L:
+ *       0  software-pipelined, one operator per offset;
+ *       1  software-pipelined, the 64 operators of non-negative offsets with
+ *          the others applied as sign-reflected copies (a smaller table);
+ *       2  two waves per SIMD, no explicit pipeline, one operator per offset.
+ *   XRL_TUNE_TS_MIN_COLS (>= 1, default 16): with XRL_M2L_MFMA, the
+ *       translations run target-stationary from this many real columns on,
+ *       offset-stationary below.
+ * Errors: XRL_E_INVALID_ARG (null plan, unknown key, bad value). */
+#define XRL_TUNE_TS_KERNEL 0
+#define XRL_TUNE_TS_MIN_COLS 1
+xrl_status xrl_plan_set_tuning(xrl_plan *plan, int32_t key, int32_t value);
+
+/* Graph mode (on != 0): the first xrl_fmm_matvec with a new argument set
+ * (x, y, leading dimensions, column count, dtype, which epilogue terms are
+ * present) runs eagerly, then captures its kernel sequence into a HIP graph
+ * on a plan-owned stream; later calls with the same arguments replay it
+ * with a single hipGraphLaunch on the caller's stream (the epilogue values
+ * themselves may change between calls).  Profiling (xrl_plan_set_profiling)
+ * bypasses the graph.  Errors: XRL_E_INVALID_ARG, XRL_E_HIP. */
+xrl_status xrl_plan_set_graph(xrl_plan *plan, int32_t on);
+
+/* Autotuner result: every form tried, in order, with its mean matvec time. */
+typedef struct {
+    int32_t n_tried;
+    int32_t engine[8];    /* XRL_M2L_* of each form tried */
+    int32_t ts_kernel[8]; /* XRL_TUNE_TS_KERNEL value of each form tried */
+    double ms[8];         /* mean time of one matvec, milliseconds */
+    int32_t best_engine, best_ts_kernel;
+    double best_ms;
+} xrl_tune_result;
+
+/* Times `reps` matvecs (after one warm-up) with each translation form that
+ * applies to the plan's precision (MFMA plans: offset-stationary and the three
+ * target-stationary forms; the vector-ALU plan has one form) on the caller's
+ * arguments, and keeps the fastest in the plan.  y is overwritten.  The
+ * forms agree to rounding, so the choice only changes speed.
+ * Errors: XRL_E_INVALID_ARG, XRL_E_STATE (not assembled), XRL_E_HIP. */
+xrl_status xrl_plan_autotune(xrl_plan *plan, const void *x, int64_t ldx, int32_t n_cols, int32_t dtype, void *y,
+                             int64_t ldy, int32_t reps, void *stream, xrl_tune_result *result);
+
 /* Debug export of plan internals to host memory (tests):
  *   item 0: perm        int32 [n_panels]   sorted position -> global panel
  *   item 1: box_range   int32 [n_boxes][2] panel range [begin, end) per box
@@ -286,6 +335,15 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
  *   item 9: leaf_tpad   int32 [n_leaves]   padded target count of each leaf block
  * With buf == NULL only *nbytes is set. */
 xrl_status xrl_plan_export(const xrl_plan *plan, int32_t item, void *buf, int64_t *nbytes);
+
+/* Host-only: the FP64 M2L operator of the plan's translations for the
+ * integer offset (ox, oy, oz) = (target centre - source centre) / h, order p
+ * (2..12, even), written row-major to out[(p+1)^2][(p+1)^2] (real harmonic
+ * coefficients, rows: local, columns: multipole).  It is the translation of
+ * the FMM of Sec. II-C between same-level boxes.  Needs no device.
+ * Errors: XRL_E_INVALID_ARG (null out, offset inside [-1,1]^3 or outside
+ * [-3,3]^3), XRL_E_UNSUPPORTED (order). */
+xrl_status xrl_m2l_operator(int32_t order, int32_t ox, int32_t oy, int32_t oz, double *out);
 
 /* Self-test of the 16x16x4 MFMA operand layout used by the M2L kernel:
  * D[16][16] = A[16][4] * B[4][16], row-major host arrays of float

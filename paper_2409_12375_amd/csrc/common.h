@@ -179,6 +179,9 @@ struct TransPass {
     xrl::DevBuf<int32_t> red_tgt;     // [n_red] target boxes
     xrl::DevBuf<int32_t> red_ptr;     // [n_red+1]
     xrl::DevBuf<int32_t> red_slot;    // [n_pairs] sorted position of each pair, target order
+    xrl::DevBuf<int32_t> ts_src;      // [n_pairs] source box of each pair, target order
+    xrl::DevBuf<int32_t> ts_op;       // [n_pairs] target order: operator index << 3 | reflection bits
+    xrl::DevBuf<int32_t> ts_op_full;  // [n_pairs] target order: plain operator index << 3 (M2L only)
     mutable std::vector<std::pair<int64_t, xrl::DevBuf<int32_t>>> item_cache;  // key: (engine, cols)
 };
 
@@ -232,6 +235,15 @@ struct xrl_plan {
     // [n_op][KK][KP] for the vector-ALU GEMM (M2L: 343 slots, M2M/L2L: 8)
     xrl::DevBuf<double> op_m2l64f, op_m2m64f, op_l2l64f, op_m2m64k, op_l2l64k;
     xrl::DevBuf<float> op_m2l32f, op_m2m32f, op_l2l32f, op_m2m32k, op_l2l32k;
+    // Operators for the target-stationary kernel in vector fragment order
+    // [op][row tile][k step / VEC][lane][VEC] (VEC = 16 bytes / element):
+    // M2L for the 64 offsets with non-negative components (every other offset
+    // is one of these under coordinate reflections), M2M and L2L (8 each).
+    xrl::DevBuf<double> op_m2lc64v, op_m2m64v, op_l2l64v, op_m2l64v;
+    xrl::DevBuf<float> op_m2lc32v, op_m2m32v, op_l2l32v, op_m2l32v;
+    // form of the target-stationary M2L (XRL_TUNE_TS_KERNEL)
+    int ts_kernel = 0;
+    int ts_min_cols = 16;  // MFMA engine: target-stationary from this many real columns on
     int KP = 96, KK = 84;  // padded row / k dims of the M2L operator tiles
     // moment table per sorted panel, scaled to its leaf: [N][K]
     xrl::DevBuf<double> mom64;
@@ -255,4 +267,24 @@ struct xrl_plan {
     mutable double phase_ms[XRL_N_PHASES] = {0};
     mutable hipEvent_t ev[XRL_N_PHASES + 1] = {};
     bool events_made = false;
+    // epilogue scalars of the current call, [alpha re, im][beta re, im] per
+    // column (plan-owned, so no call allocates or waits for them)
+    mutable xrl::DevBuf<double> ep_dev;
+    // HIP graph of the whole matvec for one argument set (graph mode)
+    bool use_graph = false;
+    mutable hipStream_t cap_stream = nullptr;
+    mutable hipGraphExec_t gexec = nullptr;
+    struct GraphKey {
+        const void *x = nullptr;
+        void *y = nullptr;
+        int64_t ldx = 0, ldy = 0;
+        int ncols = 0, dtype = 0, alpha = 0, beta = 0;
+        bool operator==(const GraphKey &o) const
+        {
+            return x == o.x && y == o.y && ldx == o.ldx && ldy == o.ldy && ncols == o.ncols && dtype == o.dtype &&
+                   alpha == o.alpha && beta == o.beta;
+        }
+    };
+    mutable GraphKey gkey;
+    mutable int64_t graph_launches = 0;
 };

@@ -136,6 +136,81 @@ __global__ __launch_bounds__(256) void k_p2p(const int32_t *__restrict__ leaf_bo
     }
 }
 
+// Wide-column form (FP32, C > 16): one workgroup per (leaf, tile of up to
+// CT columns), so the value stream of a leaf is read once for every 48
+// columns.  A thread owns two consecutive targets of a row (one 8-byte
+// load) and all CT columns; the row groups are summed through LDS in chunks
+// of RC columns, in a fixed order.
+template <int CT>
+__global__ __launch_bounds__(256) void k_p2p_wide(const int32_t *__restrict__ leaf_box,
+                                                  const int32_t *__restrict__ box_beg,
+                                                  const int32_t *__restrict__ box_end,
+                                                  const int32_t *__restrict__ near_rows,
+                                                  const int32_t *__restrict__ near_src,
+                                                  const int32_t *__restrict__ leaf_tpad,
+                                                  const int64_t *__restrict__ val_off, const float *__restrict__ val,
+                                                  const float *__restrict__ xs, float *__restrict__ ys, int C)
+{
+    constexpr int VT = 2, ROWS = 128, RC = 12;
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    __shared__ __align__(16) float sx[ROWS * CT];
+    __shared__ float red[256 * VT * RC];
+    const int64_t li = blockIdx.x;
+    const int c0 = blockIdx.y * CT;
+    const int32_t tb = leaf_box[li];
+    const int32_t kb = box_beg[tb], nt = box_end[tb] - kb;
+    const int32_t r0 = near_rows[li], nr = near_rows[li + 1] - r0;
+    const int G = leaf_tpad[li];
+    const int tpr = G / VT, groups = 256 / tpr;
+    const int jv = (threadIdx.x % tpr) * VT, grp = threadIdx.x / tpr;
+    const float *vb = val + val_off[li];
+    float acc[VT][CT];
+#pragma unroll
+    for (int v = 0; v < VT; ++v)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[v][c] = 0.f;
+    for (int32_t rc = 0; rc < nr; rc += ROWS) {
+        const int nrc = min(ROWS, nr - rc);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nrc * CT; i += 256) {
+            const int r = i / CT, c = i - r * CT;
+            sx[i] = (c0 + c < C) ? xs[(int64_t)near_src[r0 + rc + r] * C + c0 + c] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int r = grp; r < nrc; r += groups) {
+            const f32x2 v = *reinterpret_cast<const f32x2 *>(vb + (int64_t)(rc + r) * G + jv);
+            const f32x4 *xr = reinterpret_cast<const f32x4 *>(sx + r * CT);
+#pragma unroll
+            for (int c4 = 0; c4 < CT / 4; ++c4) {
+                const f32x4 xv = xr[c4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    acc[0][4 * c4 + e] += v[0] * xv[e];
+                    acc[1][4 * c4 + e] += v[1] * xv[e];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int cc = 0; cc < CT; cc += RC) {
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < VT; ++v)
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                if (cc + c < CT) red[(grp * G + jv + v) * RC + c] = acc[v][cc + c];
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < nt * RC; idx += 256) {
+            const int jj = idx / RC, c = idx - jj * RC;
+            if (cc + c >= CT || c0 + cc + c >= C) continue;
+            float sum = 0.f;
+            for (int g = 0; g < groups; ++g) sum += red[(g * G + jj) * RC + c];
+            ys[(int64_t)(kb + jj) * C + c0 + cc + c] = sum;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- P2M
 template <typename T, int CT>
 __global__ __launch_bounds__(256) void k_p2m(const int32_t *__restrict__ leaf_box, const int32_t *__restrict__ box_beg,
@@ -355,6 +430,313 @@ __global__ __launch_bounds__(256) void k_m2l_os_valu(const int32_t *__restrict__
     }
 }
 
+// Target-stationary translation for wide column blocks: one wave per item
+// (target, WT consecutive 16-column tiles).  The wave visits the pairs of its
+// target in their list order and accumulates T_o M_s in registers, so there
+// is no scratch array and no second pass, and the sum order is fixed.  Per
+// pair the source expansion is read once (its rows are contiguous runs of C
+// values, so the WT tiles of one wave cover whole cache lines) and the
+// operator is streamed one 16-row tile of fragments at a time.
+//
+// Launch: 256 threads, 4 items per workgroup.  Workgroups are dealt to the
+// eight XCDs in turn, so block b is remapped to make every XCD walk one
+// contiguous range of targets (neighbouring targets share most sources,
+// which then hit in that XCD's L2).
+__device__ inline int xcd_contiguous_block(int b, int nb)
+{
+    const int full = nb >> 3, rem = nb & 7, x = b & 7, q = b >> 3;
+    return (x < rem ? x * (full + 1) : rem * (full + 1) + (x - rem) * full) + q;
+}
+
+// Widest item (column tiles) whose accumulators, double-buffered B
+// fragments and two operator halves stay within about 480 registers.
+template <typename T, int ORD>
+constexpr int ts_max_tiles()
+{
+    using D = M2LDims<ORD>;
+    constexpr int r = sizeof(T) / 4, vec = 16 / sizeof(T);
+    constexpr int a = 2 * ((D::NRT + 1) / 2) * ((D::NKS + vec - 1) / vec) * vec;
+    int w = 4;
+    while (w > 1 && (D::NRT * 4 * w + 2 * D::NKS * w + a) * r > 480) --w;
+    return w;
+}
+
+// Sign of the real coefficient k under the reflections x -> -x, y -> -y and
+// z -> -z (bits 0, 1, 2 set where the sign flips).  With the normalised
+// harmonics R_n^m ~ P_n^m(cos theta) e^{i m phi}: x -> -x takes phi to
+// pi - phi, (-1)^m times the conjugate; y -> -y takes phi to -phi, the
+// conjugate; z -> -z takes cos theta to -cos theta, (-1)^(n+m).  Multipole
+// and local coefficients both change this way, so the M2L operator of a
+// reflected offset is S T S with S = diag(signs).
+__device__ inline int reflection_signs(int k)
+{
+    int n = (int)sqrtf((float)k);
+    while (n * n > k) --n;
+    while ((n + 1) * (n + 1) <= k) ++n;
+    const int d = k - n * n, m = (d + 1) >> 1, im = (d > 0 && !(d & 1)) ? 1 : 0;
+    return ((m & 1) ^ im) | (im << 1) | (((n + m) & 1) << 2);
+}
+
+template <typename T>
+__device__ inline T flip_sign(T v, uint32_t bit)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __int_as_float(__float_as_int(v) ^ (int)(bit << 31));
+    } else {
+        return __longlong_as_double(__double_as_longlong(v) ^ (long long)((uint64_t)bit << 63));
+    }
+}
+
+// REFL: the operator code of a pair is (index of the non-negative offset
+// |o|) << 3 | reflection bits, and T_o = S T_|o| S is applied by flipping
+// the signs of the B fragments (columns) and of the A fragments (rows), so
+// only 64 operators (L2-resident) are streamed instead of 316.
+template <typename T, int ORD, int WT, bool REFL>
+__global__ __launch_bounds__(256) void k_trans_ts(int n_items, int items_per_tgt, const int32_t *__restrict__ red_tgt,
+                                                  const int32_t *__restrict__ red_ptr,
+                                                  const int32_t *__restrict__ ts_src,
+                                                  const int32_t *__restrict__ ts_op, const T *__restrict__ op_vec,
+                                                  const T *__restrict__ in, int C, int accumulate,
+                                                  T *__restrict__ out)
+{
+    using D = M2LDims<ORD>;
+    using VT = typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type;
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int NKV = (D::NKS + VEC - 1) / VEC;
+    using AV = T __attribute__((ext_vector_type(VEC)));
+    // wave-uniform values are made explicit so that list entries come in
+    // through scalar loads
+    const int w = __builtin_amdgcn_readfirstlane(xcd_contiguous_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
+    if (w >= n_items) return;
+    const int lane = threadIdx.x & 63, li = lane & 15, kq = lane >> 4;
+    const int ti = w / items_per_tgt;
+    const int cb = (w - ti * items_per_tgt) * WT * 16;  // first column of the item
+    const int t = red_tgt[ti], j0 = red_ptr[ti], j1 = red_ptr[ti + 1];
+    // Columns are interleaved over the WT tiles: lane li feeds column
+    // cb + WT li + ct to tile ct, so its B values of one coefficient row are
+    // WT consecutive floats, one vector load.  Loads are unconditional: a
+    // column past C runs into the next row (or the slack after the array)
+    // and only feeds a discarded output column; the coefficient row of the
+    // last k step is clamped to K - 1, where the operator column is zero.
+    const int boff = kq * C + cb + WT * li;
+    const int blast = min(4 * (D::NKS - 1) + kq, D::K - 1) * C - 4 * (D::NKS - 1) * C - kq * C;
+    struct BV {
+        T v[WT];
+    };
+    VT acc[D::NRT][WT];
+#pragma unroll
+    for (int rt = 0; rt < D::NRT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) acc[rt][ct] = VT{0, 0, 0, 0};
+    // Reflection sign masks of this lane, per axis a: bit ks of col[a] for
+    // the coefficient 4 ks + kq it feeds as B, bit 4 rt + e of acm[a] for the
+    // accumulator element (rt, e), whose row is 16 rt + mfma_row(kq, e).
+    uint64_t col[3] = {0, 0, 0}, acm[3] = {0, 0, 0};
+    if constexpr (REFL) {
+        for (int ks = 0; ks < D::NKS; ++ks) {
+            const int kk = 4 * ks + kq;
+            const int sg = kk < D::K ? reflection_signs(kk) : 0;
+            for (int a = 0; a < 3; ++a) col[a] |= (uint64_t)((sg >> a) & 1) << ks;
+        }
+        for (int rt = 0; rt < D::NRT; ++rt)
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * rt + mfma_row<T>(kq, e);
+                const int sg = r < D::K ? reflection_signs(r) : 0;
+                for (int a = 0; a < 3; ++a) acm[a] |= (uint64_t)((sg >> a) & 1) << (4 * rt + e);
+            }
+    }
+    auto mask_of = [&](const uint64_t (&m)[3], int rf) {
+        uint64_t x = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (rf >> a & 1) x ^= m[a];
+        return x;
+    };
+    // T_o = S T_|o| S for a reflected offset.  The column sign goes on the B
+    // fragments; the row sign is carried by the accumulator, which holds
+    // S_f (sum so far) for the reflection f of the pairs being summed: the
+    // pairs of a target come sorted by reflection, and the accumulator is
+    // re-signed (S_f S_g = S_(f^g)) only when the reflection changes.
+    auto flip_acc = [&](int d) {
+        const uint64_t m = mask_of(acm, d);
+#pragma unroll
+        for (int rt = 0; rt < D::NRT; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < WT; ++ct)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[rt][ct][e] = flip_sign(acc[rt][ct][e], (uint32_t)(m >> (4 * rt + e)) & 1u);
+    };
+    // Software pipeline over the pairs: the operator is held in two halves
+    // of row tiles; while the MFMAs of one half run, the next pair's B
+    // fragments and operator half are in flight (loads complete in issue
+    // order, so each wait covers only what the next step needs).
+    constexpr int H0 = (D::NRT + 1) / 2, H1 = D::NRT - H0;
+    AV a0[H0][NKV], a1[H0][NKV];
+    T bc[WT][D::NKS], bn[WT][D::NKS];
+    auto load_b = [&](int j, T (&dst)[WT][D::NKS]) {
+        const T *Ms = in + (int64_t)ts_src[j] * D::K * C;
+#pragma unroll
+        for (int ks = 0; ks < D::NKS; ++ks) {
+            const int rofs = 4 * ks * C + (ks == D::NKS - 1 ? blast : 0);
+            const BV v = *reinterpret_cast<const BV *>(Ms + rofs + boff);
+#pragma unroll
+            for (int ct = 0; ct < WT; ++ct) dst[ct][ks] = v.v[ct];
+        }
+    };
+    auto load_a = [&](int code, int rt0, int nrt, AV (&dst)[H0][NKV]) {
+        const AV *Tv = reinterpret_cast<const AV *>(op_vec) + (int64_t)(code >> 3) * D::NRT * NKV * 64 + lane;
+#pragma unroll
+        for (int r = 0; r < H0; ++r)
+            if (r < nrt)
+#pragma unroll
+                for (int kv = 0; kv < NKV; ++kv) dst[r][kv] = Tv[((rt0 + r) * NKV + kv) * 64];
+    };
+    auto take_b = [&](int code) {
+        const uint64_t cm = REFL ? mask_of(col, code & 7) : 0;
+#pragma unroll
+        for (int ks = 0; ks < D::NKS; ++ks)
+#pragma unroll
+            for (int ct = 0; ct < WT; ++ct)
+                bc[ct][ks] = REFL ? flip_sign(bn[ct][ks], (uint32_t)(cm >> ks) & 1u) : bn[ct][ks];
+    };
+    auto compute = [&](int rt0, int nrt, AV (&av)[H0][NKV]) {
+#pragma unroll
+        for (int r = 0; r < H0; ++r) {
+            if (r >= nrt) break;
+#pragma unroll
+            for (int ks = 0; ks < D::NKS; ++ks)
+#pragma unroll
+                for (int ct = 0; ct < WT; ++ct)
+                    mfma_16x16x4<T>(av[r][ks / VEC][ks % VEC], bc[ct][ks], acc[rt0 + r][ct]);
+        }
+    };
+    if (j0 < j1) {
+        int code = ts_op[j0], frame = 0;
+        load_b(j0, bn);
+        load_a(code, 0, H0, a0);
+        load_a(code, H0, H1, a1);
+        take_b(code);
+        // the scheduling barriers keep each group of loads where it is
+        // issued here (the scheduler would otherwise sink them next to their
+        // uses and expose their latency)
+        for (int j = j0; j < j1; ++j) {
+            if constexpr (REFL) {
+                if ((code & 7) != frame) {
+                    flip_acc((code & 7) ^ frame);
+                    frame = code & 7;
+                }
+            }
+            const int jn = min(j + 1, j1 - 1);  // the last prefetch repeats the last pair (unused)
+            const int ncode = ts_op[jn];
+            __builtin_amdgcn_sched_barrier(0);
+            compute(0, H0, a0);
+            __builtin_amdgcn_sched_barrier(0);
+            load_b(jn, bn);
+            load_a(ncode, 0, H0, a0);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(H0, H1, a1);
+            __builtin_amdgcn_sched_barrier(0);
+            load_a(ncode, H0, H1, a1);
+            __builtin_amdgcn_sched_barrier(0);
+            code = ncode;
+            take_b(code);
+        }
+        if constexpr (REFL)
+            if (frame) flip_acc(frame);
+    }
+#pragma unroll
+    for (int rt = 0; rt < D::NRT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) {
+            const int col = cb + WT * li + ct;
+            if (col >= C) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = rt * 16 + mfma_row<T>(kq, e);
+                if (row >= D::K) continue;
+                T *o = out + ((int64_t)t * D::K + row) * C + col;
+                *o = accumulate ? *o + acc[rt][ct][e] : acc[rt][ct][e];
+            }
+        }
+}
+
+// Lean form of the target-stationary kernel for the full operator table:
+// no software pipeline, one operator row tile ahead, registers capped for
+// two waves per SIMD so that the other wave covers each wait.
+template <typename T, int ORD, int WT>
+__global__ __launch_bounds__(256, 2) void k_trans_ts_lean(int n_items, int items_per_tgt,
+                                                          const int32_t *__restrict__ red_tgt,
+                                                          const int32_t *__restrict__ red_ptr,
+                                                          const int32_t *__restrict__ ts_src,
+                                                          const int32_t *__restrict__ ts_op,
+                                                          const T *__restrict__ op_vec, const T *__restrict__ in,
+                                                          int C, int accumulate, T *__restrict__ out)
+{
+    using D = M2LDims<ORD>;
+    using VT = typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type;
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int NKV = (D::NKS + VEC - 1) / VEC;
+    using AV = T __attribute__((ext_vector_type(VEC)));
+    struct BV {
+        T v[WT];
+    };
+    const int w = __builtin_amdgcn_readfirstlane(xcd_contiguous_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
+    if (w >= n_items) return;
+    const int lane = threadIdx.x & 63, li = lane & 15, kq = lane >> 4;
+    const int ti = w / items_per_tgt;
+    const int cb = (w - ti * items_per_tgt) * WT * 16;
+    const int t = red_tgt[ti], j0 = red_ptr[ti], j1 = red_ptr[ti + 1];
+    const int boff = kq * C + cb + WT * li;
+    const int blast = min(4 * (D::NKS - 1) + kq, D::K - 1) * C - 4 * (D::NKS - 1) * C - kq * C;
+    VT acc[D::NRT][WT];
+#pragma unroll
+    for (int rt = 0; rt < D::NRT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) acc[rt][ct] = VT{0, 0, 0, 0};
+    for (int j = j0; j < j1; ++j) {
+        const T *Ms = in + (int64_t)ts_src[j] * D::K * C;
+        const AV *Tv = reinterpret_cast<const AV *>(op_vec) + (int64_t)(ts_op[j] >> 3) * D::NRT * NKV * 64 + lane;
+        T b[WT][D::NKS];
+#pragma unroll
+        for (int ks = 0; ks < D::NKS; ++ks) {
+            const int rofs = 4 * ks * C + (ks == D::NKS - 1 ? blast : 0);
+            const BV v = *reinterpret_cast<const BV *>(Ms + rofs + boff);
+#pragma unroll
+            for (int ct = 0; ct < WT; ++ct) b[ct][ks] = v.v[ct];
+        }
+        AV an[NKV];
+#pragma unroll
+        for (int kv = 0; kv < NKV; ++kv) an[kv] = Tv[kv * 64];
+#pragma unroll
+        for (int rt = 0; rt < D::NRT; ++rt) {
+            AV ac[NKV];
+#pragma unroll
+            for (int kv = 0; kv < NKV; ++kv) ac[kv] = an[kv];
+            if (rt + 1 < D::NRT)
+#pragma unroll
+                for (int kv = 0; kv < NKV; ++kv) an[kv] = Tv[((rt + 1) * NKV + kv) * 64];
+#pragma unroll
+            for (int ks = 0; ks < D::NKS; ++ks)
+#pragma unroll
+                for (int ct = 0; ct < WT; ++ct) mfma_16x16x4<T>(ac[ks / VEC][ks % VEC], b[ct][ks], acc[rt][ct]);
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < D::NRT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) {
+            const int col = cb + WT * li + ct;
+            if (col >= C) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = rt * 16 + mfma_row<T>(kq, e);
+                if (row >= D::K) continue;
+                T *o = out + ((int64_t)t * D::K + row) * C + col;
+                *o = accumulate ? *o + acc[rt][ct][e] : acc[rt][ct][e];
+            }
+        }
+}
+
 // out[t][row][c0 + c] (=|+=) sum over the pairs of t (fixed order) of
 // tmp[slot][c][row].
 template <typename T, int ORD>
@@ -418,13 +800,58 @@ static const int32_t *pass_items(const TransPass &T, bool mfma, int Cc, int *n_i
 
 // One translation pass: grouped GEMM into the scratch array, then the
 // per-target reduction into `out` (overwrite or accumulate).
+// op_vec: the operators of the target-stationary kernel (vector fragment
+// order); refl: its codes carry reflection bits (M2L) or not (M2M, L2L).
 template <typename T, int ORD>
-static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag, const T *op_k, const T *in, T *out,
-                        int accumulate, DevBuf<T> &tmp, int C, hipStream_t s)
+static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag, const T *op_k, const T *op_vec,
+                        bool refl, const T *in, T *out, int accumulate, DevBuf<T> &tmp, int C, hipStream_t s,
+                        const T *op_full = nullptr)
 {
     using D = M2LDims<ORD>;
     if (TP.n_pairs == 0) return;
-    const bool mfma = P->m2l_engine == XRL_M2L_MFMA;
+    const int eng = P->m2l_engine;
+    if (eng == XRL_M2L_MFMA_TS || (eng == XRL_M2L_MFMA && C >= P->ts_min_cols)) {
+        // tiles per wave: the widest (up to the register budget) that wastes
+        // the fewest padded tiles
+        const int ntiles = (int)cdiv(C, 16);
+        const int wmax = ts_max_tiles<T, ORD>();
+        int WT = 1;
+        for (int w = 1; w <= wmax; ++w)
+            if (cdiv(ntiles, w) * w <= cdiv(ntiles, WT) * WT) WT = w;
+        const int ipt = (int)cdiv(ntiles, WT);
+        const int64_t n_items = TP.n_red * ipt;
+        XRL_CHECK(n_items < (int64_t(1) << 31), XRL_E_UNSUPPORTED, "xrl_fmm_matvec: too many translation items");
+        const unsigned nb = (unsigned)cdiv(n_items, 4);
+        auto go = [&](auto wt) {
+            constexpr int W = decltype(wt)::value;
+            if (refl && P->ts_kernel == 1)
+                k_trans_ts<T, ORD, W, true><<<nb, 256, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                                                               TP.ts_src.p, TP.ts_op.p, op_vec, in, C, accumulate,
+                                                               out);
+            else if (refl && P->ts_kernel == 2)
+                k_trans_ts_lean<T, ORD, W><<<nb, 256, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                                                              TP.ts_src.p, TP.ts_op_full.p, op_full, in, C,
+                                                              accumulate, out);
+            else if (refl)
+                k_trans_ts<T, ORD, W, false><<<nb, 256, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                                                                TP.ts_src.p, TP.ts_op_full.p, op_full, in, C,
+                                                                accumulate, out);
+            else
+                k_trans_ts<T, ORD, W, false><<<nb, 256, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                                                                TP.ts_src.p, TP.ts_op.p, op_vec, in, C, accumulate,
+                                                                out);
+        };
+        if (WT == 1) go(std::integral_constant<int, 1>());
+        if constexpr (ts_max_tiles<T, ORD>() >= 2)
+            if (WT == 2) go(std::integral_constant<int, 2>());
+        if constexpr (ts_max_tiles<T, ORD>() >= 3)
+            if (WT == 3) go(std::integral_constant<int, 3>());
+        if constexpr (ts_max_tiles<T, ORD>() >= 4)
+            if (WT == 4) go(std::integral_constant<int, 4>());
+        XRL_HIP(hipGetLastError());
+        return;
+    }
+    const bool mfma = eng != XRL_M2L_VALU;
     // column chunk so that the per-pair scratch stays within 4 GiB
     const int64_t per_col = TP.n_pairs * (int64_t)D::KP * (int64_t)sizeof(T);
     const int Cc = (int)std::max<int64_t>(1, std::min<int64_t>(C, (int64_t(4) << 30) / per_col));
@@ -464,6 +891,26 @@ template <typename T>
 static void p2p_launch(const xrl_plan *P, const T *val, const T *xs, T *ys, int C, hipStream_t s)
 {
     if (P->n_leaves == 0) return;
+    if constexpr (sizeof(T) == 4) {
+        if (C > 16) {
+            auto wide = [&](auto ctc) {
+                constexpr int CT = decltype(ctc)::value;
+                dim3 grid((unsigned)P->n_leaves, (unsigned)cdiv(C, CT));
+                k_p2p_wide<CT><<<grid, 256, 0, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p, P->near_rows.p,
+                                                    P->near_src.p, P->leaf_tpad.p, P->near_val_off.p, val, xs, ys, C);
+            };
+            if (C <= 24)
+                wide(std::integral_constant<int, 24>());
+            else if (C <= 32)
+                wide(std::integral_constant<int, 32>());
+            else if (C <= 36)
+                wide(std::integral_constant<int, 36>());
+            else
+                wide(std::integral_constant<int, 48>());
+            XRL_HIP(hipGetLastError());
+            return;
+        }
+    }
     auto go = [&](auto ctc) {
         constexpr int CT = decltype(ctc)::value;
         dim3 grid((unsigned)P->n_leaves, (unsigned)cdiv(C, CT));
@@ -484,6 +931,8 @@ static void p2p_launch(const xrl_plan *P, const T *val, const T *xs, T *ys, int 
 template <typename T>
 struct Ops {
     const T *near, *mom, *m2m_f, *m2m_k, *l2l_f, *l2l_k, *m2l_f, *m2l_k;
+    const T *m2m_v, *l2l_v, *m2l_v;  // target-stationary operators (M2L: non-negative offsets)
+    const T *m2l_full;               // target-stationary M2L operators of every offset
 };
 
 template <typename T, int ORD>
@@ -493,23 +942,28 @@ static void translations(const xrl_plan *P, const Ops<T> &op, T *M, T *L, DevBuf
     using D = M2LDims<ORD>;
     mark(3);
     for (int l = P->depth - 1; l >= 0; --l)
-        pass_launch<T, ORD>(P, P->m2m[l], op.m2m_f, op.m2m_k, M, M, 0, tmp, C, s);
+        pass_launch<T, ORD>(P, P->m2m[l], op.m2m_f, op.m2m_k, op.m2m_v, false, M, M, 0, tmp, C, s);
     // zero every local expansion (a fill kernel, so the sequence stays
     // capturable into a HIP graph without memset nodes)
     const int64_t nL = P->B * (int64_t)D::K * C;
     k_fill_zero<T><<<(unsigned)std::min<int64_t>(cdiv(nL, 256), 65536), 256, 0, s>>>(L, nL);
     XRL_HIP(hipGetLastError());
     mark(4);
-    pass_launch<T, ORD>(P, P->m2l, op.m2l_f, op.m2l_k, M, L, 0, tmp, C, s);
+    pass_launch<T, ORD>(P, P->m2l, op.m2l_f, op.m2l_k, op.m2l_v, true, M, L, 0, tmp, C, s, op.m2l_full);
     mark(5);
-    for (int l = 3; l <= P->depth; ++l) pass_launch<T, ORD>(P, P->l2l[l], op.l2l_f, op.l2l_k, L, L, 1, tmp, C, s);
+    for (int l = 3; l <= P->depth; ++l)
+        pass_launch<T, ORD>(P, P->l2l[l], op.l2l_f, op.l2l_k, op.l2l_v, false, L, L, 1, tmp, C, s);
     mark(6);
 }
 
+// Enqueue one matvec on stream s: kernels only (no allocation, no host
+// synchronisation once the work buffers exist), so the same sequence can be
+// captured into a HIP graph.  The epilogue scalars are read from the plan's
+// ep_dev buffer when has_alpha / has_beta.
 template <typename T>
 static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols, int dtype, void *y, int64_t ldy,
-                       const double *alpha, const double *beta, hipStream_t s, DevBuf<T> &xs, DevBuf<T> &ys,
-                       DevBuf<T> &M, DevBuf<T> &L, DevBuf<T> &tmp, const Ops<T> &op)
+                       bool has_alpha, bool has_beta, hipStream_t s, DevBuf<T> &xs, DevBuf<T> &ys, DevBuf<T> &M,
+                       DevBuf<T> &L, DevBuf<T> &tmp, const Ops<T> &op)
 {
     const int C = 2 * ncols;
     const int K = P->K;
@@ -518,9 +972,11 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
         xs.alloc(N * C);
         ys.alloc(N * C);
     }
-    if (M.n < (size_t)(B * K * C)) {
-        M.alloc(B * K * C);
-        L.alloc(B * K * C);
+    if (M.n < (size_t)(B * K * C + 256)) {
+        // slack after the expansions: the target-stationary kernel reads
+        // (and discards) up to 16 WT columns past the last record
+        M.alloc(B * K * C + 256);
+        L.alloc(B * K * C + 256);
     }
     const bool prof = P->profiling;
     std::function<void(int)> mark = [&](int i) {
@@ -567,20 +1023,8 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
         XRL_HIP(hipGetLastError());
     }
     mark(7);
-    DevBuf<double> dab;
-    const double *da = nullptr, *db = nullptr;
-    if (alpha || beta) {
-        std::vector<double> h(4 * ncols, 0.0);
-        for (int c = 0; c < ncols; ++c) {
-            h[2 * c] = alpha ? alpha[2 * c] : 1.0;
-            h[2 * c + 1] = alpha ? alpha[2 * c + 1] : 0.0;
-            h[2 * ncols + 2 * c] = beta ? beta[2 * c] : 0.0;
-            h[2 * ncols + 2 * c + 1] = beta ? beta[2 * c + 1] : 0.0;
-        }
-        dab.upload(h, s);
-        da = dab.p;
-        db = beta ? dab.p + 2 * ncols : nullptr;
-    }
+    const double *da = (has_alpha || has_beta) ? P->ep_dev.p : nullptr;
+    const double *db = has_beta ? P->ep_dev.p + 2 * ncols : nullptr;
     const unsigned gy = (unsigned)std::min<int64_t>(cdiv(N * ncols, bs), 1 << 20);
     if (dtype == XRL_C64)
         k_scatter_y<float, T><<<gy, bs, 0, s>>>(N, P->perm.p, ys.p, P->area.p, (const float *)x, ldx, (float *)y, ldy,
@@ -590,7 +1034,6 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
                                                  ldy, ncols, da, db);
     XRL_HIP(hipGetLastError());
     mark(8);
-    if (dab.p) XRL_HIP(hipStreamSynchronize(s));  // keep the epilogue scalars alive until used
     if (prof) {
         XRL_HIP(hipEventSynchronize(P->ev[8]));
         // public phase order: gather, P2P, P2M, M2M, M2L, L2L, L2P, scatter
@@ -605,6 +1048,85 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
 }  // namespace xrl
 
 using namespace xrl;
+
+// Epilogue scalars to the plan's device buffer (ordered on s before the
+// kernels that read them).
+static void upload_epilogue(const xrl_plan *P, int ncols, const double *alpha, const double *beta, hipStream_t s)
+{
+    if (!alpha && !beta) return;
+    std::vector<double> h(4 * (size_t)ncols, 0.0);
+    for (int c = 0; c < ncols; ++c) {
+        h[2 * c] = alpha ? alpha[2 * c] : 1.0;
+        h[2 * c + 1] = alpha ? alpha[2 * c + 1] : 0.0;
+        h[2 * ncols + 2 * c] = beta ? beta[2 * c] : 0.0;
+        h[2 * ncols + 2 * c + 1] = beta ? beta[2 * c + 1] : 0.0;
+    }
+    if (P->ep_dev.n < h.size()) P->ep_dev.alloc(4 * (size_t)P->max_cols);
+    XRL_HIP(hipMemcpyAsync(P->ep_dev.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s));
+}
+
+static void enqueue_matvec(const xrl_plan *P, const void *x, int64_t ldx, int n_cols, int dtype, void *y, int64_t ldy,
+                           bool ha, bool hb, hipStream_t s)
+{
+    xrl_plan *Pm = const_cast<xrl_plan *>(P);
+    if (P->precision == XRL_PREC_FP64) {
+        Ops<double> op{P->near64.p, P->mom64.p, P->op_m2m64f.p, P->op_m2m64k.p, P->op_l2l64f.p, P->op_l2l64k.p,
+                       P->op_m2l64f.p, P->op_m2l64k.p, P->op_m2m64v.p, P->op_l2l64v.p, P->op_m2lc64v.p,
+                       P->op_m2l64v.p};
+        run_matvec<double>(P, x, ldx, n_cols, dtype, y, ldy, ha, hb, s, Pm->xs64, Pm->ys64, Pm->M64, Pm->L64,
+                           Pm->os_tmp64, op);
+    } else {
+        Ops<float> op{P->near32.p, P->mom32.p, P->op_m2m32f.p, P->op_m2m32k.p, P->op_l2l32f.p, P->op_l2l32k.p,
+                      P->op_m2l32f.p, P->op_m2l32k.p, P->op_m2m32v.p, P->op_l2l32v.p, P->op_m2lc32v.p,
+                      P->op_m2l32v.p};
+        run_matvec<float>(P, x, ldx, n_cols, dtype, y, ldy, ha, hb, s, Pm->xs32, Pm->ys32, Pm->M32, Pm->L32,
+                          Pm->os_tmp32, op);
+    }
+}
+
+// Graph mode: the first call with a new argument set runs eagerly (which
+// sizes the work buffers and builds the work lists), then captures the same
+// kernel sequence on the plan's capture stream and instantiates it; later
+// calls with the same arguments replay it with one hipGraphLaunch.
+static void graph_matvec(const xrl_plan *P, const void *x, int64_t ldx, int n_cols, int dtype, void *y, int64_t ldy,
+                         bool ha, bool hb, hipStream_t s)
+{
+    xrl_plan::GraphKey k;
+    k.x = x;
+    k.y = y;
+    k.ldx = ldx;
+    k.ldy = ldy;
+    k.ncols = n_cols;
+    k.dtype = dtype;
+    k.alpha = ha;
+    k.beta = hb;
+    if (P->gexec && k == P->gkey) {
+        XRL_HIP(hipGraphLaunch(P->gexec, s));
+        ++P->graph_launches;
+        return;
+    }
+    if (P->gexec) {
+        XRL_HIP(hipGraphExecDestroy(P->gexec));
+        P->gexec = nullptr;
+    }
+    enqueue_matvec(P, x, ldx, n_cols, dtype, y, ldy, ha, hb, s);
+    XRL_HIP(hipStreamSynchronize(s));
+    if (!P->cap_stream) XRL_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    XRL_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue_matvec(P, x, ldx, n_cols, dtype, y, ldy, ha, hb, P->cap_stream);
+    } catch (...) {
+        (void)hipStreamEndCapture(P->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    XRL_HIP(hipStreamEndCapture(P->cap_stream, &g));
+    const hipError_t e = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    XRL_HIP(e);
+    P->gkey = k;
+}
 
 extern "C" xrl_status xrl_fmm_matvec(const xrl_plan *P, const void *x, int64_t ldx, int32_t n_cols, int32_t dtype,
                                      void *y, int64_t ldy, const xrl_epilogue *ep, void *stream)
@@ -624,17 +1146,97 @@ extern "C" xrl_status xrl_fmm_matvec(const xrl_plan *P, const void *x, int64_t l
             Pm->events_made = true;
         }
         const double *al = ep ? ep->alpha : nullptr, *be = ep ? ep->beta : nullptr;
-        if (P->precision == XRL_PREC_FP64) {
-            Ops<double> op{P->near64.p, P->mom64.p, P->op_m2m64f.p, P->op_m2m64k.p, P->op_l2l64f.p, P->op_l2l64k.p,
-                           P->op_m2l64f.p, P->op_m2l64k.p};
-            run_matvec<double>(P, x, ldx, n_cols, dtype, y, ldy, al, be, s, Pm->xs64, Pm->ys64, Pm->M64, Pm->L64,
-                               Pm->os_tmp64, op);
-        } else {
-            Ops<float> op{P->near32.p, P->mom32.p, P->op_m2m32f.p, P->op_m2m32k.p, P->op_l2l32f.p, P->op_l2l32k.p,
-                          P->op_m2l32f.p, P->op_m2l32k.p};
-            run_matvec<float>(P, x, ldx, n_cols, dtype, y, ldy, al, be, s, Pm->xs32, Pm->ys32, Pm->M32, Pm->L32,
-                              Pm->os_tmp32, op);
+        upload_epilogue(P, n_cols, al, be, s);
+        if (P->use_graph && !P->profiling)
+            graph_matvec(P, x, ldx, n_cols, dtype, y, ldy, al != nullptr, be != nullptr, s);
+        else
+            enqueue_matvec(P, x, ldx, n_cols, dtype, y, ldy, al != nullptr, be != nullptr, s);
+    });
+}
+
+extern "C" xrl_status xrl_plan_set_graph(xrl_plan *P, int32_t on)
+{
+    return guarded([&] {
+        XRL_CHECK(P, XRL_E_INVALID_ARG, "xrl_plan_set_graph: null plan");
+        P->use_graph = on != 0;
+        if (!P->use_graph && P->gexec) {
+            XRL_HIP(hipGraphExecDestroy(P->gexec));
+            P->gexec = nullptr;
         }
+    });
+}
+
+// Kernel-shape autotuner: times every translation form that applies to the
+// plan's precision on the caller's arguments and keeps the fastest.
+extern "C" xrl_status xrl_plan_autotune(xrl_plan *P, const void *x, int64_t ldx, int32_t n_cols, int32_t dtype,
+                                        void *y, int64_t ldy, int32_t reps, void *stream, xrl_tune_result *res)
+{
+    return guarded([&] {
+        XRL_CHECK(P && x && y && res && reps >= 1, XRL_E_INVALID_ARG, "xrl_plan_autotune: bad arguments");
+        XRL_CHECK(P->assembled, XRL_E_STATE, "xrl_plan_autotune: call xrl_nearfield_assemble first");
+        XRL_CHECK(n_cols >= 1 && n_cols <= P->max_cols && ldx >= n_cols && ldy >= n_cols &&
+                      (dtype == XRL_C64 || dtype == XRL_C128) && x != y,
+                  XRL_E_INVALID_ARG, "xrl_plan_autotune: bad matvec arguments");
+        hipStream_t s = (hipStream_t)stream;
+        *res = xrl_tune_result{};
+        struct Cand {
+            int engine, ts_kernel;
+        };
+        std::vector<Cand> cands;
+        if (P->m2l_engine == XRL_M2L_VALU) {
+            cands.push_back({XRL_M2L_VALU, P->ts_kernel});
+        } else {
+            cands.push_back({XRL_M2L_MFMA_OS, 0});
+            for (int k = 0; k < 3; ++k) cands.push_back({XRL_M2L_MFMA_TS, k});
+        }
+        hipEvent_t e0, e1;
+        XRL_HIP(hipEventCreate(&e0));
+        XRL_HIP(hipEventCreate(&e1));
+        const bool prof = P->profiling, graph = P->use_graph;
+        P->profiling = false;
+        P->use_graph = false;
+        double best = 1e300;
+        Cand pick = cands[0];
+        try {
+            for (size_t i = 0; i < cands.size() && i < 8; ++i) {
+                P->m2l_engine = cands[i].engine;
+                P->ts_kernel = cands[i].ts_kernel;
+                enqueue_matvec(P, x, ldx, n_cols, dtype, y, ldy, false, false, s);  // warm-up
+                XRL_HIP(hipEventRecord(e0, s));
+                for (int r = 0; r < reps; ++r) enqueue_matvec(P, x, ldx, n_cols, dtype, y, ldy, false, false, s);
+                XRL_HIP(hipEventRecord(e1, s));
+                XRL_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                XRL_HIP(hipEventElapsedTime(&ms, e0, e1));
+                res->ms[i] = ms / reps;
+                res->engine[i] = cands[i].engine;
+                res->ts_kernel[i] = cands[i].ts_kernel;
+                res->n_tried = (int32_t)(i + 1);
+                if (ms / reps < best) {
+                    best = ms / reps;
+                    pick = cands[i];
+                }
+            }
+        } catch (...) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            P->profiling = prof;
+            P->use_graph = graph;
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        P->profiling = prof;
+        P->use_graph = graph;
+        P->m2l_engine = pick.engine;
+        P->ts_kernel = pick.ts_kernel;
+        if (P->gexec) {  // a captured graph holds the old kernel shapes
+            XRL_HIP(hipGraphExecDestroy(P->gexec));
+            P->gexec = nullptr;
+        }
+        res->best_engine = pick.engine;
+        res->best_ts_kernel = pick.ts_kernel;
+        res->best_ms = best;
     });
 }
 
@@ -673,6 +1275,24 @@ extern "C" xrl_status xrl_plan_set_profiling(xrl_plan *P, int32_t on)
     return guarded([&] {
         XRL_CHECK(P, XRL_E_INVALID_ARG, "xrl_plan_set_profiling: null plan");
         P->profiling = on != 0;
+    });
+}
+
+extern "C" xrl_status xrl_plan_set_tuning(xrl_plan *P, int32_t key, int32_t value)
+{
+    return guarded([&] {
+        XRL_CHECK(P, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: null plan");
+        switch (key) {
+            case XRL_TUNE_TS_KERNEL:
+                XRL_CHECK(value >= 0 && value <= 2, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: kernel form must be 0..2");
+                P->ts_kernel = value;
+                break;
+            case XRL_TUNE_TS_MIN_COLS:
+                XRL_CHECK(value >= 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: min columns must be >= 1");
+                P->ts_min_cols = value;
+                break;
+            default: fail(XRL_E_INVALID_ARG, "xrl_plan_set_tuning: unknown key %d", key);
+        }
     });
 }
 

@@ -16,6 +16,7 @@
 //       Mh_n^m = s_nm M_n^m / h^n,   Lh_n^m = h^{n+1} L_n^m / s_nm,
 // which makes every operator independent of the level.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -263,3 +264,15 @@ void gauss_legendre01(int n, double *x, double *w)
 }
 
 }  // namespace xrl
+
+extern "C" xrl_status xrl_m2l_operator(int32_t order, int32_t ox, int32_t oy, int32_t oz, double *out)
+{
+    return xrl::guarded([&] {
+        XRL_CHECK(out, XRL_E_INVALID_ARG, "xrl_m2l_operator: null output");
+        XRL_CHECK(order >= 2 && order <= 12 && order % 2 == 0, XRL_E_UNSUPPORTED,
+                  "xrl_m2l_operator: order must be even in 2..12 (got %d)", order);
+        const int a = std::max(std::abs(ox), std::max(std::abs(oy), std::abs(oz)));
+        XRL_CHECK(a >= 2 && a <= 3, XRL_E_INVALID_ARG, "xrl_m2l_operator: offset must lie in [-3,3]^3 outside [-1,1]^3");
+        xrl::build_m2l(order, ox, oy, oz, out);
+    });
+}

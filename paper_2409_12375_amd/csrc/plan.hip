@@ -316,11 +316,25 @@ __global__ void k_panel_leaf(int64_t nleaf, const int32_t *__restrict__ leaf_box
     for (int32_t k = beg[b] + threadIdx.x; k < end[b]; k += blockDim.x) panel_leaf[k] = (int32_t)li;
 }
 
+// M2L offset slot (ox+3) + 7 (oy+3) + 49 (oz+3) -> index of the offset
+// (|ox|, |oy|, |oz|) in the 64-entry table of non-negative offsets, shifted
+// left by 3, with the reflection bits (1: x, 2: y, 4: z) of the signs.
+static int32_t m2l_reflected_code(int32_t slot)
+{
+    const int ox = slot % 7 - 3, oy = (slot / 7) % 7 - 3, oz = slot / 49 - 3;
+    const int canon = std::abs(ox) + 4 * std::abs(oy) + 16 * std::abs(oz);
+    return canon << 3 | (ox < 0 ? 1 : 0) | (oy < 0 ? 2 : 0) | (oz < 0 ? 4 : 0);
+}
+
 // Sort the (target, source, operator) triples of one pass by operator; the
 // input is grouped by target (targets ascending, pairs of a target
-// contiguous).
+// contiguous).  ts_code: operator code of each pair for the
+// target-stationary kernel (input order); empty = the operator index
+// itself, no reflection.  That kernel visits the pairs of a target sorted by
+// reflection bits (then in input order), so its accumulator changes frame
+// at most seven times per target.
 static void build_pass(TransPass &T, const std::vector<int32_t> &tgt, const std::vector<int32_t> &src,
-                       const std::vector<int32_t> &code, hipStream_t s)
+                       const std::vector<int32_t> &code, hipStream_t s, const std::vector<int32_t> &ts_code = {})
 {
     const int64_t n = (int64_t)tgt.size();
     T.n_pairs = n;
@@ -354,6 +368,24 @@ static void build_pass(TransPass &T, const std::vector<int32_t> &tgt, const std:
     T.red_tgt.upload(rt, s);
     T.red_ptr.upload(rp, s);
     T.red_slot.upload(slot, s);
+    // target order: source and operator code of every pair
+    std::vector<int32_t> c8(n), tsrc(n), tord(n);
+    for (int64_t j = 0; j < n; ++j) c8[j] = ts_code.empty() ? code[j] << 3 : ts_code[j];
+    std::iota(tord.begin(), tord.end(), 0);
+    for (size_t i = 0; i + 1 < rp.size(); ++i)
+        std::stable_sort(tord.begin() + rp[i], tord.begin() + rp[i + 1],
+                         [&](int32_t a, int32_t b) { return (c8[a] & 7) < (c8[b] & 7); });
+    std::vector<int32_t> tcode(n);
+    for (int64_t j = 0; j < n; ++j) {
+        tsrc[j] = src[tord[j]];
+        tcode[j] = c8[tord[j]];
+    }
+    T.ts_src.upload(tsrc, s);
+    T.ts_op.upload(tcode, s);
+    if (!ts_code.empty()) {
+        for (int64_t j = 0; j < n; ++j) tcode[j] = code[tord[j]] << 3;
+        T.ts_op_full.upload(tcode, s);
+    }
 }
 
 }  // namespace xrl
@@ -567,14 +599,15 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     P->leaf_tpad.upload(tpad, s);
     // ---------------- translation passes: M2L (all levels), M2M and L2L per level
     {
-        std::vector<int32_t> tg, sr, cd;
+        std::vector<int32_t> tg, sr, cd, rc;
         for (int64_t b = 0; b < B; ++b)
             for (int64_t j = voff[b]; j < voff[b + 1]; ++j) {
                 tg.push_back((int32_t)b);
                 sr.push_back(hsrc[j]);
                 cd.push_back(hcode[j]);
+                rc.push_back(m2l_reflected_code(hcode[j]));
             }
-        build_pass(P->m2l, tg, sr, cd, s);
+        build_pass(P->m2l, tg, sr, cd, s, rc);
         P->m2m.clear();
         P->l2l.clear();
         P->m2m.resize(depth + 1);
@@ -665,6 +698,24 @@ static void build_plan(xrl_plan *P, hipStream_t s)
         k64.upload(kmaj, s);
         k32.upload(to32(kmaj), s);
     };
+    // vector fragment order: element e of the 16-byte vector kv of a lane is
+    // the A operand of k step VEC kv + e (zero past the last step)
+    auto vec_layouts = [&](const std::vector<double> &pad, int nop, DevBuf<double> &v64, DevBuf<float> &v32) {
+        for (int vec : {2, 4}) {
+            const int nkv = (nks + vec - 1) / vec;
+            std::vector<double> v((size_t)nop * nrt * nkv * 64 * vec, 0.0);
+            for (int c = 0; c < nop; ++c)
+                for (int rt = 0; rt < nrt; ++rt)
+                    for (int ks = 0; ks < nks; ++ks)
+                        for (int lane = 0; lane < 64; ++lane)
+                            v[((((size_t)c * nrt + rt) * nkv + ks / vec) * 64 + lane) * vec + ks % vec] =
+                                pad[((size_t)c * P->KP + rt * 16 + (lane & 15)) * P->KK + 4 * ks + (lane >> 4)];
+            if (vec == 2)
+                v64.upload(v, s);
+            else
+                v32.upload(to32(v), s);
+        }
+    };
     auto padded = [&](const std::vector<double> &dense, int nop) {
         std::vector<double> out((size_t)nop * P->KP * P->KK, 0.0);
         for (int c = 0; c < nop; ++c)
@@ -674,6 +725,22 @@ static void build_plan(xrl_plan *P, hipStream_t s)
         return out;
     };
     layouts(m2l, 343, P->op_m2l64f, P->op_m2l32f, P->op_m2l64k, P->op_m2l32k);
+    {
+        // the non-negative offsets that some used offset reflects onto
+        std::vector<double> m2lc(64 * (size_t)P->KP * P->KK, 0.0);
+        std::vector<char> cu(64, 0);
+        for (int c : grp_off) cu[m2l_reflected_code(c) >> 3] = 1;
+        for (int c = 0; c < 64; ++c) {
+            if (!cu[c]) continue;
+            build_m2l(p, c % 4, (c / 4) % 4, c / 16, tmp.data());
+            for (int r = 0; r < K; ++r)
+                for (int k = 0; k < K; ++k) m2lc[((size_t)c * P->KP + r) * P->KK + k] = tmp[(size_t)r * K + k];
+        }
+        vec_layouts(m2lc, 64, P->op_m2lc64v, P->op_m2lc32v);
+        vec_layouts(m2l, 343, P->op_m2l64v, P->op_m2l32v);
+    }
+    vec_layouts(padded(m2m, 8), 8, P->op_m2m64v, P->op_m2m32v);
+    vec_layouts(padded(l2l, 8), 8, P->op_l2l64v, P->op_l2l32v);
     layouts(padded(m2m, 8), 8, P->op_m2m64f, P->op_m2m32f, P->op_m2m64k, P->op_m2m32k);
     layouts(padded(l2l, 8), 8, P->op_l2l64f, P->op_l2l32f, P->op_l2l64k, P->op_l2l32k);
     P->op_m2m64.upload(m2m, s);
@@ -721,7 +788,7 @@ extern "C" xrl_status xrl_fmm_plan(xrl_tree *const *trees, int32_t n_trees, cons
         XRL_CHECK(opts->order >= 2 && opts->order <= 12 && opts->order % 2 == 0, XRL_E_UNSUPPORTED,
                   "xrl_fmm_plan: order must be even in 2..12 (got %d)", opts->order);
         XRL_CHECK(opts->precision >= 0 && opts->precision <= 2, XRL_E_INVALID_ARG, "xrl_fmm_plan: bad precision");
-        XRL_CHECK(opts->m2l_engine >= 0 && opts->m2l_engine <= 2, XRL_E_INVALID_ARG, "xrl_fmm_plan: bad engine");
+        XRL_CHECK(opts->m2l_engine >= 0 && opts->m2l_engine <= 4, XRL_E_INVALID_ARG, "xrl_fmm_plan: bad engine");
         XRL_CHECK(opts->max_cols >= 1 && opts->max_cols <= 4096, XRL_E_INVALID_ARG,
                   "xrl_fmm_plan: max_cols must be in 1..4096");
         auto P = std::make_unique<xrl_plan>();
@@ -743,6 +810,8 @@ extern "C" void xrl_plan_destroy(xrl_plan *plan)
     if (!plan) return;
     if (plan->events_made)
         for (auto &e : plan->ev) (void)hipEventDestroy(e);
+    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;
 }
 

@@ -363,3 +363,30 @@ def bga(n_grid=20, pitch=0.5, hole_r=0.2, thick=0.035, n_theta=64, nr=6, wall_nz
         Tlist.append(Ts + nv)
         nv += len(Vs)
     return np.concatenate(Vlist), np.concatenate(Tlist).astype(np.int32)
+
+
+# --------------------------------------------------------------------------
+# batch of uneven meshes
+# --------------------------------------------------------------------------
+def batch_meshes(n_meshes=32, n_min=10_000, n_max=500_000, seed=GEOM_SEED + 4):
+    """Independent meshes of uneven size for the batched matvec: N_i drawn
+    log-uniformly in [n_min, n_max], each a bar, a coil pair or a plane with
+    holes (seeded choice), meshed close to N_i.  Returns a list of
+    (kind, V, T); the meshes are disjoint problems (each has its own P)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_meshes):
+        n = int(round(np.exp(rng.uniform(np.log(n_min), np.log(n_max)))))
+        kind = ("bar", "coil", "plane")[int(rng.integers(3))]
+        if kind == "bar":
+            L = float(rng.uniform(5.0, 20.0))
+            k = max(2, int(round(np.sqrt(n / (4.0 * (2.0 * L + 1.0))))))
+            V, T = bar(k, k, max(2, int(round(k * L))), size=(1.0, 1.0, L), seed=seed + 100 + i)
+        elif kind == "coil":
+            small = n < 100_000
+            V, T = coils(n, nw=4 if small else 8, nt=2 if small else 3)
+        else:
+            g = max(2, int(round(np.sqrt(n / 2016.0))))
+            V, T = bga(n_grid=g, n_via=0)
+        out.append((kind, V, T))
+    return out

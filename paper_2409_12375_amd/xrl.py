@@ -15,7 +15,7 @@ _lib = None
 
 C64, C128 = 1, 2
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
-ENGINE = {"auto": 0, "mfma": 1, "valu": 2}
+ENGINE = {"auto": 0, "mfma": 1, "valu": 2, "mfma_os": 3, "mfma_ts": 4}
 N_PHASES = 8
 PHASES = ["gather", "p2p", "p2m", "m2m", "m2l", "l2l", "l2p", "scatter"]
 
@@ -37,6 +37,11 @@ class MeshDesc(ctypes.Structure):
 class TreeInfo(ctypes.Structure):
     _fields_ = [("n_panels", _i64), ("n_boxes", _i64), ("n_leaves", _i64), ("depth", _i32),
                 ("n_overfull_leaves", _i32), ("root_center", ctypes.c_double * 3), ("root_size", ctypes.c_double)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("n_tried", _i32), ("engine", _i32 * 8), ("ts_kernel", _i32 * 8), ("ms", ctypes.c_double * 8),
+                ("best_engine", _i32), ("best_ts_kernel", _i32), ("best_ms", ctypes.c_double)]
 
 
 class PlanOpts(ctypes.Structure):
@@ -104,6 +109,9 @@ def lib():
         L.xrl_fmm_matvec.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _i64, ctypes.POINTER(Epilogue), _vp]
         L.xrl_plan_set_profiling.argtypes = [_vp, _i32]
         L.xrl_plan_get_phase_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
+        L.xrl_plan_set_tuning.argtypes = [_vp, _i32, _i32]
+        L.xrl_plan_set_graph.argtypes = [_vp, _i32]
+        L.xrl_plan_autotune.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _i64, _i32, _vp, ctypes.POINTER(TuneResult)]
         L.xrl_plan_export.argtypes = [_vp, _i32, _vp, ctypes.POINTER(_i64)]
         L.xrl_surrogate_features.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp]
         L.xrl_mlp_train.argtypes = [_vp, _vp, _i64, ctypes.POINTER(MlpTrainOpts), _vp, _vp, _vp]
@@ -228,6 +236,30 @@ class Plan:
 
     def set_profiling(self, on=True):
         _check(lib().xrl_plan_set_profiling(self.h, 1 if on else 0))
+
+    TUNE = {"ts_kernel": 0, "ts_min_cols": 1}
+
+    def set_tuning(self, key, value):
+        """Kernel-shape knob (see xrl_plan_set_tuning); results agree to rounding."""
+        _check(lib().xrl_plan_set_tuning(self.h, self.TUNE[key], int(value)))
+
+    def set_graph(self, on=True):
+        """Replay each distinct matvec argument set from a captured HIP graph."""
+        _check(lib().xrl_plan_set_graph(self.h, 1 if on else 0))
+
+    def autotune(self, x, y=None, reps=3, stream=None):
+        """Time the translation forms on (x, y) and keep the fastest; returns
+        {"tried": [(engine, ts_kernel, ms), ...], "best": (engine, ts_kernel, ms)}."""
+        import torch
+        X = x if x.dim() == 2 else x.unsqueeze(1)
+        Y = torch.empty_like(X) if y is None else y
+        dt = C64 if X.dtype == torch.complex64 else C128
+        r = TuneResult()
+        _check(lib().xrl_plan_autotune(self.h, _vp(X.data_ptr()), X.stride(0), X.shape[1], dt, _vp(Y.data_ptr()),
+                                       Y.stride(0), reps, _stream(stream), ctypes.byref(r)))
+        names = {v: k for k, v in ENGINE.items()}
+        tried = [(names[r.engine[i]], r.ts_kernel[i], r.ms[i]) for i in range(r.n_tried)]
+        return {"tried": tried, "best": (names[r.best_engine], r.best_ts_kernel, r.best_ms)}
 
     def phase_ms(self):
         a = (ctypes.c_double * N_PHASES)()

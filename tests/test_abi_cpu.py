@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -53,3 +54,45 @@ def test_argument_errors_need_no_gpu(lib):
                                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                                            ctypes.c_void_p]
     assert lib.xrl_fmm_matvec(None, None, 1, 1, 1, None, 1, None, None) == -1
+
+
+def _reflection_signs(p):
+    """Sign of each real coefficient (index n^2 for m = 0, n^2 + 2m - 1 real
+    part, n^2 + 2m imaginary part) under x -> -x, y -> -y, z -> -z, from
+    R_n^m ~ P_n^m(cos theta) e^{i m phi}: phi -> pi - phi gives (-1)^m and a
+    conjugate, phi -> -phi a conjugate, cos theta -> -cos theta (-1)^(n+m)."""
+    K = (p + 1) ** 2
+    s = np.ones((3, K))
+    for n in range(p + 1):
+        for m in range(n + 1):
+            for part in ((0,) if m == 0 else (0, 1)):
+                k = n * n if m == 0 else n * n + 2 * m - 1 + part
+                conj = -1.0 if part == 1 else 1.0
+                s[0, k] = (-1.0) ** m * conj
+                s[1, k] = conj
+                s[2, k] = (-1.0) ** (n + m)
+    return s
+
+
+def test_m2l_operator_reflections(lib):
+    """The target-stationary M2L streams only the operators of non-negative
+    offsets and applies T_o = S T_|o| S for the reflected ones."""
+    p = 8
+    K = (p + 1) ** 2
+    lib.xrl_m2l_operator.argtypes = [ctypes.c_int32] * 4 + [ctypes.c_void_p]
+
+    def op(o):
+        out = np.zeros((K, K))
+        assert lib.xrl_m2l_operator(p, o[0], o[1], o[2], out.ctypes.data) == 0
+        return out
+
+    S = _reflection_signs(p)
+    for base in [(2, 0, 0), (3, 1, 2), (2, 2, 3), (0, 3, 1), (1, 0, 2)]:
+        T0 = op(base)
+        for r in range(1, 8):
+            o = tuple(-c if r >> a & 1 else c for a, c in enumerate(base))
+            s = np.prod([S[a] for a in range(3) if r >> a & 1], axis=0)
+            assert np.allclose(op(o), s[:, None] * T0 * s[None, :], rtol=1e-12, atol=1e-12 * np.abs(T0).max())
+    # the reflection really changes the operator (the test is not vacuous)
+    assert not np.allclose(op((3, 1, 2)), op((-3, 1, 2)))
+    assert lib.xrl_m2l_operator(p, 1, 1, 0, np.zeros((K, K)).ctypes.data) != 0

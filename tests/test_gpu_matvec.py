@@ -98,6 +98,8 @@ def _run(V, T, x, precision, order=8, max_leaf=64, engine="auto", r_near=2.0):
     ("mixed", "auto", np.complex64, 5e-5),
     ("fp32", "auto", np.complex64, 5e-5),
     ("mixed", "valu", np.complex64, 5e-5),
+    ("mixed", "mfma_ts", np.complex64, 5e-5),
+    ("fp64", "mfma_ts", np.complex128, 2e-5),
 ])
 def test_bar_matvec_matches_oracle(precision, engine, dtype, tol):
     say("case: bar 4096, %s/%s" % (precision, engine))
@@ -113,12 +115,47 @@ def test_bar_matvec_matches_oracle(precision, engine, dtype, tol):
     assert err.max() <= tol
 
 
-def test_adaptive_tree_matvec_matches_oracle():
-    say("case: bar + sphere adaptive, fp64, max_leaf 16")
+def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
+    """18 complex columns (36 real: three 16-column tiles, the last one
+    partial) through the target-stationary translations, against the oracle
+    and against the offset-stationary kernels on the same plan."""
+    say("case: bar 4096, 18 columns, mixed, target- vs offset-stationary")
+    V, T = I.bar()
+    N = len(T)
+    x = I.densities(N, 18, np.complex64)
+    tree = xrl.Tree(V, T)
+    ys = {}
+    for eng in ("mfma", "mfma_os", "refl", "lean"):
+        plan = xrl.Plan(tree, order=8, precision="mixed", engine="mfma" if eng in ("refl", "lean") else eng,
+                        max_cols=18)
+        plan.assemble()
+        if eng == "refl":  # the reflected 64-operator table
+            plan.set_tuning("ts_kernel", 1)
+        if eng == "lean":  # two waves per SIMD, no explicit pipeline
+            plan.set_tuning("ts_kernel", 2)
+        ys[eng] = plan.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+        plan.close()
+    rows = sample_rows(N, 256)
+    ref, _ = O.matvec(V, T, x.astype(np.complex128), rows=rows)
+    err = relerr_cols(ys["mfma"][rows], ref)
+    say("  rel L2 per column (target-stationary)", err.max())
+    assert err.max() <= 5e-5
+    d = np.linalg.norm(ys["mfma"] - ys["mfma_os"], axis=0) / np.linalg.norm(ys["mfma_os"], axis=0)
+    say("  target- vs offset-stationary", d.max())
+    assert d.max() < 1e-6
+    for v in ("refl", "lean"):
+        d = np.linalg.norm(ys["mfma"] - ys[v], axis=0) / np.linalg.norm(ys[v], axis=0)
+        say("  kernel form %s vs default" % v, d.max())
+        assert d.max() < 1e-6
+
+
+@pytest.mark.parametrize("engine", ["auto", "mfma_ts"])
+def test_adaptive_tree_matvec_matches_oracle(engine):
+    say("case: bar + sphere adaptive, fp64, max_leaf 16, %s" % engine)
     V, T = bar_mixed_sphere()
     N = len(T)
     x = I.densities(N, 2)
-    plan, y, _ = _run(V, T, x, "fp64", max_leaf=16)
+    plan, y, _ = _run(V, T, x, "fp64", max_leaf=16, engine=engine)
     ref, _ = O.matvec(V, T, x)
     err = relerr_cols(y, ref)
     say("  rel L2 per column", err)
@@ -222,3 +259,56 @@ def test_gmres_recovers_known_solution():
     # forced non-convergence is reported, not raised
     x1, st1 = plan.gmres(b, alpha=alpha, beta=beta, restart=5, rtol=1e-12, max_iter=1)
     assert st1["status"] == -5 and st1["iterations"] == 1
+
+
+def test_graph_replay_matches_eager_every_time():
+    """Graph mode: the captured matvec is replayed several times with eager
+    work and synchronisations in between; every replay equals the eager
+    result bit for bit, also with a changed epilogue and a new argument set."""
+    say("case: graph replay, bar 4096, mixed, 3 columns")
+    V, T = I.bar()
+    N = len(T)
+    x = torch.from_numpy(I.densities(N, 3, np.complex64)).cuda()
+    tree = xrl.Tree(V, T)
+    plan = xrl.Plan(tree, order=8, precision="mixed", max_cols=3)
+    plan.assemble()
+    y_eager = plan.matvec(x)
+    y_ep = plan.matvec(x, alpha=[1 + 2j, 0.5, -1j], beta=0.25)
+    torch.cuda.synchronize()
+    plan.set_graph(True)
+    y = torch.empty_like(x)
+    for rep in range(4):
+        plan.matvec(x, y)
+        z = (x * 3).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(y, y_eager), rep
+        assert torch.isfinite(z.real)
+    y.zero_()
+    for rep in range(3):
+        plan.matvec(x, y, alpha=[1 + 2j, 0.5, -1j], beta=0.25)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y_ep), rep
+    y2 = torch.empty_like(x)  # new argument set: recaptured
+    for rep in range(2):
+        plan.matvec(x, y2)
+        torch.cuda.synchronize()
+        assert torch.equal(y2, y_eager), rep
+
+
+def test_autotune_keeps_the_fastest_form_and_the_result():
+    say("case: autotune, bar 4096, mixed, 18 columns")
+    V, T = I.bar()
+    N = len(T)
+    x = torch.from_numpy(I.densities(N, 18, np.complex64)).cuda()
+    tree = xrl.Tree(V, T)
+    plan = xrl.Plan(tree, order=8, precision="mixed", max_cols=18)
+    plan.assemble()
+    y0 = plan.matvec(x)
+    r = plan.autotune(x, reps=2)
+    say("  tried", r["tried"], "best", r["best"])
+    assert len(r["tried"]) == 4
+    assert r["best"][2] == min(t[2] for t in r["tried"])
+    y1 = plan.matvec(x)
+    torch.cuda.synchronize()
+    d = (torch.linalg.norm(y1 - y0, dim=0) / torch.linalg.norm(y0, dim=0)).max().item()
+    assert d < 1e-6
