@@ -63,9 +63,9 @@ typedef int32_t xrl_status;
 
 /* Translation engine (M2L, and M2M/L2L with it). */
 #define XRL_M2L_AUTO 0    /* MFMA for FP64 and MIXED, vector ALU for FP32 */
-#define XRL_M2L_MFMA 1    /* MFMA; the kernel shape follows the column count of each
-                             call: offset-stationary below 16 real columns,
-                             target-stationary from 16 on                              */
+#define XRL_M2L_MFMA 1    /* MFMA; M2M and L2L target-stationary; M2L follows the
+                             column count of each call: offset-stationary below 16
+                             real columns, target-stationary from 16 on               */
 #define XRL_M2L_VALU 2    /* vector ALU, offset-stationary                             */
 #define XRL_M2L_MFMA_OS 3 /* MFMA, always offset-stationary (pairs that share an
                              operator batched into one GEMM, per-target reduction)    */

@@ -438,24 +438,22 @@ __global__ __launch_bounds__(256) void k_m2l_os_valu(const int32_t *__restrict__
 // values, so the WT tiles of one wave cover whole cache lines) and the
 // operator is streamed one 16-row tile of fragments at a time.
 //
-// Launch: 256 threads, 4 items per workgroup.  Workgroups are dealt to the
-// eight XCDs in turn, so block b is remapped to make every XCD walk one
-// contiguous range of targets (neighbouring targets share most sources,
-// which then hit in that XCD's L2).
-__device__ inline int xcd_contiguous_block(int b, int nb)
-{
-    const int full = nb >> 3, rem = nb & 7, x = b & 7, q = b >> 3;
-    return (x < rem ? x * (full + 1) : rem * (full + 1) + (x - rem) * full) + q;
-}
+// Launch: one wave (64 threads) per workgroup, in target order, so that a
+// SIMD whose target has few pairs takes the next item at once instead of
+// idling until the longest target of a larger workgroup is done.  (Giving
+// each XCD one contiguous range of targets, for L2 locality, was measured
+// slower: the pair counts of spatial regions differ, and the XCD with the
+// densest range finishes last.)
 
 // Widest item (column tiles) whose accumulators, double-buffered B
-// fragments and two operator halves stay within about 480 registers.
+// fragments and the two operator ring buffers stay within about 480
+// registers.
 template <typename T, int ORD>
 constexpr int ts_max_tiles()
 {
     using D = M2LDims<ORD>;
     constexpr int r = sizeof(T) / 4, vec = 16 / sizeof(T);
-    constexpr int a = 2 * ((D::NRT + 1) / 2) * ((D::NKS + vec - 1) / vec) * vec;
+    constexpr int a = 2 * ((D::NRT + 2) / 3) * ((D::NKS + vec - 1) / vec) * vec;
     int w = 4;
     while (w > 1 && (D::NRT * 4 * w + 2 * D::NKS * w + a) * r > 480) --w;
     return w;
@@ -492,7 +490,7 @@ __device__ inline T flip_sign(T v, uint32_t bit)
 // the signs of the B fragments (columns) and of the A fragments (rows), so
 // only 64 operators (L2-resident) are streamed instead of 316.
 template <typename T, int ORD, int WT, bool REFL>
-__global__ __launch_bounds__(256) void k_trans_ts(int n_items, int items_per_tgt, const int32_t *__restrict__ red_tgt,
+__global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt, const int32_t *__restrict__ red_tgt,
                                                   const int32_t *__restrict__ red_ptr,
                                                   const int32_t *__restrict__ ts_src,
                                                   const int32_t *__restrict__ ts_op, const T *__restrict__ op_vec,
@@ -506,7 +504,7 @@ __global__ __launch_bounds__(256) void k_trans_ts(int n_items, int items_per_tgt
     using AV = T __attribute__((ext_vector_type(VEC)));
     // wave-uniform values are made explicit so that list entries come in
     // through scalar loads
-    const int w = __builtin_amdgcn_readfirstlane(xcd_contiguous_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
+    const int w = blockIdx.x;
     if (w >= n_items) return;
     const int lane = threadIdx.x & 63, li = lane & 15, kq = lane >> 4;
     const int ti = w / items_per_tgt;
@@ -566,12 +564,15 @@ __global__ __launch_bounds__(256) void k_trans_ts(int n_items, int items_per_tgt
 #pragma unroll
                 for (int e = 0; e < 4; ++e) acc[rt][ct][e] = flip_sign(acc[rt][ct][e], (uint32_t)(m >> (4 * rt + e)) & 1u);
     };
-    // Software pipeline over the pairs: the operator is held in two halves
-    // of row tiles; while the MFMAs of one half run, the next pair's B
-    // fragments and operator half are in flight (loads complete in issue
-    // order, so each wait covers only what the next step needs).
-    constexpr int H0 = (D::NRT + 1) / 2, H1 = D::NRT - H0;
-    AV a0[H0][NKV], a1[H0][NKV];
+    // Software pipeline over (pair, row-tile group) steps: the operator of a
+    // pair is streamed in three groups of row tiles through a ring of two
+    // register buffers, each group's loads issued two steps before its
+    // MFMAs; the next pair's B fragments are issued at the first group of
+    // the current pair.  Loads complete in issue order, so each wait covers
+    // only what the next step needs, and the ring keeps the registers low
+    // enough that the accumulators never leave their registers.
+    constexpr int GR = (D::NRT + 2) / 3;  // row tiles per group
+    AV r0[GR][NKV], r1[GR][NKV];
     T bc[WT][D::NKS], bn[WT][D::NKS];
     auto load_b = [&](int j, T (&dst)[WT][D::NKS]) {
         const T *Ms = in + (int64_t)ts_src[j] * D::K * C;
@@ -583,13 +584,13 @@ __global__ __launch_bounds__(256) void k_trans_ts(int n_items, int items_per_tgt
             for (int ct = 0; ct < WT; ++ct) dst[ct][ks] = v.v[ct];
         }
     };
-    auto load_a = [&](int code, int rt0, int nrt, AV (&dst)[H0][NKV]) {
+    auto load_g = [&](int code, int g, AV (&dst)[GR][NKV]) {
         const AV *Tv = reinterpret_cast<const AV *>(op_vec) + (int64_t)(code >> 3) * D::NRT * NKV * 64 + lane;
 #pragma unroll
-        for (int r = 0; r < H0; ++r)
-            if (r < nrt)
+        for (int r = 0; r < GR; ++r)
+            if (g * GR + r < D::NRT)
 #pragma unroll
-                for (int kv = 0; kv < NKV; ++kv) dst[r][kv] = Tv[((rt0 + r) * NKV + kv) * 64];
+                for (int kv = 0; kv < NKV; ++kv) dst[r][kv] = Tv[((g * GR + r) * NKV + kv) * 64];
     };
     auto take_b = [&](int code) {
         const uint64_t cm = REFL ? mask_of(col, code & 7) : 0;
@@ -599,47 +600,72 @@ __global__ __launch_bounds__(256) void k_trans_ts(int n_items, int items_per_tgt
             for (int ct = 0; ct < WT; ++ct)
                 bc[ct][ks] = REFL ? flip_sign(bn[ct][ks], (uint32_t)(cm >> ks) & 1u) : bn[ct][ks];
     };
-    auto compute = [&](int rt0, int nrt, AV (&av)[H0][NKV]) {
+    auto compute = [&](int g, AV (&av)[GR][NKV]) {
 #pragma unroll
-        for (int r = 0; r < H0; ++r) {
-            if (r >= nrt) break;
+        for (int r = 0; r < GR; ++r) {
+            if (g * GR + r >= D::NRT) break;
 #pragma unroll
             for (int ks = 0; ks < D::NKS; ++ks)
 #pragma unroll
                 for (int ct = 0; ct < WT; ++ct)
-                    mfma_16x16x4<T>(av[r][ks / VEC][ks % VEC], bc[ct][ks], acc[rt0 + r][ct]);
+                    mfma_16x16x4<T>(av[r][ks / VEC][ks % VEC], bc[ct][ks], acc[g * GR + r][ct]);
         }
     };
     if (j0 < j1) {
-        int code = ts_op[j0], frame = 0;
+        auto clampj = [&](int j) { return j < j1 ? j : j1 - 1; };
+        int frame = 0;
+        int c0 = ts_op[j0], c1 = ts_op[clampj(j0 + 1)];
         load_b(j0, bn);
-        load_a(code, 0, H0, a0);
-        load_a(code, H0, H1, a1);
-        take_b(code);
-        // the scheduling barriers keep each group of loads where it is
-        // issued here (the scheduler would otherwise sink them next to their
-        // uses and expose their latency)
-        for (int j = j0; j < j1; ++j) {
+        load_g(c0, 0, r0);
+        load_g(c0, 1, r1);
+        take_b(c0);
+        auto reframe = [&](int code) {
             if constexpr (REFL) {
                 if ((code & 7) != frame) {
                     flip_acc((code & 7) ^ frame);
                     frame = code & 7;
                 }
             }
-            const int jn = min(j + 1, j1 - 1);  // the last prefetch repeats the last pair (unused)
-            const int ncode = ts_op[jn];
+        };
+        // two pairs per trip, so that the ring parity is static
+        for (int j = j0; j < j1; j += 2) {
+            const int c2 = ts_op[clampj(j + 2)];
+            reframe(c0);
             __builtin_amdgcn_sched_barrier(0);
-            compute(0, H0, a0);
+            compute(0, r0);
             __builtin_amdgcn_sched_barrier(0);
-            load_b(jn, bn);
-            load_a(ncode, 0, H0, a0);
+            load_b(clampj(j + 1), bn);
+            load_g(c0, 2, r0);
             __builtin_amdgcn_sched_barrier(0);
-            compute(H0, H1, a1);
+            compute(1, r1);
             __builtin_amdgcn_sched_barrier(0);
-            load_a(ncode, H0, H1, a1);
+            load_g(c1, 0, r1);
             __builtin_amdgcn_sched_barrier(0);
-            code = ncode;
-            take_b(code);
+            compute(2, r0);
+            __builtin_amdgcn_sched_barrier(0);
+            load_g(c1, 1, r0);
+            __builtin_amdgcn_sched_barrier(0);
+            take_b(c1);
+            if (j + 1 < j1) {
+                reframe(c1);
+                __builtin_amdgcn_sched_barrier(0);
+                compute(0, r1);
+                __builtin_amdgcn_sched_barrier(0);
+                load_b(clampj(j + 2), bn);
+                load_g(c1, 2, r1);
+                __builtin_amdgcn_sched_barrier(0);
+                compute(1, r0);
+                __builtin_amdgcn_sched_barrier(0);
+                load_g(c2, 0, r0);
+                __builtin_amdgcn_sched_barrier(0);
+                compute(2, r1);
+                __builtin_amdgcn_sched_barrier(0);
+                load_g(c2, 1, r1);
+                __builtin_amdgcn_sched_barrier(0);
+                take_b(c2);
+            }
+            c0 = c2;
+            c1 = ts_op[clampj(j + 3)];
         }
         if constexpr (REFL)
             if (frame) flip_acc(frame);
@@ -664,7 +690,7 @@ __global__ __launch_bounds__(256) void k_trans_ts(int n_items, int items_per_tgt
 // no software pipeline, one operator row tile ahead, registers capped for
 // two waves per SIMD so that the other wave covers each wait.
 template <typename T, int ORD, int WT>
-__global__ __launch_bounds__(256, 2) void k_trans_ts_lean(int n_items, int items_per_tgt,
+__global__ __launch_bounds__(64, 2) void k_trans_ts_lean(int n_items, int items_per_tgt,
                                                           const int32_t *__restrict__ red_tgt,
                                                           const int32_t *__restrict__ red_ptr,
                                                           const int32_t *__restrict__ ts_src,
@@ -680,7 +706,7 @@ __global__ __launch_bounds__(256, 2) void k_trans_ts_lean(int n_items, int items
     struct BV {
         T v[WT];
     };
-    const int w = __builtin_amdgcn_readfirstlane(xcd_contiguous_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
+    const int w = blockIdx.x;
     if (w >= n_items) return;
     const int lane = threadIdx.x & 63, li = lane & 15, kq = lane >> 4;
     const int ti = w / items_per_tgt;
@@ -810,7 +836,9 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
     using D = M2LDims<ORD>;
     if (TP.n_pairs == 0) return;
     const int eng = P->m2l_engine;
-    if (eng == XRL_M2L_MFMA_TS || (eng == XRL_M2L_MFMA && C >= P->ts_min_cols)) {
+    // MFMA: M2M and L2L (few pairs per target) always target-stationary;
+    // M2L target-stationary from ts_min_cols real columns on
+    if (eng == XRL_M2L_MFMA_TS || (eng == XRL_M2L_MFMA && (!refl || C >= P->ts_min_cols))) {
         // tiles per wave: the widest (up to the register budget) that wastes
         // the fewest padded tiles
         const int ntiles = (int)cdiv(C, 16);
@@ -821,23 +849,23 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
         const int ipt = (int)cdiv(ntiles, WT);
         const int64_t n_items = TP.n_red * ipt;
         XRL_CHECK(n_items < (int64_t(1) << 31), XRL_E_UNSUPPORTED, "xrl_fmm_matvec: too many translation items");
-        const unsigned nb = (unsigned)cdiv(n_items, 4);
+        const unsigned nb = (unsigned)n_items;
         auto go = [&](auto wt) {
             constexpr int W = decltype(wt)::value;
             if (refl && P->ts_kernel == 1)
-                k_trans_ts<T, ORD, W, true><<<nb, 256, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                k_trans_ts<T, ORD, W, true><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
                                                                TP.ts_src.p, TP.ts_op.p, op_vec, in, C, accumulate,
                                                                out);
             else if (refl && P->ts_kernel == 2)
-                k_trans_ts_lean<T, ORD, W><<<nb, 256, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                k_trans_ts_lean<T, ORD, W><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
                                                               TP.ts_src.p, TP.ts_op_full.p, op_full, in, C,
                                                               accumulate, out);
             else if (refl)
-                k_trans_ts<T, ORD, W, false><<<nb, 256, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                k_trans_ts<T, ORD, W, false><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
                                                                 TP.ts_src.p, TP.ts_op_full.p, op_full, in, C,
                                                                 accumulate, out);
             else
-                k_trans_ts<T, ORD, W, false><<<nb, 256, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                k_trans_ts<T, ORD, W, false><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
                                                                 TP.ts_src.p, TP.ts_op.p, op_vec, in, C, accumulate,
                                                                 out);
         };
