@@ -241,6 +241,11 @@ struct xrl_plan {
     // is one of these under coordinate reflections), M2M and L2L (8 each).
     xrl::DevBuf<double> op_m2lc64v, op_m2m64v, op_l2l64v, op_m2l64v;
     xrl::DevBuf<float> op_m2lc32v, op_m2m32v, op_l2l32v, op_m2l32v;
+    // last operator row (K - 1) of the same operators, [op][k % 4][k / 4]
+    // (padded to the vector length), for orders with K = 16 n + 1 whose last
+    // row is applied on the vector ALU instead of a 16-row MFMA tile
+    xrl::DevBuf<double> op_m2m64t, op_l2l64t, op_m2l64t;
+    xrl::DevBuf<float> op_m2m32t, op_l2l32t, op_m2l32t;
     // form of the target-stationary M2L (XRL_TUNE_TS_KERNEL)
     int ts_kernel = 0;
     int ts_min_cols = 16;  // MFMA engine: target-stationary from this many real columns on

@@ -494,16 +494,21 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
                                                   const int32_t *__restrict__ red_ptr,
                                                   const int32_t *__restrict__ ts_src,
                                                   const int32_t *__restrict__ ts_op, const T *__restrict__ op_vec,
-                                                  const T *__restrict__ in, int C, int accumulate,
-                                                  T *__restrict__ out)
+                                                  const T *__restrict__ op_tail, const T *__restrict__ in, int C,
+                                                  int accumulate, T *__restrict__ out)
 {
     using D = M2LDims<ORD>;
     using VT = typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type;
     constexpr int VEC = 16 / sizeof(T);
     constexpr int NKV = (D::NKS + VEC - 1) / VEC;
     using AV = T __attribute__((ext_vector_type(VEC)));
-    // wave-uniform values are made explicit so that list entries come in
-    // through scalar loads
+    // K = 16 n + 1 (orders 6 and 8): the last operator row is applied on the
+    // vector ALU from the B fragments already in registers (21 FMAs per
+    // column tile and pair), instead of a 16-row MFMA tile that is 15/16
+    // padding; the four k-subsets of a column are summed across lanes once
+    // per target
+    constexpr bool TAIL = !REFL && D::K % 16 == 1;
+    constexpr int NRTM = TAIL ? D::K / 16 : D::NRT;  // row tiles on MFMA
     const int w = blockIdx.x;
     if (w >= n_items) return;
     const int lane = threadIdx.x & 63, li = lane & 15, kq = lane >> 4;
@@ -521,11 +526,14 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
     struct BV {
         T v[WT];
     };
-    VT acc[D::NRT][WT];
+    VT acc[NRTM][WT];
 #pragma unroll
-    for (int rt = 0; rt < D::NRT; ++rt)
+    for (int rt = 0; rt < NRTM; ++rt)
 #pragma unroll
         for (int ct = 0; ct < WT; ++ct) acc[rt][ct] = VT{0, 0, 0, 0};
+    T tacc[WT];
+#pragma unroll
+    for (int ct = 0; ct < WT; ++ct) tacc[ct] = T(0);
     // Reflection sign masks of this lane, per axis a: bit ks of col[a] for
     // the coefficient 4 ks + kq it feeds as B, bit 4 rt + e of acm[a] for the
     // accumulator element (rt, e), whose row is 16 rt + mfma_row(kq, e).
@@ -558,7 +566,7 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
     auto flip_acc = [&](int d) {
         const uint64_t m = mask_of(acm, d);
 #pragma unroll
-        for (int rt = 0; rt < D::NRT; ++rt)
+        for (int rt = 0; rt < NRTM; ++rt)
 #pragma unroll
             for (int ct = 0; ct < WT; ++ct)
 #pragma unroll
@@ -571,9 +579,25 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
     // the current pair.  Loads complete in issue order, so each wait covers
     // only what the next step needs, and the ring keeps the registers low
     // enough that the accumulators never leave their registers.
-    constexpr int GR = (D::NRT + 2) / 3;  // row tiles per group
+    constexpr int GR = (NRTM + 2) / 3;  // row tiles per group
     AV r0[GR][NKV], r1[GR][NKV];
     T bc[WT][D::NKS], bn[WT][D::NKS];
+    AV tn[TAIL ? NKV : 1], tcv[TAIL ? NKV : 1];
+    auto load_t = [&](int code) {
+        if constexpr (TAIL) {
+            const AV *tp = reinterpret_cast<const AV *>(op_tail + ((int64_t)(code >> 3) * 4 + kq) * NKV * VEC);
+#pragma unroll
+            for (int kv = 0; kv < NKV; ++kv) tn[kv] = tp[kv];
+        }
+    };
+    auto tail_fma = [&]() {
+        if constexpr (TAIL) {
+#pragma unroll
+            for (int ks = 0; ks < D::NKS; ++ks)
+#pragma unroll
+                for (int ct = 0; ct < WT; ++ct) tacc[ct] += tcv[ks / VEC][ks % VEC] * bc[ct][ks];
+        }
+    };
     auto load_b = [&](int j, T (&dst)[WT][D::NKS]) {
         const T *Ms = in + (int64_t)ts_src[j] * D::K * C;
 #pragma unroll
@@ -588,7 +612,7 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
         const AV *Tv = reinterpret_cast<const AV *>(op_vec) + (int64_t)(code >> 3) * D::NRT * NKV * 64 + lane;
 #pragma unroll
         for (int r = 0; r < GR; ++r)
-            if (g * GR + r < D::NRT)
+            if (g * GR + r < NRTM)
 #pragma unroll
                 for (int kv = 0; kv < NKV; ++kv) dst[r][kv] = Tv[((g * GR + r) * NKV + kv) * 64];
     };
@@ -599,11 +623,14 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
 #pragma unroll
             for (int ct = 0; ct < WT; ++ct)
                 bc[ct][ks] = REFL ? flip_sign(bn[ct][ks], (uint32_t)(cm >> ks) & 1u) : bn[ct][ks];
+        if constexpr (TAIL)
+#pragma unroll
+            for (int kv = 0; kv < NKV; ++kv) tcv[kv] = tn[kv];
     };
     auto compute = [&](int g, AV (&av)[GR][NKV]) {
 #pragma unroll
         for (int r = 0; r < GR; ++r) {
-            if (g * GR + r >= D::NRT) break;
+            if (g * GR + r >= NRTM) break;
 #pragma unroll
             for (int ks = 0; ks < D::NKS; ++ks)
 #pragma unroll
@@ -616,6 +643,7 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
         int frame = 0;
         int c0 = ts_op[j0], c1 = ts_op[clampj(j0 + 1)];
         load_b(j0, bn);
+        load_t(c0);
         load_g(c0, 0, r0);
         load_g(c0, 1, r1);
         take_b(c0);
@@ -633,8 +661,10 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
             reframe(c0);
             __builtin_amdgcn_sched_barrier(0);
             compute(0, r0);
+            tail_fma();
             __builtin_amdgcn_sched_barrier(0);
             load_b(clampj(j + 1), bn);
+            load_t(c1);
             load_g(c0, 2, r0);
             __builtin_amdgcn_sched_barrier(0);
             compute(1, r1);
@@ -650,8 +680,10 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
                 reframe(c1);
                 __builtin_amdgcn_sched_barrier(0);
                 compute(0, r1);
+                tail_fma();
                 __builtin_amdgcn_sched_barrier(0);
                 load_b(clampj(j + 2), bn);
+                load_t(c2);
                 load_g(c1, 2, r1);
                 __builtin_amdgcn_sched_barrier(0);
                 compute(1, r0);
@@ -671,7 +703,7 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
             if (frame) flip_acc(frame);
     }
 #pragma unroll
-    for (int rt = 0; rt < D::NRT; ++rt)
+    for (int rt = 0; rt < NRTM; ++rt)
 #pragma unroll
         for (int ct = 0; ct < WT; ++ct) {
             const int col = cb + WT * li + ct;
@@ -684,6 +716,19 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
                 *o = accumulate ? *o + acc[rt][ct][e] : acc[rt][ct][e];
             }
         }
+    if constexpr (TAIL) {
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) {
+            T v = tacc[ct];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            const int col = cb + WT * li + ct;
+            if (kq == 0 && col < C) {
+                T *o = out + ((int64_t)t * D::K + D::K - 1) * C + col;
+                *o = accumulate ? *o + v : v;
+            }
+        }
+    }
 }
 
 // Lean form of the target-stationary kernel for the full operator table:
@@ -830,8 +875,8 @@ static const int32_t *pass_items(const TransPass &T, bool mfma, int Cc, int *n_i
 // order); refl: its codes carry reflection bits (M2L) or not (M2M, L2L).
 template <typename T, int ORD>
 static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag, const T *op_k, const T *op_vec,
-                        bool refl, const T *in, T *out, int accumulate, DevBuf<T> &tmp, int C, hipStream_t s,
-                        const T *op_full = nullptr)
+                        const T *op_tail, bool refl, const T *in, T *out, int accumulate, DevBuf<T> &tmp, int C,
+                        hipStream_t s, const T *op_full = nullptr, const T *op_full_tail = nullptr)
 {
     using D = M2LDims<ORD>;
     if (TP.n_pairs == 0) return;
@@ -854,20 +899,20 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
             constexpr int W = decltype(wt)::value;
             if (refl && P->ts_kernel == 1)
                 k_trans_ts<T, ORD, W, true><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
-                                                               TP.ts_src.p, TP.ts_op.p, op_vec, in, C, accumulate,
-                                                               out);
+                                                              TP.ts_src.p, TP.ts_op.p, op_vec, nullptr, in, C,
+                                                              accumulate, out);
             else if (refl && P->ts_kernel == 2)
                 k_trans_ts_lean<T, ORD, W><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
                                                               TP.ts_src.p, TP.ts_op_full.p, op_full, in, C,
                                                               accumulate, out);
             else if (refl)
                 k_trans_ts<T, ORD, W, false><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
-                                                                TP.ts_src.p, TP.ts_op_full.p, op_full, in, C,
-                                                                accumulate, out);
+                                                               TP.ts_src.p, TP.ts_op_full.p, op_full, op_full_tail, in,
+                                                               C, accumulate, out);
             else
                 k_trans_ts<T, ORD, W, false><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
-                                                                TP.ts_src.p, TP.ts_op.p, op_vec, in, C, accumulate,
-                                                                out);
+                                                               TP.ts_src.p, TP.ts_op.p, op_vec, op_tail, in, C,
+                                                               accumulate, out);
         };
         if (WT == 1) go(std::integral_constant<int, 1>());
         if constexpr (ts_max_tiles<T, ORD>() >= 2)
@@ -961,6 +1006,7 @@ struct Ops {
     const T *near, *mom, *m2m_f, *m2m_k, *l2l_f, *l2l_k, *m2l_f, *m2l_k;
     const T *m2m_v, *l2l_v, *m2l_v;  // target-stationary operators (M2L: non-negative offsets)
     const T *m2l_full;               // target-stationary M2L operators of every offset
+    const T *m2m_t, *l2l_t, *m2l_full_t;  // their last rows (orders with K = 16 n + 1)
 };
 
 template <typename T, int ORD>
@@ -970,17 +1016,18 @@ static void translations(const xrl_plan *P, const Ops<T> &op, T *M, T *L, DevBuf
     using D = M2LDims<ORD>;
     mark(3);
     for (int l = P->depth - 1; l >= 0; --l)
-        pass_launch<T, ORD>(P, P->m2m[l], op.m2m_f, op.m2m_k, op.m2m_v, false, M, M, 0, tmp, C, s);
+        pass_launch<T, ORD>(P, P->m2m[l], op.m2m_f, op.m2m_k, op.m2m_v, op.m2m_t, false, M, M, 0, tmp, C, s);
     // zero every local expansion (a fill kernel, so the sequence stays
     // capturable into a HIP graph without memset nodes)
     const int64_t nL = P->B * (int64_t)D::K * C;
     k_fill_zero<T><<<(unsigned)std::min<int64_t>(cdiv(nL, 256), 65536), 256, 0, s>>>(L, nL);
     XRL_HIP(hipGetLastError());
     mark(4);
-    pass_launch<T, ORD>(P, P->m2l, op.m2l_f, op.m2l_k, op.m2l_v, true, M, L, 0, tmp, C, s, op.m2l_full);
+    pass_launch<T, ORD>(P, P->m2l, op.m2l_f, op.m2l_k, op.m2l_v, nullptr, true, M, L, 0, tmp, C, s, op.m2l_full,
+                        op.m2l_full_t);
     mark(5);
     for (int l = 3; l <= P->depth; ++l)
-        pass_launch<T, ORD>(P, P->l2l[l], op.l2l_f, op.l2l_k, op.l2l_v, false, L, L, 1, tmp, C, s);
+        pass_launch<T, ORD>(P, P->l2l[l], op.l2l_f, op.l2l_k, op.l2l_v, op.l2l_t, false, L, L, 1, tmp, C, s);
     mark(6);
 }
 
@@ -1100,13 +1147,13 @@ static void enqueue_matvec(const xrl_plan *P, const void *x, int64_t ldx, int n_
     if (P->precision == XRL_PREC_FP64) {
         Ops<double> op{P->near64.p, P->mom64.p, P->op_m2m64f.p, P->op_m2m64k.p, P->op_l2l64f.p, P->op_l2l64k.p,
                        P->op_m2l64f.p, P->op_m2l64k.p, P->op_m2m64v.p, P->op_l2l64v.p, P->op_m2lc64v.p,
-                       P->op_m2l64v.p};
+                       P->op_m2l64v.p, P->op_m2m64t.p, P->op_l2l64t.p, P->op_m2l64t.p};
         run_matvec<double>(P, x, ldx, n_cols, dtype, y, ldy, ha, hb, s, Pm->xs64, Pm->ys64, Pm->M64, Pm->L64,
                            Pm->os_tmp64, op);
     } else {
         Ops<float> op{P->near32.p, P->mom32.p, P->op_m2m32f.p, P->op_m2m32k.p, P->op_l2l32f.p, P->op_l2l32k.p,
                       P->op_m2l32f.p, P->op_m2l32k.p, P->op_m2m32v.p, P->op_l2l32v.p, P->op_m2lc32v.p,
-                      P->op_m2l32v.p};
+                      P->op_m2l32v.p, P->op_m2m32t.p, P->op_l2l32t.p, P->op_m2l32t.p};
         run_matvec<float>(P, x, ldx, n_cols, dtype, y, ldy, ha, hb, s, Pm->xs32, Pm->ys32, Pm->M32, Pm->L32,
                           Pm->os_tmp32, op);
     }

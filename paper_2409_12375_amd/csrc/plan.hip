@@ -700,9 +700,21 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     };
     // vector fragment order: element e of the 16-byte vector kv of a lane is
     // the A operand of k step VEC kv + e (zero past the last step)
-    auto vec_layouts = [&](const std::vector<double> &pad, int nop, DevBuf<double> &v64, DevBuf<float> &v32) {
+    auto vec_layouts = [&](const std::vector<double> &pad, int nop, DevBuf<double> &v64, DevBuf<float> &v32,
+                           DevBuf<double> *t64 = nullptr, DevBuf<float> *t32 = nullptr) {
         for (int vec : {2, 4}) {
             const int nkv = (nks + vec - 1) / vec;
+            if (t64) {
+                std::vector<double> t((size_t)nop * 4 * nkv * vec, 0.0);
+                for (int c = 0; c < nop; ++c)
+                    for (int kq = 0; kq < 4; ++kq)
+                        for (int ks = 0; ks < nks; ++ks)
+                            t[((size_t)c * 4 + kq) * nkv * vec + ks] = pad[((size_t)c * P->KP + K - 1) * P->KK + 4 * ks + kq];
+                if (vec == 2)
+                    t64->upload(t, s);
+                else
+                    t32->upload(to32(t), s);
+            }
             std::vector<double> v((size_t)nop * nrt * nkv * 64 * vec, 0.0);
             for (int c = 0; c < nop; ++c)
                 for (int rt = 0; rt < nrt; ++rt)
@@ -737,10 +749,10 @@ static void build_plan(xrl_plan *P, hipStream_t s)
                 for (int k = 0; k < K; ++k) m2lc[((size_t)c * P->KP + r) * P->KK + k] = tmp[(size_t)r * K + k];
         }
         vec_layouts(m2lc, 64, P->op_m2lc64v, P->op_m2lc32v);
-        vec_layouts(m2l, 343, P->op_m2l64v, P->op_m2l32v);
+        vec_layouts(m2l, 343, P->op_m2l64v, P->op_m2l32v, &P->op_m2l64t, &P->op_m2l32t);
     }
-    vec_layouts(padded(m2m, 8), 8, P->op_m2m64v, P->op_m2m32v);
-    vec_layouts(padded(l2l, 8), 8, P->op_l2l64v, P->op_l2l32v);
+    vec_layouts(padded(m2m, 8), 8, P->op_m2m64v, P->op_m2m32v, &P->op_m2m64t, &P->op_m2m32t);
+    vec_layouts(padded(l2l, 8), 8, P->op_l2l64v, P->op_l2l32v, &P->op_l2l64t, &P->op_l2l32t);
     layouts(padded(m2m, 8), 8, P->op_m2m64f, P->op_m2m32f, P->op_m2m64k, P->op_m2m32k);
     layouts(padded(l2l, 8), 8, P->op_l2l64f, P->op_l2l32f, P->op_l2l64k, P->op_l2l32k);
     P->op_m2m64.upload(m2m, s);
