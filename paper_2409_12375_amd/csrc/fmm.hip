@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_p2p(const int32_t *__restrict__ leaf_bo
 
 // Wide-column form (FP32, C > 16): one workgroup per (leaf, tile of up to
 // CT columns), so the value stream of a leaf is read once for every 48
-// columns.  A thread owns two consecutive targets of a row (one 8-byte
+// columns.  A thread owns VT consecutive targets of a row (one vector
 // load) and all CT columns; the row groups are summed through LDS in chunks
 // of RC columns, in a fixed order.
 template <int CT>
@@ -151,8 +151,7 @@ __global__ __launch_bounds__(256) void k_p2p_wide(const int32_t *__restrict__ le
                                                   const int64_t *__restrict__ val_off, const float *__restrict__ val,
                                                   const float *__restrict__ xs, float *__restrict__ ys, int C)
 {
-    constexpr int VT = 2, ROWS = 128, RC = 12;
-    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    constexpr int VT = 2, ROWS = 64, RC = 12;
     __shared__ __align__(16) float sx[ROWS * CT];
     __shared__ float red[256 * VT * RC];
     const int64_t li = blockIdx.x;
@@ -169,26 +168,50 @@ __global__ __launch_bounds__(256) void k_p2p_wide(const int32_t *__restrict__ le
     for (int v = 0; v < VT; ++v)
 #pragma unroll
         for (int c = 0; c < CT; ++c) acc[v][c] = 0.f;
+    // the source densities and the block values of the next chunk are
+    // fetched into registers while the current chunk is multiplied out, so
+    // every thread keeps a whole chunk of loads in flight
+    typedef float fv_t __attribute__((ext_vector_type(VT)));
+    constexpr int PER = ROWS * CT / 256;
+    constexpr int RMAX = ROWS * 64 / (256 * VT);  // rows per thread and chunk at the widest block (G = 64)
+    float xn[PER];
+    fv_t vn[RMAX], vc[RMAX];
+    auto fetch = [&](int rc) {
+        const int nrc = min(ROWS, nr - rc);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = threadIdx.x + 256 * q, r = i / CT, c = i - r * CT;
+            xn[q] = (r < nrc && c0 + c < C) ? xs[(int64_t)near_src[r0 + rc + r] * C + c0 + c] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q) {
+            const int r = grp + q * groups;
+            vn[q] = r < nrc ? *reinterpret_cast<const fv_t *>(vb + (int64_t)(rc + r) * G + jv) : fv_t(0.f);
+        }
+    };
+    if (nr > 0) fetch(0);
     for (int32_t rc = 0; rc < nr; rc += ROWS) {
         const int nrc = min(ROWS, nr - rc);
         __syncthreads();
-        for (int i = threadIdx.x; i < nrc * CT; i += 256) {
-            const int r = i / CT, c = i - r * CT;
-            sx[i] = (c0 + c < C) ? xs[(int64_t)near_src[r0 + rc + r] * C + c0 + c] : 0.f;
-        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) sx[threadIdx.x + 256 * q] = xn[q];
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q) vc[q] = vn[q];
         __syncthreads();
-#pragma unroll 2
-        for (int r = grp; r < nrc; r += groups) {
-            const f32x2 v = *reinterpret_cast<const f32x2 *>(vb + (int64_t)(rc + r) * G + jv);
+        if (rc + ROWS < nr) fetch(rc + ROWS);
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q) {
+            const int r = grp + q * groups;
+            if (r >= nrc) break;
+            const fv_t v = vc[q];
             const f32x4 *xr = reinterpret_cast<const f32x4 *>(sx + r * CT);
 #pragma unroll
             for (int c4 = 0; c4 < CT / 4; ++c4) {
                 const f32x4 xv = xr[c4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    acc[0][4 * c4 + e] += v[0] * xv[e];
-                    acc[1][4 * c4 + e] += v[1] * xv[e];
-                }
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int t = 0; t < VT; ++t) acc[t][4 * c4 + e] += v[t] * xv[e];
             }
         }
     }
@@ -972,14 +995,17 @@ static void p2p_launch(const xrl_plan *P, const T *val, const T *xs, T *ys, int 
                 k_p2p_wide<CT><<<grid, 256, 0, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p, P->near_rows.p,
                                                     P->near_src.p, P->leaf_tpad.p, P->near_val_off.p, val, xs, ys, C);
             };
-            if (C <= 24)
+            // the tile width (24, 32 or 36) with the least padding, the
+            // widest among equals
+            int ct = 24;
+            for (int w : {32, 36})
+                if (cdiv(C, w) * w <= cdiv(C, ct) * ct) ct = w;
+            if (ct == 24)
                 wide(std::integral_constant<int, 24>());
-            else if (C <= 32)
+            else if (ct == 32)
                 wide(std::integral_constant<int, 32>());
-            else if (C <= 36)
-                wide(std::integral_constant<int, 36>());
             else
-                wide(std::integral_constant<int, 48>());
+                wide(std::integral_constant<int, 36>());
             XRL_HIP(hipGetLastError());
             return;
         }
