@@ -1,22 +1,33 @@
 """Benchmark: panel-interactions/s of one FMM matvec y = P x on one MI355X.
 
-Workload (default, --workload coils): two 5-turn square planar coils (trace
-width 0.1, thickness 0.035, spacing 0.1, gap 0.5), ~200k flat triangle panels,
-three current components as complex64 densities N(0,1), single right-hand
-side, expansion order p = 8, leaves <= 64 panels, plain FP32 (M2L on the
-vector ALUs).  The mixed-precision variant (FP32 M2L on MFMA, FP64 singular
-integrals) and the surrogate + mixed variant (learned near-singular pairs)
-run on the same inputs and are reported beside it.
---workload bga: the ~1M-panel BGA-like package with 6 ports x 3 components
-= 18 complex columns, mixed precision as its own variant.
+Default workload (--workload bga): a BGA-like package, ~1.03M flat triangle
+panels (a 10x10 plane with 400 circular holes, 100 vias through the central
+holes and 100 solder-ball spheres), 6 ports x 3 current components = 18
+complex64 density columns N(0,1) carried together (batched right-hand sides),
+expansion order p = 8, leaves <= 64 panels.  Three variants run on the same
+inputs: mixed precision (the headline: FP32 M2L on MFMA with FP32
+accumulation, FP64 self and touching integrals), plain FP32 (every phase in
+FP32, M2L on the vector ALUs) and surrogate + mixed (learned near-singular
+pairs, quadrature fall-back).
+--workload coils: two 5-turn square planar coils, ~200k panels, 3 columns.
+--workload pop: a package-on-package-like stack, ~2.1M panels, 8 ports x 3
+components = 24 columns, surrogate + mixed as the headline.
+--workload batch: 32 independent meshes of uneven size (10k-500k panels,
+~4.3M in all) with 384 complex columns each (8 ports x 16 frequencies x 3
+components), one batched plan, kernel shapes autotuned, matvec replayed
+from a captured HIP graph.
 
 A step is one full matvec (gather, P2P, P2M, M2M, M2L, L2L, L2P, scatter)
 with the near field already assembled and x, y resident in HBM.
-panel-interactions per matvec = n_complex_columns * N^2.
+panel-interactions per matvec = n_complex_columns * sum over meshes of N^2.
+Per-phase device times come from HIP events that the library records on the
+matvec stream inside the timed steps.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -25,43 +36,81 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32 = 157.3e12      # FP32 vector / FP32 MFMA (dense), MI355X
+PEAK_FP32 = 157.3e12      # FP32 MFMA (dense) = FP32 vector with packed math, MI355X
 PEAK_FP64 = 78.6e12
 PEAK_HBM = 8.0e12
+K = (8 + 1) ** 2
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "m2l_bga_hbm_traffic.md")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_variant(xrl, torch, tree, x, precision, steps, warmup, order=8, surrogate=None, engine="auto"):
+def source_hash():
+    """Hash of the translation kernels' source: HBM traffic figures taken
+    with counters stay valid only while it is unchanged."""
+    return hashlib.sha256(open(os.path.join(ROOT, "paper_2409_12375_amd", "csrc", "fmm.hip"), "rb").read()).hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per M2L launch from the committed counter summary, or None
+    when it is missing or was taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    h = re.search(r"fmm\.hip sha256:\s*([0-9a-f]{64})", txt)
+    b = re.search(r"HBM bytes per launch \(calibrated\):\s*([0-9.eE+]+)", txt)
+    if not h or not b or h.group(1) != source_hash():
+        return None
+    return float(b.group(1))
+
+
+def run_variant(xrl, torch, trees, x, precision, steps, warmup, surrogate=None, engine="auto", graph=False,
+                autotune=False):
     n_cols = x.shape[1]
-    plan = xrl.Plan(tree, order=order, precision=precision, engine=engine, max_cols=n_cols)
+    plan = xrl.Plan(trees, order=8, precision=precision, engine=engine, max_cols=n_cols)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = plan.assemble(surrogate=surrogate, audit_every=100 if surrogate is not None else 0)
     t_asm = time.perf_counter() - t0
     y = torch.empty_like(x)
+    tune = plan.autotune(x, y, reps=1) if autotune else None
+    if graph:
+        plan.set_graph(True)
     for _ in range(warmup):
         plan.matvec(x, y)
     torch.cuda.synchronize()
-    # timed region: exactly `steps` matvecs, no profiling events inside
+    if not graph:
+        plan.set_profiling(True)  # events on the matvec stream, no host wait per step
+    # timed region: exactly `steps` matvecs
     t0 = time.perf_counter()
     for _ in range(steps):
         plan.matvec(x, y)
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / steps
-    # per-phase device times from HIP events on the matvec stream
-    plan.set_profiling(True)
-    ph = {k: [] for k in xrl.PHASES}
-    for _ in range(max(3, min(steps, 10))):
-        plan.matvec(x, y)
-        for k, v in plan.phase_ms().items():
-            ph[k].append(v)
+    if graph:  # graph replays carry no events: phases from eager profiled matvecs
+        plan.set_graph(False)
+        plan.set_profiling(True)
+        for _ in range(min(steps, 3)):
+            plan.matvec(x, y)
+    ph = plan.phase_ms()
     plan.set_profiling(False)
     torch.cuda.synchronize()
-    ph = {k: float(np.mean(v)) for k, v in ph.items()}
-    return plan, y, t, t_asm, st, ph
+    return plan, y, t, t_asm, st, ph, tune
+
+
+def copy_calibration(nbytes):
+    """A plain device-to-device copy of known size (three launches), for
+    scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "launches": 3}), flush=True)
 
 
 def main():
@@ -69,17 +118,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="coils", choices=["coils", "bga"])
+    ap.add_argument("--workload", default="bga", choices=["bga", "coils", "pop", "batch"])
     ap.add_argument("--n", type=int, default=200_000, help="target panel count of the coil mesh")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--variants", default=None, help="comma list of fp32, mixed, surrogate (first = headline); "
+    ap.add_argument("--variants", default=None, help="comma list of mixed, fp32, surrogate (first = headline); "
                     "name@engine overrides the translation engine (auto, mfma, valu, mfma_os, mfma_ts)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain copy of BYTES bytes (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the matvec would shard).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import torch
 
@@ -87,25 +141,46 @@ def main():
     from paper_2409_12375_amd import xrl
 
     torch.cuda.set_device(0)
+    graph = autotune = False
     if args.workload == "coils":
-        V, T = I.coils(args.n)
+        meshes = [I.coils(args.n)]
         n_c = 3
         variants = args.variants or "fp32,mixed,surrogate"
         desc = "two 5-turn square coils, %d triangle panels, 3 complex64 columns"
-    else:
-        V, T = I.bga()
+    elif args.workload == "bga":
+        meshes = [I.bga()]
         n_c = 18
         variants = args.variants or "mixed,fp32,surrogate"
         desc = "BGA-like package (10x10 plane, 400 holes, 100 vias, 100 balls), %d triangle panels, " \
                "18 complex64 columns (6 ports x 3 components)"
-    N = len(T)
-    xh = I.densities(N, n_c, np.complex64)
-    x = torch.from_numpy(xh).cuda()
-    log("%s: N=%d panels" % (args.workload, N))
-    tree = xrl.Tree(V, T, max_leaf=64)
+    elif args.workload == "pop":
+        meshes = [I.pop()]
+        n_c = 24
+        variants = args.variants or "surrogate,mixed,fp32"
+        desc = "package-on-package-like stack (two 12x12 planes 1.0 apart, 900 vias, 2 x 29 traces), " \
+               "%d triangle panels, 24 complex64 columns (8 ports x 3 components)"
+    else:
+        meshes = [(V, T) for _, V, T in I.batch_meshes()]
+        n_c = 384
+        variants = args.variants or "mixed"
+        graph = autotune = True
+        desc = "32 uneven meshes (bar/coil/plane, 10k-500k panels), %d triangle panels in all, " \
+               "384 complex64 columns per mesh (8 ports x 16 frequencies x 3 components), autotuned, HIP graph"
+    Ns = [len(T) for _, T in meshes]
+    N = sum(Ns)
+    pairs = float(sum(float(n) * n for n in Ns))
+    if args.workload == "batch":  # densities generated on the device (seeded)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(I.DENS_SEED)
+        x = torch.view_as_complex(torch.randn(N, n_c, 2, generator=g, device="cuda"))
+        xh = None
+    else:
+        xh = I.densities(N, n_c, np.complex64)
+        x = torch.from_numpy(xh).cuda()
+    log("%s: N=%d panels in %d mesh(es)" % (args.workload, N, len(meshes)))
+    trees = [xrl.Tree(V, T, max_leaf=64) for V, T in meshes]
     sur_path = os.path.join(ROOT, "tests", "golden", "surrogate_mlp.npz")
-    results = {}
-    ys = {}
+    results, ys = {}, {}
     for name in variants.split(","):
         base, _, engine = name.partition("@")
         prec = "mixed" if base == "surrogate" else base
@@ -115,17 +190,17 @@ def main():
                 log("no trained surrogate weights, skipping the surrogate variant")
                 continue
             sur = xrl.Surrogate.load(sur_path)
-        plan, y, t, t_asm, st, ph = run_variant(xrl, torch, tree, x, prec, args.steps, args.warmup, surrogate=sur,
-                                                    engine=engine or "auto")
+        plan, y, t, t_asm, st, ph, tune = run_variant(xrl, torch, trees, x, prec, args.steps, args.warmup,
+                                                      surrogate=sur, engine=engine or "auto", graph=graph,
+                                                      autotune=autotune)
         info = plan.info()
-        K = (8 + 1) ** 2
         C = 2 * n_c
         m2l_flops = 2.0 * K * K * C * info["n_m2l_pairs"]
         near_bytes = 4.0 * info["n_near_entries"] + 4.0 * info["n_near_rows"]
         results[name] = {
             "precision": prec, "ms_per_matvec": 1e3 * t, "assemble_s": t_asm,
-            "panel_interactions_per_s": n_c * float(N) * N / t,
-            "amortized_panel_interactions_per_s": n_c * float(N) * N / (t + t_asm / 36.0),
+            "panel_interactions_per_s": n_c * pairs / t,
+            "amortized_panel_interactions_per_s": n_c * pairs / (t + t_asm / 36.0),
             "phase_ms": ph, "n_m2l_pairs": info["n_m2l_pairs"], "n_near_entries": info["n_near_entries"],
             "n_boxes": info["n_boxes"], "n_leaves": info["n_leaves"], "max_sep_ratio": info["max_sep_ratio"],
             "n_demoted_pairs": info["n_demoted_pairs"],
@@ -135,49 +210,88 @@ def main():
                                              "n_mlp_accepted", "n_mlp_fallback", "audit_max_rel_err",
                                              "audit_rms_rel_err", "ms")},
         }
-        ys[name] = y.cpu().numpy()
+        if tune is not None:
+            results[name]["autotune"] = tune
+        if args.workload == "batch":
+            ys[name] = y  # stays on the device; sampled below
+        else:
+            ys[name] = y.cpu().numpy()
         plan.close()
         log(name, json.dumps(results[name]))
 
     main_v = variants.split(",")[0]
     R = results[main_v]
-    # dominant phase and its roofline
+    # dominant phase and the roofline of its kernel (algorithmic work per
+    # launch over the launch's event-timed duration)
     dom = max(R["phase_ms"], key=R["phase_ms"].get)
-    bound, achieved, peak, unit = "alu", R["m2l_tflops"], PEAK_FP32 / 1e12, "TFLOP/s"
     if dom == "p2p":
-        bound, achieved, peak, unit = "hbm", R["p2p_gbps"], PEAK_HBM / 1e9, "GB/s"
-    elif results[main_v]["precision"] == "mixed":
-        bound = "mfma"
-    roof = {"bound": bound, "kernel": "m2l" if dom != "p2p" else "p2p", "achieved": achieved, "peak": peak,
-            "unit": unit, "frac": achieved / peak, "traffic": None}
+        roof = {"bound": "hbm", "kernel": "P2P (near-field block apply)", "achieved": R["p2p_gbps"],
+                "peak": PEAK_HBM / 1e9, "unit": "GB/s", "traffic": None}
+    else:
+        mfma = R["precision"] != "fp32"
+        roof = {"bound": "mfma" if mfma else "alu",
+                "kernel": "M2L (%s)" % ("k_trans_ts, FP32 MFMA" if mfma else "k_m2l_os_valu, FP32 vector ALU"),
+                "achieved": R["m2l_tflops"], "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                "traffic": recorded_traffic() if (args.workload == "bga" and mfma) else None}
+    roof["frac"] = roof["achieved"] / roof["peak"]
 
     # accuracy and CPU baseline: the FP64 oracle on a bounded row sample
     cpu = None
     acc = {}
     if not args.no_cpu:
         import oracle as O
-        rng = np.random.default_rng(7)
-        order = rng.permutation(N)
-        t0 = time.perf_counter()
-        first = np.sort(order[:64])
-        ref1, used = O.matvec(V, T, xh.astype(np.complex128), rows=first)
-        t1 = time.perf_counter() - t0
-        m_more = int(max(0, min(N - 64, (args.cpu_seconds - t1) / max(t1, 1e-3) * 64)))
-        rows = np.sort(order[64:64 + m_more])
-        if len(rows):
-            ref2, _ = O.matvec(V, T, xh.astype(np.complex128), rows=rows)
-        t_cpu = time.perf_counter() - t0
-        allrows = np.concatenate([first, rows])
-        ref = np.concatenate([ref1, ref2]) if len(rows) else ref1
-        m = len(allrows)
-        cpu = {"value": n_c * float(m) * N / t_cpu, "unit": "panel-interactions/s", "cores": int(used),
-               "kind": "oracle",
-               "sample": "%d random target rows x all %d source panels x %d complex columns, FP64 direct "
-                         "summation, %.1f s" % (m, N, n_c, t_cpu)}
-        for v, yv in ys.items():
-            e = np.linalg.norm(yv[allrows] - ref, axis=0) / np.linalg.norm(ref, axis=0)
-            acc[v] = float(e.max())
-            results[v]["max_col_rel_l2"] = float(e.max())
+        if args.workload == "batch":
+            # rows of three meshes (smallest, median, largest), each against all its sources
+            NB_ROWS = 48
+            offs = np.concatenate([[0], np.cumsum(Ns)])
+            pick = sorted(set([int(np.argmin(Ns)), int(np.argsort(Ns)[len(Ns) // 2]), int(np.argmax(Ns))]))
+            errs = {v: [] for v in ys}
+            t0 = time.perf_counter()
+            used = 1
+            for i in pick:
+                V, T = meshes[i]
+                rows = np.sort(np.random.default_rng(7 + i).choice(Ns[i], NB_ROWS, replace=False))
+                xi = x[offs[i]:offs[i + 1]].cpu().numpy().astype(np.complex128)
+                ref, used = O.matvec(V, T, xi, rows=rows)
+                for v, yv in ys.items():
+                    yi = yv[offs[i]:offs[i + 1]][torch.from_numpy(rows).cuda()].cpu().numpy()
+                    errs[v].append(np.linalg.norm(yi - ref, axis=0) / np.linalg.norm(ref, axis=0))
+            t_cpu = time.perf_counter() - t0
+            cpu = {"value": n_c * float(NB_ROWS * sum(Ns[i] for i in pick)) / t_cpu, "unit": "panel-interactions/s",
+                   "cores": int(used), "kind": "oracle",
+                   "sample": "%d random target rows of each of meshes %s (N = %s) x all their source panels x %d "
+                             "complex columns, FP64 direct summation, %.1f s" % (
+                                 NB_ROWS, pick, [Ns[i] for i in pick], n_c, t_cpu)}
+            for v in ys:
+                e = np.concatenate(errs[v])
+                acc[v] = float(e.max())
+                results[v]["max_col_rel_l2"] = acc[v]
+                results[v]["median_col_rel_l2"] = float(np.median(e))
+                results[v]["per_mesh_max_col_rel_l2"] = {str(i): float(errs[v][q].max()) for q, i in enumerate(pick)}
+        else:
+            V, T = meshes[0]
+            rng = np.random.default_rng(7)
+            order = rng.permutation(N)
+            t0 = time.perf_counter()
+            first = np.sort(order[:16])
+            ref1, used = O.matvec(V, T, xh.astype(np.complex128), rows=first)
+            t1 = time.perf_counter() - t0
+            m_more = int(max(0, min(N - 16, (args.cpu_seconds - t1) / max(t1, 1e-3) * 16)))
+            rows = np.sort(order[16:16 + m_more])
+            if len(rows):
+                ref2, _ = O.matvec(V, T, xh.astype(np.complex128), rows=rows)
+            t_cpu = time.perf_counter() - t0
+            allrows = np.concatenate([first, rows])
+            ref = np.concatenate([ref1, ref2]) if len(rows) else ref1
+            m = len(allrows)
+            cpu = {"value": n_c * float(m) * N / t_cpu, "unit": "panel-interactions/s", "cores": int(used),
+                   "kind": "oracle",
+                   "sample": "%d random target rows x all %d source panels x %d complex columns, FP64 direct "
+                             "summation, %.1f s" % (m, N, n_c, t_cpu)}
+            for v, yv in ys.items():
+                e = np.linalg.norm(yv[allrows] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+                acc[v] = float(e.max())
+                results[v]["max_col_rel_l2"] = acc[v]
 
     line = {
         "metric": "panel-interactions/s per FMM matvec at 1e-4 rel L2; surrogate+MP vs plain FP32",
@@ -186,11 +300,11 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": R["ms_per_matvec"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if main_v == "fp32" else ("f64" if main_v == "fp64" else "f32+f64"),
+        "dtype": "f32" if R["precision"] == "fp32" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": (desc % N) + ", p=8, leaf<=64, %s" % (
-                       "plain FP32" if main_v == "fp32" else "mixed precision (FP32 MFMA M2L, FP64 singular)"),
-                   "n_panels": N, "complex_columns": n_c, "order": 8, "max_leaf": 64},
+                       "plain FP32" if R["precision"] == "fp32" else "mixed precision (FP32 MFMA M2L, FP64 singular)"),
+                   "n_panels": N, "n_meshes": len(meshes), "complex_columns": n_c, "order": 8, "max_leaf": 64},
         "roofline": roof,
         "cpu_baseline": cpu,
         "max_col_rel_l2": acc.get(main_v),

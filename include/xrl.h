@@ -272,8 +272,10 @@ xrl_status xrl_fmm_matvec(const xrl_plan *plan, const void *x, int64_t ldx, int3
                           int32_t dtype, void *y, int64_t ldy, const xrl_epilogue *ep,
                           void *stream);
 
-/* Per-phase device times (milliseconds) of the last matvec, recorded with
- * HIP events on the matvec stream when profiling is on:
+/* Per-phase device times (milliseconds), recorded with HIP events on the
+ * matvec stream while profiling is on (no host wait inside the matvec):
+ * xrl_plan_get_phase_ms waits for the recorded events and returns the mean
+ * over the matvecs since profiling was switched on (the last 256 at most).
  * [0] gather [1] P2P [2] P2M [3] M2M [4] M2L [5] L2L [6] L2P [7] scatter. */
 #define XRL_N_PHASES 8
 xrl_status xrl_plan_set_profiling(xrl_plan *plan, int32_t on);

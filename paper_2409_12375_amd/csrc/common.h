@@ -269,9 +269,11 @@ struct xrl_plan {
     mutable int64_t work_cols = 0;
     // profiling
     bool profiling = false;
-    mutable double phase_ms[XRL_N_PHASES] = {0};
-    mutable hipEvent_t ev[XRL_N_PHASES + 1] = {};
-    bool events_made = false;
+    // ring of per-matvec event sets (recorded without any host wait; read
+    // and averaged by xrl_plan_get_phase_ms)
+    static constexpr int kProfRing = 256;
+    mutable std::vector<std::vector<hipEvent_t>> prof_ev;
+    mutable int64_t prof_count = 0;
     // epilogue scalars of the current call, [alpha re, im][beta re, im] per
     // column (plan-owned, so no call allocates or waits for them)
     mutable xrl::DevBuf<double> ep_dev;

@@ -1081,7 +1081,7 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
     }
     const bool prof = P->profiling;
     std::function<void(int)> mark = [&](int i) {
-        if (prof) XRL_HIP(hipEventRecord(P->ev[i], s));
+        if (prof) XRL_HIP(hipEventRecord(P->prof_ev[P->prof_count % xrl_plan::kProfRing][i], s));
     };
     mark(0);
     const int bs = 256;
@@ -1135,15 +1135,7 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
                                                  ldy, ncols, da, db);
     XRL_HIP(hipGetLastError());
     mark(8);
-    if (prof) {
-        XRL_HIP(hipEventSynchronize(P->ev[8]));
-        // public phase order: gather, P2P, P2M, M2M, M2L, L2L, L2P, scatter
-        for (int i = 0; i < XRL_N_PHASES; ++i) {
-            float ms = 0;
-            XRL_HIP(hipEventElapsedTime(&ms, P->ev[i], P->ev[i + 1]));
-            P->phase_ms[i] = ms;
-        }
-    }
+    if (prof) ++P->prof_count;
 }
 
 }  // namespace xrl
@@ -1242,9 +1234,13 @@ extern "C" xrl_status xrl_fmm_matvec(const xrl_plan *P, const void *x, int64_t l
         XRL_CHECK(x != y, XRL_E_INVALID_ARG, "xrl_fmm_matvec: x and y must not alias");
         hipStream_t s = (hipStream_t)stream;
         xrl_plan *Pm = const_cast<xrl_plan *>(P);
-        if (Pm->profiling && !Pm->events_made) {
-            for (auto &e : Pm->ev) XRL_HIP(hipEventCreate(&e));
-            Pm->events_made = true;
+        if (Pm->profiling) {
+            auto &ring = Pm->prof_ev;
+            const size_t slot = (size_t)(Pm->prof_count % xrl_plan::kProfRing);
+            if (ring.size() <= slot) {
+                ring.emplace_back(XRL_N_PHASES + 1, nullptr);
+                for (auto &e : ring.back()) XRL_HIP(hipEventCreate(&e));
+            }
         }
         const double *al = ep ? ep->alpha : nullptr, *be = ep ? ep->beta : nullptr;
         upload_epilogue(P, n_cols, al, be, s);
@@ -1287,7 +1283,11 @@ extern "C" xrl_status xrl_plan_autotune(xrl_plan *P, const void *x, int64_t ldx,
         if (P->m2l_engine == XRL_M2L_VALU) {
             cands.push_back({XRL_M2L_VALU, P->ts_kernel});
         } else {
-            cands.push_back({XRL_M2L_MFMA_OS, 0});
+            // the offset-stationary form only while its per-pair scratch
+            // holds the columns in at most two chunks
+            const int64_t per_col = P->m2l.n_pairs * (int64_t)P->KP * (P->precision == XRL_PREC_FP64 ? 8 : 4);
+            const int64_t cc = std::max<int64_t>(1, (int64_t(4) << 30) / std::max<int64_t>(1, per_col));
+            if (cdiv(2 * (int64_t)n_cols, cc) <= 2) cands.push_back({XRL_M2L_MFMA_OS, 0});
             for (int k = 0; k < 3; ++k) cands.push_back({XRL_M2L_MFMA_TS, k});
         }
         hipEvent_t e0, e1;
@@ -1376,6 +1376,7 @@ extern "C" xrl_status xrl_plan_set_profiling(xrl_plan *P, int32_t on)
     return guarded([&] {
         XRL_CHECK(P, XRL_E_INVALID_ARG, "xrl_plan_set_profiling: null plan");
         P->profiling = on != 0;
+        P->prof_count = 0;
     });
 }
 
@@ -1401,6 +1402,17 @@ extern "C" xrl_status xrl_plan_get_phase_ms(const xrl_plan *P, double *ms)
 {
     return guarded([&] {
         XRL_CHECK(P && ms, XRL_E_INVALID_ARG, "xrl_plan_get_phase_ms: null argument");
-        for (int i = 0; i < XRL_N_PHASES; ++i) ms[i] = P->phase_ms[i];
+        for (int i = 0; i < XRL_N_PHASES; ++i) ms[i] = 0;
+        const int64_t n = std::min<int64_t>(P->prof_count, xrl_plan::kProfRing);
+        for (int64_t q = 0; q < n; ++q) {
+            const auto &ev = P->prof_ev[(size_t)((P->prof_count - 1 - q) % xrl_plan::kProfRing)];
+            XRL_HIP(hipEventSynchronize(ev[XRL_N_PHASES]));
+            // public phase order: gather, P2P, P2M, M2M, M2L, L2L, L2P, scatter
+            for (int i = 0; i < XRL_N_PHASES; ++i) {
+                float t = 0;
+                XRL_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+                ms[i] += t / (double)n;
+            }
+        }
     });
 }

@@ -820,8 +820,8 @@ extern "C" xrl_status xrl_fmm_plan(xrl_tree *const *trees, int32_t n_trees, cons
 extern "C" void xrl_plan_destroy(xrl_plan *plan)
 {
     if (!plan) return;
-    if (plan->events_made)
-        for (auto &e : plan->ev) (void)hipEventDestroy(e);
+    for (auto &set : plan->prof_ev)
+        for (auto &e : set) (void)hipEventDestroy(e);
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     delete plan;

@@ -298,15 +298,11 @@ def _cylinder(cx, cy, r, z0, z1, nfac, nz, welder, caps, flip=False):
     return np.concatenate(tris)
 
 
-def bga(n_grid=20, pitch=0.5, hole_r=0.2, thick=0.035, n_theta=64, nr=6, wall_nz=3, n_via=10, via_r=0.15,
-        via_len=0.5, via_fac=16, via_nz=40, ball_r=0.2, ball_gap=0.1, ball_level=3):
-    """BGA-like package: a square plane (n_grid x n_grid cells of side pitch,
-    thickness thick) with a circular hole in every cell, cylindrical vias
-    (16 facets, capped) through the central n_via x n_via holes without
-    contact, and a solder-ball sphere ball_gap below the lower end of every via.
-    Defaults: 10 x 10 plane, 400 holes of radius 0.2, 100 vias of radius 0.15
-    and length 0.5, 100 balls of radius 0.2; about 1.03M triangles."""
-    W = _Welder(tol=1e-10)
+def _holed_plane(n_grid, pitch, hole_r, thick, z0, n_theta, nr, wall_nz, W):
+    """Closed surface of a square plane of n_grid x n_grid cells of side
+    `pitch`, thickness `thick`, bottom face at z0, with a circular hole of
+    radius hole_r in every cell (top and bottom ring faces, hole walls and the
+    outer rim).  Returns a list of triangle arrays (vertex ids in W)."""
     half = 0.5 * pitch
     L = n_grid * pitch
     x0 = -0.5 * L
@@ -314,9 +310,9 @@ def bga(n_grid=20, pitch=0.5, hole_r=0.2, thick=0.035, n_theta=64, nr=6, wall_nz
     for i in range(n_grid):
         for j in range(n_grid):
             cx, cy = x0 + (i + 0.5) * pitch, x0 + (j + 0.5) * pitch
-            tris.append(_square_ring_cell(cx, cy, half, hole_r, n_theta, nr, thick, W, flip=False))
-            tris.append(_square_ring_cell(cx, cy, half, hole_r, n_theta, nr, 0.0, W, flip=True))
-            tris.append(_cylinder(cx, cy, hole_r, 0.0, thick, n_theta, wall_nz, W, caps=False, flip=True))
+            tris.append(_square_ring_cell(cx, cy, half, hole_r, n_theta, nr, z0 + thick, W, flip=False))
+            tris.append(_square_ring_cell(cx, cy, half, hole_r, n_theta, nr, z0, W, flip=True))
+            tris.append(_cylinder(cx, cy, hole_r, z0, z0 + thick, n_theta, wall_nz, W, caps=False, flip=True))
     # outer rim: the square-boundary points of the border cells, top to bottom
     nside = n_theta // 8  # boundary points per half side of a cell
     for side in range(4):
@@ -339,9 +335,24 @@ def bga(n_grid=20, pitch=0.5, hole_r=0.2, thick=0.035, n_theta=64, nr=6, wall_nz
             P = np.stack([pts, np.full_like(pts, x0)], 1)
         idx = np.empty((wall_nz + 1, len(P)), dtype=np.int64)
         for k in range(wall_nz + 1):
-            z = thick * k / wall_nz
+            z = z0 + thick * k / wall_nz
             idx[k] = W.add_many(np.column_stack([P, np.full(len(P), z)]))
         tris.append(_grid_tris(idx, flip=True))
+    return tris
+
+
+def bga(n_grid=20, pitch=0.5, hole_r=0.2, thick=0.035, n_theta=64, nr=6, wall_nz=3, n_via=10, via_r=0.15,
+        via_len=0.5, via_fac=16, via_nz=40, ball_r=0.2, ball_gap=0.1, ball_level=3):
+    """BGA-like package: a square plane (n_grid x n_grid cells of side pitch,
+    thickness thick) with a circular hole in every cell, cylindrical vias
+    (16 facets, capped) through the central n_via x n_via holes without
+    contact, and a solder-ball sphere ball_gap below the lower end of every via.
+    Defaults: 10 x 10 plane, 400 holes of radius 0.2, 100 vias of radius 0.15
+    and length 0.5, 100 balls of radius 0.2; about 1.03M triangles."""
+    W = _Welder(tol=1e-10)
+    half = 0.5 * pitch
+    x0 = -0.5 * n_grid * pitch
+    tris = _holed_plane(n_grid, pitch, hole_r, thick, 0.0, n_theta, nr, wall_nz, W)
     # vias through the central holes and balls below them
     first = (n_grid - n_via) // 2
     zmid = 0.5 * thick
@@ -390,3 +401,39 @@ def batch_meshes(n_meshes=32, n_min=10_000, n_max=500_000, seed=GEOM_SEED + 4):
             V, T = bga(n_grid=g, n_via=0)
         out.append((kind, V, T))
     return out
+
+
+# --------------------------------------------------------------------------
+# package-on-package-like stack
+# --------------------------------------------------------------------------
+def pop(size=12.0, n_grid=30, gap=1.0, thick=0.035, clear_r=0.15, via_r=0.1, via_fac=16, via_nz=30,
+        via_over=0.1, n_theta=32, nr=3, wall_nz=2, trace_w=0.1, trace_ds=0.05, trace_nw=4, trace_nt=2):
+    """Package-on-package-like stack: two square planes (size x size,
+    thickness thick) `gap` apart (facing surfaces), each with a clearance hole
+    of radius clear_r in every one of its n_grid x n_grid cells (pitch
+    size / n_grid = 0.4); a via of radius via_r (16 facets, capped) through
+    every hole pair without contact, reaching via_over past both planes; and
+    two layers of parallel traces of width trace_w between the planes, in
+    the channels between the via rows (along x in the lower layer, along y in
+    the upper).  Defaults: 900 vias, 2 x 29 traces, about 2.1M triangles."""
+    W = _Welder(tol=1e-10)
+    pitch = size / n_grid
+    x0 = -0.5 * size
+    tris = []
+    z_lo, z_hi = 0.0, thick + gap  # bottom faces of the two planes
+    tris += _holed_plane(n_grid, pitch, clear_r, thick, z_lo, n_theta, nr, wall_nz, W)
+    tris += _holed_plane(n_grid, pitch, clear_r, thick, z_hi, n_theta, nr, wall_nz, W)
+    for i in range(n_grid):
+        for j in range(n_grid):
+            cx, cy = x0 + (i + 0.5) * pitch, x0 + (j + 0.5) * pitch
+            tris.append(_cylinder(cx, cy, via_r, z_lo - via_over, z_hi + thick + via_over, via_fac, via_nz, W,
+                                  caps=True))
+    # traces in the channels between via rows, inset from the plane edge
+    zt = [thick + gap / 3.0, thick + 2.0 * gap / 3.0]
+    end = 0.5 * size - 0.5 * pitch
+    for layer, z in enumerate(zt):
+        for k in range(1, n_grid):
+            c = x0 + k * pitch
+            poly = [(-end, c), (end, c)] if layer == 0 else [(c, -end), (c, end)]
+            tris.append(swept_trace(poly, trace_w, thick, z, trace_nw, trace_nt, trace_ds, W))
+    return W.vertices(), np.concatenate(tris).astype(np.int32)

@@ -306,9 +306,34 @@ def test_autotune_keeps_the_fastest_form_and_the_result():
     y0 = plan.matvec(x)
     r = plan.autotune(x, reps=2)
     say("  tried", r["tried"], "best", r["best"])
-    assert len(r["tried"]) == 4
+    assert len(r["tried"]) in (3, 4)
     assert r["best"][2] == min(t[2] for t in r["tried"])
     y1 = plan.matvec(x)
     torch.cuda.synchronize()
     d = (torch.linalg.norm(y1 - y0, dim=0) / torch.linalg.norm(y0, dim=0)).max().item()
     assert d < 1e-6
+
+
+def test_many_columns_several_items_per_target():
+    """96 complex columns (192 real): the target-stationary translations split
+    every target into several column items and P2P into several column tiles;
+    against the offset-stationary kernels and against the oracle."""
+    say("case: bar 4096, 96 columns, several items per target")
+    V, T = I.bar()
+    N = len(T)
+    x = I.densities(N, 96, np.complex64, seed=31)
+    tree = xrl.Tree(V, T)
+    ys = {}
+    for eng in ("mfma", "mfma_os"):
+        plan = xrl.Plan(tree, order=8, precision="mixed", engine=eng, max_cols=96)
+        plan.assemble()
+        ys[eng] = plan.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+        plan.close()
+    d = np.linalg.norm(ys["mfma"] - ys["mfma_os"], axis=0) / np.linalg.norm(ys["mfma_os"], axis=0)
+    say("  target- vs offset-stationary", d.max())
+    assert d.max() < 1e-6
+    rows = sample_rows(N, 64)
+    ref, _ = O.matvec(V, T, x.astype(np.complex128), rows=rows)
+    err = relerr_cols(ys["mfma"][rows], ref)
+    say("  rel L2 per column: max", err.max(), "median", np.median(err))
+    assert err.max() <= 5e-5
