@@ -948,9 +948,17 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
         return;
     }
     const bool mfma = eng != XRL_M2L_VALU;
-    // column chunk so that the per-pair scratch stays within 4 GiB
+    // column chunk so that the per-pair scratch stays within the plan's
+    // scratch budget (a quarter of the device memory free at the first
+    // translation, at least 4 GiB; fixed from then on, so that a captured
+    // graph sees the same chunks)
+    if (P->scratch_budget == 0) {
+        size_t fr = 0, tot = 0;
+        XRL_HIP(hipMemGetInfo(&fr, &tot));
+        P->scratch_budget = std::max<int64_t>(int64_t(4) << 30, (int64_t)(fr / 4));
+    }
     const int64_t per_col = TP.n_pairs * (int64_t)D::KP * (int64_t)sizeof(T);
-    const int Cc = (int)std::max<int64_t>(1, std::min<int64_t>(C, (int64_t(4) << 30) / per_col));
+    const int Cc = (int)std::max<int64_t>(1, std::min<int64_t>(C, P->scratch_budget / per_col));
     if (tmp.n < (size_t)(TP.n_pairs * (int64_t)Cc * D::KP)) tmp.alloc(TP.n_pairs * (int64_t)Cc * D::KP);
     for (int c0 = 0; c0 < C; c0 += Cc) {
         const int cc = std::min(Cc, C - c0);
@@ -1286,7 +1294,8 @@ extern "C" xrl_status xrl_plan_autotune(xrl_plan *P, const void *x, int64_t ldx,
             // the offset-stationary form only while its per-pair scratch
             // holds the columns in at most two chunks
             const int64_t per_col = P->m2l.n_pairs * (int64_t)P->KP * (P->precision == XRL_PREC_FP64 ? 8 : 4);
-            const int64_t cc = std::max<int64_t>(1, (int64_t(4) << 30) / std::max<int64_t>(1, per_col));
+            const int64_t budget = P->scratch_budget ? P->scratch_budget : int64_t(4) << 30;
+            const int64_t cc = std::max<int64_t>(1, budget / std::max<int64_t>(1, per_col));
             if (cdiv(2 * (int64_t)n_cols, cc) <= 2) cands.push_back({XRL_M2L_MFMA_OS, 0});
             for (int k = 0; k < 3; ++k) cands.push_back({XRL_M2L_MFMA_TS, k});
         }
