@@ -48,9 +48,13 @@ def log(*a):
 
 
 def source_hash():
-    """Hash of the translation kernels' source: HBM traffic figures taken
-    with counters stay valid only while it is unchanged."""
-    return hashlib.sha256(open(os.path.join(ROOT, "paper_2409_12375_amd", "csrc", "fmm.hip"), "rb").read()).hexdigest()
+    """Hash of the translation kernels' source and of the plan that lays out
+    their operators and pair lists: HBM traffic figures taken with counters
+    stay valid only while both are unchanged."""
+    h = hashlib.sha256()
+    for f in ("fmm.hip", "plan.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2409_12375_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def recorded_traffic():
@@ -59,7 +63,7 @@ def recorded_traffic():
     if not os.path.exists(TRAFFIC_FILE):
         return None
     txt = open(TRAFFIC_FILE).read()
-    h = re.search(r"fmm\.hip sha256:\s*([0-9a-f]{64})", txt)
+    h = re.search(r"fmm\.hip \+ plan\.hip sha256:\s*([0-9a-f]{64})", txt)
     b = re.search(r"HBM bytes per launch \(calibrated\):\s*([0-9.eE+]+)", txt)
     if not h or not b or h.group(1) != source_hash():
         return None
