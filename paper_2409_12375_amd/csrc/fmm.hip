@@ -235,26 +235,61 @@ __global__ __launch_bounds__(256) void k_p2p_wide(const int32_t *__restrict__ le
 }
 
 // ---------------------------------------------------------------- P2M
+// One workgroup per (leaf, tile of CT columns):
+//     M[b][i][c] = sum over the leaf's panels k of mom[k][i] x[k][c].
+// The panels' moment rows and densities are staged in LDS in chunks of NP
+// panels (any leaf size); a thread owns one coefficient i and four
+// consecutive columns, so each staged moment feeds four FMAs.
+constexpr int kP2MPanels = 32;
+constexpr int kMaxK = 169;  // (p + 1)^2 at the largest supported order, 12
+
 template <typename T, int CT>
 __global__ __launch_bounds__(256) void k_p2m(const int32_t *__restrict__ leaf_box, const int32_t *__restrict__ box_beg,
                                              const int32_t *__restrict__ box_end, const T *__restrict__ mom,
                                              const T *__restrict__ xs, T *__restrict__ M, int C, int K)
 {
-    __shared__ T sx[64 * CT];
+    constexpr int NP = kP2MPanels, NQ = CT / 4;
+    constexpr int MAXO = (kMaxK * NQ + 255) / 256;  // outputs (of four columns) per thread
+    using V4 = typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type;
+    __shared__ T smom[NP * kMaxK];
+    __shared__ __align__(16) T sx[NP * CT];
     const int32_t b = leaf_box[blockIdx.x];
     const int c0 = blockIdx.y * CT;
     const int32_t kb = box_beg[b], nt = box_end[b] - kb;
-    for (int idx = threadIdx.x; idx < nt * CT; idx += blockDim.x) {
-        const int k = idx / CT, c = idx - k * CT;
-        sx[idx] = (c0 + c < C) ? xs[(int64_t)(kb + k) * C + c0 + c] : T(0);
+    V4 acc[MAXO];
+#pragma unroll
+    for (int o = 0; o < MAXO; ++o) acc[o] = V4{0, 0, 0, 0};
+    for (int kc = 0; kc < nt; kc += NP) {
+        const int nk = min(NP, nt - kc);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < nk * K; idx += 256) smom[idx] = mom[(int64_t)(kb + kc) * K + idx];
+        for (int idx = threadIdx.x; idx < nk * CT; idx += 256) {
+            const int k = idx / CT, c = idx - k * CT;
+            sx[idx] = (c0 + c < C) ? xs[(int64_t)(kb + kc + k) * C + c0 + c] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < MAXO; ++o) {
+            const int idx = threadIdx.x + 256 * o;
+            if (idx >= K * NQ) break;
+            const int i = idx / NQ, q = idx - i * NQ;
+            for (int k = 0; k < nk; ++k) {
+                const T m = smom[k * K + i];
+                const V4 xv = *reinterpret_cast<const V4 *>(sx + k * CT + 4 * q);
+                acc[o] += m * xv;
+            }
+        }
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < K * CT; idx += blockDim.x) {
-        const int i = idx / CT, c = idx - i * CT;
-        if (c0 + c >= C) continue;
-        T acc = 0;
-        for (int k = 0; k < nt; ++k) acc += mom[(int64_t)(kb + k) * K + i] * sx[k * CT + c];
-        M[((int64_t)b * K + i) * C + c0 + c] = acc;
+#pragma unroll
+    for (int o = 0; o < MAXO; ++o) {
+        const int idx = threadIdx.x + 256 * o;
+        if (idx >= K * NQ) break;
+        const int i = idx / NQ, q = idx - i * NQ;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = c0 + 4 * q + e;
+            if (c < C) M[((int64_t)b * K + i) * C + c] = acc[o][e];
+        }
     }
 }
 
@@ -932,6 +967,10 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
                 k_trans_ts<T, ORD, W, false><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
                                                                TP.ts_src.p, TP.ts_op_full.p, op_full, op_full_tail, in,
                                                                C, accumulate, out);
+            else if (TP.n_pairs < 2 * TP.n_red)  // L2L: one pair per target, nothing to pipeline across
+                k_trans_ts_lean<T, ORD, W><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                                                              TP.ts_src.p, TP.ts_op.p, op_vec, in, C, accumulate,
+                                                              out);
             else
                 k_trans_ts<T, ORD, W, false><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
                                                                TP.ts_src.p, TP.ts_op.p, op_vec, op_tail, in, C,
@@ -1102,15 +1141,23 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
     mark(1);
     p2p_launch<T>(P, op.near, xs.p, ys.p, C, s);
     mark(2);
-    const int CT = (sizeof(T) == 8 || C <= 8) ? 8 : 16;
-    const unsigned ntile = (unsigned)cdiv(C, CT);
+    // column tile of P2M / L2P: the narrowest of 8, 16, 24, 32, 48 (FP32) or
+    // 8, 16 (FP64) that holds all columns, else the widest
+    auto moment_tiles = [&](auto fn) {
+        if (C <= 8) return fn(std::integral_constant<int, 8>());
+        if (sizeof(T) == 8 || C <= 16) return fn(std::integral_constant<int, 16>());
+        if constexpr (sizeof(T) == 4) {
+            if (C <= 24) return fn(std::integral_constant<int, 24>());
+            if (C <= 32) return fn(std::integral_constant<int, 32>());
+            return fn(std::integral_constant<int, 48>());
+        }
+    };
     if (P->n_leaves > 0) {
-        if (CT == 8)
-            k_p2m<T, 8><<<dim3((unsigned)P->n_leaves, ntile), 256, 0, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p,
-                                                                           op.mom, xs.p, M.p, C, K);
-        else
-            k_p2m<T, 16><<<dim3((unsigned)P->n_leaves, ntile), 256, 0, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p,
-                                                                            op.mom, xs.p, M.p, C, K);
+        moment_tiles([&](auto ctc) {
+            constexpr int CT = decltype(ctc)::value;
+            k_p2m<T, CT><<<dim3((unsigned)P->n_leaves, (unsigned)cdiv(C, CT)), 256, 0, s>>>(
+                P->leaf_box.p, P->box_beg.p, P->box_end.p, op.mom, xs.p, M.p, C, K);
+        });
         XRL_HIP(hipGetLastError());
     }
     switch (P->p) {
@@ -1122,6 +1169,8 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
         default: translations<T, 12>(P, op, M.p, L.p, tmp, C, s, mark); break;
     }
     if (P->n_leaves > 0) {
+        const int CT = (sizeof(T) == 8 || C <= 8) ? 8 : 16;
+        const unsigned ntile = (unsigned)cdiv(C, CT);
         const size_t sm = (size_t)K * CT * sizeof(T);
         if (CT == 8)
             k_l2p<T, 8><<<dim3((unsigned)P->n_leaves, ntile), 256, sm, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p,
