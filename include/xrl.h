@@ -140,8 +140,9 @@ typedef struct {
  * Several trees make one batched plan: the meshes are stacked in the order
  * given, densities are concatenated along the panel axis.  The trees must
  * outlive the plan.
- * Errors: XRL_E_INVALID_ARG, XRL_E_UNSUPPORTED (order or engine), XRL_E_OOM,
- *         XRL_E_HIP. */
+ * Errors: XRL_E_INVALID_ARG, XRL_E_UNSUPPORTED (order or engine; or a leaf
+ *         holding more than 64 panels at the maximum depth, i.e. nearly
+ *         coincident centroids), XRL_E_OOM, XRL_E_HIP. */
 xrl_status xrl_fmm_plan(xrl_tree *const *trees, int32_t n_trees, const xrl_plan_opts *opts,
                         void *stream, xrl_plan **out);
 void xrl_plan_destroy(xrl_plan *plan);

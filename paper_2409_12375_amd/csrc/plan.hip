@@ -572,6 +572,13 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     for (int64_t li = 0; li < P->n_leaves; ++li) {
         const int32_t T = leaves[li];
         const int nt = end[T] - beg[T];
+        // the near-field block of a leaf holds at most 64 targets; a leaf can
+        // exceed that only at the maximum depth (centroids closer than the
+        // root size / 2^21), which is refused rather than mis-stored
+        XRL_CHECK(nt <= kMaxLeaf, XRL_E_UNSUPPORTED,
+                  "xrl_fmm_plan: a leaf at the maximum depth holds %d panels (more than %d); "
+                  "the mesh has (nearly) coincident panel centroids",
+                  nt, kMaxLeaf);
         tpad[li] = nt <= 16 ? 16 : (nt <= 32 ? 32 : 64);
         // sort source boxes by their panel range so the rows are in Morton order
         std::vector<std::pair<int32_t, int32_t>> rg;
