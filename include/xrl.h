@@ -292,9 +292,13 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
  *   XRL_TUNE_TS_MIN_COLS (>= 1, default 16): with XRL_M2L_MFMA, the
  *       translations run target-stationary from this many real columns on,
  *       offset-stationary below.
+ *   XRL_TUNE_P2P_FORM    (0/1, default 0): P2P above 16 FP32 columns with the
+ *       source densities staged in LDS (0) or read as wave-uniform scalars
+ *       (1, one lane per target).
  * Errors: XRL_E_INVALID_ARG (null plan, unknown key, bad value). */
 #define XRL_TUNE_TS_KERNEL 0
 #define XRL_TUNE_TS_MIN_COLS 1
+#define XRL_TUNE_P2P_FORM 2
 xrl_status xrl_plan_set_tuning(xrl_plan *plan, int32_t key, int32_t value);
 
 /* Graph mode (on != 0): the first xrl_fmm_matvec with a new argument set
@@ -314,13 +318,17 @@ typedef struct {
     double ms[8];         /* mean time of one matvec, milliseconds */
     int32_t best_engine, best_ts_kernel;
     double best_ms;
+    int32_t n_p2p_tried;  /* P2P forms timed with the best translation form (0 when one applies) */
+    double p2p_ms[2];     /* mean matvec time with XRL_TUNE_P2P_FORM = 0, 1 */
+    int32_t best_p2p_form;
 } xrl_tune_result;
 
 /* Times `reps` matvecs (after one warm-up) with each translation form that
  * applies to the plan's precision (MFMA plans: offset-stationary and the three
  * target-stationary forms; the vector-ALU plan has one form) on the caller's
- * arguments, and keeps the fastest in the plan.  y is overwritten.  The
- * forms agree to rounding, so the choice only changes speed.
+ * arguments, keeps the fastest in the plan, then does the same for the two
+ * P2P forms when more than 16 FP32 columns are carried.  y is overwritten.
+ * The forms agree to rounding, so the choice only changes speed.
  * Errors: XRL_E_INVALID_ARG, XRL_E_STATE (not assembled), XRL_E_HIP. */
 xrl_status xrl_plan_autotune(xrl_plan *plan, const void *x, int64_t ldx, int32_t n_cols, int32_t dtype, void *y,
                              int64_t ldy, int32_t reps, void *stream, xrl_tune_result *result);

@@ -234,6 +234,60 @@ __global__ __launch_bounds__(256) void k_p2p_wide(const int32_t *__restrict__ le
     }
 }
 
+// Scalar-density form (FP32, C > 16): one wave per (leaf, tile of CT
+// columns), lane = target of the leaf block.  A source row's densities are
+// the same for every lane, so they come in through scalar loads and enter
+// the FMAs as SGPR operands: no LDS traffic, and each lane's block value
+// (one coalesced 4-byte load per row) feeds CT FMAs.  Lanes past the block
+// width idle (the price for leaves of 16 or 32 targets).
+template <int CT>
+__global__ __launch_bounds__(64) void k_p2p_sx(const int32_t *__restrict__ leaf_box,
+                                               const int32_t *__restrict__ box_beg,
+                                               const int32_t *__restrict__ box_end,
+                                               const int32_t *__restrict__ near_rows,
+                                               const int32_t *__restrict__ near_src,
+                                               const int32_t *__restrict__ leaf_tpad,
+                                               const int64_t *__restrict__ val_off, const float *__restrict__ val,
+                                               const float *__restrict__ xs, float *__restrict__ ys, int C)
+{
+    const int li = blockIdx.x;
+    const int c0 = blockIdx.y * CT;
+    const int lane = threadIdx.x;
+    const int32_t tb = leaf_box[li];
+    const int32_t kb = box_beg[tb], nt = box_end[tb] - kb;
+    const int32_t r0 = near_rows[li], nr = near_rows[li + 1] - r0;
+    const int G = leaf_tpad[li];
+    const bool act = lane < G;
+    const float *vb = val + val_off[li] + (act ? lane : 0);
+    const int ncol = min(CT, C - c0);
+    float acc[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[c] = 0.f;
+    if (ncol == CT) {
+#pragma unroll 2
+        for (int r = 0; r < nr; ++r) {
+            const float *xr = xs + (int64_t)near_src[r0 + r] * C + c0;
+            const float v = act ? vb[(int64_t)r * G] : 0.f;
+#pragma unroll
+            for (int c = 0; c < CT; ++c) acc[c] += v * xr[c];
+        }
+    } else {
+        for (int r = 0; r < nr; ++r) {
+            const float *xr = xs + (int64_t)near_src[r0 + r] * C + c0;
+            const float v = act ? vb[(int64_t)r * G] : 0.f;
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                if (c < ncol) acc[c] += v * xr[c];
+        }
+    }
+    if (lane < nt) {
+        float *yo = ys + (int64_t)(kb + lane) * C + c0;
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+            if (c < ncol) yo[c] = acc[c];
+    }
+}
+
 // ---------------------------------------------------------------- P2M
 // One workgroup per (leaf, tile of CT columns):
 //     M[b][i][c] = sum over the leaf's panels k of mom[k][i] x[k][c].
@@ -1035,6 +1089,27 @@ static void p2p_launch(const xrl_plan *P, const T *val, const T *xs, T *ys, int 
 {
     if (P->n_leaves == 0) return;
     if constexpr (sizeof(T) == 4) {
+        if (C > 16 && P->p2p_form == 1) {
+            auto sx = [&](auto ctc) {
+                constexpr int CT = decltype(ctc)::value;
+                dim3 grid((unsigned)P->n_leaves, (unsigned)cdiv(C, CT));
+                k_p2p_sx<CT><<<grid, 64, 0, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p, P->near_rows.p,
+                                                 P->near_src.p, P->leaf_tpad.p, P->near_val_off.p, val, xs, ys, C);
+            };
+            int ct = 24;
+            for (int w : {32, 36, 48})
+                if (cdiv(C, w) * w <= cdiv(C, ct) * ct) ct = w;
+            if (ct == 24)
+                sx(std::integral_constant<int, 24>());
+            else if (ct == 32)
+                sx(std::integral_constant<int, 32>());
+            else if (ct == 36)
+                sx(std::integral_constant<int, 36>());
+            else
+                sx(std::integral_constant<int, 48>());
+            XRL_HIP(hipGetLastError());
+            return;
+        }
         if (C > 16) {
             auto wide = [&](auto ctc) {
                 constexpr int CT = decltype(ctc)::value;
@@ -1389,6 +1464,32 @@ extern "C" xrl_status xrl_plan_autotune(xrl_plan *P, const void *x, int64_t ldx,
         P->use_graph = graph;
         P->m2l_engine = pick.engine;
         P->ts_kernel = pick.ts_kernel;
+        res->best_p2p_form = P->p2p_form;
+        if (P->precision != XRL_PREC_FP64 && n_cols > 8) {  // more than 16 real FP32 columns
+            hipEvent_t f0, f1;
+            XRL_HIP(hipEventCreate(&f0));
+            XRL_HIP(hipEventCreate(&f1));
+            double bp = 1e300;
+            for (int f = 0; f < 2; ++f) {
+                P->p2p_form = f;
+                enqueue_matvec(P, x, ldx, n_cols, dtype, y, ldy, false, false, s);
+                XRL_HIP(hipEventRecord(f0, s));
+                for (int r = 0; r < reps; ++r) enqueue_matvec(P, x, ldx, n_cols, dtype, y, ldy, false, false, s);
+                XRL_HIP(hipEventRecord(f1, s));
+                XRL_HIP(hipEventSynchronize(f1));
+                float ms = 0;
+                XRL_HIP(hipEventElapsedTime(&ms, f0, f1));
+                res->p2p_ms[f] = ms / reps;
+                res->n_p2p_tried = f + 1;
+                if (ms / reps < bp) {
+                    bp = ms / reps;
+                    res->best_p2p_form = f;
+                }
+            }
+            (void)hipEventDestroy(f0);
+            (void)hipEventDestroy(f1);
+            P->p2p_form = res->best_p2p_form;
+        }
         if (P->gexec) {  // a captured graph holds the old kernel shapes
             XRL_HIP(hipGraphExecDestroy(P->gexec));
             P->gexec = nullptr;
@@ -1446,6 +1547,10 @@ extern "C" xrl_status xrl_plan_set_tuning(xrl_plan *P, int32_t key, int32_t valu
             case XRL_TUNE_TS_KERNEL:
                 XRL_CHECK(value >= 0 && value <= 2, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: kernel form must be 0..2");
                 P->ts_kernel = value;
+                break;
+            case XRL_TUNE_P2P_FORM:
+                XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: P2P form must be 0 or 1");
+                P->p2p_form = value;
                 break;
             case XRL_TUNE_TS_MIN_COLS:
                 XRL_CHECK(value >= 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: min columns must be >= 1");

@@ -41,7 +41,8 @@ class TreeInfo(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("n_tried", _i32), ("engine", _i32 * 8), ("ts_kernel", _i32 * 8), ("ms", ctypes.c_double * 8),
-                ("best_engine", _i32), ("best_ts_kernel", _i32), ("best_ms", ctypes.c_double)]
+                ("best_engine", _i32), ("best_ts_kernel", _i32), ("best_ms", ctypes.c_double),
+                ("n_p2p_tried", _i32), ("p2p_ms", ctypes.c_double * 2), ("best_p2p_form", _i32)]
 
 
 class PlanOpts(ctypes.Structure):
@@ -237,7 +238,7 @@ class Plan:
     def set_profiling(self, on=True):
         _check(lib().xrl_plan_set_profiling(self.h, 1 if on else 0))
 
-    TUNE = {"ts_kernel": 0, "ts_min_cols": 1}
+    TUNE = {"ts_kernel": 0, "ts_min_cols": 1, "p2p_form": 2}
 
     def set_tuning(self, key, value):
         """Kernel-shape knob (see xrl_plan_set_tuning); results agree to rounding."""
@@ -259,7 +260,8 @@ class Plan:
                                        Y.stride(0), reps, _stream(stream), ctypes.byref(r)))
         names = {v: k for k, v in ENGINE.items()}
         tried = [(names[r.engine[i]], r.ts_kernel[i], r.ms[i]) for i in range(r.n_tried)]
-        return {"tried": tried, "best": (names[r.best_engine], r.best_ts_kernel, r.best_ms)}
+        return {"tried": tried, "best": (names[r.best_engine], r.best_ts_kernel, r.best_ms),
+                "p2p_tried": [(f, r.p2p_ms[f]) for f in range(r.n_p2p_tried)], "best_p2p_form": r.best_p2p_form}
 
     def phase_ms(self):
         a = (ctypes.c_double * N_PHASES)()
