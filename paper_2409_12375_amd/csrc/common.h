@@ -244,8 +244,8 @@ struct xrl_plan {
     // last operator row (K - 1) of the same operators, [op][k % 4][k / 4]
     // (padded to the vector length), for orders with K = 16 n + 1 whose last
     // row is applied on the vector ALU instead of a 16-row MFMA tile
-    xrl::DevBuf<double> op_m2m64t, op_l2l64t, op_m2l64t;
-    xrl::DevBuf<float> op_m2m32t, op_l2l32t, op_m2l32t;
+    xrl::DevBuf<double> op_m2m64t, op_l2l64t, op_m2l64t, op_m2lc64t;
+    xrl::DevBuf<float> op_m2m32t, op_l2l32t, op_m2l32t, op_m2lc32t;
     // form of the target-stationary M2L (XRL_TUNE_TS_KERNEL)
     int ts_kernel = 0;
     int ts_min_cols = 16;  // MFMA engine: target-stationary from this many real columns on

@@ -619,7 +619,7 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
     // column tile and pair), instead of a 16-row MFMA tile that is 15/16
     // padding; the four k-subsets of a column are summed across lanes once
     // per target
-    constexpr bool TAIL = !REFL && D::K % 16 == 1;
+    constexpr bool TAIL = D::K % 16 == 1;
     constexpr int NRTM = TAIL ? D::K / 16 : D::NRT;  // row tiles on MFMA
     const int w = blockIdx.x;
     if (w >= n_items) return;
@@ -683,6 +683,15 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
             for (int ct = 0; ct < WT; ++ct)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) acc[rt][ct][e] = flip_sign(acc[rt][ct][e], (uint32_t)(m >> (4 * rt + e)) & 1u);
+        if constexpr (TAIL) {  // the last row, summed on the vector ALU
+            const int sg = reflection_signs(D::K - 1);
+            int f = 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (d >> a & 1) f ^= (sg >> a) & 1;
+#pragma unroll
+            for (int ct = 0; ct < WT; ++ct) tacc[ct] = flip_sign(tacc[ct], (uint32_t)f);
+        }
     };
     // Software pipeline over (pair, row-tile group) steps: the operator of a
     // pair is streamed in three groups of row tiles through a ring of two
@@ -1011,7 +1020,7 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
             constexpr int W = decltype(wt)::value;
             if (refl && P->ts_kernel == 1)
                 k_trans_ts<T, ORD, W, true><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
-                                                              TP.ts_src.p, TP.ts_op.p, op_vec, nullptr, in, C,
+                                                              TP.ts_src.p, TP.ts_op.p, op_vec, op_tail, in, C,
                                                               accumulate, out);
             else if (refl && P->ts_kernel == 2)
                 k_trans_ts_lean<T, ORD, W><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
@@ -1154,7 +1163,7 @@ struct Ops {
     const T *near, *mom, *m2m_f, *m2m_k, *l2l_f, *l2l_k, *m2l_f, *m2l_k;
     const T *m2m_v, *l2l_v, *m2l_v;  // target-stationary operators (M2L: non-negative offsets)
     const T *m2l_full;               // target-stationary M2L operators of every offset
-    const T *m2m_t, *l2l_t, *m2l_full_t;  // their last rows (orders with K = 16 n + 1)
+    const T *m2m_t, *l2l_t, *m2l_full_t, *m2l_t;  // their last rows (orders with K = 16 n + 1)
 };
 
 template <typename T, int ORD>
@@ -1171,7 +1180,7 @@ static void translations(const xrl_plan *P, const Ops<T> &op, T *M, T *L, DevBuf
     k_fill_zero<T><<<(unsigned)std::min<int64_t>(cdiv(nL, 256), 65536), 256, 0, s>>>(L, nL);
     XRL_HIP(hipGetLastError());
     mark(4);
-    pass_launch<T, ORD>(P, P->m2l, op.m2l_f, op.m2l_k, op.m2l_v, nullptr, true, M, L, 0, tmp, C, s, op.m2l_full,
+    pass_launch<T, ORD>(P, P->m2l, op.m2l_f, op.m2l_k, op.m2l_v, op.m2l_t, true, M, L, 0, tmp, C, s, op.m2l_full,
                         op.m2l_full_t);
     mark(5);
     for (int l = 3; l <= P->depth; ++l)
@@ -1297,13 +1306,13 @@ static void enqueue_matvec(const xrl_plan *P, const void *x, int64_t ldx, int n_
     if (P->precision == XRL_PREC_FP64) {
         Ops<double> op{P->near64.p, P->mom64.p, P->op_m2m64f.p, P->op_m2m64k.p, P->op_l2l64f.p, P->op_l2l64k.p,
                        P->op_m2l64f.p, P->op_m2l64k.p, P->op_m2m64v.p, P->op_l2l64v.p, P->op_m2lc64v.p,
-                       P->op_m2l64v.p, P->op_m2m64t.p, P->op_l2l64t.p, P->op_m2l64t.p};
+                       P->op_m2l64v.p, P->op_m2m64t.p, P->op_l2l64t.p, P->op_m2l64t.p, P->op_m2lc64t.p};
         run_matvec<double>(P, x, ldx, n_cols, dtype, y, ldy, ha, hb, s, Pm->xs64, Pm->ys64, Pm->M64, Pm->L64,
                            Pm->os_tmp64, op);
     } else {
         Ops<float> op{P->near32.p, P->mom32.p, P->op_m2m32f.p, P->op_m2m32k.p, P->op_l2l32f.p, P->op_l2l32k.p,
                       P->op_m2l32f.p, P->op_m2l32k.p, P->op_m2m32v.p, P->op_l2l32v.p, P->op_m2lc32v.p,
-                      P->op_m2l32v.p, P->op_m2m32t.p, P->op_l2l32t.p, P->op_m2l32t.p};
+                      P->op_m2l32v.p, P->op_m2m32t.p, P->op_l2l32t.p, P->op_m2l32t.p, P->op_m2lc32t.p};
         run_matvec<float>(P, x, ldx, n_cols, dtype, y, ldy, ha, hb, s, Pm->xs32, Pm->ys32, Pm->M32, Pm->L32,
                           Pm->os_tmp32, op);
     }

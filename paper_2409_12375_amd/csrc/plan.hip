@@ -755,7 +755,7 @@ static void build_plan(xrl_plan *P, hipStream_t s)
             for (int r = 0; r < K; ++r)
                 for (int k = 0; k < K; ++k) m2lc[((size_t)c * P->KP + r) * P->KK + k] = tmp[(size_t)r * K + k];
         }
-        vec_layouts(m2lc, 64, P->op_m2lc64v, P->op_m2lc32v);
+        vec_layouts(m2lc, 64, P->op_m2lc64v, P->op_m2lc32v, &P->op_m2lc64t, &P->op_m2lc32t);
         vec_layouts(m2l, 343, P->op_m2l64v, P->op_m2l32v, &P->op_m2l64t, &P->op_m2l32t);
     }
     vec_layouts(padded(m2m, 8), 8, P->op_m2m64v, P->op_m2m32v, &P->op_m2m64t, &P->op_m2m32t);
