@@ -132,8 +132,8 @@ def main():
                     help="only run a plain copy of BYTES bytes (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the matvec would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the matvec runs in one process on one device "
+              "(there is no multi-GPU path).", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)

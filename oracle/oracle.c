@@ -3,7 +3,7 @@
  * (arXiv 2409.12375, Sec. II-A, eq. (6), second term; Sec. II-C, eq. (9)).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the independent reference against
- * which the GPU path is judged.  Only the test-suite, the smoke check and the
+ * which the GPU path is checked.  Only the test-suite, the smoke check and the
  * CPU-baseline leg of the benchmark load it.  It shares no code, header, table
  * or constant generator with the GPU library.
  *
