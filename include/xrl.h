@@ -295,10 +295,16 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
  *   XRL_TUNE_P2P_FORM    (0/1, default 0): P2P above 16 FP32 columns with the
  *       source densities staged in LDS (0) or read as wave-uniform scalars
  *       (1, one lane per target).
+ *   XRL_TUNE_TS_NARROW_COLS (0/1, default 1): FP32 target-stationary forms
+ *       0 and 1 with 1..4 real columns past the last full 16-column tile
+ *       (C = 16 n + 1 .. 16 n + 4, e.g. 18 complex columns): those columns
+ *       on 4x4x1 MFMA blocks beside the n 16x16x4 tiles (1) or in a further,
+ *       mostly padded 16x16x4 tile (0).
  * Errors: XRL_E_INVALID_ARG (null plan, unknown key, bad value). */
 #define XRL_TUNE_TS_KERNEL 0
 #define XRL_TUNE_TS_MIN_COLS 1
 #define XRL_TUNE_P2P_FORM 2
+#define XRL_TUNE_TS_NARROW_COLS 3
 xrl_status xrl_plan_set_tuning(xrl_plan *plan, int32_t key, int32_t value);
 
 /* Graph mode (on != 0): the first xrl_fmm_matvec with a new argument set
@@ -360,6 +366,12 @@ xrl_status xrl_m2l_operator(int32_t order, int32_t ox, int32_t oy, int32_t oz, d
  * D[16][16] = A[16][4] * B[4][16], row-major host arrays of float
  * (elem_bytes = 4) or double (8).  Runs one wave on the current device. */
 xrl_status xrl_selftest_mfma(int32_t elem_bytes, const void *A, const void *B, void *D);
+
+/* Self-test of the 16-block 4x4x1 FP32 MFMA layout used for the columns
+ * past the last full tile of the target-stationary translation: for each
+ * block b, D[b][4][4] = A[b][4] (column) * B[b][4] (row); A, B: [16][4],
+ * D: [16][4][4] row-major host float arrays.  One wave on the current device. */
+xrl_status xrl_selftest_mfma_4x4(const float *A, const float *B, float *D);
 
 /* ------------------------------------------------------------------ */
 /* Iterative solve                                                     */

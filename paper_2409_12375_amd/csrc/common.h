@@ -250,6 +250,7 @@ struct xrl_plan {
     int ts_kernel = 0;
     int ts_min_cols = 16;  // MFMA engine: target-stationary from this many real columns on
     int p2p_form = 0;      // P2P above 16 FP32 columns: 0 LDS-staged densities, 1 scalar densities (XRL_TUNE_P2P_FORM)
+    int ts_narrow_cols = 1;  // FP32 target-stationary: 1..4 columns past the last full tile on 4x4 MFMA blocks
     mutable int64_t scratch_budget = 0;  // bytes for the offset-stationary per-pair scratch (0: not set)
     int KP = 96, KK = 84;  // padded row / k dims of the M2L operator tiles
     // moment table per sorted panel, scaled to its leaf: [N][K]

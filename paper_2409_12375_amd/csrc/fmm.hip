@@ -601,7 +601,18 @@ __device__ inline T flip_sign(T v, uint32_t bit)
 // |o|) << 3 | reflection bits, and T_o = S T_|o| S is applied by flipping
 // the signs of the B fragments (columns) and of the A fragments (rows), so
 // only 64 operators (L2-resident) are streamed instead of 316.
-template <typename T, int ORD, int WT, bool REFL>
+//
+// XC = 4 (FP32): the item also owns the (up to) four columns after its WT
+// tiles and applies the operator to them with the 16-block 4x4x1 MFMA on
+// the operator fragments already in registers, instead of a further 16x16x4
+// tile that would be at most a quarter useful (C = 36: two tiles plus 4x4
+// blocks, a quarter of the MFMA cycles less per pair).  Lane (li, kq) holds
+// operator row 16 rt + li at k = 4 ks + kq and loads density column
+// cx + (li & 3) of row 4 ks + kq, so block b = lane / 4 sees rows
+// 16 rt + 4 (li / 4) + 0..3 times the four columns at one k; each block sums
+// its k-subset, and the four k-subsets are added across lanes once per
+// target.
+template <typename T, int ORD, int WT, bool REFL, int XC = 0>
 __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt, const int32_t *__restrict__ red_tgt,
                                                   const int32_t *__restrict__ red_ptr,
                                                   const int32_t *__restrict__ ts_src,
@@ -614,6 +625,7 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
     constexpr int VEC = 16 / sizeof(T);
     constexpr int NKV = (D::NKS + VEC - 1) / VEC;
     using AV = T __attribute__((ext_vector_type(VEC)));
+    static_assert(XC == 0 || (XC == 4 && sizeof(T) == 4), "4x4-block columns: four, FP32 only");
     // K = 16 n + 1 (orders 6 and 8): the last operator row is applied on the
     // vector ALU from the B fragments already in registers (21 FMAs per
     // column tile and pair), instead of a 16-row MFMA tile that is 15/16
@@ -635,6 +647,8 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
     // last k step is clamped to K - 1, where the operator column is zero.
     const int boff = kq * C + cb + WT * li;
     const int blast = min(4 * (D::NKS - 1) + kq, D::K - 1) * C - 4 * (D::NKS - 1) * C - kq * C;
+    const int cx = cb + WT * 16;  // first vector-ALU column (XC > 0)
+    const int xoff = kq * C + cx + (li & 3);
     struct BV {
         T v[WT];
     };
@@ -646,22 +660,33 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
     T tacc[WT];
 #pragma unroll
     for (int ct = 0; ct < WT; ++ct) tacc[ct] = T(0);
+    VT accx[XC ? NRTM : 1], taccx = VT{0, 0, 0, 0};
+#pragma unroll
+    for (int rt = 0; rt < (XC ? NRTM : 1); ++rt) accx[rt] = VT{0, 0, 0, 0};
     // Reflection sign masks of this lane, per axis a: bit ks of col[a] for
     // the coefficient 4 ks + kq it feeds as B, bit 4 rt + e of acm[a] for the
     // accumulator element (rt, e), whose row is 16 rt + mfma_row(kq, e).
-    uint64_t col[3] = {0, 0, 0}, acm[3] = {0, 0, 0};
+    // Bit 4 rt + i of axm[a]: the same for element i of the 4x4-block
+    // accumulator of row tile rt, whose row is 16 rt + 4 (li / 4) + i.
+    uint64_t col[3] = {0, 0, 0}, acm[3] = {0, 0, 0}, axm[3] = {0, 0, 0};
     if constexpr (REFL) {
         for (int ks = 0; ks < D::NKS; ++ks) {
             const int kk = 4 * ks + kq;
             const int sg = kk < D::K ? reflection_signs(kk) : 0;
             for (int a = 0; a < 3; ++a) col[a] |= (uint64_t)((sg >> a) & 1) << ks;
         }
-        for (int rt = 0; rt < D::NRT; ++rt)
+        for (int rt = 0; rt < D::NRT; ++rt) {
             for (int e = 0; e < 4; ++e) {
                 const int r = 16 * rt + mfma_row<T>(kq, e);
                 const int sg = r < D::K ? reflection_signs(r) : 0;
                 for (int a = 0; a < 3; ++a) acm[a] |= (uint64_t)((sg >> a) & 1) << (4 * rt + e);
             }
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * rt + 4 * (li >> 2) + i;
+                const int sg = r < D::K ? reflection_signs(r) : 0;
+                for (int a = 0; a < 3; ++a) axm[a] |= (uint64_t)((sg >> a) & 1) << (4 * rt + i);
+            }
+        }
     }
     auto mask_of = [&](const uint64_t (&m)[3], int rf) {
         uint64_t x = 0;
@@ -683,6 +708,13 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
             for (int ct = 0; ct < WT; ++ct)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) acc[rt][ct][e] = flip_sign(acc[rt][ct][e], (uint32_t)(m >> (4 * rt + e)) & 1u);
+        if constexpr (XC > 0) {
+            const uint64_t mx = mask_of(axm, d);
+#pragma unroll
+            for (int rt = 0; rt < NRTM; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) accx[rt][i] = flip_sign(accx[rt][i], (uint32_t)(mx >> (4 * rt + i)) & 1u);
+        }
         if constexpr (TAIL) {  // the last row, summed on the vector ALU
             const int sg = reflection_signs(D::K - 1);
             int f = 0;
@@ -691,6 +723,9 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
                 if (d >> a & 1) f ^= (sg >> a) & 1;
 #pragma unroll
             for (int ct = 0; ct < WT; ++ct) tacc[ct] = flip_sign(tacc[ct], (uint32_t)f);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (XC) taccx[i] = flip_sign(taccx[i], (uint32_t)f);
         }
     };
     // Software pipeline over (pair, row-tile group) steps: the operator of a
@@ -703,7 +738,11 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
     constexpr int GR = (NRTM + 2) / 3;  // row tiles per group
     AV r0[GR][NKV], r1[GR][NKV];
     T bc[WT][D::NKS], bn[WT][D::NKS];
+    T xc[XC ? D::NKS : 1], xn[XC ? D::NKS : 1];
     AV tn[TAIL ? NKV : 1], tcv[TAIL ? NKV : 1];
+    auto xmfma = [&](VT &d, T a, T x) {
+        if constexpr (XC > 0) d = __builtin_amdgcn_mfma_f32_4x4x1f32(a, x, d, 0, 0, 0);
+    };
     auto load_t = [&](int code) {
         if constexpr (TAIL) {
             const AV *tp = reinterpret_cast<const AV *>(op_tail + ((int64_t)(code >> 3) * 4 + kq) * NKV * VEC);
@@ -717,6 +756,9 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
             for (int ks = 0; ks < D::NKS; ++ks)
 #pragma unroll
                 for (int ct = 0; ct < WT; ++ct) tacc[ct] += tcv[ks / VEC][ks % VEC] * bc[ct][ks];
+            if constexpr (XC > 0)
+#pragma unroll
+                for (int ks = 0; ks < D::NKS; ++ks) xmfma(taccx, tcv[ks / VEC][ks % VEC], xc[ks]);
         }
     };
     auto load_b = [&](int j, T (&dst)[WT][D::NKS]) {
@@ -727,6 +769,7 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
             const BV v = *reinterpret_cast<const BV *>(Ms + rofs + boff);
 #pragma unroll
             for (int ct = 0; ct < WT; ++ct) dst[ct][ks] = v.v[ct];
+            if constexpr (XC > 0) xn[ks] = Ms[rofs + xoff];
         }
     };
     auto load_g = [&](int code, int g, AV (&dst)[GR][NKV]) {
@@ -744,6 +787,9 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
 #pragma unroll
             for (int ct = 0; ct < WT; ++ct)
                 bc[ct][ks] = REFL ? flip_sign(bn[ct][ks], (uint32_t)(cm >> ks) & 1u) : bn[ct][ks];
+        if constexpr (XC > 0)
+#pragma unroll
+            for (int ks = 0; ks < D::NKS; ++ks) xc[ks] = REFL ? flip_sign(xn[ks], (uint32_t)(cm >> ks) & 1u) : xn[ks];
         if constexpr (TAIL)
 #pragma unroll
             for (int kv = 0; kv < NKV; ++kv) tcv[kv] = tn[kv];
@@ -753,10 +799,12 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
         for (int r = 0; r < GR; ++r) {
             if (g * GR + r >= NRTM) break;
 #pragma unroll
-            for (int ks = 0; ks < D::NKS; ++ks)
+            for (int ks = 0; ks < D::NKS; ++ks) {
 #pragma unroll
                 for (int ct = 0; ct < WT; ++ct)
                     mfma_16x16x4<T>(av[r][ks / VEC][ks % VEC], bc[ct][ks], acc[g * GR + r][ct]);
+                if constexpr (XC > 0) xmfma(accx[g * GR + r], av[r][ks / VEC][ks % VEC], xc[ks]);
+            }
         }
     };
     if (j0 < j1) {
@@ -845,6 +893,36 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
             v += __shfl_xor(v, 32);
             const int col = cb + WT * li + ct;
             if (kq == 0 && col < C) {
+                T *o = out + ((int64_t)t * D::K + D::K - 1) * C + col;
+                *o = accumulate ? *o + v : v;
+            }
+        }
+    }
+    if constexpr (XC > 0) {
+        // 4x4 block accumulators: lane (li, kq) holds column cx + (li & 3),
+        // rows 16 rt + 4 (li / 4) + i in element i, for its k-subset; after
+        // the sum over the four k-subsets it stores element i = kq
+        const int col = cx + (li & 3);
+#pragma unroll
+        for (int rt = 0; rt < NRTM; ++rt) {
+            VT v = accx[rt];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v[i] += __shfl_xor(v[i], 16);
+                v[i] += __shfl_xor(v[i], 32);
+            }
+            const T mine = kq == 0 ? v[0] : kq == 1 ? v[1] : kq == 2 ? v[2] : v[3];
+            const int row = 16 * rt + 4 * (li >> 2) + kq;
+            if (col < C && row < D::K) {
+                T *o = out + ((int64_t)t * D::K + row) * C + col;
+                *o = accumulate ? *o + mine : mine;
+            }
+        }
+        if constexpr (TAIL) {  // every row of a block holds the last operator row
+            T v = taccx[0];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (kq == 0 && li < 4 && col < C) {
                 T *o = out + ((int64_t)t * D::K + D::K - 1) * C + col;
                 *o = accumulate ? *o + v : v;
             }
@@ -1006,46 +1084,61 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
     // M2L target-stationary from ts_min_cols real columns on
     if (eng == XRL_M2L_MFMA_TS || (eng == XRL_M2L_MFMA && (!refl || C >= P->ts_min_cols))) {
         // tiles per wave: the widest (up to the register budget) that wastes
-        // the fewest padded tiles
+        // the fewest padded tiles; in FP32, one to four columns past the last
+        // full tile go to 4x4 MFMA blocks of the same wave instead of a tile
+        const bool lean = refl ? P->ts_kernel == 2 : TP.n_pairs < 2 * TP.n_red;
         const int ntiles = (int)cdiv(C, 16);
         const int wmax = ts_max_tiles<T, ORD>();
+        // (up to two full tiles: with three, the accumulators of the extra
+        // blocks no longer fit the registers)
+        const bool xc = !lean && sizeof(T) == 4 && P->ts_narrow_cols && C > 16 && C % 16 >= 1 && C % 16 <= 4 &&
+                        ntiles - 1 <= std::min(wmax, 2);
         int WT = 1;
-        for (int w = 1; w <= wmax; ++w)
-            if (cdiv(ntiles, w) * w <= cdiv(ntiles, WT) * WT) WT = w;
-        const int ipt = (int)cdiv(ntiles, WT);
+        if (xc)
+            WT = ntiles - 1;
+        else
+            for (int w = 1; w <= wmax; ++w)
+                if (cdiv(ntiles, w) * w <= cdiv(ntiles, WT) * WT) WT = w;
+        const int ipt = xc ? 1 : (int)cdiv(ntiles, WT);
         const int64_t n_items = TP.n_red * ipt;
         XRL_CHECK(n_items < (int64_t(1) << 31), XRL_E_UNSUPPORTED, "xrl_fmm_matvec: too many translation items");
         const unsigned nb = (unsigned)n_items;
-        auto go = [&](auto wt) {
-            constexpr int W = decltype(wt)::value;
+        auto go = [&](auto wt, auto xcols) {
+            constexpr int W = decltype(wt)::value, X = decltype(xcols)::value;
             if (refl && P->ts_kernel == 1)
-                k_trans_ts<T, ORD, W, true><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
-                                                              TP.ts_src.p, TP.ts_op.p, op_vec, op_tail, in, C,
-                                                              accumulate, out);
-            else if (refl && P->ts_kernel == 2)
+                k_trans_ts<T, ORD, W, true, X><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                                                                 TP.ts_src.p, TP.ts_op.p, op_vec, op_tail, in, C,
+                                                                 accumulate, out);
+            else if (lean)
                 k_trans_ts_lean<T, ORD, W><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
-                                                              TP.ts_src.p, TP.ts_op_full.p, op_full, in, C,
-                                                              accumulate, out);
+                                                              TP.ts_src.p, refl ? TP.ts_op_full.p : TP.ts_op.p,
+                                                              refl ? op_full : op_vec, in, C, accumulate, out);
             else if (refl)
-                k_trans_ts<T, ORD, W, false><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
-                                                               TP.ts_src.p, TP.ts_op_full.p, op_full, op_full_tail, in,
-                                                               C, accumulate, out);
-            else if (TP.n_pairs < 2 * TP.n_red)  // L2L: one pair per target, nothing to pipeline across
-                k_trans_ts_lean<T, ORD, W><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
-                                                              TP.ts_src.p, TP.ts_op.p, op_vec, in, C, accumulate,
-                                                              out);
+                k_trans_ts<T, ORD, W, false, X><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                                                                  TP.ts_src.p, TP.ts_op_full.p, op_full, op_full_tail,
+                                                                  in, C, accumulate, out);
             else
-                k_trans_ts<T, ORD, W, false><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
-                                                               TP.ts_src.p, TP.ts_op.p, op_vec, op_tail, in, C,
-                                                               accumulate, out);
+                k_trans_ts<T, ORD, W, false, X><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                                                                  TP.ts_src.p, TP.ts_op.p, op_vec, op_tail, in, C,
+                                                                  accumulate, out);
         };
-        if (WT == 1) go(std::integral_constant<int, 1>());
+        using I0 = std::integral_constant<int, 0>;
+        auto go_w = [&](auto wt) {
+            if constexpr (sizeof(T) == 4) {
+                if (xc) {
+                    go(wt, std::integral_constant<int, 4>());
+                    return;
+                }
+            }
+            go(wt, I0());
+        };
+        if (WT == 1) go_w(std::integral_constant<int, 1>());
         if constexpr (ts_max_tiles<T, ORD>() >= 2)
-            if (WT == 2) go(std::integral_constant<int, 2>());
+            if (WT == 2) go_w(std::integral_constant<int, 2>());
         if constexpr (ts_max_tiles<T, ORD>() >= 3)
-            if (WT == 3) go(std::integral_constant<int, 3>());
+            if (WT == 3) go(std::integral_constant<int, 3>(), I0());
         if constexpr (ts_max_tiles<T, ORD>() >= 4)
-            if (WT == 4) go(std::integral_constant<int, 4>());
+            if (WT == 4) go(std::integral_constant<int, 4>(), I0());
         XRL_HIP(hipGetLastError());
         return;
     }
@@ -1539,6 +1632,29 @@ extern "C" xrl_status xrl_selftest_mfma(int32_t dtype, const void *A, const void
     });
 }
 
+// 16 blocks of 4x4x1: lane l = 4 b + r supplies A[b][r] and B[b][r] and
+// receives D_b[i][r] in element i.
+__global__ void k_mfma4_probe(const float *A, const float *B, float *D)
+{
+    const int l = threadIdx.x;
+    f32x4 d = {0, 0, 0, 0};
+    d = __builtin_amdgcn_mfma_f32_4x4x1f32(A[l], B[l], d, 0, 0, 0);
+    for (int i = 0; i < 4; ++i) D[((l >> 2) * 4 + i) * 4 + (l & 3)] = d[i];
+}
+
+extern "C" xrl_status xrl_selftest_mfma_4x4(const float *A, const float *B, float *D)
+{
+    return guarded([&] {
+        XRL_CHECK(A && B && D, XRL_E_INVALID_ARG, "xrl_selftest_mfma_4x4: bad arguments");
+        DevBuf<float> dA(64), dB(64), dD(256);
+        XRL_HIP(hipMemcpy(dA.p, A, 64 * sizeof(float), hipMemcpyHostToDevice));
+        XRL_HIP(hipMemcpy(dB.p, B, 64 * sizeof(float), hipMemcpyHostToDevice));
+        k_mfma4_probe<<<1, 64>>>(dA.p, dB.p, dD.p);
+        XRL_HIP(hipGetLastError());
+        XRL_HIP(hipMemcpy(D, dD.p, 256 * sizeof(float), hipMemcpyDeviceToHost));
+    });
+}
+
 extern "C" xrl_status xrl_plan_set_profiling(xrl_plan *P, int32_t on)
 {
     return guarded([&] {
@@ -1564,6 +1680,11 @@ extern "C" xrl_status xrl_plan_set_tuning(xrl_plan *P, int32_t key, int32_t valu
             case XRL_TUNE_TS_MIN_COLS:
                 XRL_CHECK(value >= 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: min columns must be >= 1");
                 P->ts_min_cols = value;
+                break;
+            case XRL_TUNE_TS_NARROW_COLS:
+                XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG,
+                          "xrl_plan_set_tuning: narrow columns must be 0 or 1");
+                P->ts_narrow_cols = value;
                 break;
             default: fail(XRL_E_INVALID_ARG, "xrl_plan_set_tuning: unknown key %d", key);
         }

@@ -56,6 +56,14 @@ def test_mfma_operand_layout():
         assert L.xrl_selftest_mfma(eb, A.ctypes.data, B.ctypes.data, D.ctypes.data) == 0
         tol = 1e-5 if eb == 4 else 1e-13
         assert np.allclose(D, A.astype(np.float64) @ B.astype(np.float64), rtol=tol, atol=tol)
+    # 16 blocks of 4x4x1 (the columns past the last full tile)
+    L.xrl_selftest_mfma_4x4.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    A = rng.standard_normal((16, 4)).astype(np.float32)
+    B = rng.standard_normal((16, 4)).astype(np.float32)
+    D = np.zeros((16, 4, 4), dtype=np.float32)
+    assert L.xrl_selftest_mfma_4x4(A.ctypes.data, B.ctypes.data, D.ctypes.data) == 0
+    ref = A.astype(np.float64)[:, :, None] * B.astype(np.float64)[:, None, :]
+    assert np.allclose(D, ref, rtol=1e-6, atol=1e-6)
 
 
 def test_interaction_lists_cover_every_pair_exactly_once():
@@ -125,11 +133,13 @@ def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
     x = I.densities(N, 18, np.complex64)
     tree = xrl.Tree(V, T)
     ys = {}
-    for eng in ("mfma", "mfma_os", "refl", "lean", "p2p_scalar"):
-        plan = xrl.Plan(tree, order=8, precision="mixed",
-                        engine="mfma" if eng in ("refl", "lean", "p2p_scalar") else eng, max_cols=18)
+    for eng in ("mfma", "mfma_os", "refl", "lean", "p2p_scalar", "padded", "refl_padded"):
+        plan = xrl.Plan(tree, order=8, precision="mixed", engine="mfma_os" if eng == "mfma_os" else "mfma",
+                        max_cols=18)
         plan.assemble()
-        if eng == "refl":  # the reflected 64-operator table
+        if eng in ("padded", "refl_padded"):  # the last four columns in a padded 16-column tile
+            plan.set_tuning("ts_narrow_cols", 0)
+        if eng in ("refl", "refl_padded"):  # the reflected 64-operator table
             plan.set_tuning("ts_kernel", 1)
         if eng == "lean":  # two waves per SIMD, no explicit pipeline
             plan.set_tuning("ts_kernel", 2)
@@ -145,10 +155,42 @@ def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
     d = np.linalg.norm(ys["mfma"] - ys["mfma_os"], axis=0) / np.linalg.norm(ys["mfma_os"], axis=0)
     say("  target- vs offset-stationary", d.max())
     assert d.max() < 1e-6
-    for v in ("refl", "lean", "p2p_scalar"):
+    for v in ("refl", "lean", "p2p_scalar", "padded", "refl_padded"):
         d = np.linalg.norm(ys["mfma"] - ys[v], axis=0) / np.linalg.norm(ys[v], axis=0)
         say("  kernel form %s vs default" % v, d.max())
         assert d.max() < 1e-6
+
+
+@pytest.mark.parametrize("ncomplex", [9, 10, 17])
+def test_narrow_columns_past_the_last_tile(ncomplex):
+    """C = 16 n + 2 or + 4 real columns: the columns past the last full tile
+    on 4x4 MFMA blocks (default), against the padded tile, the
+    offset-stationary kernels and the oracle."""
+    say("case: bar 4096, %d columns, narrow columns on 4x4 blocks" % ncomplex)
+    V, T = I.bar()
+    N = len(T)
+    x = I.densities(N, ncomplex, np.complex64, seed=40 + ncomplex)
+    tree = xrl.Tree(V, T)
+    ys = {}
+    for v in ("narrow", "padded", "refl", "mfma_os"):
+        plan = xrl.Plan(tree, order=8, precision="mixed", engine="mfma_os" if v == "mfma_os" else "mfma",
+                        max_cols=ncomplex)
+        plan.assemble()
+        if v == "padded":
+            plan.set_tuning("ts_narrow_cols", 0)
+        if v == "refl":
+            plan.set_tuning("ts_kernel", 1)
+        ys[v] = plan.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+        plan.close()
+    for v in ("padded", "refl", "mfma_os"):
+        d = np.linalg.norm(ys["narrow"] - ys[v], axis=0) / np.linalg.norm(ys[v], axis=0)
+        say("  narrow vs %s" % v, d.max())
+        assert d.max() < 1e-6
+    rows = sample_rows(N, 64)
+    ref, _ = O.matvec(V, T, x.astype(np.complex128), rows=rows)
+    err = relerr_cols(ys["narrow"][rows], ref)
+    say("  rel L2 per column", err.max())
+    assert err.max() <= 5e-5
 
 
 @pytest.mark.parametrize("engine", ["auto", "mfma_ts"])
