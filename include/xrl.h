@@ -295,6 +295,9 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
  *   XRL_TUNE_P2P_FORM    (0/1, default 0): P2P above 16 FP32 columns with the
  *       source densities staged in LDS (0) or read as wave-uniform scalars
  *       (1, one lane per target).
+ *   XRL_TUNE_TS_ORDER    (0/1, default 1): launch order of the
+ *       target-stationary translations: the targets with the most pairs
+ *       first (1) or in box order (0).
  *   XRL_TUNE_TS_NARROW_COLS (0/1, default 1): FP32 target-stationary forms
  *       0 and 1 with 1..4 real columns past the last full 16-column tile
  *       (C = 16 n + 1 .. 16 n + 4, e.g. 18 complex columns): those columns
@@ -305,6 +308,7 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
 #define XRL_TUNE_TS_MIN_COLS 1
 #define XRL_TUNE_P2P_FORM 2
 #define XRL_TUNE_TS_NARROW_COLS 3
+#define XRL_TUNE_TS_ORDER 4
 xrl_status xrl_plan_set_tuning(xrl_plan *plan, int32_t key, int32_t value);
 
 /* Graph mode (on != 0): the first xrl_fmm_matvec with a new argument set

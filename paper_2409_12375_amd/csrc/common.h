@@ -182,6 +182,7 @@ struct TransPass {
     xrl::DevBuf<int32_t> ts_src;      // [n_pairs] source box of each pair, target order
     xrl::DevBuf<int32_t> ts_op;       // [n_pairs] target order: operator index << 3 | reflection bits
     xrl::DevBuf<int32_t> ts_op_full;  // [n_pairs] target order: plain operator index << 3 (M2L only)
+    xrl::DevBuf<int32_t> ts_order;    // [n_red] target indices, most pairs first (ties in target order)
     mutable std::vector<std::pair<int64_t, xrl::DevBuf<int32_t>>> item_cache;  // key: (engine, cols)
 };
 
@@ -250,6 +251,7 @@ struct xrl_plan {
     int ts_kernel = 0;
     int ts_min_cols = 16;  // MFMA engine: target-stationary from this many real columns on
     int p2p_form = 0;      // P2P above 16 FP32 columns: 0 LDS-staged densities, 1 scalar densities (XRL_TUNE_P2P_FORM)
+    int ts_order = 1;        // target-stationary launch order: 1 most pairs first, 0 target order
     int ts_narrow_cols = 1;  // FP32 target-stationary: 1..4 columns past the last full tile on 4x4 MFMA blocks
     mutable int64_t scratch_budget = 0;  // bytes for the offset-stationary per-pair scratch (0: not set)
     int KP = 96, KK = 84;  // padded row / k dims of the M2L operator tiles

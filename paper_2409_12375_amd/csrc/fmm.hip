@@ -560,6 +560,59 @@ __global__ __launch_bounds__(256) void k_m2l_os_valu(const int32_t *__restrict__
 // Widest item (column tiles) whose accumulators, double-buffered B
 // fragments and the two operator ring buffers stay within about 480
 // registers.
+// Raw buffer loads: the per-pair base goes into the (scalar) resource, the
+// lane part into one vector offset and the per-step part into the scalar
+// offset, so the address arithmetic stays off the vector ALU.  Every access
+// lies inside the record count given here (a range check would return
+// zeros, never fault).
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int W>
+struct Words {
+    uint32_t w[W];
+};
+
+template <int W>
+__device__ inline Words<W> buf_load_words(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    Words<W> o;
+    if constexpr (W == 1) {
+        o.w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    } else if constexpr (W == 2) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+        o.w[0] = v[0];
+        o.w[1] = v[1];
+    } else if constexpr (W == 3) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
+        o.w[0] = v[0];
+        o.w[1] = v[1];
+        o.w[2] = v[2];
+    } else if constexpr (W == 4) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        o.w[0] = v[0];
+        o.w[1] = v[1];
+        o.w[2] = v[2];
+        o.w[3] = v[3];
+    } else {
+        const Words<4> a = buf_load_words<4>(r, voff, soff);
+        const Words<W - 4> b = buf_load_words<W - 4>(r, voff + 16, soff);
+        for (int i = 0; i < 4; ++i) o.w[i] = a.w[i];
+        for (int i = 0; i < W - 4; ++i) o.w[4 + i] = b.w[i];
+    }
+    return o;
+}
+
+// A value of type V (a whole number of 32-bit words) by one buffer load.
+template <typename V>
+__device__ inline V buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    static_assert(sizeof(V) % 4 == 0, "word-sized values only");
+    return __builtin_bit_cast(V, buf_load_words<sizeof(V) / 4>(r, voff, soff));
+}
+
 template <typename T, int ORD>
 constexpr int ts_max_tiles()
 {
@@ -613,7 +666,8 @@ __device__ inline T flip_sign(T v, uint32_t bit)
 // its k-subset, and the four k-subsets are added across lanes once per
 // target.
 template <typename T, int ORD, int WT, bool REFL, int XC = 0>
-__global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt, const int32_t *__restrict__ red_tgt,
+__global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt, const int32_t *__restrict__ order,
+                                                  const int32_t *__restrict__ red_tgt,
                                                   const int32_t *__restrict__ red_ptr,
                                                   const int32_t *__restrict__ ts_src,
                                                   const int32_t *__restrict__ ts_op, const T *__restrict__ op_vec,
@@ -636,8 +690,11 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
     const int w = blockIdx.x;
     if (w >= n_items) return;
     const int lane = threadIdx.x & 63, li = lane & 15, kq = lane >> 4;
-    const int ti = w / items_per_tgt;
-    const int cb = (w - ti * items_per_tgt) * WT * 16;  // first column of the item
+    // targets in launch order (order: a permutation of the target list,
+    // those with the most pairs first, so that no long target starts last)
+    const int slot = w / items_per_tgt;
+    const int ti = order ? order[slot] : slot;
+    const int cb = (w - slot * items_per_tgt) * WT * 16;  // first column of the item
     const int t = red_tgt[ti], j0 = red_ptr[ti], j1 = red_ptr[ti + 1];
     // Columns are interleaved over the WT tiles: lane li feeds column
     // cb + WT li + ct to tile ct, so its B values of one coefficient row are
@@ -737,64 +794,74 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
     // enough that the accumulators never leave their registers.
     constexpr int GR = (NRTM + 2) / 3;  // row tiles per group
     AV r0[GR][NKV], r1[GR][NKV];
-    T bc[WT][D::NKS], bn[WT][D::NKS];
-    T xc[XC ? D::NKS : 1], xn[XC ? D::NKS : 1];
-    AV tn[TAIL ? NKV : 1], tcv[TAIL ? NKV : 1];
+    // per-pair operands (B fragments, 4x4-block densities, last operator
+    // row), in two sets that alternate between the two pairs of a trip, so
+    // the next pair's loads land in place without copies
+    struct PB {
+        T b[WT][D::NKS];
+        T x[XC ? D::NKS : 1];
+        AV t[TAIL ? NKV : 1];
+    };
+    PB p0, p1;
     auto xmfma = [&](VT &d, T a, T x) {
         if constexpr (XC > 0) d = __builtin_amdgcn_mfma_f32_4x4x1f32(a, x, d, 0, 0, 0);
     };
-    auto load_t = [&](int code) {
+    auto load_t = [&](int code, PB &d) {
         if constexpr (TAIL) {
-            const AV *tp = reinterpret_cast<const AV *>(op_tail + ((int64_t)(code >> 3) * 4 + kq) * NKV * VEC);
+            const auto rs = buf_rsrc(op_tail + (int64_t)(code >> 3) * 4 * NKV * VEC, 4 * NKV * VEC * sizeof(T));
 #pragma unroll
-            for (int kv = 0; kv < NKV; ++kv) tn[kv] = tp[kv];
+            for (int kv = 0; kv < NKV; ++kv) d.t[kv] = buf_load<AV>(rs, (kq * NKV + kv) * VEC * (int)sizeof(T), 0);
         }
     };
-    auto tail_fma = [&]() {
+    auto tail_fma = [&](const PB &p) {
         if constexpr (TAIL) {
 #pragma unroll
             for (int ks = 0; ks < D::NKS; ++ks)
 #pragma unroll
-                for (int ct = 0; ct < WT; ++ct) tacc[ct] += tcv[ks / VEC][ks % VEC] * bc[ct][ks];
+                for (int ct = 0; ct < WT; ++ct) tacc[ct] += p.t[ks / VEC][ks % VEC] * p.b[ct][ks];
             if constexpr (XC > 0)
 #pragma unroll
-                for (int ks = 0; ks < D::NKS; ++ks) xmfma(taccx, tcv[ks / VEC][ks % VEC], xc[ks]);
+                for (int ks = 0; ks < D::NKS; ++ks) xmfma(taccx, p.t[ks / VEC][ks % VEC], p.x[ks]);
         }
     };
-    auto load_b = [&](int j, T (&dst)[WT][D::NKS]) {
-        const T *Ms = in + (int64_t)ts_src[j] * D::K * C;
+    // the source record and the 256 elements after it (columns past C and
+    // the clamped last k step read at most that far)
+    const uint32_t mbytes = (uint32_t)((D::K * C + 256) * sizeof(T));
+    auto load_b = [&](int j, PB &d) {
+        const auto rs = buf_rsrc(in + (int64_t)ts_src[j] * D::K * C, mbytes);
 #pragma unroll
         for (int ks = 0; ks < D::NKS; ++ks) {
-            const int rofs = 4 * ks * C + (ks == D::NKS - 1 ? blast : 0);
-            const BV v = *reinterpret_cast<const BV *>(Ms + rofs + boff);
+            const int lofs = ks == D::NKS - 1 ? blast : 0;  // lane part of the clamp
+            const int sofs = 4 * ks * C * (int)sizeof(T);
+            const BV v = buf_load<BV>(rs, (boff + lofs) * (int)sizeof(T), sofs);
 #pragma unroll
-            for (int ct = 0; ct < WT; ++ct) dst[ct][ks] = v.v[ct];
-            if constexpr (XC > 0) xn[ks] = Ms[rofs + xoff];
+            for (int ct = 0; ct < WT; ++ct) d.b[ct][ks] = v.v[ct];
+            if constexpr (XC > 0) d.x[ks] = buf_load<T>(rs, (xoff + lofs) * (int)sizeof(T), sofs);
         }
     };
+    constexpr uint32_t obytes = D::NRT * NKV * 64 * 16;  // one operator in vector fragment order
     auto load_g = [&](int code, int g, AV (&dst)[GR][NKV]) {
-        const AV *Tv = reinterpret_cast<const AV *>(op_vec) + (int64_t)(code >> 3) * D::NRT * NKV * 64 + lane;
+        const auto rs = buf_rsrc(op_vec + (int64_t)(code >> 3) * D::NRT * NKV * 64 * VEC, obytes);
 #pragma unroll
         for (int r = 0; r < GR; ++r)
             if (g * GR + r < NRTM)
 #pragma unroll
-                for (int kv = 0; kv < NKV; ++kv) dst[r][kv] = Tv[((g * GR + r) * NKV + kv) * 64];
+                for (int kv = 0; kv < NKV; ++kv) dst[r][kv] = buf_load<AV>(rs, lane * 16, ((g * GR + r) * NKV + kv) * 1024);
     };
-    auto take_b = [&](int code) {
-        const uint64_t cm = REFL ? mask_of(col, code & 7) : 0;
+    // column signs of a reflected offset, applied in place once the loads
+    // have landed
+    auto flip_b = [&](int code, PB &d) {
+        if constexpr (REFL) {
+            const uint64_t cm = mask_of(col, code & 7);
 #pragma unroll
-        for (int ks = 0; ks < D::NKS; ++ks)
+            for (int ks = 0; ks < D::NKS; ++ks) {
 #pragma unroll
-            for (int ct = 0; ct < WT; ++ct)
-                bc[ct][ks] = REFL ? flip_sign(bn[ct][ks], (uint32_t)(cm >> ks) & 1u) : bn[ct][ks];
-        if constexpr (XC > 0)
-#pragma unroll
-            for (int ks = 0; ks < D::NKS; ++ks) xc[ks] = REFL ? flip_sign(xn[ks], (uint32_t)(cm >> ks) & 1u) : xn[ks];
-        if constexpr (TAIL)
-#pragma unroll
-            for (int kv = 0; kv < NKV; ++kv) tcv[kv] = tn[kv];
+                for (int ct = 0; ct < WT; ++ct) d.b[ct][ks] = flip_sign(d.b[ct][ks], (uint32_t)(cm >> ks) & 1u);
+                if constexpr (XC > 0) d.x[ks] = flip_sign(d.x[ks], (uint32_t)(cm >> ks) & 1u);
+            }
+        }
     };
-    auto compute = [&](int g, AV (&av)[GR][NKV]) {
+    auto compute = [&](int g, AV (&av)[GR][NKV], const PB &p) {
 #pragma unroll
         for (int r = 0; r < GR; ++r) {
             if (g * GR + r >= NRTM) break;
@@ -802,8 +869,8 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
             for (int ks = 0; ks < D::NKS; ++ks) {
 #pragma unroll
                 for (int ct = 0; ct < WT; ++ct)
-                    mfma_16x16x4<T>(av[r][ks / VEC][ks % VEC], bc[ct][ks], acc[g * GR + r][ct]);
-                if constexpr (XC > 0) xmfma(accx[g * GR + r], av[r][ks / VEC][ks % VEC], xc[ks]);
+                    mfma_16x16x4<T>(av[r][ks / VEC][ks % VEC], p.b[ct][ks], acc[g * GR + r][ct]);
+                if constexpr (XC > 0) xmfma(accx[g * GR + r], av[r][ks / VEC][ks % VEC], p.x[ks]);
             }
         }
     };
@@ -811,11 +878,11 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
         auto clampj = [&](int j) { return j < j1 ? j : j1 - 1; };
         int frame = 0;
         int c0 = ts_op[j0], c1 = ts_op[clampj(j0 + 1)];
-        load_b(j0, bn);
-        load_t(c0);
+        load_b(j0, p0);
+        load_t(c0, p0);
         load_g(c0, 0, r0);
         load_g(c0, 1, r1);
-        take_b(c0);
+        flip_b(c0, p0);
         auto reframe = [&](int code) {
             if constexpr (REFL) {
                 if ((code & 7) != frame) {
@@ -824,46 +891,47 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
                 }
             }
         };
-        // two pairs per trip, so that the ring parity is static
+        // two pairs per trip, so that the ring parity and the operand set
+        // of each pair are static
         for (int j = j0; j < j1; j += 2) {
             const int c2 = ts_op[clampj(j + 2)];
             reframe(c0);
             __builtin_amdgcn_sched_barrier(0);
-            compute(0, r0);
-            tail_fma();
+            compute(0, r0, p0);
+            tail_fma(p0);
             __builtin_amdgcn_sched_barrier(0);
-            load_b(clampj(j + 1), bn);
-            load_t(c1);
+            load_b(clampj(j + 1), p1);
+            load_t(c1, p1);
             load_g(c0, 2, r0);
             __builtin_amdgcn_sched_barrier(0);
-            compute(1, r1);
+            compute(1, r1, p0);
             __builtin_amdgcn_sched_barrier(0);
             load_g(c1, 0, r1);
             __builtin_amdgcn_sched_barrier(0);
-            compute(2, r0);
+            compute(2, r0, p0);
             __builtin_amdgcn_sched_barrier(0);
             load_g(c1, 1, r0);
             __builtin_amdgcn_sched_barrier(0);
-            take_b(c1);
+            flip_b(c1, p1);
             if (j + 1 < j1) {
                 reframe(c1);
                 __builtin_amdgcn_sched_barrier(0);
-                compute(0, r1);
-                tail_fma();
+                compute(0, r1, p1);
+                tail_fma(p1);
                 __builtin_amdgcn_sched_barrier(0);
-                load_b(clampj(j + 2), bn);
-                load_t(c2);
+                load_b(clampj(j + 2), p0);
+                load_t(c2, p0);
                 load_g(c1, 2, r1);
                 __builtin_amdgcn_sched_barrier(0);
-                compute(1, r0);
+                compute(1, r0, p1);
                 __builtin_amdgcn_sched_barrier(0);
                 load_g(c2, 0, r0);
                 __builtin_amdgcn_sched_barrier(0);
-                compute(2, r1);
+                compute(2, r1, p1);
                 __builtin_amdgcn_sched_barrier(0);
                 load_g(c2, 1, r1);
                 __builtin_amdgcn_sched_barrier(0);
-                take_b(c2);
+                flip_b(c2, p0);
             }
             c0 = c2;
             c1 = ts_op[clampj(j + 3)];
@@ -1103,10 +1171,11 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
         const int64_t n_items = TP.n_red * ipt;
         XRL_CHECK(n_items < (int64_t(1) << 31), XRL_E_UNSUPPORTED, "xrl_fmm_matvec: too many translation items");
         const unsigned nb = (unsigned)n_items;
+        const int32_t *ord = P->ts_order ? TP.ts_order.p : nullptr;
         auto go = [&](auto wt, auto xcols) {
             constexpr int W = decltype(wt)::value, X = decltype(xcols)::value;
             if (refl && P->ts_kernel == 1)
-                k_trans_ts<T, ORD, W, true, X><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                k_trans_ts<T, ORD, W, true, X><<<nb, 64, 0, s>>>((int)n_items, ipt, ord, TP.red_tgt.p, TP.red_ptr.p,
                                                                  TP.ts_src.p, TP.ts_op.p, op_vec, op_tail, in, C,
                                                                  accumulate, out);
             else if (lean)
@@ -1114,11 +1183,11 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
                                                               TP.ts_src.p, refl ? TP.ts_op_full.p : TP.ts_op.p,
                                                               refl ? op_full : op_vec, in, C, accumulate, out);
             else if (refl)
-                k_trans_ts<T, ORD, W, false, X><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                k_trans_ts<T, ORD, W, false, X><<<nb, 64, 0, s>>>((int)n_items, ipt, ord, TP.red_tgt.p, TP.red_ptr.p,
                                                                   TP.ts_src.p, TP.ts_op_full.p, op_full, op_full_tail,
                                                                   in, C, accumulate, out);
             else
-                k_trans_ts<T, ORD, W, false, X><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
+                k_trans_ts<T, ORD, W, false, X><<<nb, 64, 0, s>>>((int)n_items, ipt, ord, TP.red_tgt.p, TP.red_ptr.p,
                                                                   TP.ts_src.p, TP.ts_op.p, op_vec, op_tail, in, C,
                                                                   accumulate, out);
         };
@@ -1680,6 +1749,10 @@ extern "C" xrl_status xrl_plan_set_tuning(xrl_plan *P, int32_t key, int32_t valu
             case XRL_TUNE_TS_MIN_COLS:
                 XRL_CHECK(value >= 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: min columns must be >= 1");
                 P->ts_min_cols = value;
+                break;
+            case XRL_TUNE_TS_ORDER:
+                XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: order must be 0 or 1");
+                P->ts_order = value;
                 break;
             case XRL_TUNE_TS_NARROW_COLS:
                 XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG,

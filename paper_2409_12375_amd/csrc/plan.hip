@@ -382,6 +382,11 @@ static void build_pass(TransPass &T, const std::vector<int32_t> &tgt, const std:
     }
     T.ts_src.upload(tsrc, s);
     T.ts_op.upload(tcode, s);
+    std::vector<int32_t> heavy(rt.size());
+    std::iota(heavy.begin(), heavy.end(), 0);
+    std::stable_sort(heavy.begin(), heavy.end(),
+                     [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+    T.ts_order.upload(heavy, s);
     if (!ts_code.empty()) {
         for (int64_t j = 0; j < n; ++j) tcode[j] = code[tord[j]] << 3;
         T.ts_op_full.upload(tcode, s);
