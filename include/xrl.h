@@ -292,9 +292,11 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
  *   XRL_TUNE_TS_MIN_COLS (>= 1, default 16): with XRL_M2L_MFMA, the
  *       translations run target-stationary from this many real columns on,
  *       offset-stationary below.
- *   XRL_TUNE_P2P_FORM    (0/1, default 0): P2P above 16 FP32 columns with the
- *       source densities staged in LDS (0) or read as wave-uniform scalars
- *       (1, one lane per target).
+ *   XRL_TUNE_P2P_FORM    (0..2, default 0): P2P above 16 FP32 columns on
+ *       the 16x16x4 MFMA, densities times the stored block (0), on the
+ *       vector ALU with the source densities read as wave-uniform scalars
+ *       (1, one lane per target), or on the vector ALU with the source
+ *       densities staged in LDS (2).
  *   XRL_TUNE_TS_ORDER    (0/1, default 1): launch order of the
  *       target-stationary translations: the targets with the most pairs
  *       first (1) or in box order (0).
@@ -329,14 +331,14 @@ typedef struct {
     int32_t best_engine, best_ts_kernel;
     double best_ms;
     int32_t n_p2p_tried;  /* P2P forms timed with the best translation form (0 when one applies) */
-    double p2p_ms[2];     /* mean matvec time with XRL_TUNE_P2P_FORM = 0, 1 */
+    double p2p_ms[3];     /* mean matvec time with XRL_TUNE_P2P_FORM = 0, 1, 2 */
     int32_t best_p2p_form;
 } xrl_tune_result;
 
 /* Times `reps` matvecs (after one warm-up) with each translation form that
  * applies to the plan's precision (MFMA plans: offset-stationary and the three
  * target-stationary forms; the vector-ALU plan has one form) on the caller's
- * arguments, keeps the fastest in the plan, then does the same for the two
+ * arguments, keeps the fastest in the plan, then does the same for the three
  * P2P forms when more than 16 FP32 columns are carried.  y is overwritten.
  * The forms agree to rounding, so the choice only changes speed.
  * Errors: XRL_E_INVALID_ARG, XRL_E_STATE (not assembled), XRL_E_HIP. */

@@ -250,7 +250,7 @@ struct xrl_plan {
     // form of the target-stationary M2L (XRL_TUNE_TS_KERNEL)
     int ts_kernel = 0;
     int ts_min_cols = 16;  // MFMA engine: target-stationary from this many real columns on
-    int p2p_form = 0;      // P2P above 16 FP32 columns: 0 LDS-staged densities, 1 scalar densities (XRL_TUNE_P2P_FORM)
+    int p2p_form = 0;  // P2P above 16 FP32 columns: 0 MFMA, 1 scalar densities, 2 LDS-staged (XRL_TUNE_P2P_FORM)
     int ts_order = 1;        // target-stationary launch order: 1 most pairs first, 0 target order
     int ts_narrow_cols = 1;  // FP32 target-stationary: 1..4 columns past the last full tile on 4x4 MFMA blocks
     mutable int64_t scratch_budget = 0;  // bytes for the offset-stationary per-pair scratch (0: not set)

@@ -68,6 +68,59 @@ __global__ void k_scatter_y(int64_t N, const int32_t *__restrict__ perm, const T
     }
 }
 
+// Raw buffer loads: a wave-uniform base goes into the (scalar) resource,
+// the lane part into one vector offset and a uniform per-step part into the
+// scalar offset, so the address arithmetic stays off the vector ALU.  An
+// access whose vector offset lies past the record count returns zeros
+// instead of reading memory.
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int W>
+struct Words {
+    uint32_t w[W];
+};
+
+template <int W>
+__device__ inline Words<W> buf_load_words(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    Words<W> o;
+    if constexpr (W == 1) {
+        o.w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    } else if constexpr (W == 2) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+        o.w[0] = v[0];
+        o.w[1] = v[1];
+    } else if constexpr (W == 3) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
+        o.w[0] = v[0];
+        o.w[1] = v[1];
+        o.w[2] = v[2];
+    } else if constexpr (W == 4) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        o.w[0] = v[0];
+        o.w[1] = v[1];
+        o.w[2] = v[2];
+        o.w[3] = v[3];
+    } else {
+        const Words<4> a = buf_load_words<4>(r, voff, soff);
+        const Words<W - 4> b = buf_load_words<W - 4>(r, voff + 16, soff);
+        for (int i = 0; i < 4; ++i) o.w[i] = a.w[i];
+        for (int i = 0; i < W - 4; ++i) o.w[4 + i] = b.w[i];
+    }
+    return o;
+}
+
+// A value of type V (a whole number of 32-bit words) by one buffer load.
+template <typename V>
+__device__ inline V buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    static_assert(sizeof(V) % 4 == 0, "word-sized values only");
+    return __builtin_bit_cast(V, buf_load_words<sizeof(V) / 4>(r, voff, soff));
+}
+
 // ---------------------------------------------------------------- P2P
 // One workgroup per (target leaf, column tile).  The stored block of a leaf
 // is [rows][tpad]; a thread owns VEC consecutive targets of one row (one
@@ -285,6 +338,138 @@ __global__ __launch_bounds__(64) void k_p2p_sx(const int32_t *__restrict__ leaf_
 #pragma unroll
         for (int c = 0; c < CT; ++c)
             if (c < ncol) yo[c] = acc[c];
+    }
+}
+
+// Matrix-core form (FP32, C > 16): the near field of a leaf is the dense
+// product Y[t][c] = sum over rows r of V[r][t] X[src_r][c], so it runs on
+// the 16x16x4 MFMA with the densities as A (16 columns x 4 rows) and the
+// stored block as B (4 rows x 16 targets).  One wave per (leaf, item of WT
+// column tiles, plus XC = 4 narrow columns on 4x4x1 blocks as in the
+// target-stationary translation).  A lane (li, kq) takes row 4 ks + kq of
+// every k step: E = tpad / 16 consecutive targets E li .. E li + E - 1 of it
+// in one vector load (target E li + e goes to target tile e), and WT
+// consecutive densities (column cb + WT li + ct to column tile ct).  Rows
+// past the block read as zeros (range-checked buffer loads), and so do
+// their source indices, which then point at source 0: every product with
+// a missing row is zero.
+template <int WT, int XC, int E>
+__device__ inline void p2p_mfma_leaf(int lane, int nr, const float *__restrict__ vb, const int32_t *__restrict__ srcs,
+                                     const float *__restrict__ xs, int C, int cb, float *__restrict__ ys, int64_t kb,
+                                     int nt)
+{
+    constexpr int G = 16 * E, U = 4;  // block width; k steps per stage
+    using VE = typename std::conditional<E == 1, float, float __attribute__((ext_vector_type(E)))>::type;
+    struct BV {
+        float v[WT];
+    };
+    struct Stage {
+        VE v[U];
+        BV b[U];
+        float xn[U];
+    };
+    const int li = lane & 15, kq = lane >> 4;
+    f32x4 acc[E][WT], accx[XC ? E : 1];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) acc[e][ct] = f32x4{0, 0, 0, 0};
+        if (XC || e == 0) accx[XC ? e : 0] = f32x4{0, 0, 0, 0};
+    }
+    const auto rv = buf_rsrc(vb, (uint32_t)nr * G * 4);
+    const auto rs = buf_rsrc(srcs, (uint32_t)nr * 4);
+    const int xo = cb + WT * li, xno = cb + 16 * WT + (li & 3);
+    auto load = [&](int ks0, Stage &st) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = 4 * (ks0 + u) + kq;
+            st.v[u] = buf_load<VE>(rv, (r * G + E * li) * 4, 0);
+            const int src = buf_load<int>(rs, r * 4, 0);
+            const float *xr = xs + (int64_t)src * C;
+            st.b[u] = *reinterpret_cast<const BV *>(xr + xo);
+            if constexpr (XC > 0) st.xn[u] = xr[xno];
+        }
+    };
+    auto comp = [&](const Stage &st) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                float bv;
+                if constexpr (E == 1)
+                    bv = st.v[u];
+                else
+                    bv = st.v[u][e];
+#pragma unroll
+                for (int ct = 0; ct < WT; ++ct)
+                    acc[e][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(st.b[u].v[ct], bv, acc[e][ct], 0, 0, 0);
+                if constexpr (XC > 0) accx[e] = __builtin_amdgcn_mfma_f32_4x4x1f32(st.xn[u], bv, accx[e], 0, 0, 0);
+            }
+    };
+    // whole trips of 2 U k steps (the rows past the block read as zeros), so
+    // the loop has one exit and the accumulators stay where the MFMAs put
+    // them
+    const int ntrip = (nr + 8 * U - 1) / (8 * U);
+    Stage s0, s1;
+    load(0, s0);
+    for (int q = 0; q < ntrip; ++q) {
+        const int ks = 2 * U * q;
+        load(ks + U, s1);
+        comp(s0);
+        load(ks + 2 * U, s0);
+        comp(s1);
+    }
+    // D[i][j] of tile (e, ct) at lane j + 16 q, element i - 4 q: column
+    // cb + WT i + ct, target E j + e
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int t = E * li + e;
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct)
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+                const int col = cb + WT * (4 * kq + e4) + ct;
+                if (t < nt && col < C) ys[(kb + t) * C + col] = acc[e][ct][e4];
+            }
+        if constexpr (XC > 0) {
+            // block accumulators: lane (li, kq) holds target E li + e and
+            // narrow columns 0..3 in elements 0..3 for its k-subset; after the
+            // sum over the four k-subsets it stores column kq
+            f32x4 v = accx[e];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v[i] += __shfl_xor(v[i], 16);
+                v[i] += __shfl_xor(v[i], 32);
+            }
+            const float mine = kq == 0 ? v[0] : kq == 1 ? v[1] : kq == 2 ? v[2] : v[3];
+            const int col = cb + 16 * WT + kq;
+            if (t < nt && col < C) ys[(kb + t) * C + col] = mine;
+        }
+    }
+}
+
+template <int WT, int XC>
+__global__ __launch_bounds__(64) void k_p2p_mfma(int items_per_leaf, const int32_t *__restrict__ leaf_box,
+                                                 const int32_t *__restrict__ box_beg,
+                                                 const int32_t *__restrict__ box_end,
+                                                 const int32_t *__restrict__ near_rows,
+                                                 const int32_t *__restrict__ near_src,
+                                                 const int32_t *__restrict__ leaf_tpad,
+                                                 const int64_t *__restrict__ val_off, const float *__restrict__ val,
+                                                 const float *__restrict__ xs, float *__restrict__ ys, int C)
+{
+    const int w = blockIdx.x;
+    const int li = w / items_per_leaf;
+    const int cb = (w - li * items_per_leaf) * 16 * WT;
+    const int lane = threadIdx.x;
+    const int32_t tb = leaf_box[li];
+    const int32_t kb = box_beg[tb], nt = box_end[tb] - kb;
+    const int32_t r0 = near_rows[li], nr = near_rows[li + 1] - r0;
+    const float *vb = val + val_off[li];
+    switch (leaf_tpad[li]) {
+        case 16: p2p_mfma_leaf<WT, XC, 1>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
+        case 32: p2p_mfma_leaf<WT, XC, 2>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
+        default: p2p_mfma_leaf<WT, XC, 4>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
     }
 }
 
@@ -560,59 +745,6 @@ __global__ __launch_bounds__(256) void k_m2l_os_valu(const int32_t *__restrict__
 // Widest item (column tiles) whose accumulators, double-buffered B
 // fragments and the two operator ring buffers stay within about 480
 // registers.
-// Raw buffer loads: the per-pair base goes into the (scalar) resource, the
-// lane part into one vector offset and the per-step part into the scalar
-// offset, so the address arithmetic stays off the vector ALU.  Every access
-// lies inside the record count given here (a range check would return
-// zeros, never fault).
-__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
-}
-
-template <int W>
-struct Words {
-    uint32_t w[W];
-};
-
-template <int W>
-__device__ inline Words<W> buf_load_words(__amdgpu_buffer_rsrc_t r, int voff, int soff)
-{
-    Words<W> o;
-    if constexpr (W == 1) {
-        o.w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
-    } else if constexpr (W == 2) {
-        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
-        o.w[0] = v[0];
-        o.w[1] = v[1];
-    } else if constexpr (W == 3) {
-        const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
-        o.w[0] = v[0];
-        o.w[1] = v[1];
-        o.w[2] = v[2];
-    } else if constexpr (W == 4) {
-        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
-        o.w[0] = v[0];
-        o.w[1] = v[1];
-        o.w[2] = v[2];
-        o.w[3] = v[3];
-    } else {
-        const Words<4> a = buf_load_words<4>(r, voff, soff);
-        const Words<W - 4> b = buf_load_words<W - 4>(r, voff + 16, soff);
-        for (int i = 0; i < 4; ++i) o.w[i] = a.w[i];
-        for (int i = 0; i < W - 4; ++i) o.w[4 + i] = b.w[i];
-    }
-    return o;
-}
-
-// A value of type V (a whole number of 32-bit words) by one buffer load.
-template <typename V>
-__device__ inline V buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff)
-{
-    static_assert(sizeof(V) % 4 == 0, "word-sized values only");
-    return __builtin_bit_cast(V, buf_load_words<sizeof(V) / 4>(r, voff, soff));
-}
-
 template <typename T, int ORD>
 constexpr int ts_max_tiles()
 {
@@ -1260,6 +1392,39 @@ static void p2p_launch(const xrl_plan *P, const T *val, const T *xs, T *ys, int 
 {
     if (P->n_leaves == 0) return;
     if constexpr (sizeof(T) == 4) {
+        if (C > 16 && P->p2p_form == 0) {
+            // column items: WT 16-column tiles (+ four narrow columns when
+            // 1..4 columns are left past the last full tile)
+            const int ntiles = (int)cdiv(C, 16);
+            const bool xc = C % 16 >= 1 && C % 16 <= 4 && ntiles - 1 <= 4;
+            int WT = 1;
+            if (xc)
+                WT = ntiles - 1;
+            else
+                for (int w = 1; w <= 4; ++w)
+                    if (cdiv(ntiles, w) * w <= cdiv(ntiles, WT) * WT) WT = w;
+            const int ipl = xc ? 1 : (int)cdiv(ntiles, WT);
+            const int64_t n_items = P->n_leaves * ipl;
+            XRL_CHECK(n_items < (int64_t(1) << 31), XRL_E_UNSUPPORTED, "xrl_fmm_matvec: too many P2P items");
+            auto mf = [&](auto wt, auto xcols) {
+                constexpr int W = decltype(wt)::value, X = decltype(xcols)::value;
+                k_p2p_mfma<W, X><<<(unsigned)n_items, 64, 0, s>>>(ipl, P->leaf_box.p, P->box_beg.p, P->box_end.p,
+                                                                 P->near_rows.p, P->near_src.p, P->leaf_tpad.p,
+                                                                 P->near_val_off.p, val, xs, ys, C);
+            };
+            auto mw = [&](auto wt) {
+                if (xc)
+                    mf(wt, std::integral_constant<int, 4>());
+                else
+                    mf(wt, std::integral_constant<int, 0>());
+            };
+            if (WT == 1) mw(std::integral_constant<int, 1>());
+            if (WT == 2) mw(std::integral_constant<int, 2>());
+            if (WT == 3) mw(std::integral_constant<int, 3>());
+            if (WT == 4) mw(std::integral_constant<int, 4>());
+            XRL_HIP(hipGetLastError());
+            return;
+        }
         if (C > 16 && P->p2p_form == 1) {
             auto sx = [&](auto ctc) {
                 constexpr int CT = decltype(ctc)::value;
@@ -1362,9 +1527,11 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
     const int C = 2 * ncols;
     const int K = P->K;
     const int64_t N = P->N, B = P->B;
-    if (xs.n < (size_t)(N * C)) {
-        xs.alloc(N * C);
-        ys.alloc(N * C);
+    if (xs.n < (size_t)(N * C + 256)) {
+        // slack after the densities: P2P reads (and discards) the padded
+        // columns of the last source row
+        xs.alloc(N * C + 256);
+        ys.alloc(N * C + 256);
     }
     if (M.n < (size_t)(B * K * C + 256)) {
         // slack after the expansions: the target-stationary kernel reads
@@ -1641,7 +1808,7 @@ extern "C" xrl_status xrl_plan_autotune(xrl_plan *P, const void *x, int64_t ldx,
             XRL_HIP(hipEventCreate(&f0));
             XRL_HIP(hipEventCreate(&f1));
             double bp = 1e300;
-            for (int f = 0; f < 2; ++f) {
+            for (int f = 0; f < 3; ++f) {
                 P->p2p_form = f;
                 enqueue_matvec(P, x, ldx, n_cols, dtype, y, ldy, false, false, s);
                 XRL_HIP(hipEventRecord(f0, s));
@@ -1743,7 +1910,7 @@ extern "C" xrl_status xrl_plan_set_tuning(xrl_plan *P, int32_t key, int32_t valu
                 P->ts_kernel = value;
                 break;
             case XRL_TUNE_P2P_FORM:
-                XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: P2P form must be 0 or 1");
+                XRL_CHECK(value >= 0 && value <= 2, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: P2P form must be 0..2");
                 P->p2p_form = value;
                 break;
             case XRL_TUNE_TS_MIN_COLS:

@@ -42,7 +42,7 @@ class TreeInfo(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("n_tried", _i32), ("engine", _i32 * 8), ("ts_kernel", _i32 * 8), ("ms", ctypes.c_double * 8),
                 ("best_engine", _i32), ("best_ts_kernel", _i32), ("best_ms", ctypes.c_double),
-                ("n_p2p_tried", _i32), ("p2p_ms", ctypes.c_double * 2), ("best_p2p_form", _i32)]
+                ("n_p2p_tried", _i32), ("p2p_ms", ctypes.c_double * 3), ("best_p2p_form", _i32)]
 
 
 class PlanOpts(ctypes.Structure):

@@ -133,7 +133,7 @@ def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
     x = I.densities(N, 18, np.complex64)
     tree = xrl.Tree(V, T)
     ys = {}
-    for eng in ("mfma", "mfma_os", "refl", "lean", "p2p_scalar", "padded", "refl_padded"):
+    for eng in ("mfma", "mfma_os", "refl", "lean", "p2p_scalar", "p2p_lds", "padded", "refl_padded"):
         plan = xrl.Plan(tree, order=8, precision="mixed", engine="mfma_os" if eng == "mfma_os" else "mfma",
                         max_cols=18)
         plan.assemble()
@@ -143,8 +143,10 @@ def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
             plan.set_tuning("ts_kernel", 1)
         if eng == "lean":  # two waves per SIMD, no explicit pipeline
             plan.set_tuning("ts_kernel", 2)
-        if eng == "p2p_scalar":  # P2P with wave-uniform scalar densities
+        if eng == "p2p_scalar":  # P2P on the vector ALU with wave-uniform scalar densities
             plan.set_tuning("p2p_form", 1)
+        if eng == "p2p_lds":  # P2P on the vector ALU with the densities staged in LDS
+            plan.set_tuning("p2p_form", 2)
         ys[eng] = plan.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
         plan.close()
     rows = sample_rows(N, 256)
@@ -155,7 +157,7 @@ def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
     d = np.linalg.norm(ys["mfma"] - ys["mfma_os"], axis=0) / np.linalg.norm(ys["mfma_os"], axis=0)
     say("  target- vs offset-stationary", d.max())
     assert d.max() < 1e-6
-    for v in ("refl", "lean", "p2p_scalar", "padded", "refl_padded"):
+    for v in ("refl", "lean", "p2p_scalar", "p2p_lds", "padded", "refl_padded"):
         d = np.linalg.norm(ys["mfma"] - ys[v], axis=0) / np.linalg.norm(ys[v], axis=0)
         say("  kernel form %s vs default" % v, d.max())
         assert d.max() < 1e-6
@@ -351,7 +353,7 @@ def test_autotune_keeps_the_fastest_form_and_the_result():
     r = plan.autotune(x, reps=2)
     say("  tried", r["tried"], "best", r["best"])
     assert len(r["tried"]) in (3, 4)
-    assert len(r["p2p_tried"]) == 2 and r["best_p2p_form"] in (0, 1)
+    assert len(r["p2p_tried"]) == 3 and r["best_p2p_form"] in (0, 1, 2)
     assert r["best"][2] == min(t[2] for t in r["tried"])
     y1 = plan.matvec(x)
     torch.cuda.synchronize()
