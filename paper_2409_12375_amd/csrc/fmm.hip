@@ -563,6 +563,94 @@ __global__ __launch_bounds__(256) void k_l2p(const int32_t *__restrict__ leaf_bo
     }
 }
 
+// Matrix-core form (FP32, C > 16): per leaf, y[t][c] += sum over i of
+// Q[t][i] (w_i / h) L[i][c], the moment table as A (16 targets x 4
+// coefficients) and the weighted local expansion as B.  Lane (li, kq) takes
+// the NKS consecutive coefficients NKS kq .. NKS kq + NKS - 1, so its moments
+// are contiguous; coefficients past K get a zero moment (their local row is
+// clamped to K - 1).  The expansion fragments are loaded and weighted once
+// per item and reused for every 16-target tile; narrow columns (XC = 4) on
+// 4x4x1 blocks as in the translations.  Moment rows past the leaf read as
+// zeros (range-checked buffer loads).
+template <int ORD, int WT, int XC>
+__global__ __launch_bounds__(64) void k_l2p_mfma(int items_per_leaf, const int32_t *__restrict__ leaf_box,
+                                                 const int32_t *__restrict__ box_beg,
+                                                 const int32_t *__restrict__ box_end,
+                                                 const double *__restrict__ hbox, const float *__restrict__ mom,
+                                                 const float *__restrict__ L, float *__restrict__ ys, int C)
+{
+    constexpr int K = (ORD + 1) * (ORD + 1), NKS = (K + 3) / 4;
+    struct BV {
+        float v[WT];
+    };
+    const int w = blockIdx.x;
+    const int li_leaf = w / items_per_leaf;
+    const int cb = (w - li_leaf * items_per_leaf) * 16 * WT, cn = cb + 16 * WT;
+    const int lane = threadIdx.x, li = lane & 15, kq = lane >> 4;
+    const int32_t b = leaf_box[li_leaf];
+    const int32_t kb = box_beg[b], nt = box_end[b] - kb;
+    const float ih = (float)(1.0 / hbox[b]);
+    // weighted local fragments: row k = NKS kq + ks (clamped), weight 1 for
+    // the m = 0 coefficient of each degree (k = n^2), 2 otherwise
+    const auto rl = buf_rsrc(L + (int64_t)b * K * C, (uint32_t)((K * C + 256) * 4));
+    float bl[NKS][WT], bx[XC ? NKS : 1];
+    bool valid[NKS];
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+        const int k = NKS * kq + ks;
+        valid[ks] = k < K;
+        const int kc = k < K ? k : K - 1;
+        int n = (int)sqrtf((float)kc + 0.5f);
+        const float wk = (n * n == kc ? 1.f : 2.f) * ih;
+        const BV v = buf_load<BV>(rl, (kc * C + cb + WT * li) * 4, 0);
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) bl[ks][ct] = v.v[ct] * wk;
+        if constexpr (XC > 0) bx[ks] = buf_load<float>(rl, (kc * C + cn + (li & 3)) * 4, 0) * wk;
+    }
+    const auto rq = buf_rsrc(mom + (int64_t)kb * K, (uint32_t)(nt * K * 4));
+    const int ntt = (nt + 15) / 16;
+    for (int tt = 0; tt < ntt; ++tt) {
+        float a[NKS];
+        const int qo = ((16 * tt + li) * K + NKS * kq) * 4;
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            const float q = buf_load<float>(rq, qo + 4 * ks, 0);
+            a[ks] = valid[ks] ? q : 0.f;
+        }
+        f32x4 acc[WT], accx = {0, 0, 0, 0};
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) acc[ct] = f32x4{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+#pragma unroll
+            for (int ct = 0; ct < WT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], bl[ks][ct], acc[ct], 0, 0, 0);
+            if constexpr (XC > 0) accx = __builtin_amdgcn_mfma_f32_4x4x1f32(a[ks], bx[ks], accx, 0, 0, 0);
+        }
+        // D[i][j] at lane j + 16 q, element i - 4 q: target 16 tt + i,
+        // column cb + WT j + ct
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct)
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+                const int t = 16 * tt + 4 * kq + e4, col = cb + WT * li + ct;
+                if (t < nt && col < C) ys[(int64_t)(kb + t) * C + col] += acc[ct][e4];
+            }
+        if constexpr (XC > 0) {
+            // lane (li, kq): column cn + (li & 3), targets 16 tt + 4 (li / 4) + i
+            // in element i for its coefficient subset; after the sum over
+            // the four subsets it stores element i = kq
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                accx[i] += __shfl_xor(accx[i], 16);
+                accx[i] += __shfl_xor(accx[i], 32);
+            }
+            const float mine = kq == 0 ? accx[0] : kq == 1 ? accx[1] : kq == 2 ? accx[2] : accx[3];
+            const int t = 16 * tt + 4 * (li >> 2) + kq, col = cn + (li & 3);
+            if (t < nt && col < C) ys[(int64_t)(kb + t) * C + col] += mine;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- M2L
 // Offset-stationary batched GEMM.  All V-list pairs with the same integer
 // offset share one operator T_o, so for every offset group
@@ -1581,7 +1669,53 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
         case 10: translations<T, 10>(P, op, M.p, L.p, tmp, C, s, mark); break;
         default: translations<T, 12>(P, op, M.p, L.p, tmp, C, s, mark); break;
     }
-    if (P->n_leaves > 0) {
+    bool l2p_done = false;
+    if constexpr (sizeof(T) == 4) {
+        if (P->n_leaves > 0 && C > 16) {
+            // column items as in P2P: WT 16-column tiles, or the tiles plus
+            // four narrow columns
+            const int ntiles = (int)cdiv(C, 16);
+            const bool xc = C % 16 >= 1 && C % 16 <= 4 && ntiles - 1 <= 4;
+            int WT = 1;
+            if (xc)
+                WT = ntiles - 1;
+            else
+                for (int w = 1; w <= 4; ++w)
+                    if (cdiv(ntiles, w) * w <= cdiv(ntiles, WT) * WT) WT = w;
+            const int ipl = xc ? 1 : (int)cdiv(ntiles, WT);
+            const int64_t n_items = P->n_leaves * ipl;
+            XRL_CHECK(n_items < (int64_t(1) << 31), XRL_E_UNSUPPORTED, "xrl_fmm_matvec: too many L2P items");
+            auto go = [&](auto ordc, auto wt, auto xcols) {
+                constexpr int O = decltype(ordc)::value, W = decltype(wt)::value, X = decltype(xcols)::value;
+                k_l2p_mfma<O, W, X><<<(unsigned)n_items, 64, 0, s>>>(ipl, P->leaf_box.p, P->box_beg.p, P->box_end.p,
+                                                                    P->box_h.p, (const float *)op.mom, (const float *)L.p,
+                                                                    (float *)ys.p, C);
+            };
+            auto go_w = [&](auto ordc) {
+                auto gx = [&](auto wt) {
+                    if (xc)
+                        go(ordc, wt, std::integral_constant<int, 4>());
+                    else
+                        go(ordc, wt, std::integral_constant<int, 0>());
+                };
+                if (WT == 1) gx(std::integral_constant<int, 1>());
+                if (WT == 2) gx(std::integral_constant<int, 2>());
+                if (WT == 3) gx(std::integral_constant<int, 3>());
+                if (WT == 4) gx(std::integral_constant<int, 4>());
+            };
+            switch (P->p) {
+                case 2: go_w(std::integral_constant<int, 2>()); break;
+                case 4: go_w(std::integral_constant<int, 4>()); break;
+                case 6: go_w(std::integral_constant<int, 6>()); break;
+                case 8: go_w(std::integral_constant<int, 8>()); break;
+                case 10: go_w(std::integral_constant<int, 10>()); break;
+                default: go_w(std::integral_constant<int, 12>()); break;
+            }
+            XRL_HIP(hipGetLastError());
+            l2p_done = true;
+        }
+    }
+    if (P->n_leaves > 0 && !l2p_done) {
         const int CT = (sizeof(T) == 8 || C <= 8) ? 8 : 16;
         const unsigned ntile = (unsigned)cdiv(C, CT);
         const size_t sm = (size_t)K * CT * sizeof(T);
