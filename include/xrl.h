@@ -300,6 +300,9 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
  *   XRL_TUNE_TS_ORDER    (0/1, default 1): launch order of the
  *       target-stationary translations: the targets with the most pairs
  *       first (1) or in box order (0).
+ *   XRL_TUNE_L2L_FORM    (0/1, default 1): the translations with one source
+ *       per target (L2L) source-stationary, one wave per parent holding its
+ *       local expansion for all its children (1), or target-stationary (0).
  *   XRL_TUNE_TS_NARROW_COLS (0/1, default 1): FP32 target-stationary forms
  *       0 and 1 with 1..4 real columns past the last full 16-column tile
  *       (C = 16 n + 1 .. 16 n + 4, e.g. 18 complex columns): those columns
@@ -311,6 +314,7 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
 #define XRL_TUNE_P2P_FORM 2
 #define XRL_TUNE_TS_NARROW_COLS 3
 #define XRL_TUNE_TS_ORDER 4
+#define XRL_TUNE_L2L_FORM 5
 xrl_status xrl_plan_set_tuning(xrl_plan *plan, int32_t key, int32_t value);
 
 /* Graph mode (on != 0): the first xrl_fmm_matvec with a new argument set

@@ -183,6 +183,9 @@ struct TransPass {
     xrl::DevBuf<int32_t> ts_op;       // [n_pairs] target order: operator index << 3 | reflection bits
     xrl::DevBuf<int32_t> ts_op_full;  // [n_pairs] target order: plain operator index << 3 (M2L only)
     xrl::DevBuf<int32_t> ts_order;    // [n_red] target indices, most pairs first (ties in target order)
+    xrl::DevBuf<int32_t> ts_tgt;      // [n_pairs] target box of each pair, target order
+    int64_t n_ps = 0;                 // runs of consecutive pairs (target order) with the same source
+    xrl::DevBuf<int32_t> ps_beg;      // [n_ps+1] first pair of each run
     mutable std::vector<std::pair<int64_t, xrl::DevBuf<int32_t>>> item_cache;  // key: (engine, cols)
 };
 
@@ -251,6 +254,7 @@ struct xrl_plan {
     int ts_kernel = 0;
     int ts_min_cols = 16;  // MFMA engine: target-stationary from this many real columns on
     int p2p_form = 0;  // P2P above 16 FP32 columns: 0 MFMA, 1 scalar densities, 2 LDS-staged (XRL_TUNE_P2P_FORM)
+    int ps_l2l = 1;          // passes with one source per target: source-stationary (1) or lean (0)
     int ts_order = 1;        // target-stationary launch order: 1 most pairs first, 0 target order
     int ts_narrow_cols = 1;  // FP32 target-stationary: 1..4 columns past the last full tile on 4x4 MFMA blocks
     mutable int64_t scratch_budget = 0;  // bytes for the offset-stationary per-pair scratch (0: not set)

@@ -1295,6 +1295,135 @@ __global__ __launch_bounds__(64, 2) void k_trans_ts_lean(int n_items, int items_
         }
 }
 
+// Source-stationary translation for passes where each target has one
+// source and a source feeds several targets (L2L: a parent's local to its
+// children).  One wave per (run of pairs with the same source, 16-row tile
+// of the result, item of WT column tiles [+ XC narrow columns]): the source
+// fragments are loaded once and stay in registers; the wave walks the pairs
+// of the run with the next pair's operator tile (and the target values it
+// adds to) in flight, and adds each finished tile into its target.  Short
+// waves in large numbers: the passes are level by level, and the small
+// levels are bound by the length of one wave.  The operator is the padded
+// [NRT][KP] form (the last row in the last tile); the tables of a pass are
+// few and stay in the L2.
+template <typename T, int ORD, int WT, int XC>
+__global__ __launch_bounds__(64) void k_trans_ps(int n_items, int items_per_run, const int32_t *__restrict__ ps_beg,
+                                                 const int32_t *__restrict__ ts_tgt,
+                                                 const int32_t *__restrict__ ts_src,
+                                                 const int32_t *__restrict__ ts_op, const T *__restrict__ op_vec,
+                                                 const T *__restrict__ in, int C, int accumulate, T *__restrict__ out)
+{
+    using D = M2LDims<ORD>;
+    using VT = typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type;
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int NKV = (D::NKS + VEC - 1) / VEC;
+    using AV = T __attribute__((ext_vector_type(VEC)));
+    static_assert(XC == 0 || (XC == 4 && sizeof(T) == 4), "4x4-block columns: four, FP32 only");
+    struct BV {
+        T v[WT];
+    };
+    const int w = blockIdx.x;
+    if (w >= n_items) return;
+    const int g = w / (items_per_run * D::NRT);
+    const int rem = w - g * items_per_run * D::NRT;
+    const int rt = rem / items_per_run;
+    const int cb = (rem - rt * items_per_run) * WT * 16, cx = cb + WT * 16;
+    const int lane = threadIdx.x & 63, li = lane & 15, kq = lane >> 4;
+    const int j0 = ps_beg[g], j1 = ps_beg[g + 1];
+    // source fragments (columns interleaved over the tiles as in the
+    // target-stationary kernel; the last k step's row clamped to K - 1,
+    // where the operator column is zero)
+    const int boff = kq * C + cb + WT * li, xoff = kq * C + cx + (li & 3);
+    const int blast = min(4 * (D::NKS - 1) + kq, D::K - 1) * C - 4 * (D::NKS - 1) * C - kq * C;
+    const auto rm = buf_rsrc(in + (int64_t)ts_src[j0] * D::K * C, (uint32_t)((D::K * C + 256) * sizeof(T)));
+    T b[WT][D::NKS], bx[XC ? D::NKS : 1];
+#pragma unroll
+    for (int ks = 0; ks < D::NKS; ++ks) {
+        const int lofs = ks == D::NKS - 1 ? blast : 0;
+        const int sofs = 4 * ks * C * (int)sizeof(T);
+        const BV v = buf_load<BV>(rm, (boff + lofs) * (int)sizeof(T), sofs);
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) b[ct][ks] = v.v[ct];
+        if constexpr (XC > 0) bx[ks] = buf_load<T>(rm, (xoff + lofs) * (int)sizeof(T), sofs);
+    }
+    constexpr uint32_t obytes = D::NRT * NKV * 64 * 16;
+    auto load_a = [&](int step, AV (&dst)[NKV]) {
+        const int j = j0 + step;
+        const auto ro = buf_rsrc(op_vec + (int64_t)(ts_op[j] >> 3) * D::NRT * NKV * 64 * VEC, obytes);
+#pragma unroll
+        for (int kv = 0; kv < NKV; ++kv) dst[kv] = buf_load<AV>(ro, lane * 16, (rt * NKV + kv) * 1024);
+    };
+    // the target values a step adds to, fetched one step ahead with its
+    // operator tile (the rows of different steps never overlap)
+    struct Old {
+        T v[WT][4];
+        T x;
+    };
+    auto load_old = [&](int step, Old &o) {
+        const int j = j0 + step;
+        const T *tp = out + (int64_t)ts_tgt[j] * D::K * C;
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) {
+            const int col = cb + WT * li + ct;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = rt * 16 + mfma_row<T>(kq, e);
+                o.v[ct][e] = (accumulate && col < C && row < D::K) ? tp[row * C + col] : T(0);
+            }
+        }
+        if constexpr (XC > 0) {
+            const int row = 16 * rt + 4 * (li >> 2) + kq, col = cx + (li & 3);
+            o.x = (accumulate && col < C && row < D::K) ? tp[row * C + col] : T(0);
+        } else {
+            o.x = T(0);
+        }
+    };
+    const int nsteps = j1 - j0;
+    AV an[NKV];
+    Old on;
+    load_a(0, an);
+    load_old(0, on);
+    for (int step = 0; step < nsteps; ++step) {
+        AV a[NKV];
+#pragma unroll
+        for (int kv = 0; kv < NKV; ++kv) a[kv] = an[kv];
+        const Old oc = on;
+        if (step + 1 < nsteps) {
+            load_a(step + 1, an);
+            load_old(step + 1, on);
+        }
+        const int t = ts_tgt[j0 + step];
+        VT acc[WT], accx = VT{0, 0, 0, 0};
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) acc[ct] = VT{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < D::NKS; ++ks) {
+#pragma unroll
+            for (int ct = 0; ct < WT; ++ct) mfma_16x16x4<T>(a[ks / VEC][ks % VEC], b[ct][ks], acc[ct]);
+            if constexpr (XC > 0) accx = __builtin_amdgcn_mfma_f32_4x4x1f32(a[ks / VEC][ks % VEC], bx[ks], accx, 0, 0, 0);
+        }
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) {
+            const int col = cb + WT * li + ct;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = rt * 16 + mfma_row<T>(kq, e);
+                if (col < C && row < D::K) out[((int64_t)t * D::K + row) * C + col] = oc.v[ct][e] + acc[ct][e];
+            }
+        }
+        if constexpr (XC > 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                accx[i] += __shfl_xor(accx[i], 16);
+                accx[i] += __shfl_xor(accx[i], 32);
+            }
+            const T mine = kq == 0 ? accx[0] : kq == 1 ? accx[1] : kq == 2 ? accx[2] : accx[3];
+            const int row = 16 * rt + 4 * (li >> 2) + kq, col = cx + (li & 3);
+            if (col < C && row < D::K) out[((int64_t)t * D::K + row) * C + col] = oc.x + mine;
+        }
+    }
+}
+
 // out[t][row][c0 + c] (=|+=) sum over the pairs of t (fixed order) of
 // tmp[slot][c][row].
 template <typename T, int ORD>
@@ -1374,7 +1503,10 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
         // tiles per wave: the widest (up to the register budget) that wastes
         // the fewest padded tiles; in FP32, one to four columns past the last
         // full tile go to 4x4 MFMA blocks of the same wave instead of a tile
-        const bool lean = refl ? P->ts_kernel == 2 : TP.n_pairs < 2 * TP.n_red;
+        // one source per target (L2L): source-stationary; few pairs per
+        // target otherwise (or asked for): the lean form
+        const bool ss = !refl && TP.n_pairs == TP.n_red && P->ps_l2l;
+        const bool lean = !ss && (refl ? P->ts_kernel == 2 : TP.n_pairs < 2 * TP.n_red);
         const int ntiles = (int)cdiv(C, 16);
         const int wmax = ts_max_tiles<T, ORD>();
         // (up to two full tiles: with three, the accumulators of the extra
@@ -1398,6 +1530,10 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
                 k_trans_ts<T, ORD, W, true, X><<<nb, 64, 0, s>>>((int)n_items, ipt, ord, TP.red_tgt.p, TP.red_ptr.p,
                                                                  TP.ts_src.p, TP.ts_op.p, op_vec, op_tail, in, C,
                                                                  accumulate, out);
+            else if (ss)
+                k_trans_ps<T, ORD, W, X><<<(unsigned)(TP.n_ps * ipt * M2LDims<ORD>::NRT), 64, 0, s>>>(
+                    (int)(TP.n_ps * ipt * M2LDims<ORD>::NRT), ipt, TP.ps_beg.p, TP.ts_tgt.p, TP.ts_src.p, TP.ts_op.p, op_vec, in, C,
+                    accumulate, out);
             else if (lean)
                 k_trans_ts_lean<T, ORD, W><<<nb, 64, 0, s>>>((int)n_items, ipt, TP.red_tgt.p, TP.red_ptr.p,
                                                               TP.ts_src.p, refl ? TP.ts_op_full.p : TP.ts_op.p,
@@ -2050,6 +2186,10 @@ extern "C" xrl_status xrl_plan_set_tuning(xrl_plan *P, int32_t key, int32_t valu
             case XRL_TUNE_TS_MIN_COLS:
                 XRL_CHECK(value >= 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: min columns must be >= 1");
                 P->ts_min_cols = value;
+                break;
+            case XRL_TUNE_L2L_FORM:
+                XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: L2L form must be 0 or 1");
+                P->ps_l2l = value;
                 break;
             case XRL_TUNE_TS_ORDER:
                 XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: order must be 0 or 1");

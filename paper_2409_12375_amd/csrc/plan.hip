@@ -382,6 +382,17 @@ static void build_pass(TransPass &T, const std::vector<int32_t> &tgt, const std:
     }
     T.ts_src.upload(tsrc, s);
     T.ts_op.upload(tcode, s);
+    // target of every pair, and the runs of pairs with one source (the
+    // children of one parent in an L2L pass)
+    std::vector<int32_t> ttgt(n), psb;
+    for (size_t i = 0; i + 1 < rp.size(); ++i)
+        for (int32_t j = rp[i]; j < rp[i + 1]; ++j) ttgt[j] = rt[i];
+    for (int64_t j = 0; j < n; ++j)
+        if (j == 0 || tsrc[j] != tsrc[j - 1]) psb.push_back((int32_t)j);
+    psb.push_back((int32_t)n);
+    T.n_ps = n > 0 ? (int64_t)psb.size() - 1 : 0;
+    T.ts_tgt.upload(ttgt, s);
+    T.ps_beg.upload(psb, s);
     std::vector<int32_t> heavy(rt.size());
     std::iota(heavy.begin(), heavy.end(), 0);
     std::stable_sort(heavy.begin(), heavy.end(),

@@ -133,7 +133,7 @@ def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
     x = I.densities(N, 18, np.complex64)
     tree = xrl.Tree(V, T)
     ys = {}
-    for eng in ("mfma", "mfma_os", "refl", "lean", "p2p_scalar", "p2p_lds", "padded", "refl_padded"):
+    for eng in ("mfma", "mfma_os", "refl", "lean", "p2p_scalar", "p2p_lds", "padded", "refl_padded", "l2l_ts"):
         plan = xrl.Plan(tree, order=8, precision="mixed", engine="mfma_os" if eng == "mfma_os" else "mfma",
                         max_cols=18)
         plan.assemble()
@@ -147,6 +147,8 @@ def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
             plan.set_tuning("p2p_form", 1)
         if eng == "p2p_lds":  # P2P on the vector ALU with the densities staged in LDS
             plan.set_tuning("p2p_form", 2)
+        if eng == "l2l_ts":  # L2L target-stationary instead of source-stationary
+            plan.set_tuning("l2l_form", 0)
         ys[eng] = plan.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
         plan.close()
     rows = sample_rows(N, 256)
@@ -157,7 +159,7 @@ def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
     d = np.linalg.norm(ys["mfma"] - ys["mfma_os"], axis=0) / np.linalg.norm(ys["mfma_os"], axis=0)
     say("  target- vs offset-stationary", d.max())
     assert d.max() < 1e-6
-    for v in ("refl", "lean", "p2p_scalar", "p2p_lds", "padded", "refl_padded"):
+    for v in ("refl", "lean", "p2p_scalar", "p2p_lds", "padded", "refl_padded", "l2l_ts"):
         d = np.linalg.norm(ys["mfma"] - ys[v], axis=0) / np.linalg.norm(ys[v], axis=0)
         say("  kernel form %s vs default" % v, d.max())
         assert d.max() < 1e-6
