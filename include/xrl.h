@@ -303,6 +303,10 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
  *   XRL_TUNE_L2L_FORM    (0/1, default 1): the translations with one source
  *       per target (L2L) source-stationary, one wave per parent holding its
  *       local expansion for all its children (1), or target-stationary (0).
+ *   XRL_TUNE_M2M_FORM    (0..2, default 2): the translations with at most
+ *       eight pairs per target (M2M) with one wave per 16-row tile of each
+ *       target (1), one wave per target (0), or the first on levels with
+ *       fewer than 1024 targets and the second on the others (2).
  *   XRL_TUNE_TS_NARROW_COLS (0/1, default 1): FP32 target-stationary forms
  *       0 and 1 with 1..4 real columns past the last full 16-column tile
  *       (C = 16 n + 1 .. 16 n + 4, e.g. 18 complex columns): those columns
@@ -315,6 +319,7 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
 #define XRL_TUNE_TS_NARROW_COLS 3
 #define XRL_TUNE_TS_ORDER 4
 #define XRL_TUNE_L2L_FORM 5
+#define XRL_TUNE_M2M_FORM 6
 xrl_status xrl_plan_set_tuning(xrl_plan *plan, int32_t key, int32_t value);
 
 /* Graph mode (on != 0): the first xrl_fmm_matvec with a new argument set

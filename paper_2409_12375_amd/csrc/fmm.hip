@@ -1424,6 +1424,112 @@ __global__ __launch_bounds__(64) void k_trans_ps(int n_items, int items_per_run,
     }
 }
 
+// Row-tile form of the target-stationary translation for passes with few
+// pairs per target (M2M: a parent's multipole from its children).  One wave
+// per (target, 16-row tile of the result, item of WT column tiles [+ XC
+// narrow columns]) sums the target's pairs in list order in registers, the
+// next pair's source fragments and operator tile in flight, and stores its
+// tile once.  As for the source-stationary form: short waves in large
+// numbers for passes that run level by level.
+template <typename T, int ORD, int WT, int XC>
+__global__ __launch_bounds__(64) void k_trans_tr(int n_items, int items_per_tgt, const int32_t *__restrict__ red_tgt,
+                                                 const int32_t *__restrict__ red_ptr,
+                                                 const int32_t *__restrict__ ts_src,
+                                                 const int32_t *__restrict__ ts_op, const T *__restrict__ op_vec,
+                                                 const T *__restrict__ in, int C, int accumulate, T *__restrict__ out)
+{
+    using D = M2LDims<ORD>;
+    using VT = typename std::conditional<sizeof(T) == 4, f32x4, f64x4>::type;
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int NKV = (D::NKS + VEC - 1) / VEC;
+    using AV = T __attribute__((ext_vector_type(VEC)));
+    static_assert(XC == 0 || (XC == 4 && sizeof(T) == 4), "4x4-block columns: four, FP32 only");
+    struct BV {
+        T v[WT];
+    };
+    struct Step {
+        AV a[NKV];
+        T b[WT][D::NKS];
+        T x[XC ? D::NKS : 1];
+    };
+    const int w = blockIdx.x;
+    if (w >= n_items) return;
+    const int ti = w / (items_per_tgt * D::NRT);
+    const int rem = w - ti * items_per_tgt * D::NRT;
+    const int rt = rem / items_per_tgt;
+    const int cb = (rem - rt * items_per_tgt) * WT * 16, cx = cb + WT * 16;
+    const int lane = threadIdx.x & 63, li = lane & 15, kq = lane >> 4;
+    const int t = red_tgt[ti], j0 = red_ptr[ti], j1 = red_ptr[ti + 1];
+    const int boff = kq * C + cb + WT * li, xoff = kq * C + cx + (li & 3);
+    const int blast = min(4 * (D::NKS - 1) + kq, D::K - 1) * C - 4 * (D::NKS - 1) * C - kq * C;
+    const uint32_t mbytes = (uint32_t)((D::K * C + 256) * sizeof(T));
+    constexpr uint32_t obytes = D::NRT * NKV * 64 * 16;
+    auto load = [&](int j, Step &st) {
+        const auto rm = buf_rsrc(in + (int64_t)ts_src[j] * D::K * C, mbytes);
+#pragma unroll
+        for (int ks = 0; ks < D::NKS; ++ks) {
+            const int lofs = ks == D::NKS - 1 ? blast : 0;
+            const int sofs = 4 * ks * C * (int)sizeof(T);
+            const BV v = buf_load<BV>(rm, (boff + lofs) * (int)sizeof(T), sofs);
+#pragma unroll
+            for (int ct = 0; ct < WT; ++ct) st.b[ct][ks] = v.v[ct];
+            if constexpr (XC > 0) st.x[ks] = buf_load<T>(rm, (xoff + lofs) * (int)sizeof(T), sofs);
+        }
+        const auto ro = buf_rsrc(op_vec + (int64_t)(ts_op[j] >> 3) * D::NRT * NKV * 64 * VEC, obytes);
+#pragma unroll
+        for (int kv = 0; kv < NKV; ++kv) st.a[kv] = buf_load<AV>(ro, lane * 16, (rt * NKV + kv) * 1024);
+    };
+    VT acc[WT], accx = VT{0, 0, 0, 0};
+#pragma unroll
+    for (int ct = 0; ct < WT; ++ct) acc[ct] = VT{0, 0, 0, 0};
+    auto comp = [&](const Step &st) {
+#pragma unroll
+        for (int ks = 0; ks < D::NKS; ++ks) {
+#pragma unroll
+            for (int ct = 0; ct < WT; ++ct) mfma_16x16x4<T>(st.a[ks / VEC][ks % VEC], st.b[ct][ks], acc[ct]);
+            if constexpr (XC > 0)
+                accx = __builtin_amdgcn_mfma_f32_4x4x1f32(st.a[ks / VEC][ks % VEC], st.x[ks], accx, 0, 0, 0);
+        }
+    };
+    // two pairs per trip (static operand sets), the next one in flight
+    if (j0 < j1) {
+        Step s0, s1;
+        load(j0, s0);
+        for (int j = j0; j < j1; j += 2) {
+            if (j + 1 < j1) load(j + 1, s1);
+            comp(s0);
+            if (j + 1 >= j1) break;
+            if (j + 2 < j1) load(j + 2, s0);
+            comp(s1);
+        }
+    }
+#pragma unroll
+    for (int ct = 0; ct < WT; ++ct) {
+        const int col = cb + WT * li + ct;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = rt * 16 + mfma_row<T>(kq, e);
+            if (col < C && row < D::K) {
+                T *o = out + ((int64_t)t * D::K + row) * C + col;
+                *o = accumulate ? *o + acc[ct][e] : acc[ct][e];
+            }
+        }
+    }
+    if constexpr (XC > 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            accx[i] += __shfl_xor(accx[i], 16);
+            accx[i] += __shfl_xor(accx[i], 32);
+        }
+        const T mine = kq == 0 ? accx[0] : kq == 1 ? accx[1] : kq == 2 ? accx[2] : accx[3];
+        const int row = 16 * rt + 4 * (li >> 2) + kq, col = cx + (li & 3);
+        if (col < C && row < D::K) {
+            T *o = out + ((int64_t)t * D::K + row) * C + col;
+            *o = accumulate ? *o + mine : mine;
+        }
+    }
+}
+
 // out[t][row][c0 + c] (=|+=) sum over the pairs of t (fixed order) of
 // tmp[slot][c][row].
 template <typename T, int ORD>
@@ -1506,7 +1612,12 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
         // one source per target (L2L): source-stationary; few pairs per
         // target otherwise (or asked for): the lean form
         const bool ss = !refl && TP.n_pairs == TP.n_red && P->ps_l2l;
-        const bool lean = !ss && (refl ? P->ts_kernel == 2 : TP.n_pairs < 2 * TP.n_red);
+        // at most eight pairs per target (M2M): one wave per row tile when
+        // the level has fewer targets than the chip has SIMDs (tr_m2m = 2),
+        // always (1) or never (0)
+        const bool tr = !refl && !ss && TP.n_pairs <= 8 * TP.n_red &&
+                        (P->tr_m2m == 1 || (P->tr_m2m == 2 && TP.n_red < 1024));
+        const bool lean = !ss && !tr && (refl ? P->ts_kernel == 2 : TP.n_pairs < 2 * TP.n_red);
         const int ntiles = (int)cdiv(C, 16);
         const int wmax = ts_max_tiles<T, ORD>();
         // (up to two full tiles: with three, the accumulators of the extra
@@ -1530,6 +1641,10 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
                 k_trans_ts<T, ORD, W, true, X><<<nb, 64, 0, s>>>((int)n_items, ipt, ord, TP.red_tgt.p, TP.red_ptr.p,
                                                                  TP.ts_src.p, TP.ts_op.p, op_vec, op_tail, in, C,
                                                                  accumulate, out);
+            else if (tr)
+                k_trans_tr<T, ORD, W, X><<<(unsigned)(TP.n_red * ipt * M2LDims<ORD>::NRT), 64, 0, s>>>(
+                    (int)(TP.n_red * ipt * M2LDims<ORD>::NRT), ipt, TP.red_tgt.p, TP.red_ptr.p, TP.ts_src.p,
+                    TP.ts_op.p, op_vec, in, C, accumulate, out);
             else if (ss)
                 k_trans_ps<T, ORD, W, X><<<(unsigned)(TP.n_ps * ipt * M2LDims<ORD>::NRT), 64, 0, s>>>(
                     (int)(TP.n_ps * ipt * M2LDims<ORD>::NRT), ipt, TP.ps_beg.p, TP.ts_tgt.p, TP.ts_src.p, TP.ts_op.p, op_vec, in, C,
@@ -2190,6 +2305,10 @@ extern "C" xrl_status xrl_plan_set_tuning(xrl_plan *P, int32_t key, int32_t valu
             case XRL_TUNE_L2L_FORM:
                 XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: L2L form must be 0 or 1");
                 P->ps_l2l = value;
+                break;
+            case XRL_TUNE_M2M_FORM:
+                XRL_CHECK(value >= 0 && value <= 2, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: M2M form must be 0..2");
+                P->tr_m2m = value;
                 break;
             case XRL_TUNE_TS_ORDER:
                 XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: order must be 0 or 1");
