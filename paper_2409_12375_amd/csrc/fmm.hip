@@ -532,6 +532,79 @@ __global__ __launch_bounds__(256) void k_p2m(const int32_t *__restrict__ leaf_bo
     }
 }
 
+// Matrix-core form (FP32, C > 16): per leaf, M[i][c] = sum over the
+// leaf's panels t of Q[t][i] X[t][c], the moment table as A (16
+// coefficients x 4 panels, a coalesced row segment per panel) and the
+// densities as B (loaded once per item and reused for every coefficient
+// tile); narrow columns (XC = 4) on 4x4x1 blocks.  Panels past the leaf read
+// as zeros (range-checked buffer loads), so do coefficients past the last
+// panel's row; rows past K are not stored.
+template <int ORD, int WT, int XC>
+__global__ __launch_bounds__(64) void k_p2m_mfma(int items_per_leaf, const int32_t *__restrict__ leaf_box,
+                                                 const int32_t *__restrict__ box_beg,
+                                                 const int32_t *__restrict__ box_end, const float *__restrict__ mom,
+                                                 const float *__restrict__ xs, float *__restrict__ M, int C)
+{
+    constexpr int K = (ORD + 1) * (ORD + 1), NRT = (K + 15) / 16, NKS = 16;  // at most 64 panels per leaf
+    struct BV {
+        float v[WT];
+    };
+    const int w = blockIdx.x;
+    const int li_leaf = w / items_per_leaf;
+    const int cb = (w - li_leaf * items_per_leaf) * 16 * WT, cn = cb + 16 * WT;
+    const int lane = threadIdx.x, li = lane & 15, kq = lane >> 4;
+    const int32_t b = leaf_box[li_leaf];
+    const int32_t kb = box_beg[b], nt = box_end[b] - kb;
+    const int nks = (nt + 3) / 4;
+    // densities of panel 4 ks + kq (zero past the leaf)
+    const auto rx = buf_rsrc(xs + (int64_t)kb * C, (uint32_t)(nt * C * 4));
+    float bx[NKS][WT], bn[XC ? NKS : 1];
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+        if (ks >= nks) break;
+        const int t = 4 * ks + kq;
+        const BV v = buf_load<BV>(rx, (t * C + cb + WT * li) * 4, 0);
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) bx[ks][ct] = v.v[ct];
+        if constexpr (XC > 0) bn[ks] = buf_load<float>(rx, (t * C + cn + (li & 3)) * 4, 0);
+    }
+    const auto rq = buf_rsrc(mom + (int64_t)kb * K, (uint32_t)(nt * K * 4));
+    float *Mb = M + (int64_t)b * K * C;
+    for (int it = 0; it < NRT; ++it) {
+        f32x4 acc[WT], accx = {0, 0, 0, 0};
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct) acc[ct] = f32x4{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            if (ks >= nks) break;
+            const int t = 4 * ks + kq;
+            const float a = buf_load<float>(rq, (t * K + 16 * it + li) * 4, 0);
+#pragma unroll
+            for (int ct = 0; ct < WT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bx[ks][ct], acc[ct], 0, 0, 0);
+            if constexpr (XC > 0) accx = __builtin_amdgcn_mfma_f32_4x4x1f32(a, bn[ks], accx, 0, 0, 0);
+        }
+        // D[i][j] at lane j + 16 q, element i - 4 q: coefficient 16 it + i,
+        // column cb + WT j + ct
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct)
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+                const int i = 16 * it + 4 * kq + e4, col = cb + WT * li + ct;
+                if (i < K && col < C) Mb[i * C + col] = acc[ct][e4];
+            }
+        if constexpr (XC > 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                accx[i] += __shfl_xor(accx[i], 16);
+                accx[i] += __shfl_xor(accx[i], 32);
+            }
+            const float mine = kq == 0 ? accx[0] : kq == 1 ? accx[1] : kq == 2 ? accx[2] : accx[3];
+            const int i = 16 * it + 4 * (li >> 2) + kq, col = cn + (li & 3);
+            if (i < K && col < C) Mb[i * C + col] = mine;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- L2P
 template <typename T, int CT>
 __global__ __launch_bounds__(256) void k_l2p(const int32_t *__restrict__ leaf_box, const int32_t *__restrict__ box_beg,
@@ -1904,7 +1977,51 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
             return fn(std::integral_constant<int, 48>());
         }
     };
-    if (P->n_leaves > 0) {
+    bool p2m_done = false;
+    if constexpr (sizeof(T) == 4) {
+        if (P->n_leaves > 0 && C > 16) {
+            const int ntiles = (int)cdiv(C, 16);
+            const bool xc = C % 16 >= 1 && C % 16 <= 4 && ntiles - 1 <= 4;
+            int WT = 1;
+            if (xc)
+                WT = ntiles - 1;
+            else
+                for (int w = 1; w <= 4; ++w)
+                    if (cdiv(ntiles, w) * w <= cdiv(ntiles, WT) * WT) WT = w;
+            const int ipl = xc ? 1 : (int)cdiv(ntiles, WT);
+            const int64_t n_items = P->n_leaves * ipl;
+            XRL_CHECK(n_items < (int64_t(1) << 31), XRL_E_UNSUPPORTED, "xrl_fmm_matvec: too many P2M items");
+            auto go = [&](auto ordc, auto wt, auto xcols) {
+                constexpr int O = decltype(ordc)::value, W = decltype(wt)::value, X = decltype(xcols)::value;
+                k_p2m_mfma<O, W, X><<<(unsigned)n_items, 64, 0, s>>>(ipl, P->leaf_box.p, P->box_beg.p, P->box_end.p,
+                                                                    (const float *)op.mom, (const float *)xs.p,
+                                                                    (float *)M.p, C);
+            };
+            auto go_w = [&](auto ordc) {
+                auto gx = [&](auto wt) {
+                    if (xc)
+                        go(ordc, wt, std::integral_constant<int, 4>());
+                    else
+                        go(ordc, wt, std::integral_constant<int, 0>());
+                };
+                if (WT == 1) gx(std::integral_constant<int, 1>());
+                if (WT == 2) gx(std::integral_constant<int, 2>());
+                if (WT == 3) gx(std::integral_constant<int, 3>());
+                if (WT == 4) gx(std::integral_constant<int, 4>());
+            };
+            switch (P->p) {
+                case 2: go_w(std::integral_constant<int, 2>()); break;
+                case 4: go_w(std::integral_constant<int, 4>()); break;
+                case 6: go_w(std::integral_constant<int, 6>()); break;
+                case 8: go_w(std::integral_constant<int, 8>()); break;
+                case 10: go_w(std::integral_constant<int, 10>()); break;
+                default: go_w(std::integral_constant<int, 12>()); break;
+            }
+            XRL_HIP(hipGetLastError());
+            p2m_done = true;
+        }
+    }
+    if (P->n_leaves > 0 && !p2m_done) {
         moment_tiles([&](auto ctc) {
             constexpr int CT = decltype(ctc)::value;
             k_p2m<T, CT><<<dim3((unsigned)P->n_leaves, (unsigned)cdiv(C, CT)), 256, 0, s>>>(
