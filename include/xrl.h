@@ -307,6 +307,9 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
  *       eight pairs per target (M2M) with one wave per 16-row tile of each
  *       target (1), one wave per target (0), or the first on levels with
  *       fewer than 1024 targets and the second on the others (2).
+ *   XRL_TUNE_LEAF_FORM   (0/1, default 1): P2M and L2P above 16 FP32
+ *       columns as per-leaf 16x16x4 MFMA products (1) or on the vector ALU
+ *       with LDS-staged tiles (0).
  *   XRL_TUNE_TS_NARROW_COLS (0/1, default 1): FP32 target-stationary forms
  *       0 and 1 with 1..4 real columns past the last full 16-column tile
  *       (C = 16 n + 1 .. 16 n + 4, e.g. 18 complex columns): those columns
@@ -320,6 +323,7 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
 #define XRL_TUNE_TS_ORDER 4
 #define XRL_TUNE_L2L_FORM 5
 #define XRL_TUNE_M2M_FORM 6
+#define XRL_TUNE_LEAF_FORM 7
 xrl_status xrl_plan_set_tuning(xrl_plan *plan, int32_t key, int32_t value);
 
 /* Graph mode (on != 0): the first xrl_fmm_matvec with a new argument set

@@ -1979,7 +1979,7 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
     };
     bool p2m_done = false;
     if constexpr (sizeof(T) == 4) {
-        if (P->n_leaves > 0 && C > 16) {
+        if (P->n_leaves > 0 && C > 16 && P->leaf_mfma) {
             const int ntiles = (int)cdiv(C, 16);
             const bool xc = C % 16 >= 1 && C % 16 <= 4 && ntiles - 1 <= 4;
             int WT = 1;
@@ -2039,7 +2039,7 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
     }
     bool l2p_done = false;
     if constexpr (sizeof(T) == 4) {
-        if (P->n_leaves > 0 && C > 16) {
+        if (P->n_leaves > 0 && C > 16 && P->leaf_mfma) {
             // column items as in P2P: WT 16-column tiles, or the tiles plus
             // four narrow columns
             const int ntiles = (int)cdiv(C, 16);
@@ -2422,6 +2422,10 @@ extern "C" xrl_status xrl_plan_set_tuning(xrl_plan *P, int32_t key, int32_t valu
             case XRL_TUNE_L2L_FORM:
                 XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: L2L form must be 0 or 1");
                 P->ps_l2l = value;
+                break;
+            case XRL_TUNE_LEAF_FORM:
+                XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: leaf form must be 0 or 1");
+                P->leaf_mfma = value;
                 break;
             case XRL_TUNE_M2M_FORM:
                 XRL_CHECK(value >= 0 && value <= 2, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: M2M form must be 0..2");
