@@ -292,11 +292,11 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
  *   XRL_TUNE_TS_MIN_COLS (>= 1, default 16): with XRL_M2L_MFMA, the
  *       translations run target-stationary from this many real columns on,
  *       offset-stationary below.
- *   XRL_TUNE_P2P_FORM    (0..2, default 0): P2P above 16 FP32 columns on
- *       the 16x16x4 MFMA, densities times the stored block (0), on the
- *       vector ALU with the source densities read as wave-uniform scalars
- *       (1, one lane per target), or on the vector ALU with the source
- *       densities staged in LDS (2).
+ *   XRL_TUNE_P2P_FORM    (0..2, default 0; 2 on XRL_M2L_VALU plans): P2P
+ *       above 16 FP32 columns on the 16x16x4 MFMA, densities times the
+ *       stored block (0), on the vector ALU with the source densities read
+ *       as wave-uniform scalars (1, one lane per target), or on the vector
+ *       ALU with the source densities staged in LDS (2).
  *   XRL_TUNE_TS_ORDER    (0/1, default 1): launch order of the
  *       target-stationary translations: the targets with the most pairs
  *       first (1) or in box order (0).
@@ -307,9 +307,9 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
  *       eight pairs per target (M2M) with one wave per 16-row tile of each
  *       target (1), one wave per target (0), or the first on levels with
  *       fewer than 1024 targets and the second on the others (2).
- *   XRL_TUNE_LEAF_FORM   (0/1, default 1): P2M and L2P above 16 FP32
- *       columns as per-leaf 16x16x4 MFMA products (1) or on the vector ALU
- *       with LDS-staged tiles (0).
+ *   XRL_TUNE_LEAF_FORM   (0/1, default 1; 0 on XRL_M2L_VALU plans): P2M and
+ *       L2P above 16 FP32 columns as per-leaf 16x16x4 MFMA products (1) or
+ *       on the vector ALU with LDS-staged tiles (0).
  *   XRL_TUNE_TS_NARROW_COLS (0/1, default 1): FP32 target-stationary forms
  *       0 and 1 with 1..4 real columns past the last full 16-column tile
  *       (C = 16 n + 1 .. 16 n + 4, e.g. 18 complex columns): those columns

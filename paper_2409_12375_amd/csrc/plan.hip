@@ -833,6 +833,12 @@ extern "C" xrl_status xrl_fmm_plan(xrl_tree *const *trees, int32_t n_trees, cons
         P->m2l_engine = opts->m2l_engine == XRL_M2L_AUTO
                             ? (opts->precision == XRL_PREC_FP32 ? XRL_M2L_VALU : XRL_M2L_MFMA)
                             : opts->m2l_engine;
+        if (P->m2l_engine == XRL_M2L_VALU) {
+            // the vector-ALU plan (the plain FP32 method) keeps every phase
+            // off the matrix cores
+            P->p2p_form = 2;
+            P->leaf_mfma = 0;
+        }
         P->max_cols = opts->max_cols;
         P->trees.assign(trees, trees + n_trees);
         build_plan(P.get(), (hipStream_t)stream);
