@@ -204,6 +204,38 @@ def test_narrow_columns_past_the_last_tile(ncomplex):
     assert err.max() <= 5e-5
 
 
+@pytest.mark.parametrize("order", [6, 10])
+def test_other_orders_matrix_core_forms_match_vector_forms(order):
+    """Orders 6 (49 coefficients, last row on the vector ALU) and 10 (121, no
+    separate row) at 18 complex columns: the matrix-core forms (target- and
+    source-stationary translations with 4x4 narrow columns, MFMA P2P, P2M,
+    L2P) against the offset-stationary M2L with every leaf phase on the
+    vector ALU, and against the oracle within the order's truncation."""
+    say("case: bar 4096, order %d, 18 columns, matrix-core vs vector forms" % order)
+    V, T = I.bar()
+    N = len(T)
+    x = I.densities(N, 18, np.complex64, seed=60 + order)
+    tree = xrl.Tree(V, T)
+    ys = {}
+    for v in ("mfma", "vector"):
+        plan = xrl.Plan(tree, order=order, precision="mixed", engine="mfma_os" if v == "vector" else "mfma",
+                        max_cols=18)
+        plan.assemble()
+        if v == "vector":
+            plan.set_tuning("p2p_form", 2)
+            plan.set_tuning("leaf_form", 0)
+        ys[v] = plan.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+        plan.close()
+    d = np.linalg.norm(ys["mfma"] - ys["vector"], axis=0) / np.linalg.norm(ys["vector"], axis=0)
+    say("  matrix-core vs vector forms", d.max())
+    assert d.max() < 1e-6
+    rows = sample_rows(N, 64)
+    ref, _ = O.matvec(V, T, x.astype(np.complex128), rows=rows)
+    err = relerr_cols(ys["mfma"][rows], ref)
+    say("  rel L2 per column", err.max())
+    assert err.max() <= (3e-4 if order == 6 else 1e-5)
+
+
 @pytest.mark.parametrize("engine", ["auto", "mfma_ts"])
 def test_adaptive_tree_matvec_matches_oracle(engine):
     say("case: bar + sphere adaptive, fp64, max_leaf 16, %s" % engine)
