@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variants", default=None, help="comma list of mixed, fp32, surrogate (first = headline); "
                     "name@engine overrides the translation engine (auto, mfma, valu, mfma_os, mfma_ts)")
+    ap.add_argument("--max-leaf", type=int, default=128, help="octree leaf size (1..128): larger leaves trade "
+                    "M2L pairs for near-field values (128 measured fastest on every workload here)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES bytes (counter calibration) and exit")
     args = ap.parse_args()
@@ -182,7 +184,7 @@ def main():
         xh = I.densities(N, n_c, np.complex64)
         x = torch.from_numpy(xh).cuda()
     log("%s: N=%d panels in %d mesh(es)" % (args.workload, N, len(meshes)))
-    trees = [xrl.Tree(V, T, max_leaf=64) for V, T in meshes]
+    trees = [xrl.Tree(V, T, max_leaf=args.max_leaf) for V, T in meshes]
     sur_path = os.path.join(ROOT, "tests", "golden", "surrogate_mlp.npz")
     results, ys = {}, {}
     for name in variants.split(","):
@@ -306,9 +308,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if R["precision"] == "fp32" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": (desc % N) + ", p=8, leaf<=64, %s" % (
+        "config": {"workload": (desc % N) + ", p=8, leaf<=%d, %s" % (args.max_leaf,
                        "plain FP32" if R["precision"] == "fp32" else "mixed precision (FP32 MFMA M2L, FP64 singular)"),
-                   "n_panels": N, "n_meshes": len(meshes), "complex_columns": n_c, "order": 8, "max_leaf": 64},
+                   "n_panels": N, "n_meshes": len(meshes), "complex_columns": n_c, "order": 8, "max_leaf": args.max_leaf},
         "roofline": roof,
         "cpu_baseline": cpu,
         "max_col_rel_l2": acc.get(main_v),

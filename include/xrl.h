@@ -100,7 +100,9 @@ typedef struct xrl_plan xrl_plan;
  * level-by-level split of every box holding more than max_leaf centroids,
  * all on the device (the octree of the FMM of Sec. II-C, built on panel
  * centroids).  A panel belongs to the box that holds its centroid.
- *   max_leaf  : 1..64 (64 recommended)
+ *   max_leaf  : 1..128; near-field blocks are padded to 16, 32, 64 or 128
+ *               targets.  Larger leaves move work from the translations to
+ *               the near field (fewer M2L pairs, more stored values).
  *   max_depth : 1..21; a box at max_depth is a leaf whatever its count
  *               (flagged in xrl_tree_info.n_overfull_leaves).
  * Errors: XRL_E_INVALID_ARG (sizes, indices out of range),
@@ -141,7 +143,7 @@ typedef struct {
  * given, densities are concatenated along the panel axis.  The trees must
  * outlive the plan.
  * Errors: XRL_E_INVALID_ARG, XRL_E_UNSUPPORTED (order or engine; or a leaf
- *         holding more than 64 panels at the maximum depth, i.e. nearly
+ *         holding more than 128 panels at the maximum depth, i.e. nearly
  *         coincident centroids), XRL_E_OOM, XRL_E_HIP. */
 xrl_status xrl_fmm_plan(xrl_tree *const *trees, int32_t n_trees, const xrl_plan_opts *opts,
                         void *stream, xrl_plan **out);

@@ -137,7 +137,7 @@ __host__ __device__ inline uint64_t morton3(uint32_t ix, uint32_t iy, uint32_t i
 }
 
 constexpr int kMaxDepth = 21;
-constexpr int kMaxLeaf = 64;
+constexpr int kMaxLeaf = 128;
 
 }  // namespace xrl
 

@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_p2p_wide(const int32_t *__restrict__ le
     // every thread keeps a whole chunk of loads in flight
     typedef float fv_t __attribute__((ext_vector_type(VT)));
     constexpr int PER = ROWS * CT / 256;
-    constexpr int RMAX = ROWS * 64 / (256 * VT);  // rows per thread and chunk at the widest block (G = 64)
+    constexpr int RMAX = ROWS * kMaxLeaf / (256 * VT);  // rows per thread and chunk at the widest block
     float xn[PER];
     fv_t vn[RMAX], vc[RMAX];
     auto fetch = [&](int rc) {
@@ -310,9 +310,12 @@ __global__ __launch_bounds__(64) void k_p2p_sx(const int32_t *__restrict__ leaf_
     const int32_t kb = box_beg[tb], nt = box_end[tb] - kb;
     const int32_t r0 = near_rows[li], nr = near_rows[li + 1] - r0;
     const int G = leaf_tpad[li];
-    const bool act = lane < G;
-    const float *vb = val + val_off[li] + (act ? lane : 0);
     const int ncol = min(CT, C - c0);
+    // blocks wider than a wave: one pass per 64 targets
+    for (int t0 = 0; t0 < G; t0 += 64) {
+    const int t = t0 + lane;
+    const bool act = t < G;
+    const float *vb = val + val_off[li] + (act ? t : 0);
     float acc[CT];
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[c] = 0.f;
@@ -333,11 +336,12 @@ __global__ __launch_bounds__(64) void k_p2p_sx(const int32_t *__restrict__ leaf_
                 if (c < ncol) acc[c] += v * xr[c];
         }
     }
-    if (lane < nt) {
-        float *yo = ys + (int64_t)(kb + lane) * C + c0;
+    if (t < nt) {
+        float *yo = ys + (int64_t)(kb + t) * C + c0;
 #pragma unroll
         for (int c = 0; c < CT; ++c)
             if (c < ncol) yo[c] = acc[c];
+    }
     }
 }
 
@@ -469,7 +473,8 @@ __global__ __launch_bounds__(64) void k_p2p_mfma(int items_per_leaf, const int32
     switch (leaf_tpad[li]) {
         case 16: p2p_mfma_leaf<WT, XC, 1>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
         case 32: p2p_mfma_leaf<WT, XC, 2>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
-        default: p2p_mfma_leaf<WT, XC, 4>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
+        case 64: p2p_mfma_leaf<WT, XC, 4>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
+        default: p2p_mfma_leaf<WT, XC, 8>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
     }
 }
 
@@ -545,7 +550,7 @@ __global__ __launch_bounds__(64) void k_p2m_mfma(int items_per_leaf, const int32
                                                  const int32_t *__restrict__ box_end, const float *__restrict__ mom,
                                                  const float *__restrict__ xs, float *__restrict__ M, int C)
 {
-    constexpr int K = (ORD + 1) * (ORD + 1), NRT = (K + 15) / 16, NKS = 16;  // at most 64 panels per leaf
+    constexpr int K = (ORD + 1) * (ORD + 1), NRT = (K + 15) / 16, NKS = kMaxLeaf / 4;
     struct BV {
         float v[WT];
     };

@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restr
     const int32_t kb = a.box_beg[T], nt = a.box_end[T] - kb;
     const int32_t r0 = a.near_rows[li], nr = a.near_rows[li + 1] - r0;
     const int tpad = a.leaf_tpad[li];
-    const int sh = tpad == 16 ? 4 : (tpad == 32 ? 5 : 6);
+    const int sh = __ffs(tpad) - 1;  // tpad is a power of two
     const int64_t vo = a.val_off[li];
     unsigned long long c_self = 0, c_reg = 0;
     for (int64_t e = threadIdx.x; e < (int64_t)nr << sh; e += blockDim.x) {

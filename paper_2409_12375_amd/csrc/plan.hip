@@ -492,8 +492,8 @@ static void build_plan(xrl_plan *P, hipStream_t s)
         if (nchild[b] == 0) {
             leaves.push_back((int32_t)b);
             XRL_CHECK(end[b] - beg[b] <= kMaxLeaf, XRL_E_UNSUPPORTED,
-                      "xrl_fmm_plan: a leaf holds %d > 64 panels (coincident centroids at max depth)",
-                      end[b] - beg[b]);
+                      "xrl_fmm_plan: a leaf holds %d > %d panels (coincident centroids at max depth)",
+                      end[b] - beg[b], kMaxLeaf);
         }
     }
     P->h_leaf_box = leaves;
@@ -595,7 +595,7 @@ static void build_plan(xrl_plan *P, hipStream_t s)
                   "xrl_fmm_plan: a leaf at the maximum depth holds %d panels (more than %d); "
                   "the mesh has (nearly) coincident panel centroids",
                   nt, kMaxLeaf);
-        tpad[li] = nt <= 16 ? 16 : (nt <= 32 ? 32 : 64);
+        tpad[li] = nt <= 16 ? 16 : (nt <= 32 ? 32 : (nt <= 64 ? 64 : 128));
         // sort source boxes by their panel range so the rows are in Morton order
         std::vector<std::pair<int32_t, int32_t>> rg;
         for (int64_t j = noff[li]; j < noff[li + 1]; ++j) rg.push_back({beg[hnbox[j]], end[hnbox[j]]});

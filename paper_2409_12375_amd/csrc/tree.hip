@@ -181,7 +181,7 @@ extern "C" xrl_status xrl_tree_build(const xrl_mesh_desc *mesh, int32_t max_leaf
                   XRL_E_INVALID_ARG, "xrl_tree_build: bad sizes (n_panels=%lld, n_vertices=%lld)",
                   (long long)mesh->n_panels, (long long)mesh->n_vertices);
         XRL_CHECK(max_leaf >= 1 && max_leaf <= kMaxLeaf, XRL_E_INVALID_ARG,
-                  "xrl_tree_build: max_leaf must be in 1..64 (got %d)", max_leaf);
+                  "xrl_tree_build: max_leaf must be in 1..%d (got %d)", kMaxLeaf, max_leaf);
         XRL_CHECK(max_depth >= 1 && max_depth <= kMaxDepth, XRL_E_INVALID_ARG,
                   "xrl_tree_build: max_depth must be in 1..21 (got %d)", max_depth);
         hipStream_t s = (hipStream_t)stream;

@@ -236,6 +236,44 @@ def test_other_orders_matrix_core_forms_match_vector_forms(order):
     assert err.max() <= (3e-4 if order == 6 else 1e-5)
 
 
+@pytest.mark.parametrize("precision,ncomplex", [("mixed", 18), ("fp64", 3)])
+def test_leaves_of_128_panels(precision, ncomplex):
+    """max_leaf = 128 (near-field blocks 128 targets wide): every P2P form,
+    P2M and L2P against the vector forms and the oracle."""
+    say("case: bar 4096, max_leaf 128, %s, %d columns" % (precision, ncomplex))
+    V, T = I.bar()
+    N = len(T)
+    dt = np.complex128 if precision == "fp64" else np.complex64
+    x = I.densities(N, ncomplex, dt, seed=70 + ncomplex)
+    tree = xrl.Tree(V, T, max_leaf=128)
+    tp = None
+    ys = {}
+    for v in (("mfma", "scalar", "vector") if precision == "mixed" else ("auto",)):
+        plan = xrl.Plan(tree, order=8, precision=precision, engine="mfma_os" if v == "vector" else "auto",
+                        max_cols=ncomplex)
+        plan.assemble()
+        tp = plan.export(9)
+        if v == "scalar":
+            plan.set_tuning("p2p_form", 1)
+        if v == "vector":
+            plan.set_tuning("p2p_form", 2)
+            plan.set_tuning("leaf_form", 0)
+        ys[v] = plan.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+        plan.close()
+    assert tp.max() == 128
+    first = next(iter(ys))
+    for v in ys:
+        if v != first:
+            d = np.linalg.norm(ys[first] - ys[v], axis=0) / np.linalg.norm(ys[v], axis=0)
+            say("  %s vs %s" % (first, v), d.max())
+            assert d.max() < 1e-6
+    rows = sample_rows(N, 64)
+    ref, _ = O.matvec(V, T, x.astype(np.complex128), rows=rows)
+    err = relerr_cols(ys[first][rows], ref)
+    say("  rel L2 per column", err.max())
+    assert err.max() <= (2e-5 if precision == "fp64" else 5e-5)
+
+
 @pytest.mark.parametrize("engine", ["auto", "mfma_ts"])
 def test_adaptive_tree_matvec_matches_oracle(engine):
     say("case: bar + sphere adaptive, fp64, max_leaf 16, %s" % engine)
