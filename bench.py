@@ -4,10 +4,11 @@ Default workload (--workload bga): a BGA-like package, ~1.03M flat triangle
 panels (a 10x10 plane with 400 circular holes, 100 vias through the central
 holes and 100 solder-ball spheres), 6 ports x 3 current components = 18
 complex64 density columns N(0,1) carried together (batched right-hand sides),
-expansion order p = 8, leaves <= 64 panels.  Three variants run on the same
-inputs: mixed precision (the headline: FP32 M2L on MFMA with FP32
+expansion order p = 8, leaves <= 128 panels (--max-leaf; larger leaves
+give fewer M2L pairs and more near-field values).  Three variants run on the
+same inputs: mixed precision (the headline: FP32 M2L on MFMA with FP32
 accumulation, FP64 self and touching integrals), plain FP32 (every phase in
-FP32, M2L on the vector ALUs) and surrogate + mixed (learned near-singular
+FP32 on the vector ALUs) and surrogate + mixed (learned near-singular
 pairs, quadrature fall-back).
 --workload coils: two 5-turn square planar coils, ~200k panels, 3 columns.
 --workload pop: a package-on-package-like stack, ~2.1M panels, 8 ports x 3
