@@ -383,13 +383,21 @@ __device__ inline void p2p_mfma_leaf(int lane, int nr, const float *__restrict__
     const auto rv = buf_rsrc(vb, (uint32_t)nr * G * 4);
     const auto rs = buf_rsrc(srcs, (uint32_t)nr * 4);
     const int xo = cb + WT * li, xno = cb + 16 * WT + (li & 3);
-    auto load = [&](int ks0, Stage &st) {
+    // source rows of a stage, fetched two stages ahead, so that the
+    // densities they index can be requested as soon as the stage is due
+    struct Src {
+        int r[U];
+    };
+    auto load_src = [&](int ks0, Src &sr) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) sr.r[u] = buf_load<int>(rs, (4 * (ks0 + u) + kq) * 4, 0);
+    };
+    auto load = [&](int ks0, const Src &sr, Stage &st) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int r = 4 * (ks0 + u) + kq;
             st.v[u] = buf_load<VE>(rv, (r * G + E * li) * 4, 0);
-            const int src = buf_load<int>(rs, r * 4, 0);
-            const float *xr = xs + (int64_t)src * C;
+            const float *xr = xs + (int64_t)sr.r[u] * C;
             st.b[u] = *reinterpret_cast<const BV *>(xr + xo);
             if constexpr (XC > 0) st.xn[u] = xr[xno];
         }
@@ -415,12 +423,17 @@ __device__ inline void p2p_mfma_leaf(int lane, int nr, const float *__restrict__
     // them
     const int ntrip = (nr + 8 * U - 1) / (8 * U);
     Stage s0, s1;
-    load(0, s0);
+    Src ra, rb;
+    load_src(0, ra);
+    load(0, ra, s0);
+    load_src(U, rb);
     for (int q = 0; q < ntrip; ++q) {
         const int ks = 2 * U * q;
-        load(ks + U, s1);
+        load_src(ks + 2 * U, ra);
+        load(ks + U, rb, s1);
         comp(s0);
-        load(ks + 2 * U, s0);
+        load_src(ks + 3 * U, rb);
+        load(ks + 2 * U, ra, s0);
         comp(s1);
     }
     // D[i][j] of tile (e, ct) at lane j + 16 q, element i - 4 q: column
