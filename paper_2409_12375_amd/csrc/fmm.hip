@@ -563,9 +563,16 @@ __global__ __launch_bounds__(64) void k_p2m_mfma(int items_per_leaf, const int32
                                                  const int32_t *__restrict__ box_end, const float *__restrict__ mom,
                                                  const float *__restrict__ xs, float *__restrict__ M, int C)
 {
-    constexpr int K = (ORD + 1) * (ORD + 1), NRT = (K + 15) / 16, NKS = kMaxLeaf / 4;
+    constexpr int K = (ORD + 1) * (ORD + 1), NRT = (K + 15) / 16;
     struct BV {
         float v[WT];
+    };
+    // operands of one k step: the moments of panel 4 ks + kq for every
+    // coefficient tile, and its densities
+    struct Step {
+        float a[NRT];
+        BV b;
+        float x;
     };
     const int w = blockIdx.x;
     const int li_leaf = w / items_per_leaf;
@@ -573,34 +580,45 @@ __global__ __launch_bounds__(64) void k_p2m_mfma(int items_per_leaf, const int32
     const int lane = threadIdx.x, li = lane & 15, kq = lane >> 4;
     const int32_t b = leaf_box[li_leaf];
     const int32_t kb = box_beg[b], nt = box_end[b] - kb;
-    const int nks = (nt + 3) / 4;
-    // densities of panel 4 ks + kq (zero past the leaf)
     const auto rx = buf_rsrc(xs + (int64_t)kb * C, (uint32_t)(nt * C * 4));
-    float bx[NKS][WT], bn[XC ? NKS : 1];
-#pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) {
-        if (ks >= nks) break;
-        const int t = 4 * ks + kq;
-        const BV v = buf_load<BV>(rx, (t * C + cb + WT * li) * 4, 0);
-#pragma unroll
-        for (int ct = 0; ct < WT; ++ct) bx[ks][ct] = v.v[ct];
-        if constexpr (XC > 0) bn[ks] = buf_load<float>(rx, (t * C + cn + (li & 3)) * 4, 0);
-    }
     const auto rq = buf_rsrc(mom + (int64_t)kb * K, (uint32_t)(nt * K * 4));
-    float *Mb = M + (int64_t)b * K * C;
+    auto load = [&](int ks, Step &st) {
+        const int t = 4 * ks + kq;
+#pragma unroll
+        for (int it = 0; it < NRT; ++it) st.a[it] = buf_load<float>(rq, (t * K + 16 * it + li) * 4, 0);
+        st.b = buf_load<BV>(rx, (t * C + cb + WT * li) * 4, 0);
+        if constexpr (XC > 0) st.x = buf_load<float>(rx, (t * C + cn + (li & 3)) * 4, 0);
+    };
+    f32x4 acc[NRT][WT], accx[XC ? NRT : 1];
+#pragma unroll
     for (int it = 0; it < NRT; ++it) {
-        f32x4 acc[WT], accx = {0, 0, 0, 0};
 #pragma unroll
-        for (int ct = 0; ct < WT; ++ct) acc[ct] = f32x4{0, 0, 0, 0};
+        for (int ct = 0; ct < WT; ++ct) acc[it][ct] = f32x4{0, 0, 0, 0};
+        if (XC || it == 0) accx[XC ? it : 0] = f32x4{0, 0, 0, 0};
+    }
+    auto comp = [&](const Step &st) {
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) {
-            if (ks >= nks) break;
-            const int t = 4 * ks + kq;
-            const float a = buf_load<float>(rq, (t * K + 16 * it + li) * 4, 0);
+        for (int it = 0; it < NRT; ++it) {
 #pragma unroll
-            for (int ct = 0; ct < WT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bx[ks][ct], acc[ct], 0, 0, 0);
-            if constexpr (XC > 0) accx = __builtin_amdgcn_mfma_f32_4x4x1f32(a, bn[ks], accx, 0, 0, 0);
+            for (int ct = 0; ct < WT; ++ct)
+                acc[it][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(st.a[it], st.b.v[ct], acc[it][ct], 0, 0, 0);
+            if constexpr (XC > 0) accx[it] = __builtin_amdgcn_mfma_f32_4x4x1f32(st.a[it], st.x, accx[it], 0, 0, 0);
         }
+    };
+    // two k steps per trip, the next one in flight; steps past the leaf read
+    // zeros (range-checked loads), so the trip count may round up
+    const int nks = (nt + 3) / 4;
+    Step s0, s1;
+    load(0, s0);
+    for (int ks = 0; ks < nks; ks += 2) {
+        load(ks + 1, s1);
+        comp(s0);
+        load(ks + 2, s0);
+        comp(s1);
+    }
+    float *Mb = M + (int64_t)b * K * C;
+#pragma unroll
+    for (int it = 0; it < NRT; ++it) {
         // D[i][j] at lane j + 16 q, element i - 4 q: coefficient 16 it + i,
         // column cb + WT j + ct
 #pragma unroll
@@ -608,15 +626,16 @@ __global__ __launch_bounds__(64) void k_p2m_mfma(int items_per_leaf, const int32
 #pragma unroll
             for (int e4 = 0; e4 < 4; ++e4) {
                 const int i = 16 * it + 4 * kq + e4, col = cb + WT * li + ct;
-                if (i < K && col < C) Mb[i * C + col] = acc[ct][e4];
+                if (i < K && col < C) Mb[i * C + col] = acc[it][ct][e4];
             }
         if constexpr (XC > 0) {
+            f32x4 v = accx[it];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                accx[i] += __shfl_xor(accx[i], 16);
-                accx[i] += __shfl_xor(accx[i], 32);
+                v[i] += __shfl_xor(v[i], 16);
+                v[i] += __shfl_xor(v[i], 32);
             }
-            const float mine = kq == 0 ? accx[0] : kq == 1 ? accx[1] : kq == 2 ? accx[2] : accx[3];
+            const float mine = kq == 0 ? v[0] : kq == 1 ? v[1] : kq == 2 ? v[2] : v[3];
             const int i = 16 * it + 4 * (li >> 2) + kq, col = cn + (li & 3);
             if (i < K && col < C) Mb[i * C + col] = mine;
         }
