@@ -719,14 +719,37 @@ __global__ __launch_bounds__(64) void k_l2p_mfma(int items_per_leaf, const int32
     }
     const auto rq = buf_rsrc(mom + (int64_t)kb * K, (uint32_t)(nt * K * 4));
     const int ntt = (nt + 15) / 16;
-    for (int tt = 0; tt < ntt; ++tt) {
+    // a 16-target tile's moments and the values it adds to, fetched one
+    // tile ahead
+    struct Tile {
         float a[NKS];
+        float old[WT][4];
+        float ox;
+    };
+    auto load_tile = [&](int tt, Tile &T) {
         const int qo = ((16 * tt + li) * K + NKS * kq) * 4;
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) {
-            const float q = buf_load<float>(rq, qo + 4 * ks, 0);
-            a[ks] = valid[ks] ? q : 0.f;
+        for (int ks = 0; ks < NKS; ++ks) T.a[ks] = buf_load<float>(rq, qo + 4 * ks, 0);
+#pragma unroll
+        for (int ct = 0; ct < WT; ++ct)
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+                const int t = 16 * tt + 4 * kq + e4, col = cb + WT * li + ct;
+                T.old[ct][e4] = (t < nt && col < C) ? ys[(int64_t)(kb + t) * C + col] : 0.f;
+            }
+        if constexpr (XC > 0) {
+            const int t = 16 * tt + 4 * (li >> 2) + kq, col = cn + (li & 3);
+            T.ox = (t < nt && col < C) ? ys[(int64_t)(kb + t) * C + col] : 0.f;
         }
+    };
+    Tile tn;
+    if (ntt > 0) load_tile(0, tn);
+    for (int tt = 0; tt < ntt; ++tt) {
+        const Tile tc = tn;
+        if (tt + 1 < ntt) load_tile(tt + 1, tn);
+        float a[NKS];
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) a[ks] = valid[ks] ? tc.a[ks] : 0.f;
         f32x4 acc[WT], accx = {0, 0, 0, 0};
 #pragma unroll
         for (int ct = 0; ct < WT; ++ct) acc[ct] = f32x4{0, 0, 0, 0};
@@ -743,7 +766,7 @@ __global__ __launch_bounds__(64) void k_l2p_mfma(int items_per_leaf, const int32
 #pragma unroll
             for (int e4 = 0; e4 < 4; ++e4) {
                 const int t = 16 * tt + 4 * kq + e4, col = cb + WT * li + ct;
-                if (t < nt && col < C) ys[(int64_t)(kb + t) * C + col] += acc[ct][e4];
+                if (t < nt && col < C) ys[(int64_t)(kb + t) * C + col] = tc.old[ct][e4] + acc[ct][e4];
             }
         if constexpr (XC > 0) {
             // lane (li, kq): column cn + (li & 3), targets 16 tt + 4 (li / 4) + i
@@ -756,7 +779,7 @@ __global__ __launch_bounds__(64) void k_l2p_mfma(int items_per_leaf, const int32
             }
             const float mine = kq == 0 ? accx[0] : kq == 1 ? accx[1] : kq == 2 ? accx[2] : accx[3];
             const int t = 16 * tt + 4 * (li >> 2) + kq, col = cn + (li & 3);
-            if (t < nt && col < C) ys[(int64_t)(kb + t) * C + col] += mine;
+            if (t < nt && col < C) ys[(int64_t)(kb + t) * C + col] = tc.ox + mine;
         }
     }
 }
