@@ -452,11 +452,15 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
         XRL_CHECK((int64_t)(hw[0] + hw[1]) <= cap, XRL_E_OOM,
                   "xrl_nearfield_assemble: special-pair queue overflow (%llu + %llu > %lld)",
                   (unsigned long long)hw[0], (unsigned long long)hw[1], (long long)cap);
+        // mixed precision: FP64 for the touching (adjacent-panel) pairs and
+        // for the audit reference of the surrogate, FP32 (relative to the
+        // target centroid, exact inner potential) for the near-singular
+        // pairs that are not adjacent
         auto special = [&](int which, int64_t count, const int64_t *list, double *alt) {
             if (count == 0) return;
             if (P->precision == XRL_PREC_FP64)
                 k_nf_special<double, double><<<cdiv(count, 64), 64, 0, s>>>(a, R, which, count, P->near64.p, list, alt);
-            else if (P->precision == XRL_PREC_MIXED)
+            else if (P->precision == XRL_PREC_MIXED && (which == 0 || alt))
                 k_nf_special<float, double><<<cdiv(count, 64), 64, 0, s>>>(a, R, which, count, P->near32.p, list, alt);
             else
                 k_nf_special<float, float><<<cdiv(count, 64), 64, 0, s>>>(a, R, which, count, P->near32.p, list, alt);

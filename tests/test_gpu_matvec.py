@@ -287,11 +287,16 @@ def test_adaptive_tree_matvec_matches_oracle(engine):
     assert err.max() <= 2e-5
 
 
-def test_near_field_entries_match_oracle():
-    say("case: near-field entries fp64")
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_near_field_entries_match_oracle(precision):
+    """Stored near-field entries against the oracle, by pair class: FP64
+    everywhere to 1e-8; mixed precision stores FP32, with the self and
+    touching entries integrated in FP64 (to FP32 rounding) and the others in
+    FP32."""
+    say("case: near-field entries %s" % precision)
     V, T = I.bar(2, 2, 12, size=(1.0, 1.0, 6.0))
     tree = xrl.Tree(V, T, max_leaf=16)
-    plan = xrl.Plan(tree, order=4, precision="fp64", max_cols=1)
+    plan = xrl.Plan(tree, order=4, precision=precision, max_cols=1)
     plan.assemble()
     perm = plan.export(0)
     rng_ = plan.export(1).reshape(-1, 2)
@@ -318,7 +323,11 @@ def test_near_field_entries_match_oracle():
             e = abs(blk[r, j] - ref) / abs(ref)
             worst[cls] = max(worst.get(cls, 0), e)
     say("  worst relative entry error by class", worst)
-    assert max(worst.values()) < 1e-8
+    if precision == "fp64":
+        assert max(worst.values()) < 1e-8
+    else:
+        # FP64 results stored in FP32: within two FP32 rounding steps
+        assert worst.get("self", 0) < 3e-7 and worst.get("touch", 0) < 3e-7 and worst.get("other", 0) < 1e-5
 
 
 def test_linearity_determinism_and_epilogue():
