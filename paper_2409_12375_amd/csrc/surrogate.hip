@@ -379,8 +379,13 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpBf16 w, const float *__res
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, kq = lane >> 4;
     short *hbuf = sh + wave * 16 * H;
     const int64_t nchunks = (n + 15) / 16;
-    // every wave of the block runs the same number of iterations (the block
-    // barriers below are reached by all), waves past the end do no work
+    // SiLU on the hardware exponential and reciprocal: its result is rounded
+    // to BF16 at once, far coarser than their error
+    auto silu_bf = [](float z) { return f2bf(z * __builtin_amdgcn_rcpf(1.f + __expf(-z))); };
+    // each wave works on its own 16 samples and its own slice of LDS; a
+    // wave's LDS accesses complete in order, so only a wave barrier (no
+    // instruction, a fence for the compiler) separates writing the hidden
+    // layer and reading it back across lanes
     for (int64_t base = (int64_t)blockIdx.x * 4; base < nchunks; base += (int64_t)gridDim.x * 4) {
         const int64_t ch = base + wave;
         const bool active = ch < nchunks;
@@ -401,11 +406,12 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpBf16 w, const float *__res
             }
             for (int e = 0; e < 4; ++e) {
                 const int r = 4 * kq + e, c = 16 * ct + li;
-                const float z = d[e] + w.b1[c];
-                hbuf[r * H + c] = f2bf(z / (1.f + expf(-z)));
+                hbuf[r * H + c] = silu_bf(d[e] + w.b1[c]);
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // layer 2
         f32x4 d2[H / 16];
         for (int ct = 0; ct < H / 16; ++ct) d2[ct] = f32x4{0, 0, 0, 0};
@@ -416,14 +422,17 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpBf16 w, const float *__res
                 d2[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, d2[ct], 0, 0, 0);
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         for (int ct = 0; ct < H / 16; ++ct)
             for (int e = 0; e < 4; ++e) {
                 const int r = 4 * kq + e, c = 16 * ct + li;
-                const float z = d2[ct][e] + w.b2[c];
-                hbuf[r * H + c] = f2bf(z / (1.f + expf(-z)));
+                hbuf[r * H + c] = silu_bf(d2[ct][e] + w.b2[c]);
             }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // layer 3 (2 outputs, rows of W3 padded to 16)
         f32x4 d3 = {0, 0, 0, 0};
         for (int ks = 0; ks < H / 16; ++ks) {
@@ -436,7 +445,9 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpBf16 w, const float *__res
                 const int64_t sidx = s0 + 4 * kq + e;
                 if (sidx < n) out[2 * sidx + li] = (d3[e] + w.b3[li]) * (li == 0 ? out_scale(X + sidx * 18) : 1.f);
             }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
