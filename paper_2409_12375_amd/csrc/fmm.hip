@@ -1138,15 +1138,19 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
                 if (XC) taccx[i] = flip_sign(taccx[i], (uint32_t)f);
         }
     };
-    // Software pipeline over (pair, row-tile group) steps: the operator of a
-    // pair is streamed in three groups of row tiles through a ring of two
-    // register buffers, each group's loads issued two steps before its
-    // MFMAs; the next pair's B fragments are issued at the first group of
-    // the current pair.  Loads complete in issue order, so each wait covers
-    // only what the next step needs, and the ring keeps the registers low
-    // enough that the accumulators never leave their registers.
-    constexpr int GR = (NRTM + 2) / 3;  // row tiles per group
-    AV r0[GR][NKV], r1[GR][NKV];
+    // Software pipeline over (pair, row-tile group) steps; the next pair's B
+    // fragments are issued at the first group of the current pair, and
+    // loads complete in issue order, so each wait covers only what the next
+    // step needs.  FP32 with the full operator table up to order 8: one
+    // register buffer per operator row tile, the next pair's tile issued
+    // right after the current pair's, as many steps ahead as there are
+    // tiles less one.  Otherwise (FP64 has twice the registers per tile,
+    // reflections need their sign masks, higher orders more tiles): three
+    // groups of row tiles through a ring of two buffers, each group's loads
+    // issued two steps before its MFMAs, so that the accumulators stay in
+    // their registers as far as they fit.
+    constexpr bool TILE_RING = sizeof(T) == 4 && !REFL && ORD <= 8;
+    constexpr int GR = TILE_RING ? 1 : (NRTM + 2) / 3;  // row tiles per group
     // per-pair operands (B fragments, 4x4-block densities, last operator
     // row), in two sets that alternate between the two pairs of a trip, so
     // the next pair's loads land in place without copies
@@ -1180,8 +1184,9 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
     // the source record and the 256 elements after it (columns past C and
     // the clamped last k step read at most that far)
     const uint32_t mbytes = (uint32_t)((D::K * C + 256) * sizeof(T));
-    auto load_b = [&](int j, PB &d) {
-        const auto rs = buf_rsrc(in + (int64_t)ts_src[j] * D::K * C, mbytes);
+    // live = false: a record of zero bytes, every load of it returns zero
+    auto load_b = [&](int j, PB &d, bool live = true) {
+        const auto rs = buf_rsrc(in + (int64_t)ts_src[j] * D::K * C, live ? mbytes : 0u);
 #pragma unroll
         for (int ks = 0; ks < D::NKS; ++ks) {
             const int lofs = ks == D::NKS - 1 ? blast : 0;  // lane part of the clamp
@@ -1227,25 +1232,80 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
             }
         }
     };
-    if (j0 < j1) {
-        auto clampj = [&](int j) { return j < j1 ? j : j1 - 1; };
-        int frame = 0;
+    auto clampj = [&](int j) { return j < j1 ? j : j1 - 1; };
+    int frame = 0;
+    auto reframe = [&](int code) {
+        if constexpr (REFL) {
+            if ((code & 7) != frame) {
+                flip_acc((code & 7) ^ frame);
+                frame = code & 7;
+            }
+        }
+    };
+    // Two pairs per trip, so that the buffer of each step and the operand
+    // set of each pair are static.  With one buffer per tile a target with
+    // an odd number of pairs ends on a phantom pair: the operator of its
+    // last pair applied to densities that load as zeros.  That trip has no
+    // branch, so the compiler cannot move the next pair's loads down to
+    // their first use, which would undo the prefetch; the prologue issues
+    // its loads in the order of the trip's, so that the waits of the first
+    // step hold for every trip.  The ring of two keeps the branch around
+    // the second pair (both operand sets live at once would not fit).
+    if constexpr (TILE_RING) {
+        AV rb[NRTM][GR][NKV];
+        // one pair: tile rt computed, then the same tile of the next pair
+        // (code cn) loaded into its buffer; the next pair's operands go
+        // out after the first tile
+        auto pair = [&](const PB &p, int cn, PB &pn, int jn, bool live) {
+            __builtin_amdgcn_sched_barrier(0);
+            compute(0, rb[0], p);
+            tail_fma(p);
+            __builtin_amdgcn_sched_barrier(0);
+            load_b(jn, pn, live);
+            load_t(cn, pn);
+            load_g(cn, 0, rb[0]);
+#pragma unroll
+            for (int rt = 1; rt < NRTM; ++rt) {
+                __builtin_amdgcn_sched_barrier(0);
+                compute(rt, rb[rt], p);
+                __builtin_amdgcn_sched_barrier(0);
+                load_g(cn, rt, rb[rt]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            flip_b(cn, pn);
+        };
+        if (j0 < j1) {
+            int c0 = ts_op[j0], c1 = ts_op[clampj(j0 + 1)];
+            load_b(j0, p0);
+            load_t(c0, p0);
+            load_g(c0, 0, rb[0]);
+#pragma unroll
+            for (int rt = 1; rt < NRTM; ++rt) {
+                __builtin_amdgcn_sched_barrier(0);
+                load_g(c0, rt, rb[rt]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            flip_b(c0, p0);
+            for (int j = j0; j < j1; j += 2) {
+                const int c2 = ts_op[clampj(j + 2)];
+                reframe(c0);
+                pair(p0, c1, p1, clampj(j + 1), j + 1 < j1);
+                reframe(c1);
+                pair(p1, c2, p0, clampj(j + 2), true);
+                c0 = c2;
+                c1 = ts_op[clampj(j + 3)];
+            }
+            if constexpr (REFL)
+                if (frame) flip_acc(frame);
+        }
+    } else if (j0 < j1) {
+        AV r0[GR][NKV], r1[GR][NKV];
         int c0 = ts_op[j0], c1 = ts_op[clampj(j0 + 1)];
         load_b(j0, p0);
         load_t(c0, p0);
         load_g(c0, 0, r0);
         load_g(c0, 1, r1);
         flip_b(c0, p0);
-        auto reframe = [&](int code) {
-            if constexpr (REFL) {
-                if ((code & 7) != frame) {
-                    flip_acc((code & 7) ^ frame);
-                    frame = code & 7;
-                }
-            }
-        };
-        // two pairs per trip, so that the ring parity and the operand set
-        // of each pair are static
         for (int j = j0; j < j1; j += 2) {
             const int c2 = ts_op[clampj(j + 2)];
             reframe(c0);
@@ -1253,7 +1313,7 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
             compute(0, r0, p0);
             tail_fma(p0);
             __builtin_amdgcn_sched_barrier(0);
-            load_b(clampj(j + 1), p1);
+            load_b(clampj(j + 1), p1, j + 1 < j1);
             load_t(c1, p1);
             load_g(c0, 2, r0);
             __builtin_amdgcn_sched_barrier(0);
