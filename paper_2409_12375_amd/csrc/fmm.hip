@@ -1219,15 +1219,44 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
             }
         }
     };
+    // K = 4 n + 1 (every even order): the last k step holds one operator
+    // column, K - 1, a rank-one update.  On the FP32 per-tile path it goes
+    // to 4x4 blocks instead of a 16x16x4 tile that is 3/4 padding: block b
+    // takes rows 4 (b / 4) .. + 3 and columns 4 (b % 4) .. + 3 of the tile,
+    // so its A value at lane (li, kq) is operator row 16 rt + 4 kq + li % 4
+    // (one word of the tile's last fragment, the one lane 4 kq + li % 4
+    // holds, loaded on its own with the tile), its B value is the density
+    // row K - 1 already loaded for that step, and its result lands in the
+    // 16x16 accumulator's own lane layout (lane (li, kq), element e: row
+    // 4 kq + e, column li), so it accumulates in place.  Taken at order 8
+    // with more than 16 columns, where the wave holds over 256 registers
+    // anyway: the loaded values would cost the narrower forms their second
+    // wave.
+    constexpr bool RANK1 = TILE_RING && D::K % 4 == 1 && ORD == 8 && WT * 16 + XC > 16;
+    constexpr int NKM = RANK1 ? D::NKS - 1 : D::NKS;  // k steps on 16x16x4
+    T ra[RANK1 ? NRTM : 1];
+    auto load_a1 = [&](int code, int rt) {
+        if constexpr (RANK1) {
+            const auto rs = buf_rsrc(op_vec + (int64_t)(code >> 3) * D::NRT * NKV * 64 * VEC, obytes);
+            ra[rt] = buf_load<T>(rs, (4 * kq + (li & 3)) * 16, (rt * NKV + NKV - 1) * 1024);
+        }
+    };
     auto compute = [&](int g, AV (&av)[GR][NKV], const PB &p) {
 #pragma unroll
         for (int r = 0; r < GR; ++r) {
             if (g * GR + r >= NRTM) break;
-#pragma unroll
-            for (int ks = 0; ks < D::NKS; ++ks) {
+            // the rank-one blocks go first, on accumulators last written a
+            // pair ago, so that they wait on no MFMA chain
+            if constexpr (RANK1)
 #pragma unroll
                 for (int ct = 0; ct < WT; ++ct)
-                    mfma_16x16x4<T>(av[r][ks / VEC][ks % VEC], p.b[ct][ks], acc[g * GR + r][ct]);
+                    acc[g * GR + r][ct] = __builtin_amdgcn_mfma_f32_4x4x1f32(ra[g * GR + r], p.b[ct][D::NKS - 1], acc[g * GR + r][ct], 0, 0, 0);
+#pragma unroll
+            for (int ks = 0; ks < D::NKS; ++ks) {
+                if (ks < NKM)
+#pragma unroll
+                    for (int ct = 0; ct < WT; ++ct)
+                        mfma_16x16x4<T>(av[r][ks / VEC][ks % VEC], p.b[ct][ks], acc[g * GR + r][ct]);
                 if constexpr (XC > 0) xmfma(accx[g * GR + r], av[r][ks / VEC][ks % VEC], p.x[ks]);
             }
         }
@@ -1264,12 +1293,14 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
             load_b(jn, pn, live);
             load_t(cn, pn);
             load_g(cn, 0, rb[0]);
+            load_a1(cn, 0);
 #pragma unroll
             for (int rt = 1; rt < NRTM; ++rt) {
                 __builtin_amdgcn_sched_barrier(0);
                 compute(rt, rb[rt], p);
                 __builtin_amdgcn_sched_barrier(0);
                 load_g(cn, rt, rb[rt]);
+                load_a1(cn, rt);
             }
             __builtin_amdgcn_sched_barrier(0);
             flip_b(cn, pn);
@@ -1279,10 +1310,12 @@ __global__ __launch_bounds__(64) void k_trans_ts(int n_items, int items_per_tgt,
             load_b(j0, p0);
             load_t(c0, p0);
             load_g(c0, 0, rb[0]);
+            load_a1(c0, 0);
 #pragma unroll
             for (int rt = 1; rt < NRTM; ++rt) {
                 __builtin_amdgcn_sched_barrier(0);
                 load_g(c0, rt, rb[rt]);
+                load_a1(c0, rt);
             }
             __builtin_amdgcn_sched_barrier(0);
             flip_b(c0, p0);
