@@ -24,16 +24,29 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- gather / scatter
-template <typename TI, typename TW>
+// One thread per complex density: one load of the (re, im) pair when the
+// caller's array is aligned to a pair (PAIR), else two scalar loads.
+template <typename TI, typename TW, bool PAIR>
 __global__ void k_gather_x(int64_t N, const int32_t *__restrict__ perm, const TI *__restrict__ x, int64_t ldx,
                            int ncols, TW *__restrict__ xs)
 {
-    const int C = 2 * ncols;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N * C; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / C;
-        const int c = (int)(e - i * C);
+    typedef TI TI2 __attribute__((ext_vector_type(2)));
+    typedef TW TW2 __attribute__((ext_vector_type(2)));
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N * ncols;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / ncols;
+        const int c = (int)(e - i * ncols);
         const int64_t u = perm[i];
-        xs[e] = (TW)x[2 * (u * ldx + (c >> 1)) + (c & 1)];
+        TI re, im;
+        if constexpr (PAIR) {
+            const TI2 v = reinterpret_cast<const TI2 *>(x)[u * ldx + c];
+            re = v[0];
+            im = v[1];
+        } else {
+            re = x[2 * (u * ldx + c)];
+            im = x[2 * (u * ldx + c) + 1];
+        }
+        reinterpret_cast<TW2 *>(xs)[e] = TW2{(TW)re, (TW)im};
     }
 }
 
@@ -2110,11 +2123,20 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
     };
     mark(0);
     const int bs = 256;
-    const unsigned gx = (unsigned)std::min<int64_t>(cdiv(N * C, bs), 1 << 20);
-    if (dtype == XRL_C64)
-        k_gather_x<float, T><<<gx, bs, 0, s>>>(N, P->perm.p, (const float *)x, ldx, ncols, xs.p);
-    else
-        k_gather_x<double, T><<<gx, bs, 0, s>>>(N, P->perm.p, (const double *)x, ldx, ncols, xs.p);
+    const unsigned gx = (unsigned)std::min<int64_t>(cdiv(N * ncols, bs), 1 << 20);
+    const size_t pair = dtype == XRL_C64 ? 2 * sizeof(float) : 2 * sizeof(double);
+    const bool aligned = (uintptr_t)x % pair == 0;
+    if (dtype == XRL_C64) {
+        if (aligned)
+            k_gather_x<float, T, true><<<gx, bs, 0, s>>>(N, P->perm.p, (const float *)x, ldx, ncols, xs.p);
+        else
+            k_gather_x<float, T, false><<<gx, bs, 0, s>>>(N, P->perm.p, (const float *)x, ldx, ncols, xs.p);
+    } else {
+        if (aligned)
+            k_gather_x<double, T, true><<<gx, bs, 0, s>>>(N, P->perm.p, (const double *)x, ldx, ncols, xs.p);
+        else
+            k_gather_x<double, T, false><<<gx, bs, 0, s>>>(N, P->perm.p, (const double *)x, ldx, ncols, xs.p);
+    }
     XRL_HIP(hipGetLastError());
     mark(1);
     p2p_launch<T>(P, op.near, xs.p, ys.p, C, s);
