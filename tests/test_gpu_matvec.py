@@ -472,3 +472,31 @@ def test_many_columns_several_items_per_target():
     err = relerr_cols(ys["mfma"][rows], ref)
     say("  rel L2 per column: max", err.max(), "median", np.median(err))
     assert err.max() <= 5e-5
+
+
+def test_densities_not_aligned_to_complex_pairs():
+    """x handed over the C ABI 4 bytes off an 8-byte boundary: the gather
+    takes its scalar-load form and the product equals the aligned call's."""
+    say("case: bar 4096, 5 columns, x at a 4-byte offset")
+    V, T = I.bar()
+    N = len(T)
+    nc = 5
+    x = I.densities(N, nc, np.complex64, seed=41)
+    tree = xrl.Tree(V, T)
+    plan = xrl.Plan(tree, order=8, precision="mixed", max_cols=nc)
+    plan.assemble()
+    xd = torch.from_numpy(x).cuda()
+    y_ref = plan.matvec(xd).cpu().numpy()
+    # the same values, interleaved (re, im), one float after an aligned start
+    buf = torch.zeros(2 * N * nc + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = torch.view_as_real(xd).reshape(-1)
+    y = torch.empty_like(xd)
+    torch.cuda.synchronize()
+    code = xrl.lib().xrl_fmm_matvec(plan.h, ctypes.c_void_p(buf.data_ptr() + 4), nc, nc, xrl.C64,
+                                    ctypes.c_void_p(y.data_ptr()), nc, None, xrl._stream(None))
+    torch.cuda.synchronize()
+    assert code == 0, xrl.lib().xrl_last_error()
+    d = np.abs(y.cpu().numpy() - y_ref).max()
+    say("  max |difference| from the aligned call", d)
+    assert d == 0.0
+    plan.close()
