@@ -6,10 +6,11 @@ holes and 100 solder-ball spheres), 6 ports x 3 current components = 18
 complex64 density columns N(0,1) carried together (batched right-hand sides),
 expansion order p = 8, leaves <= 128 panels (--max-leaf; larger leaves
 give fewer M2L pairs and more near-field values).  Three variants run on the
-same inputs: mixed precision (the headline: FP32 M2L on MFMA with FP32
-accumulation, FP64 self and touching integrals), plain FP32 (every phase in
-FP32 on the vector ALUs) and surrogate + mixed (learned near-singular
-pairs, quadrature fall-back).
+same inputs: surrogate + mixed precision (the headline, as the metric names
+it: FP32 M2L on MFMA with FP32 accumulation, FP64 self and touching
+integrals, learned near-singular pairs with quadrature fall-back), mixed
+precision without the surrogate, and plain FP32 (every phase in FP32 on the
+vector ALUs, all near field by quadrature).
 --workload coils: two 5-turn square planar coils, ~200k panels, 3 columns.
 --workload pop: a package-on-package-like stack, ~2.1M panels, 8 ports x 3
 components = 24 columns, surrogate + mixed as the headline.
@@ -71,11 +72,24 @@ def recorded_traffic():
     return float(b.group(1))
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def run_variant(xrl, torch, trees, x, precision, steps, warmup, surrogate=None, engine="auto", graph=False,
                 autotune=False):
     n_cols = x.shape[1]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     plan = xrl.Plan(trees, order=8, precision=precision, engine=engine, max_cols=n_cols)
     torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
     t0 = time.perf_counter()
     st = plan.assemble(surrogate=surrogate, audit_every=100 if surrogate is not None else 0)
     t_asm = time.perf_counter() - t0
@@ -102,7 +116,7 @@ def run_variant(xrl, torch, trees, x, precision, steps, warmup, surrogate=None, 
     ph = plan.phase_ms()
     plan.set_profiling(False)
     torch.cuda.synchronize()
-    return plan, y, t, t_asm, st, ph, tune
+    return plan, y, t, t_asm, st, ph, tune, t_plan
 
 
 def copy_calibration(nbytes):
@@ -157,7 +171,7 @@ def main():
     elif args.workload == "bga":
         meshes = [I.bga()]
         n_c = 18
-        variants = args.variants or "mixed,fp32,surrogate"
+        variants = args.variants or "surrogate,mixed,fp32"
         desc = "BGA-like package (10x10 plane, 400 holes, 100 vias, 100 balls), %d triangle panels, " \
                "18 complex64 columns (6 ports x 3 components)"
     elif args.workload == "pop":
@@ -185,7 +199,11 @@ def main():
         xh = I.densities(N, n_c, np.complex64)
         x = torch.from_numpy(xh).cuda()
     log("%s: N=%d panels in %d mesh(es)" % (args.workload, N, len(meshes)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     trees = [xrl.Tree(V, T, max_leaf=args.max_leaf) for V, T in meshes]
+    torch.cuda.synchronize()
+    t_tree = time.perf_counter() - t0
     sur_path = os.path.join(ROOT, "tests", "golden", "surrogate_mlp.npz")
     results, ys = {}, {}
     for name in variants.split(","):
@@ -197,18 +215,23 @@ def main():
                 log("no trained surrogate weights, skipping the surrogate variant")
                 continue
             sur = xrl.Surrogate.load(sur_path)
-        plan, y, t, t_asm, st, ph, tune = run_variant(xrl, torch, trees, x, prec, args.steps, args.warmup,
-                                                      surrogate=sur, engine=engine or "auto", graph=graph,
-                                                      autotune=autotune)
+        plan, y, t, t_asm, st, ph, tune, t_plan = run_variant(xrl, torch, trees, x, prec, args.steps, args.warmup,
+                                                              surrogate=sur, engine=engine or "auto", graph=graph,
+                                                              autotune=autotune)
         info = plan.info()
         C = 2 * n_c
         m2l_flops = 2.0 * K * K * C * info["n_m2l_pairs"]
-        near_bytes = 4.0 * info["n_near_entries"] + 4.0 * info["n_near_rows"]
+        # P2P algorithmic bytes: every unpadded near-field value once (FP32
+        # in the FP32 storage modes) plus the densities read and the
+        # potentials written once; the padded block stores n_near_entries
+        vb = 8.0 if prec == "fp64" else 4.0
+        near_bytes = vb * info["n_near_pairs"] + 2.0 * vb * C * N
         results[name] = {
-            "precision": prec, "ms_per_matvec": 1e3 * t, "assemble_s": t_asm,
+            "precision": prec, "ms_per_matvec": 1e3 * t, "assemble_s": t_asm, "plan_s": t_plan,
             "panel_interactions_per_s": n_c * pairs / t,
             "amortized_panel_interactions_per_s": n_c * pairs / (t + t_asm / 36.0),
             "phase_ms": ph, "n_m2l_pairs": info["n_m2l_pairs"], "n_near_entries": info["n_near_entries"],
+            "n_near_pairs": info["n_near_pairs"], "theta": info["theta"],
             "n_boxes": info["n_boxes"], "n_leaves": info["n_leaves"], "max_sep_ratio": info["max_sep_ratio"],
             "n_demoted_pairs": info["n_demoted_pairs"],
             "m2l_flops": m2l_flops, "m2l_tflops": m2l_flops / (ph["m2l"] * 1e-3) / 1e12,
@@ -232,7 +255,7 @@ def main():
     # launch over the launch's event-timed duration)
     dom = max(R["phase_ms"], key=R["phase_ms"].get)
     if dom == "p2p":
-        roof = {"bound": "hbm", "kernel": "P2P (near-field block apply)", "achieved": R["p2p_gbps"],
+        roof = {"bound": "hbm", "kernel": "P2P (near-field block apply, unpadded bytes)", "achieved": R["p2p_gbps"],
                 "peak": PEAK_HBM / 1e9, "unit": "GB/s", "traffic": None}
     else:
         mfma = R["precision"] != "fp32"
@@ -265,7 +288,7 @@ def main():
                     errs[v].append(np.linalg.norm(yi - ref, axis=0) / np.linalg.norm(ref, axis=0))
             t_cpu = time.perf_counter() - t0
             cpu = {"value": n_c * float(NB_ROWS * sum(Ns[i] for i in pick)) / t_cpu, "unit": "panel-interactions/s",
-                   "cores": int(used), "kind": "oracle",
+                   "cores": int(used), "kind": "oracle", "cpu_model": cpu_model(),
                    "sample": "%d random target rows of each of meshes %s (N = %s) x all their source panels x %d "
                              "complex columns, FP64 direct summation, %.1f s" % (
                                  NB_ROWS, pick, [Ns[i] for i in pick], n_c, t_cpu)}
@@ -291,10 +314,17 @@ def main():
             allrows = np.concatenate([first, rows])
             ref = np.concatenate([ref1, ref2]) if len(rows) else ref1
             m = len(allrows)
+            # the same oracle on one core, on the first rows
+            t0 = time.perf_counter()
+            m1 = 4
+            O.matvec(V, T, xh.astype(np.complex128), rows=first[:m1], nthreads=1)
+            t_one = time.perf_counter() - t0
             cpu = {"value": n_c * float(m) * N / t_cpu, "unit": "panel-interactions/s", "cores": int(used),
-                   "kind": "oracle",
+                   "kind": "oracle", "cpu_model": cpu_model(),
+                   "single_core_value": n_c * float(m1) * N / t_one,
                    "sample": "%d random target rows x all %d source panels x %d complex columns, FP64 direct "
-                             "summation, %.1f s" % (m, N, n_c, t_cpu)}
+                             "summation, %.1f s on %d threads; single core: %d rows, %.1f s" % (
+                                 m, N, n_c, t_cpu, int(used), m1, t_one)}
             for v, yv in ys.items():
                 e = np.linalg.norm(yv[allrows] - ref, axis=0) / np.linalg.norm(ref, axis=0)
                 acc[v] = float(e.max())
@@ -310,13 +340,20 @@ def main():
         "dtype": "f32" if R["precision"] == "fp32" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": (desc % N) + ", p=8, leaf<=%d, %s" % (args.max_leaf,
-                       "plain FP32" if R["precision"] == "fp32" else "mixed precision (FP32 MFMA M2L, FP64 singular)"),
+                       "plain FP32" if R["precision"] == "fp32" else
+                       ("learned near-singular surrogate + " if main_v.startswith("surrogate") else "") +
+                       "mixed precision (FP32 MFMA M2L, FP64 singular)"),
                    "n_panels": N, "n_meshes": len(meshes), "complex_columns": n_c, "order": 8, "max_leaf": args.max_leaf},
         "roofline": roof,
         "cpu_baseline": cpu,
         "max_col_rel_l2": acc.get(main_v),
+        "tree_build_s": t_tree,
         "variants": results,
     }
+    if "fp32" in results and main_v != "fp32":
+        line["vs_plain_fp32"] = R["panel_interactions_per_s"] / results["fp32"]["panel_interactions_per_s"]
+        line["amortized_vs_plain_fp32"] = (R["amortized_panel_interactions_per_s"] /
+                                           results["fp32"]["amortized_panel_interactions_per_s"])
     print(json.dumps(line), flush=True)
 
 

@@ -106,7 +106,9 @@ typedef struct xrl_plan xrl_plan;
  *   max_depth : 1..21; a box at max_depth is a leaf whatever its count
  *               (flagged in xrl_tree_info.n_overfull_leaves).
  * Errors: XRL_E_INVALID_ARG (sizes, indices out of range),
- *         XRL_E_DEGENERATE_PANEL (area <= 1e-14 * diameter^2, or non-finite),
+ *         XRL_E_DEGENERATE_PANEL (area <= 1e-14 * diameter^2, a non-finite
+ *         vertex, or two panels with the same three vertex indices or the
+ *         same three vertex positions: coincident panels make P singular),
  *         XRL_E_OOM, XRL_E_HIP. */
 xrl_status xrl_tree_build(const xrl_mesh_desc *mesh, int32_t max_leaf, int32_t max_depth,
                           void *stream, xrl_tree **out);
@@ -131,7 +133,13 @@ typedef struct {
     int32_t precision; /* XRL_PREC_* */
     int32_t m2l_engine;/* XRL_M2L_* */
     int32_t max_cols;  /* largest number of complex columns one matvec will carry */
+    double theta;      /* separation criterion of the M2L (V-list) pairs: a same-level
+                          pair is translated only if r_t + r_s < theta * |c_t - c_s|
+                          (r: panel-inclusive box radii), else applied directly as
+                          near field.  0 selects the default (XRL_DEFAULT_THETA);
+                          otherwise 0.5 <= theta <= 1. */
 } xrl_plan_opts;
+#define XRL_DEFAULT_THETA 0.9
 
 /* Interaction lists of the adaptive octree (U: adjacent leaves, V: same-level
  * well-separated boxes, W and X: the adaptive lists), translated into a
@@ -162,6 +170,7 @@ typedef struct {
     double max_sep_ratio; /* max over M2L pairs of (rad_t + rad_s) / |c_t - c_s| */
     int64_t n_demoted_pairs; /* V-list candidates whose panel-inclusive radii do not
                                 separate them; applied directly as near field */
+    double theta;            /* separation criterion in use (xrl_plan_opts.theta) */
 } xrl_plan_info;
 xrl_status xrl_plan_get_info(const xrl_plan *plan, xrl_plan_info *info);
 
@@ -371,6 +380,8 @@ xrl_status xrl_plan_autotune(xrl_plan *plan, const void *x, int64_t ldx, int32_t
  *   item 7: box_parent  int32 [n_boxes]
  *   item 8: near_values float64 [n_near_entries] (per leaf [rows][tpad])
  *   item 9: leaf_tpad   int32 [n_leaves]   padded target count of each leaf block
+ *   item 10: m2l_ratio  float64 [n_m2l_pairs] (r_t + r_s) / |c_t - c_s| of each
+ *                       pair of item 5, in the same order
  * With buf == NULL only *nbytes is set. */
 xrl_status xrl_plan_export(const xrl_plan *plan, int32_t item, void *buf, int64_t *nbytes);
 
@@ -409,12 +420,17 @@ typedef struct {
  * restarted GMRES, restart 50, relative residual 1e-4 or 1e-6).  Arnoldi
  * orthogonalisation (classical Gram-Schmidt, twice) and the least-squares
  * update are FP64 whatever the plan's precision.
- *   b, x : device, [n_panels][n_rhs] complex128, user panel order; x holds
- *          the initial guess on entry and the solution on exit.
+ *   b, x : device, [n_panels][n_rhs] complex of type dtype (XRL_C64 or
+ *          XRL_C128), user panel order; x holds the initial guess on entry
+ *          and the solution on exit.  Complex64 data is widened to complex128
+ *          for the iteration (the Krylov basis is always FP64) and the
+ *          solution rounded back to complex64.
+ * The solver's operator applications never replay a captured graph (each
+ * Arnoldi step hands over a new vector), whatever xrl_plan_set_graph says.
  * Errors: XRL_E_INVALID_ARG, XRL_E_STATE, XRL_E_NOT_CONVERGED (stats filled),
  *         XRL_E_HIP. */
 xrl_status xrl_gmres_solve(const xrl_plan *plan, const xrl_epilogue *op, const void *b, void *x,
-                           int32_t n_rhs, int32_t restart, double rtol, int32_t max_iter,
+                           int32_t n_rhs, int32_t dtype, int32_t restart, double rtol, int32_t max_iter,
                            void *stream, xrl_gmres_stats *stats);
 
 #ifdef __cplusplus

@@ -136,8 +136,9 @@ __device__ inline V buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff)
 
 // ---------------------------------------------------------------- P2P
 // One workgroup per (target leaf, column tile).  The stored block of a leaf
-// is [rows][tpad]; a thread owns VEC consecutive targets of one row (one
-// 16-byte load) and the tpad/VEC threads of a row group stride over the rows.
+// is [rows][tpad] (tpad a multiple of 16); a thread owns VEC consecutive
+// targets of one row (one 16-byte load) and the tpad/VEC threads of a row
+// group stride over the rows (threads past the last whole group idle).
 // Source indices and the source densities of a chunk of 256 rows are staged
 // in LDS first, so the value stream is the only global load in the inner
 // loop.  The row groups are summed in a fixed order at the end.
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(256) void k_p2p(const int32_t *__restrict__ leaf_bo
         }
         __syncthreads();
 #pragma unroll 4
-        for (int r = grp; r < nrc; r += groups) {
+        for (int r = grp < groups ? grp : nrc; r < nrc; r += groups) {
             const V4 v = *reinterpret_cast<const V4 *>(vb + (int64_t)(rc + r) * G + jv);
             const T *xr = sx + r * CT;
 #pragma unroll
@@ -188,10 +189,11 @@ __global__ __launch_bounds__(256) void k_p2p(const int32_t *__restrict__ leaf_bo
             }
         }
     }
+    if (grp < groups)
 #pragma unroll
-    for (int e = 0; e < VEC; ++e)
+        for (int e = 0; e < VEC; ++e)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) red[(grp * G + jv + e) * CT + c] = acc[e][c];
+            for (int c = 0; c < CT; ++c) red[(grp * G + jv + e) * CT + c] = acc[e][c];
     __syncthreads();
     for (int idx = threadIdx.x; idx < nt * CT; idx += 256) {
         const int jj = idx / CT, c = idx - jj * CT;
@@ -228,6 +230,7 @@ __global__ __launch_bounds__(256) void k_p2p_wide(const int32_t *__restrict__ le
     const int G = leaf_tpad[li];
     const int tpr = G / VT, groups = 256 / tpr;
     const int jv = (threadIdx.x % tpr) * VT, grp = threadIdx.x / tpr;
+    const bool in_group = grp < groups;  // threads past the last whole row group idle
     const float *vb = val + val_off[li];
     float acc[VT][CT];
 #pragma unroll
@@ -252,7 +255,8 @@ __global__ __launch_bounds__(256) void k_p2p_wide(const int32_t *__restrict__ le
 #pragma unroll
         for (int q = 0; q < RMAX; ++q) {
             const int r = grp + q * groups;
-            vn[q] = r < nrc ? *reinterpret_cast<const fv_t *>(vb + (int64_t)(rc + r) * G + jv) : fv_t(0.f);
+            vn[q] = (in_group && r < nrc) ? *reinterpret_cast<const fv_t *>(vb + (int64_t)(rc + r) * G + jv)
+                                          : fv_t(0.f);
         }
     };
     if (nr > 0) fetch(0);
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(256) void k_p2p_wide(const int32_t *__restrict__ le
 #pragma unroll
         for (int q = 0; q < RMAX; ++q) {
             const int r = grp + q * groups;
-            if (r >= nrc) break;
+            if (!in_group || r >= nrc) break;
             const fv_t v = vc[q];
             const f32x4 *xr = reinterpret_cast<const f32x4 *>(sx + r * CT);
 #pragma unroll
@@ -284,11 +288,12 @@ __global__ __launch_bounds__(256) void k_p2p_wide(const int32_t *__restrict__ le
 #pragma unroll
     for (int cc = 0; cc < CT; cc += RC) {
         __syncthreads();
+        if (in_group)
 #pragma unroll
-        for (int v = 0; v < VT; ++v)
+            for (int v = 0; v < VT; ++v)
 #pragma unroll
-            for (int c = 0; c < RC; ++c)
-                if (cc + c < CT) red[(grp * G + jv + v) * RC + c] = acc[v][cc + c];
+                for (int c = 0; c < RC; ++c)
+                    if (cc + c < CT) red[(grp * G + jv + v) * RC + c] = acc[v][cc + c];
         __syncthreads();
         for (int idx = threadIdx.x; idx < nt * RC; idx += 256) {
             const int jj = idx / RC, c = idx - jj * RC;
@@ -376,7 +381,7 @@ __device__ inline void p2p_mfma_leaf(int lane, int nr, const float *__restrict__
                                      int nt)
 {
     constexpr int G = 16 * E, U = 4;  // block width; k steps per stage
-    using VE = typename std::conditional<E == 1, float, float __attribute__((ext_vector_type(E)))>::type;
+    using VE = Words<E>;  // E consecutive block values, one (or two) buffer loads
     struct BV {
         float v[WT];
     };
@@ -409,7 +414,7 @@ __device__ inline void p2p_mfma_leaf(int lane, int nr, const float *__restrict__
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int r = 4 * (ks0 + u) + kq;
-            st.v[u] = buf_load<VE>(rv, (r * G + E * li) * 4, 0);
+            st.v[u] = buf_load_words<E>(rv, (r * G + E * li) * 4, 0);
             const float *xr = xs + (int64_t)sr.r[u] * C;
             st.b[u] = *reinterpret_cast<const BV *>(xr + xo);
             if constexpr (XC > 0) st.xn[u] = xr[xno];
@@ -420,11 +425,7 @@ __device__ inline void p2p_mfma_leaf(int lane, int nr, const float *__restrict__
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                float bv;
-                if constexpr (E == 1)
-                    bv = st.v[u];
-                else
-                    bv = st.v[u][e];
+                const float bv = __uint_as_float(st.v[u].w[e]);
 #pragma unroll
                 for (int ct = 0; ct < WT; ++ct)
                     acc[e][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(st.b[u].v[ct], bv, acc[e][ct], 0, 0, 0);
@@ -499,7 +500,11 @@ __global__ __launch_bounds__(64) void k_p2p_mfma(int items_per_leaf, const int32
     switch (leaf_tpad[li]) {
         case 16: p2p_mfma_leaf<WT, XC, 1>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
         case 32: p2p_mfma_leaf<WT, XC, 2>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
+        case 48: p2p_mfma_leaf<WT, XC, 3>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
         case 64: p2p_mfma_leaf<WT, XC, 4>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
+        case 80: p2p_mfma_leaf<WT, XC, 5>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
+        case 96: p2p_mfma_leaf<WT, XC, 6>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
+        case 112: p2p_mfma_leaf<WT, XC, 7>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
         default: p2p_mfma_leaf<WT, XC, 8>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
     }
 }
@@ -1836,15 +1841,16 @@ static const int32_t *pass_items(const TransPass &T, bool mfma, int Cc, int *n_i
 // order); refl: its codes carry reflection bits (M2L) or not (M2M, L2L).
 template <typename T, int ORD>
 static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag, const T *op_k, const T *op_vec,
-                        const T *op_tail, bool refl, const T *in, T *out, int accumulate, DevBuf<T> &tmp, int C,
-                        hipStream_t s, const T *op_full = nullptr, const T *op_full_tail = nullptr)
+                        const T *op_tail, bool refl, const T *in, T *out, int accumulate, DevBuf<T> *tmp, int C,
+                        hipStream_t s, bool force_ts, const T *op_full = nullptr, const T *op_full_tail = nullptr)
 {
     using D = M2LDims<ORD>;
     if (TP.n_pairs == 0) return;
     const int eng = P->m2l_engine;
     // MFMA: M2M and L2L (few pairs per target) always target-stationary;
-    // M2L target-stationary from ts_min_cols real columns on
-    if (eng == XRL_M2L_MFMA_TS || (eng == XRL_M2L_MFMA && (!refl || C >= P->ts_min_cols))) {
+    // M2L target-stationary from ts_min_cols real columns on (always when
+    // force_ts: the caller has no per-pair scratch to give)
+    if (force_ts || eng == XRL_M2L_MFMA_TS || (eng == XRL_M2L_MFMA && (!refl || C >= P->ts_min_cols))) {
         // tiles per wave: the widest (up to the register budget) that wastes
         // the fewest padded tiles; in FP32, one to four columns past the last
         // full tile go to 4x4 MFMA blocks of the same wave instead of a tile
@@ -1922,6 +1928,7 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
         return;
     }
     const bool mfma = eng != XRL_M2L_VALU;
+    XRL_CHECK(tmp, XRL_E_UNSUPPORTED, "xrl_fmm_matvec: offset-stationary translations need the per-pair scratch");
     // column chunk so that the per-pair scratch stays within the plan's
     // scratch budget (a quarter of the device memory free at the first
     // translation, at least 4 GiB; fixed from then on, so that a captured
@@ -1933,25 +1940,25 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
     }
     const int64_t per_col = TP.n_pairs * (int64_t)D::KP * (int64_t)sizeof(T);
     const int Cc = (int)std::max<int64_t>(1, std::min<int64_t>(C, P->scratch_budget / per_col));
-    if (tmp.n < (size_t)(TP.n_pairs * (int64_t)Cc * D::KP)) tmp.alloc(TP.n_pairs * (int64_t)Cc * D::KP);
+    if (tmp->n < (size_t)(TP.n_pairs * (int64_t)Cc * D::KP)) tmp->alloc(TP.n_pairs * (int64_t)Cc * D::KP);
     for (int c0 = 0; c0 < C; c0 += Cc) {
         const int cc = std::min(Cc, C - c0);
         int n_items = 0;
         const int32_t *items = pass_items(TP, mfma, cc, &n_items, s);
         if (mfma) {
             k_m2l_os_mfma<T, ORD><<<(unsigned)cdiv(n_items, 4), 256, 0, s>>>(
-                items, n_items, TP.gbeg.p, TP.goff.p, TP.src.p, op_frag, in, C, c0, cc, tmp.p);
+                items, n_items, TP.gbeg.p, TP.goff.p, TP.src.p, op_frag, in, C, c0, cc, tmp->p);
         } else {
             // the LDS-staged operator of the vector-ALU kernel fits up to order 8
             if constexpr (ORD <= 8 && (sizeof(T) == 4 || ORD <= 6))
                 k_m2l_os_valu<T, ORD><<<(unsigned)n_items, 256, 0, s>>>(items, TP.gbeg.p, TP.goff.p, TP.src.p, op_k,
-                                                                        in, C, c0, cc, tmp.p);
+                                                                        in, C, c0, cc, tmp->p);
             else
                 fail(XRL_E_UNSUPPORTED, "xrl_fmm_matvec: the vector-ALU translations support order <= 8 "
                                         "(<= 6 in FP64)");
         }
         XRL_HIP(hipGetLastError());
-        k_pass_reduce<T, ORD><<<(unsigned)TP.n_red, 256, 0, s>>>(TP.red_tgt.p, TP.red_ptr.p, TP.red_slot.p, tmp.p, C,
+        k_pass_reduce<T, ORD><<<(unsigned)TP.n_red, 256, 0, s>>>(TP.red_tgt.p, TP.red_ptr.p, TP.red_slot.p, tmp->p, C,
                                                                  c0, cc, accumulate, out);
         XRL_HIP(hipGetLastError());
     }
@@ -2072,24 +2079,26 @@ struct Ops {
 };
 
 template <typename T, int ORD>
-static void translations(const xrl_plan *P, const Ops<T> &op, T *M, T *L, DevBuf<T> &tmp, int C, hipStream_t s,
-                         const std::function<void(int)> &mark)
+static void translations(const xrl_plan *P, const Ops<T> &op, T *M, T *L, DevBuf<T> *tmp, int C, hipStream_t s,
+                         bool force_ts, const std::function<void(int)> &mark)
 {
     using D = M2LDims<ORD>;
     mark(3);
     for (int l = P->depth - 1; l >= 0; --l)
-        pass_launch<T, ORD>(P, P->m2m[l], op.m2m_f, op.m2m_k, op.m2m_v, op.m2m_t, false, M, M, 0, tmp, C, s);
+        pass_launch<T, ORD>(P, P->m2m[l], op.m2m_f, op.m2m_k, op.m2m_v, op.m2m_t, false, M, M, 0, tmp, C, s,
+                            force_ts);
     // zero every local expansion (a fill kernel, so the sequence stays
     // capturable into a HIP graph without memset nodes)
     const int64_t nL = P->B * (int64_t)D::K * C;
     k_fill_zero<T><<<(unsigned)std::min<int64_t>(cdiv(nL, 256), 65536), 256, 0, s>>>(L, nL);
     XRL_HIP(hipGetLastError());
     mark(4);
-    pass_launch<T, ORD>(P, P->m2l, op.m2l_f, op.m2l_k, op.m2l_v, op.m2l_t, true, M, L, 0, tmp, C, s, op.m2l_full,
-                        op.m2l_full_t);
+    pass_launch<T, ORD>(P, P->m2l, op.m2l_f, op.m2l_k, op.m2l_v, op.m2l_t, true, M, L, 0, tmp, C, s, force_ts,
+                        op.m2l_full, op.m2l_full_t);
     mark(5);
     for (int l = 3; l <= P->depth; ++l)
-        pass_launch<T, ORD>(P, P->l2l[l], op.l2l_f, op.l2l_k, op.l2l_v, op.l2l_t, false, L, L, 1, tmp, C, s);
+        pass_launch<T, ORD>(P, P->l2l[l], op.l2l_f, op.l2l_k, op.l2l_v, op.l2l_t, false, L, L, 1, tmp, C, s,
+                            force_ts);
     mark(6);
 }
 
@@ -2097,27 +2106,30 @@ static void translations(const xrl_plan *P, const Ops<T> &op, T *M, T *L, DevBuf
 // synchronisation once the work buffers exist), so the same sequence can be
 // captured into a HIP graph.  The epilogue scalars are read from the plan's
 // ep_dev buffer when has_alpha / has_beta.
+// Work arrays of one matvec (sorted panel order, real columns): densities
+// and potentials [N][C] + 256, expansions [B][K][C] + 256 elements each.  The
+// slack after the densities: P2P reads (and discards) the padded columns of
+// the last source row; after the expansions: the target-stationary kernel
+// reads (and discards) up to 16 WT columns past the last record.
+template <typename T>
+struct Work {
+    T *xs, *ys, *M, *L;
+    DevBuf<T> *tmp;  // per-pair scratch of the offset-stationary translations (null: target-stationary only)
+    const double *alpha, *beta;  // epilogue scalars on the device ([2 C_complex] each) or null
+    bool force_ts;
+    bool profile;  // record the phase events of the plan's profiling ring
+};
+inline int64_t work_dens_elems(const xrl_plan *P, int C) { return P->N * (int64_t)C + 256; }
+inline int64_t work_exp_elems(const xrl_plan *P, int C) { return P->B * (int64_t)P->K * C + 256; }
+
 template <typename T>
 static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols, int dtype, void *y, int64_t ldy,
-                       bool has_alpha, bool has_beta, hipStream_t s, DevBuf<T> &xs, DevBuf<T> &ys, DevBuf<T> &M,
-                       DevBuf<T> &L, DevBuf<T> &tmp, const Ops<T> &op)
+                       hipStream_t s, const Work<T> &wk, const Ops<T> &op)
 {
     const int C = 2 * ncols;
     const int K = P->K;
-    const int64_t N = P->N, B = P->B;
-    if (xs.n < (size_t)(N * C + 256)) {
-        // slack after the densities: P2P reads (and discards) the padded
-        // columns of the last source row
-        xs.alloc(N * C + 256);
-        ys.alloc(N * C + 256);
-    }
-    if (M.n < (size_t)(B * K * C + 256)) {
-        // slack after the expansions: the target-stationary kernel reads
-        // (and discards) up to 16 WT columns past the last record
-        M.alloc(B * K * C + 256);
-        L.alloc(B * K * C + 256);
-    }
-    const bool prof = P->profiling;
+    const int64_t N = P->N;
+    const bool prof = wk.profile;
     std::function<void(int)> mark = [&](int i) {
         if (prof) XRL_HIP(hipEventRecord(P->prof_ev[P->prof_count % xrl_plan::kProfRing][i], s));
     };
@@ -2128,18 +2140,18 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
     const bool aligned = (uintptr_t)x % pair == 0;
     if (dtype == XRL_C64) {
         if (aligned)
-            k_gather_x<float, T, true><<<gx, bs, 0, s>>>(N, P->perm.p, (const float *)x, ldx, ncols, xs.p);
+            k_gather_x<float, T, true><<<gx, bs, 0, s>>>(N, P->perm.p, (const float *)x, ldx, ncols, wk.xs);
         else
-            k_gather_x<float, T, false><<<gx, bs, 0, s>>>(N, P->perm.p, (const float *)x, ldx, ncols, xs.p);
+            k_gather_x<float, T, false><<<gx, bs, 0, s>>>(N, P->perm.p, (const float *)x, ldx, ncols, wk.xs);
     } else {
         if (aligned)
-            k_gather_x<double, T, true><<<gx, bs, 0, s>>>(N, P->perm.p, (const double *)x, ldx, ncols, xs.p);
+            k_gather_x<double, T, true><<<gx, bs, 0, s>>>(N, P->perm.p, (const double *)x, ldx, ncols, wk.xs);
         else
-            k_gather_x<double, T, false><<<gx, bs, 0, s>>>(N, P->perm.p, (const double *)x, ldx, ncols, xs.p);
+            k_gather_x<double, T, false><<<gx, bs, 0, s>>>(N, P->perm.p, (const double *)x, ldx, ncols, wk.xs);
     }
     XRL_HIP(hipGetLastError());
     mark(1);
-    p2p_launch<T>(P, op.near, xs.p, ys.p, C, s);
+    p2p_launch<T>(P, op.near, wk.xs, wk.ys, C, s);
     mark(2);
     // column tile of P2M / L2P: the narrowest of 8, 16, 24, 32, 48 (FP32) or
     // 8, 16 (FP64) that holds all columns, else the widest
@@ -2169,8 +2181,8 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
             auto go = [&](auto ordc, auto wt, auto xcols) {
                 constexpr int O = decltype(ordc)::value, W = decltype(wt)::value, X = decltype(xcols)::value;
                 k_p2m_mfma<O, W, X><<<(unsigned)n_items, 64, 0, s>>>(ipl, P->leaf_box.p, P->box_beg.p, P->box_end.p,
-                                                                    (const float *)op.mom, (const float *)xs.p,
-                                                                    (float *)M.p, C);
+                                                                    (const float *)op.mom, (const float *)wk.xs,
+                                                                    (float *)wk.M, C);
             };
             auto go_w = [&](auto ordc) {
                 auto gx = [&](auto wt) {
@@ -2200,17 +2212,17 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
         moment_tiles([&](auto ctc) {
             constexpr int CT = decltype(ctc)::value;
             k_p2m<T, CT><<<dim3((unsigned)P->n_leaves, (unsigned)cdiv(C, CT)), 256, 0, s>>>(
-                P->leaf_box.p, P->box_beg.p, P->box_end.p, op.mom, xs.p, M.p, C, K);
+                P->leaf_box.p, P->box_beg.p, P->box_end.p, op.mom, wk.xs, wk.M, C, K);
         });
         XRL_HIP(hipGetLastError());
     }
     switch (P->p) {
-        case 2: translations<T, 2>(P, op, M.p, L.p, tmp, C, s, mark); break;
-        case 4: translations<T, 4>(P, op, M.p, L.p, tmp, C, s, mark); break;
-        case 6: translations<T, 6>(P, op, M.p, L.p, tmp, C, s, mark); break;
-        case 8: translations<T, 8>(P, op, M.p, L.p, tmp, C, s, mark); break;
-        case 10: translations<T, 10>(P, op, M.p, L.p, tmp, C, s, mark); break;
-        default: translations<T, 12>(P, op, M.p, L.p, tmp, C, s, mark); break;
+        case 2: translations<T, 2>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark); break;
+        case 4: translations<T, 4>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark); break;
+        case 6: translations<T, 6>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark); break;
+        case 8: translations<T, 8>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark); break;
+        case 10: translations<T, 10>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark); break;
+        default: translations<T, 12>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark); break;
     }
     bool l2p_done = false;
     if constexpr (sizeof(T) == 4) {
@@ -2231,8 +2243,8 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
             auto go = [&](auto ordc, auto wt, auto xcols) {
                 constexpr int O = decltype(ordc)::value, W = decltype(wt)::value, X = decltype(xcols)::value;
                 k_l2p_mfma<O, W, X><<<(unsigned)n_items, 64, 0, s>>>(ipl, P->leaf_box.p, P->box_beg.p, P->box_end.p,
-                                                                    P->box_h.p, (const float *)op.mom, (const float *)L.p,
-                                                                    (float *)ys.p, C);
+                                                                    P->box_h.p, (const float *)op.mom, (const float *)wk.L,
+                                                                    (float *)wk.ys, C);
             };
             auto go_w = [&](auto ordc) {
                 auto gx = [&](auto wt) {
@@ -2264,21 +2276,20 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
         const size_t sm = (size_t)K * CT * sizeof(T);
         if (CT == 8)
             k_l2p<T, 8><<<dim3((unsigned)P->n_leaves, ntile), 256, sm, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p,
-                                                                            P->box_h.p, op.mom, L.p, ys.p, C, K);
+                                                                            P->box_h.p, op.mom, wk.L, wk.ys, C, K);
         else
             k_l2p<T, 16><<<dim3((unsigned)P->n_leaves, ntile), 256, sm, s>>>(P->leaf_box.p, P->box_beg.p, P->box_end.p,
-                                                                             P->box_h.p, op.mom, L.p, ys.p, C, K);
+                                                                             P->box_h.p, op.mom, wk.L, wk.ys, C, K);
         XRL_HIP(hipGetLastError());
     }
     mark(7);
-    const double *da = (has_alpha || has_beta) ? P->ep_dev.p : nullptr;
-    const double *db = has_beta ? P->ep_dev.p + 2 * ncols : nullptr;
+    const double *da = wk.alpha, *db = wk.beta;
     const unsigned gy = (unsigned)std::min<int64_t>(cdiv(N * ncols, bs), 1 << 20);
     if (dtype == XRL_C64)
-        k_scatter_y<float, T><<<gy, bs, 0, s>>>(N, P->perm.p, ys.p, P->area.p, (const float *)x, ldx, (float *)y, ldy,
+        k_scatter_y<float, T><<<gy, bs, 0, s>>>(N, P->perm.p, wk.ys, P->area.p, (const float *)x, ldx, (float *)y, ldy,
                                                 ncols, da, db);
     else
-        k_scatter_y<double, T><<<gy, bs, 0, s>>>(N, P->perm.p, ys.p, P->area.p, (const double *)x, ldx, (double *)y,
+        k_scatter_y<double, T><<<gy, bs, 0, s>>>(N, P->perm.p, wk.ys, P->area.p, (const double *)x, ldx, (double *)y,
                                                  ldy, ncols, da, db);
     XRL_HIP(hipGetLastError());
     mark(8);
@@ -2305,23 +2316,53 @@ static void upload_epilogue(const xrl_plan *P, int ncols, const double *alpha, c
     XRL_HIP(hipMemcpyAsync(P->ep_dev.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s));
 }
 
-static void enqueue_matvec(const xrl_plan *P, const void *x, int64_t ldx, int n_cols, int dtype, void *y, int64_t ldy,
-                           bool ha, bool hb, hipStream_t s)
+static Ops<double> ops64(const xrl_plan *P)
 {
-    xrl_plan *Pm = const_cast<xrl_plan *>(P);
-    if (P->precision == XRL_PREC_FP64) {
-        Ops<double> op{P->near64.p, P->mom64.p, P->op_m2m64f.p, P->op_m2m64k.p, P->op_l2l64f.p, P->op_l2l64k.p,
+    return Ops<double>{P->near64.p, P->mom64.p, P->op_m2m64f.p, P->op_m2m64k.p, P->op_l2l64f.p, P->op_l2l64k.p,
                        P->op_m2l64f.p, P->op_m2l64k.p, P->op_m2m64v.p, P->op_l2l64v.p, P->op_m2lc64v.p,
                        P->op_m2l64v.p, P->op_m2m64t.p, P->op_l2l64t.p, P->op_m2l64t.p, P->op_m2lc64t.p};
-        run_matvec<double>(P, x, ldx, n_cols, dtype, y, ldy, ha, hb, s, Pm->xs64, Pm->ys64, Pm->M64, Pm->L64,
-                           Pm->os_tmp64, op);
-    } else {
-        Ops<float> op{P->near32.p, P->mom32.p, P->op_m2m32f.p, P->op_m2m32k.p, P->op_l2l32f.p, P->op_l2l32k.p,
+}
+static Ops<float> ops32(const xrl_plan *P)
+{
+    return Ops<float>{P->near32.p, P->mom32.p, P->op_m2m32f.p, P->op_m2m32k.p, P->op_l2l32f.p, P->op_l2l32k.p,
                       P->op_m2l32f.p, P->op_m2l32k.p, P->op_m2m32v.p, P->op_l2l32v.p, P->op_m2lc32v.p,
                       P->op_m2l32v.p, P->op_m2m32t.p, P->op_l2l32t.p, P->op_m2l32t.p, P->op_m2lc32t.p};
-        run_matvec<float>(P, x, ldx, n_cols, dtype, y, ldy, ha, hb, s, Pm->xs32, Pm->ys32, Pm->M32, Pm->L32,
-                          Pm->os_tmp32, op);
+}
+
+// The plan-owned work arrays, grown (hipMalloc) to the call's column count.
+template <typename T>
+static Work<T> plan_work(const xrl_plan *P, int C, bool ha, bool hb, bool profile, DevBuf<T> &xs, DevBuf<T> &ys,
+                         DevBuf<T> &M, DevBuf<T> &L, DevBuf<T> &tmp)
+{
+    if (xs.n < (size_t)work_dens_elems(P, C)) {
+        xs.alloc(work_dens_elems(P, C));
+        ys.alloc(work_dens_elems(P, C));
     }
+    if (M.n < (size_t)work_exp_elems(P, C)) {
+        M.alloc(work_exp_elems(P, C));
+        L.alloc(work_exp_elems(P, C));
+    }
+    const double *da = (ha || hb) ? P->ep_dev.p : nullptr;
+    const double *db = hb ? P->ep_dev.p + C : nullptr;
+    return Work<T>{xs.p, ys.p, M.p, L.p, &tmp, da, db, false, profile && P->profiling};
+}
+
+// profile: record the plan's phase events when its profiling is on (the
+// caller has made the ring slot); the solver's inner products pass false.
+static void enqueue_matvec(const xrl_plan *P, const void *x, int64_t ldx, int n_cols, int dtype, void *y, int64_t ldy,
+                           bool ha, bool hb, hipStream_t s, bool profile = true)
+{
+    xrl_plan *Pm = const_cast<xrl_plan *>(P);
+    const int C = 2 * n_cols;
+    if (P->precision == XRL_PREC_FP64)
+        run_matvec<double>(P, x, ldx, n_cols, dtype, y, ldy, s,
+                           plan_work<double>(P, C, ha, hb, profile, Pm->xs64, Pm->ys64, Pm->M64, Pm->L64,
+                                             Pm->os_tmp64),
+                           ops64(P));
+    else
+        run_matvec<float>(P, x, ldx, n_cols, dtype, y, ldy, s,
+                          plan_work<float>(P, C, ha, hb, profile, Pm->xs32, Pm->ys32, Pm->M32, Pm->L32, Pm->os_tmp32),
+                          ops32(P));
 }
 
 // Graph mode: the first call with a new argument set runs eagerly (which
@@ -2395,6 +2436,22 @@ extern "C" xrl_status xrl_fmm_matvec(const xrl_plan *P, const void *x, int64_t l
             graph_matvec(P, x, ldx, n_cols, dtype, y, ldy, al != nullptr, be != nullptr, s);
         else
             enqueue_matvec(P, x, ldx, n_cols, dtype, y, ldy, al != nullptr, be != nullptr, s);
+    });
+}
+
+// Eager matvec for the solver: every Arnoldi step hands over a new vector,
+// so graph mode (one captured graph per argument set) would capture anew at
+// each step; this path never uses the graph.
+xrl_status xrl_matvec_eager(const xrl_plan *P, const void *x, int64_t ldx, int32_t n_cols, int32_t dtype, void *y,
+                            int64_t ldy, const xrl_epilogue *ep, void *stream)
+{
+    return guarded([&] {
+        XRL_CHECK(P && x && y && P->assembled && n_cols >= 1 && n_cols <= P->max_cols, XRL_E_INVALID_ARG,
+                  "gmres matvec: bad arguments");
+        hipStream_t s = (hipStream_t)stream;
+        const double *al = ep ? ep->alpha : nullptr, *be = ep ? ep->beta : nullptr;
+        upload_epilogue(P, n_cols, al, be, s);
+        enqueue_matvec(P, x, ldx, n_cols, dtype, y, ldy, al != nullptr, be != nullptr, s, false);
     });
 }
 
@@ -2616,6 +2673,12 @@ extern "C" xrl_status xrl_plan_set_tuning(xrl_plan *P, int32_t key, int32_t valu
                 P->ts_narrow_cols = value;
                 break;
             default: fail(XRL_E_INVALID_ARG, "xrl_plan_set_tuning: unknown key %d", key);
+        }
+        // a captured graph holds the old kernel forms: drop it, the next
+        // graph-mode matvec captures the new ones
+        if (P->gexec) {
+            XRL_HIP(hipGraphExecDestroy(P->gexec));
+            P->gexec = nullptr;
         }
     });
 }

@@ -84,12 +84,25 @@ __global__ void k_sub(const double *__restrict__ a, const double *__restrict__ b
     if (e < n) out[e] = a[e] - b[e];
 }
 
+// Widen / narrow complex64 <-> complex128 (interleaved, n complex values).
+__global__ void k_widen(const float *__restrict__ in, int64_t n, double *__restrict__ out)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < 2 * n) out[e] = (double)in[e];
+}
+__global__ void k_narrow(const double *__restrict__ in, int64_t n, float *__restrict__ out)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < 2 * n) out[e] = (float)in[e];
+}
+
 }  // namespace xrl
 
 using namespace xrl;
 
-extern "C" xrl_status xrl_fmm_matvec(const xrl_plan *P, const void *x, int64_t ldx, int32_t n_cols, int32_t dtype,
-                                     void *y, int64_t ldy, const xrl_epilogue *ep, void *stream);
+// Eager matvec of the operator (fmm.hip): never replays a captured graph.
+xrl_status xrl_matvec_eager(const xrl_plan *P, const void *x, int64_t ldx, int32_t n_cols, int32_t dtype, void *y,
+                            int64_t ldy, const xrl_epilogue *ep, void *stream);
 
 namespace {
 
@@ -104,7 +117,7 @@ struct Solver {
 
     void apply(const double *x, double *y)
     {
-        xrl_status st = xrl_fmm_matvec(P, x, R, R, XRL_C128, y, R, &op, s);
+        xrl_status st = xrl_matvec_eager(P, x, R, R, XRL_C128, y, R, &op, s);
         if (st != XRL_OK) throw Error{st, std::string("gmres matvec: ") + xrl_last_error()};
     }
     // dots[i][c] = <V_i, w>_c for i < m
@@ -150,13 +163,14 @@ struct Solver {
 }  // namespace
 
 extern "C" xrl_status xrl_gmres_solve(const xrl_plan *P, const xrl_epilogue *op, const void *b, void *x,
-                                      int32_t n_rhs, int32_t restart, double rtol, int32_t max_iter, void *stream,
-                                      xrl_gmres_stats *stats)
+                                      int32_t n_rhs, int32_t dtype, int32_t restart, double rtol, int32_t max_iter,
+                                      void *stream, xrl_gmres_stats *stats)
 {
     xrl_status result = XRL_OK;
     xrl_status g = guarded([&] {
         XRL_CHECK(P && b && x && n_rhs >= 1 && restart >= 1 && restart <= 1000 && rtol > 0 && max_iter >= 1,
                   XRL_E_INVALID_ARG, "xrl_gmres_solve: bad arguments");
+        XRL_CHECK(dtype == XRL_C64 || dtype == XRL_C128, XRL_E_INVALID_ARG, "xrl_gmres_solve: bad dtype %d", dtype);
         XRL_CHECK(n_rhs <= P->max_cols, XRL_E_INVALID_ARG, "xrl_gmres_solve: n_rhs > plan max_cols");
         XRL_CHECK(P->assembled, XRL_E_STATE, "xrl_gmres_solve: call xrl_nearfield_assemble first");
         Solver S;
@@ -169,8 +183,20 @@ extern "C" xrl_status xrl_gmres_solve(const xrl_plan *P, const xrl_epilogue *op,
         const int64_t N = S.N, R = n_rhs, NR2 = 2 * N * R;
         const int m = restart;
         DevBuf<double> V((size_t)(m + 1) * NR2), w(NR2), r(NR2);
+        // complex64 right-hand sides and solutions are widened to complex128
+        // for the iteration and the solution narrowed back at the end
+        DevBuf<double> b64, x64;
         double *X = (double *)x;
         const double *Bv = (const double *)b;
+        if (dtype == XRL_C64) {
+            b64.alloc(NR2);
+            x64.alloc(NR2);
+            k_widen<<<cdiv(NR2, 256), 256, 0, S.s>>>((const float *)b, N * R, b64.p);
+            k_widen<<<cdiv(NR2, 256), 256, 0, S.s>>>((const float *)x, N * R, x64.p);
+            XRL_HIP(hipGetLastError());
+            X = x64.p;
+            Bv = b64.p;
+        }
         std::vector<double> bnorm = S.norms(Bv);
         for (auto &v : bnorm)
             if (v == 0) v = 1;
@@ -262,6 +288,10 @@ extern "C" xrl_status xrl_gmres_solve(const xrl_plan *P, const xrl_epilogue *op,
             stats->restarts = restarts;
             stats->converged = conv;
             stats->max_rel_residual = mx;
+        }
+        if (dtype == XRL_C64) {
+            k_narrow<<<cdiv(NR2, 256), 256, 0, S.s>>>(X, N * R, (float *)x);
+            XRL_HIP(hipGetLastError());
         }
         XRL_HIP(hipStreamSynchronize(S.s));
         if (conv < R) {

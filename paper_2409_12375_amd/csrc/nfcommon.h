@@ -7,10 +7,14 @@ namespace xrl {
 
 struct NFRules {
     double gx[40], gw[40];  // Gauss-Legendre on [0,1], n_touch points
-    double nx[8], nw[8];    // near-singular conical rule, n = 6
+    double tx[40], tw[40];  // the same nodes through the sigmoidal map u^3/(u^3+(1-u)^3), weights times its derivative
+    // near-singular pairs, by class c (r >= 1.5, 0.75 <= r < 1.5, r < 0.75):
+    // an ns_n[c] x ns_n[c] conical rule on 4^ns_lev[c] sub-triangles
+    double nx[3][8], nw[3][8];
+    int ns_n[3], ns_lev[3];
     double rx4[8], rw4[8];  // regular, n_hi points
     double rx3[8], rw3[8];  // regular, n_lo points
-    int n_touch, n_ns, n_hi, n_lo;
+    int n_touch, n_hi, n_lo;
 };
 
 struct NFArgs {

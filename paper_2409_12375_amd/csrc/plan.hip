@@ -528,7 +528,7 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     XRL_HIP(hipGetLastError());
     // ---------------- V lists (and pairs demoted to the near field)
     DevBuf<int32_t> vcnt(B), dcnt(B);
-    const double theta = 1.0;
+    const double theta = P->theta;
     k_vlist<<<cdiv(B, 128), 128, 0, s>>>(bv, B, coll.p, P->box_center.p, P->box_rad.p, theta, vcnt.p, dcnt.p,
                                          nullptr, nullptr, nullptr, nullptr, nullptr);
     XRL_HIP(hipGetLastError());
@@ -595,7 +595,8 @@ static void build_plan(xrl_plan *P, hipStream_t s)
                   "xrl_fmm_plan: a leaf at the maximum depth holds %d panels (more than %d); "
                   "the mesh has (nearly) coincident panel centroids",
                   nt, kMaxLeaf);
-        tpad[li] = nt <= 16 ? 16 : (nt <= 32 ? 32 : (nt <= 64 ? 64 : 128));
+        // block rows padded to the next multiple of 16 targets (one MFMA tile)
+        tpad[li] = 16 * (int32_t)cdiv(nt, 16);
         // sort source boxes by their panel range so the rows are in Morton order
         std::vector<std::pair<int32_t, int32_t>> rg;
         for (int64_t j = noff[li]; j < noff[li + 1]; ++j) rg.push_back({beg[hnbox[j]], end[hnbox[j]]});
@@ -654,6 +655,7 @@ static void build_plan(xrl_plan *P, hipStream_t s)
         }
     }
     P->h_m2l_pairs.resize(2 * nV);
+    P->h_m2l_ratio.resize(nV);
     std::vector<double> hrad = P->box_rad.download(s);
     double maxsep = 0;
     for (int64_t b = 0, q = 0; b < B; ++b)
@@ -666,7 +668,8 @@ static void build_plan(xrl_plan *P, hipStream_t s)
                 const double dd = center[3 * b + d] - center[3 * sb + d];
                 d2 += dd * dd;
             }
-            maxsep = std::max(maxsep, (hrad[b] + hrad[sb]) / std::sqrt(d2));
+            P->h_m2l_ratio[q] = (hrad[b] + hrad[sb]) / std::sqrt(d2);
+            maxsep = std::max(maxsep, P->h_m2l_ratio[q]);
         }
     P->max_sep_ratio = maxsep;
     std::vector<int32_t> grp_off;
@@ -826,6 +829,8 @@ extern "C" xrl_status xrl_fmm_plan(xrl_tree *const *trees, int32_t n_trees, cons
         XRL_CHECK(opts->m2l_engine >= 0 && opts->m2l_engine <= 4, XRL_E_INVALID_ARG, "xrl_fmm_plan: bad engine");
         XRL_CHECK(opts->max_cols >= 1 && opts->max_cols <= 4096, XRL_E_INVALID_ARG,
                   "xrl_fmm_plan: max_cols must be in 1..4096");
+        XRL_CHECK(opts->theta == 0.0 || (opts->theta >= 0.5 && opts->theta <= 1.0), XRL_E_INVALID_ARG,
+                  "xrl_fmm_plan: theta must be 0 (default) or in [0.5, 1] (got %g)", opts->theta);
         auto P = std::make_unique<xrl_plan>();
         P->p = opts->order;
         P->K = (P->p + 1) * (P->p + 1);
@@ -840,6 +845,7 @@ extern "C" xrl_status xrl_fmm_plan(xrl_tree *const *trees, int32_t n_trees, cons
             P->leaf_mfma = 0;
         }
         P->max_cols = opts->max_cols;
+        P->theta = opts->theta == 0.0 ? XRL_DEFAULT_THETA : opts->theta;
         P->trees.assign(trees, trees + n_trees);
         build_plan(P.get(), (hipStream_t)stream);
         *out = P.release();
@@ -871,6 +877,7 @@ extern "C" xrl_status xrl_plan_get_info(const xrl_plan *P, xrl_plan_info *info)
         info->precision = P->precision;
         info->max_sep_ratio = P->max_sep_ratio;
         info->n_demoted_pairs = P->n_demoted;
+        info->theta = P->theta;
     });
 }
 
@@ -895,10 +902,14 @@ extern "C" xrl_status xrl_plan_export(const xrl_plan *P, int32_t item, void *buf
             case 6: v = P->h_leaf_box; break;
             case 7: v = P->h_box_parent; break;
             case 9: v = const_cast<xrl_plan *>(P)->leaf_tpad.download(0); break;
-            case 8: {
-                // near-field values as float64 (layout: items 3, 4, 9)
+            case 8:
+            case 10: {
+                // near-field values as float64 (layout: items 3, 4, 9), or the
+                // separation ratio of every M2L pair (order of item 5)
                 std::vector<double> d;
-                if (P->near64.p)
+                if (item == 10)
+                    d = P->h_m2l_ratio;
+                else if (P->near64.p)
                     d = const_cast<xrl_plan *>(P)->near64.download(0, P->n_near_entries);
                 else {
                     auto f = const_cast<xrl_plan *>(P)->near32.download(0, P->n_near_entries);

