@@ -284,6 +284,27 @@ xrl_status xrl_fmm_matvec(const xrl_plan *plan, const void *x, int64_t ldx, int3
                           int32_t dtype, void *y, int64_t ldy, const xrl_epilogue *ep,
                           void *stream);
 
+/* The same product for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the call allocates nothing.  Its work arrays (sorted densities
+ * and potentials, multipole and local expansions, epilogue scalars) live in
+ * one fixed 64 MiB device array of the library, one copy per device, held
+ * until the process ends; the plan, x and y are the caller's as above.
+ *   - Needs 4*8*n_cols + 2*(N*2*n_cols + 256)*E + 2*(B*K*2*n_cols + 256)*E
+ *     bytes (E = 8 for FP64 plans, else 4; each part rounded up to 256; N
+ *     panels, B boxes, K = (p+1)^2); larger requests fail with
+ *     XRL_E_INVALID_ARG and a message naming the size.
+ *   - The translations always run target-stationary on the matrix cores (no
+ *     per-pair scratch); results agree with xrl_fmm_matvec to rounding.
+ *   - Runs eagerly: graph mode and profiling of the plan do not apply.
+ *   - Every call on one device shares that device's array: calls that
+ *     overlap on one device (concurrent streams or threads) race and give
+ *     undefined results.  The array keeps the last call's contents; the call
+ *     overwrites every element it reads.
+ * Errors: XRL_E_INVALID_ARG, XRL_E_STATE, XRL_E_HIP. */
+xrl_status xrl_fmm_matvec_noalloc(const xrl_plan *plan, const void *x, int64_t ldx, int32_t n_cols,
+                                  int32_t dtype, void *y, int64_t ldy, const xrl_epilogue *ep, void *stream);
+
 /* Per-phase device times (milliseconds), recorded with HIP events on the
  * matvec stream while profiling is on (no host wait inside the matvec):
  * xrl_plan_get_phase_ms waits for the recorded events and returns the mean

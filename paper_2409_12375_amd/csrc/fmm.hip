@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <functional>
+#include <mutex>
 #include <type_traits>
 
 #include "common.h"
@@ -2436,6 +2437,108 @@ extern "C" xrl_status xrl_fmm_matvec(const xrl_plan *P, const void *x, int64_t l
             graph_matvec(P, x, ldx, n_cols, dtype, y, ldy, al != nullptr, be != nullptr, s);
         else
             enqueue_matvec(P, x, ldx, n_cols, dtype, y, ldy, al != nullptr, be != nullptr, s);
+    });
+}
+
+// ---------------------------------------------------------------- matvec without allocation
+// The work arrays of xrl_fmm_matvec_noalloc live in this fixed device array
+// (each device that runs the library holds its own copy until the process
+// ends).  Host code never uses the name `scratch` itself, only the address
+// hipGetSymbolAddress returns for the current device.
+static constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// This device's address of `scratch`, looked up once per device.
+static unsigned char *scratch_ptr()
+{
+    int dev = -1;
+    XRL_HIP(hipGetDevice(&dev));
+    XRL_CHECK(dev >= 0 && dev < kMaxDevices, XRL_E_UNSUPPORTED, "xrl_fmm_matvec_noalloc: device %d out of range",
+              dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        XRL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        XRL_CHECK(p, XRL_E_HIP, "xrl_fmm_matvec_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = (unsigned char *)p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+__global__ void k_fill_pairs(double *__restrict__ p, int n, double re, double im)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        p[2 * i] = re;
+        p[2 * i + 1] = im;
+    }
+}
+
+template <typename T>
+static void noalloc_matvec(const xrl_plan *P, const void *x, int64_t ldx, int n_cols, int dtype, void *y,
+                           int64_t ldy, const double *alpha, const double *beta, hipStream_t s)
+{
+    const int C = 2 * n_cols;
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t ep_b = up(4 * (size_t)n_cols * sizeof(double));
+    const size_t dens_b = up((size_t)work_dens_elems(P, C) * sizeof(T));
+    const size_t exp_b = up((size_t)work_exp_elems(P, C) * sizeof(T));
+    const size_t need = ep_b + 2 * dens_b + 2 * exp_b;
+    XRL_CHECK(need <= kScratchBytes, XRL_E_INVALID_ARG,
+              "xrl_fmm_matvec_noalloc: this plan and column count need %zu bytes of work arrays, more than the "
+              "%zu-byte scratch (use xrl_fmm_matvec)",
+              need, kScratchBytes);
+    unsigned char *base = scratch_ptr();
+    double *ep = (double *)base;
+    const bool has = alpha || beta;
+    if (has) {
+        // alpha (default 1) in [0, 2 n_cols), beta (default 0) after it
+        if (alpha)
+            XRL_HIP(hipMemcpyAsync(ep, alpha, 2 * (size_t)n_cols * sizeof(double), hipMemcpyHostToDevice, s));
+        else
+            k_fill_pairs<<<(unsigned)cdiv(n_cols, 256), 256, 0, s>>>(ep, n_cols, 1.0, 0.0);
+        if (beta)
+            XRL_HIP(hipMemcpyAsync(ep + C, beta, 2 * (size_t)n_cols * sizeof(double), hipMemcpyHostToDevice, s));
+        XRL_HIP(hipGetLastError());
+    }
+    unsigned char *q = base + ep_b;
+    Work<T> wk;
+    wk.xs = (T *)q;
+    wk.ys = (T *)(q + dens_b);
+    wk.M = (T *)(q + 2 * dens_b);
+    wk.L = (T *)(q + 2 * dens_b + exp_b);
+    wk.tmp = nullptr;
+    wk.alpha = has ? ep : nullptr;
+    wk.beta = beta ? ep + C : nullptr;
+    wk.force_ts = true;
+    wk.profile = false;
+    if constexpr (sizeof(T) == 8)
+        run_matvec<double>(P, x, ldx, n_cols, dtype, y, ldy, s, wk, ops64(P));
+    else
+        run_matvec<float>(P, x, ldx, n_cols, dtype, y, ldy, s, wk, ops32(P));
+}
+
+extern "C" xrl_status xrl_fmm_matvec_noalloc(const xrl_plan *P, const void *x, int64_t ldx, int32_t n_cols,
+                                             int32_t dtype, void *y, int64_t ldy, const xrl_epilogue *ep,
+                                             void *stream)
+{
+    return guarded([&] {
+        XRL_CHECK(P && x && y, XRL_E_INVALID_ARG, "xrl_fmm_matvec_noalloc: null argument");
+        XRL_CHECK(P->assembled, XRL_E_STATE, "xrl_fmm_matvec_noalloc: call xrl_nearfield_assemble first");
+        XRL_CHECK(n_cols >= 1 && n_cols <= P->max_cols, XRL_E_INVALID_ARG,
+                  "xrl_fmm_matvec_noalloc: n_cols must be in 1..max_cols (%d), got %d", P->max_cols, n_cols);
+        XRL_CHECK(ldx >= n_cols && ldy >= n_cols, XRL_E_INVALID_ARG, "xrl_fmm_matvec_noalloc: ldx/ldy < n_cols");
+        XRL_CHECK(dtype == XRL_C64 || dtype == XRL_C128, XRL_E_INVALID_ARG, "xrl_fmm_matvec_noalloc: bad dtype %d",
+                  dtype);
+        XRL_CHECK(x != y, XRL_E_INVALID_ARG, "xrl_fmm_matvec_noalloc: x and y must not alias");
+        const double *al = ep ? ep->alpha : nullptr, *be = ep ? ep->beta : nullptr;
+        if (P->precision == XRL_PREC_FP64)
+            noalloc_matvec<double>(P, x, ldx, n_cols, dtype, y, ldy, al, be, (hipStream_t)stream);
+        else
+            noalloc_matvec<float>(P, x, ldx, n_cols, dtype, y, ldy, al, be, (hipStream_t)stream);
     });
 }
 

@@ -110,6 +110,7 @@ def lib():
         L.xrl_plan_get_info.argtypes = [_vp, ctypes.POINTER(PlanInfo)]
         L.xrl_nearfield_assemble.argtypes = [_vp, ctypes.POINTER(NfOpts), _vp, ctypes.POINTER(NfStats)]
         L.xrl_fmm_matvec.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _i64, ctypes.POINTER(Epilogue), _vp]
+        L.xrl_fmm_matvec_noalloc.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _i64, ctypes.POINTER(Epilogue), _vp]
         L.xrl_plan_set_profiling.argtypes = [_vp, _i32]
         L.xrl_plan_get_phase_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
         L.xrl_plan_set_tuning.argtypes = [_vp, _i32, _i32]
