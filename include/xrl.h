@@ -454,6 +454,72 @@ xrl_status xrl_gmres_solve(const xrl_plan *plan, const xrl_epilogue *op, const v
                            int32_t n_rhs, int32_t dtype, int32_t restart, double rtol, int32_t max_iter,
                            void *stream, xrl_gmres_stats *stats);
 
+/* ------------------------------------------------------------------ */
+/* Loop analysis around the panel operator                             */
+/* ------------------------------------------------------------------ */
+/* PEEC graph of a closed conforming triangle mesh (Sec. II-A, Fig. 1):
+ * panel centroids are nodes, each edge shared by panels i < j is a branch
+ * whose global current runs from i to j.  The centroid-midpoint maps
+ * A_1..A_3 of Algorithm 1 (row = branch: rho_{i,e} = m_e - c_i at column i,
+ * -rho_{j,e} at column j) and a loop basis M (Sec. II-B, eq. (7); rows of
+ * +-1 per branch): one fan of panels around every mesh vertex except one per
+ * connected surface, plus two loops per handle from a tree-cotree split of
+ * the mesh; the loops span exactly the branch currents that conserve charge
+ * at every panel (eq. (2)), N_loops = N_edges - N_panels + components.
+ * The mesh (host arrays, same panel order as the plan it is used with) is
+ * read during the call only.  Errors: XRL_E_INVALID_ARG, XRL_E_UNSUPPORTED
+ * (an edge not shared by exactly two panels, a non-manifold vertex),
+ * XRL_E_OOM, XRL_E_HIP. */
+typedef struct xrl_loops xrl_loops;
+typedef struct {
+    int64_t n_panels, n_edges, n_loops;
+    int64_t n_vertex_loops, n_global_loops, n_components;
+    int64_t nnz_loop_matrix;
+} xrl_loops_info;
+xrl_status xrl_loops_build(const xrl_mesh_desc *mesh, void *stream, xrl_loops **out);
+void xrl_loops_destroy(xrl_loops *loops);
+xrl_status xrl_loops_get_info(const xrl_loops *loops, xrl_loops_info *info);
+/* Host copies (int32): item 0 the panels (i, j) of each branch [N_edges][2];
+ * item 1 the mesh vertices of each branch [N_edges][2]; item 2 the loop
+ * matrix as (loop, branch, sign) triples.  buf == NULL: only *nbytes. */
+xrl_status xrl_loops_export(const xrl_loops *loops, int32_t item, void *buf, int64_t *nbytes);
+
+/* Surface impedance of eq. (3) (double-plane model, Sec. II-A) at n
+ * frequencies (Hz, > 0) for conductivity sigma (S/m) and thickness (m):
+ * zs[2 i], zs[2 i + 1] = Re, Im Z_s(freq[i]).  Host only. */
+xrl_status xrl_surface_impedance(double sigma, double thickness, const double *freq, int32_t n, double *zs);
+
+/* Branch-space operator of eq. (5)-(6), V_edge = sum_t A_t (beta area +
+ * alpha P) A_t^T I_edge, for n_cols columns (alpha_c = j omega mu0 / 4 pi,
+ * beta_c = Z_s per column from op; NULL terms as in xrl_epilogue).  The
+ * product with P runs through xrl_fmm_matvec on 3 n_cols columns, so the
+ * plan (built on the same mesh) needs max_cols >= 3 n_cols.
+ *   i_edge, v_edge : device, [N_edges][n_cols] complex128.
+ * Errors: XRL_E_INVALID_ARG, XRL_E_STATE, XRL_E_HIP. */
+xrl_status xrl_edge_matvec(const xrl_loops *loops, const xrl_plan *plan, const xrl_epilogue *op, const void *i_edge,
+                           void *v_edge, int32_t n_cols, void *stream);
+
+/* Solve the loop system eq. (8), M (sum_t A_t (beta area + alpha P) A_t^T)
+ * M^T I_l = M V_edge, for n_rhs columns sharing every FMM matvec (restarted
+ * GMRES, FP64 Arnoldi as in xrl_gmres_solve), and return the branch
+ * currents I_edge = M^T I_l.
+ *   v_edge, i_edge : device, [N_edges][n_rhs] complex128.
+ *   precond: XRL_PRECOND_NONE, XRL_PRECOND_DIAG_P (eq. (10): M sum_t A_t
+ *   (beta area + alpha P_d) A_t^T M^T with P_d the diagonal of P, applied
+ *   from the right as in eq. (11)) or XRL_PRECOND_DIAG_L (the surface part
+ *   plus the diagonal of the branch interaction matrix sum_t A_t P A_t^T).
+ *   The preconditioner is factored once per column by the library's own
+ *   sparse LDL^T (reverse Cuthill-McKee envelope, host) in place of a
+ *   vendor solver; its entries of P come from the assembled near field.
+ * Errors: XRL_E_INVALID_ARG, XRL_E_STATE, XRL_E_NOT_CONVERGED (stats
+ * filled), XRL_E_HIP. */
+#define XRL_PRECOND_NONE 0
+#define XRL_PRECOND_DIAG_P 1
+#define XRL_PRECOND_DIAG_L 2
+xrl_status xrl_loop_gmres_solve(const xrl_loops *loops, const xrl_plan *plan, const xrl_epilogue *op,
+                                const void *v_edge, void *i_edge, int32_t n_rhs, int32_t precond, int32_t restart,
+                                double rtol, int32_t max_iter, void *stream, xrl_gmres_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

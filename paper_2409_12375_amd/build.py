@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libxrl.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["tree.hip", "plan.hip", "operators.cpp", "nearfield.hip", "surrogate.hip", "fmm.hip", "gmres.hip"]
+SOURCES = ["tree.hip", "plan.hip", "operators.cpp", "nearfield.hip", "surrogate.hip", "fmm.hip", "gmres.hip",
+           "loops.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -37,8 +37,8 @@ __device__ inline T dot3(const T *a, const T *b) { return a[0] * b[0] + a[1] * b
 // with f = R + s (or R0^2/(R - s) behind the foot of r), R0^2 = t0^2 + h^2.
 // ln(f+/f-) is taken as log1p of L (S + s- + s+)/(S (R- + s-)) (S = R- + R+)
 // when both ends lie on the same side of the foot (the ratio tends to 1 far
-// from the edge) and the two arc tangents as one atan2 of their difference,
-// whose numerator uses s+ R- - s- R+ = R0^2 L (s+ + s-)/(s+ R- + s- R+).
+// from the edge); the arc-tangent terms of the three edges add up to the
+// solid angle of the triangle, taken at once.
 template <typename T>
 struct TriPot {
     T n[3], a[3][3], s[3][3], m[3][3], L[3];
@@ -87,20 +87,27 @@ struct TriPot {
             const T Rm = R[i], Rp = R[(i + 1) % 3];
             const T R0s = t0 * t0 + h * h;
             const T S = Rm + Rp;
-            T lg;
+            // ln(f+/f-) = log1p(z), z >= 0 in all three cases (one
+            // transcendental whichever side of the foot the edge lies on)
+            T z;
             if (sm >= 0)
-                lg = log1p(L[i] * (S + sm + sp) / (S * (Rm + sm)));
+                z = L[i] * (S + sm + sp) / (S * (Rm + sm));
             else if (sp <= 0)
-                lg = log1p(L[i] * (S - sm - sp) / (S * (Rp - sp)));
+                z = L[i] * (S - sm - sp) / (S * (Rp - sp));
             else
-                lg = log((Rp + sp) * (Rm - sm) / R0s);
-            phi += t0 * lg;
-            if (ah > eps * L[i]) {
-                const T D = sp * sm > 0 ? R0s * L[i] * (sp + sm) / (sp * Rm + sm * Rp) : sp * Rm - sm * Rp;
-                const T Dp = R0s + ah * Rp, Dm = R0s + ah * Rm;
-                phi -= ah * atan2(t0 * (R0s * L[i] + ah * D), Dp * Dm + t0 * t0 * sp * sm);
-            }
+                z = (Rp + sp) * (Rm - sm) / R0s - T(1);
+            phi += t0 * log1p(z);
         }
+        // the arc-tangent terms of the three edges sum to the solid angle of
+        // the triangle seen from r: one atan2 (Van Oosterom and Strackee 1983)
+        // (in the triangle's plane the term vanishes)
+        const T *d0 = dd[0], *d1 = dd[1], *d2 = dd[2];
+        const T num = d0[0] * (d1[1] * d2[2] - d1[2] * d2[1]) + d0[1] * (d1[2] * d2[0] - d1[0] * d2[2]) +
+                      d0[2] * (d1[0] * d2[1] - d1[1] * d2[0]);
+        const T den = R[0] * R[1] * R[2] + (d0[0] * d1[0] + d0[1] * d1[1] + d0[2] * d1[2]) * R[2] +
+                      (d0[0] * d2[0] + d0[1] * d2[1] + d0[2] * d2[2]) * R[1] +
+                      (d1[0] * d2[0] + d1[1] * d2[1] + d1[2] * d2[2]) * R[0];
+        if (ah > eps * (L[0] + L[1] + L[2])) phi -= ah * fabs(T(2) * atan2(num, den));
         return phi;
     }
 };
@@ -247,28 +254,6 @@ __device__ T regular_pair(const T *tv, const T *sv, const double *gx, const doub
 
 
 
-// Queue slot for a special entry: touching pairs fill the queue from the
-// front (which = 0), near-singular pairs from the back (which = 1).  One
-// atomic per wave and queue (lanes counted with a ballot), not one per entry.
-__device__ inline int64_t queue_slot(const NFArgs &a, int which)
-{
-    int64_t pos = -1;
-    for (int q = 0; q < 2; ++q) {
-        const unsigned long long mask = __ballot(which == q);
-        if (mask == 0) continue;
-        const int lane = __lane_id();
-        const int leader = __ffsll((long long)mask) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(&a.work_n[q], (unsigned long long)__popcll(mask));
-        base = __shfl(base, leader);
-        if (which == q) {
-            const unsigned long long rank = __popcll(mask & ((1ull << lane) - 1ull));
-            pos = q == 0 ? (int64_t)(base + rank) : a.work_cap - 1 - (int64_t)(base + rank);
-        }
-    }
-    return pos;
-}
-
 __device__ inline int shared_vertex(const int32_t *ik, const int32_t *il)
 {
     for (int a = 0; a < 3; ++a)
@@ -277,18 +262,131 @@ __device__ inline int shared_vertex(const int32_t *ik, const int32_t *il)
     return -1;
 }
 
-// Pass 1: one workgroup per target leaf; self and regular entries computed,
-// touching and near-singular entries queued.
+// Class of an entry from the squared distance ratio d2 = (|c_k - c_l| /
+// max(diam_k, diam_l))^2; the counting pass and the filling pass call this
+// with bit-identical arguments, so they agree on every entry.
+template <typename T>
+__device__ inline int entry_class(bool self, bool touch, T d2, T rn2)
+{
+    if (self) return kSelf;
+    if (touch) return kQTouch;
+    if (d2 < rn2) return d2 < T(0.5625) ? kQNs2 : (d2 < T(2.25) ? kQNs1 : kQNs0);
+    return kRegular;
+}
+
+__device__ inline double ratio2_64(const NFArgs &a, int32_t k, int32_t l)
+{
+    const double dx = a.cen[3 * k] - a.cen[3 * l], dy = a.cen[3 * k + 1] - a.cen[3 * l + 1],
+                 dz = a.cen[3 * k + 2] - a.cen[3 * l + 2];
+    const double dm = fmax(a.diam[k], a.diam[l]);
+    return (dx * dx + dy * dy + dz * dz) / (dm * dm);
+}
+
+__device__ inline float ratio2_32(float4 ck, float4 cl)
+{
+    const float dx = ck.x - cl.x, dy = ck.y - cl.y, dz = ck.z - cl.z;
+    const float dm = fmaxf(ck.w, cl.w);
+    return fmaf(dx, dx, fmaf(dy, dy, dz * dz)) / (dm * dm);
+}
+
+// Centroid relative to the leaf's reference point, and diameter, in FP32.
+__device__ inline float4 meta32(const NFArgs &a, int32_t k, const double *c0)
+{
+    return make_float4((float)(a.cen[3 * k] - c0[0]), (float)(a.cen[3 * k + 1] - c0[1]),
+                       (float)(a.cen[3 * k + 2] - c0[2]), (float)a.diam[k]);
+}
+
+__device__ inline bool share_vertex4(int4 ik, int4 il)
+{
+    return ik.x == il.x || ik.x == il.y || ik.x == il.z || ik.y == il.x || ik.y == il.y || ik.y == il.z ||
+           ik.z == il.x || ik.z == il.y || ik.z == il.z;
+}
+
+// Value index of the stored entry (target l, source k) in the block of
+// leaf(l), or -1 when k is not among that leaf's source rows.
+__device__ inline int64_t mirror_index(const NFArgs &a, int32_t k, int32_t l)
+{
+    const int32_t li = a.panel_leaf[l];
+    int32_t lo = a.near_rows[li], hi = a.near_rows[li + 1];
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (a.near_src[mid] < k)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    if (lo >= a.near_rows[li + 1] || a.near_src[lo] != k) return -1;
+    return a.val_off[li] + (int64_t)(lo - a.near_rows[li]) * a.leaf_tpad[li] + (l - a.box_beg[a.leaf_box[li]]);
+}
+
+// Counting pass: per leaf, the number of entries of each queue (touching,
+// near-singular classes 0..2), cnt[4 li + q].  FP32 classifies as the FP32
+// filling pass does (centroids relative to the leaf's first centroid),
+// FP64 as the FP64 one.
+template <bool FP64>
+__global__ __launch_bounds__(256) void k_nf_count(NFArgs a, int64_t *__restrict__ cnt)
+{
+    const int64_t li = blockIdx.x;
+    if (li >= a.n_leaves) return;
+    __shared__ int s_cnt[kNQueues];
+    __shared__ unsigned long long s_all[2];
+    const int32_t Tb = a.leaf_box[li];
+    const int32_t kb = a.box_beg[Tb], nt = a.box_end[Tb] - kb;
+    const int32_t r0 = a.near_rows[li], nr = a.near_rows[li + 1] - r0;
+    const double c0[3] = {a.cen[3 * (int64_t)kb], a.cen[3 * (int64_t)kb + 1], a.cen[3 * (int64_t)kb + 2]};
+    if (threadIdx.x < kNQueues) s_cnt[threadIdx.x] = 0;
+    if (threadIdx.x < 2) s_all[threadIdx.x] = 0;
+    __syncthreads();
+    int my[kNQueues] = {0, 0, 0, 0};
+    unsigned long long all[2] = {0, 0};
+    const float rn2f = (float)(a.r_near * a.r_near);
+    for (int64_t e = threadIdx.x; e < (int64_t)nr * nt; e += blockDim.x) {
+        const int32_t r = (int32_t)(e / nt), j = (int32_t)(e - (int64_t)r * nt);
+        const int32_t k = kb + j, l = a.near_src[r0 + r];
+        const int4 ik = make_int4(a.pvid[3 * k], a.pvid[3 * k + 1], a.pvid[3 * k + 2], k);
+        const int4 il = make_int4(a.pvid[3 * l], a.pvid[3 * l + 1], a.pvid[3 * l + 2], l);
+        int c;
+        if (FP64)
+            c = entry_class<double>(k == l, share_vertex4(ik, il), ratio2_64(a, k, l), a.r_near * a.r_near);
+        else
+            c = entry_class<float>(k == l, share_vertex4(ik, il), ratio2_32(meta32(a, k, c0), meta32(a, l, c0)),
+                                   rn2f);
+        if (c < kNQueues) {
+            ++all[c == kQTouch ? 0 : 1];
+            if (k < l || mirror_index(a, l, k) < 0) ++my[c];
+        }
+    }
+    for (int q = 0; q < kNQueues; ++q)
+        if (my[q]) atomicAdd(&s_cnt[q], my[q]);
+    if (all[0]) atomicAdd(&s_all[0], all[0]);
+    if (all[1]) atomicAdd(&s_all[1], all[1]);
+    __syncthreads();
+    if (threadIdx.x < kNQueues) cnt[4 * li + threadIdx.x] = s_cnt[threadIdx.x];
+    // stored entries per class (both orientations), for the statistics
+    if (threadIdx.x == 0) {
+        atomicAdd(&a.counters[1], s_all[0]);
+        atomicAdd(&a.counters[2], s_all[1]);
+    }
+}
+
+// Pass 1 in FP64: one workgroup per target leaf; self and regular entries
+// computed, the others written to their queue at the leaf's offset (slots
+// within a leaf from LDS counters).
 template <typename V, bool FP64>
 __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restrict__ val)
 {
     const int64_t li = blockIdx.x;
     if (li >= a.n_leaves) return;
+    __shared__ unsigned long long s_cnt[2];
+    __shared__ unsigned long long s_q[kNQueues];
     const int32_t T = a.leaf_box[li];
     const int32_t kb = a.box_beg[T], nt = a.box_end[T] - kb;
     const int32_t r0 = a.near_rows[li], nr = a.near_rows[li + 1] - r0;
     const int tpad = a.leaf_tpad[li];
     const int64_t vo = a.val_off[li];
+    if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0;
+    if (threadIdx.x < kNQueues) s_q[threadIdx.x] = (unsigned long long)a.q_off[4 * li + threadIdx.x];
+    __syncthreads();
     unsigned long long c_self = 0, c_reg = 0;
     for (int64_t e = threadIdx.x; e < (int64_t)nr * tpad; e += blockDim.x) {
         const int32_t r = (int32_t)(e / tpad), j = (int32_t)(e - (int64_t)r * tpad);
@@ -297,50 +395,38 @@ __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restr
             continue;
         }
         const int32_t k = kb + j, l = a.near_src[r0 + r];
-        if (k == l) {
+        const int4 ik = make_int4(a.pvid[3 * k], a.pvid[3 * k + 1], a.pvid[3 * k + 2], k);
+        const int4 il = make_int4(a.pvid[3 * l], a.pvid[3 * l + 1], a.pvid[3 * l + 2], l);
+        const double d2 = ratio2_64(a, k, l);
+        const int c = entry_class<double>(k == l, share_vertex4(ik, il), d2, a.r_near * a.r_near);
+        if (c == kSelf) {
             val[vo + e] = (V)self_term(a.pv + 9 * (int64_t)k);
             ++c_self;
             continue;
         }
-        const int sv = shared_vertex(a.pvid + 3 * (int64_t)k, a.pvid + 3 * (int64_t)l);
-        const double dx = a.cen[3 * k] - a.cen[3 * l], dy = a.cen[3 * k + 1] - a.cen[3 * l + 1],
-                     dz = a.cen[3 * k + 2] - a.cen[3 * l + 2];
-        const double rr = sqrt(dx * dx + dy * dy + dz * dz) / fmax(a.diam[k], a.diam[l]);
-        if (sv >= 0 || rr < a.r_near) {
-            const int which = sv >= 0 ? 0 : 1;
-            const int64_t pos = queue_slot(a, which);
-            if (pos >= 0 && pos < a.work_cap) {
+        if (c < kNQueues) {
+            // k > l with a stored mirror: written when (l, k) is integrated
+            const int64_t mir = mirror_index(a, k < l ? k : l, k < l ? l : k);
+            if (k < l || mir < 0) {
+                const int64_t pos = (int64_t)atomicAdd(&s_q[c], 1ull);
                 a.work[pos] = vo + e;
                 a.work_meta[2 * pos] = k;
                 a.work_meta[2 * pos + 1] = l;
+                a.work_mirror[pos] = k < l ? mir : -1;
+                val[vo + e] = V(0);
             }
-            val[vo + e] = V(0);
             continue;
         }
         ++c_reg;
-        if (FP64) {
-            double tv[9], svv[9];
-            for (int i = 0; i < 9; ++i) {
-                tv[i] = a.pv[9 * (int64_t)k + i];
-                svv[i] = a.pv[9 * (int64_t)l + i];
-            }
-            val[vo + e] = (V)(rr < a.r_mid ? regular_pair<double, 5>(tv, svv, R.rx4, R.rw4)
-                                           : regular_pair<double, 4>(tv, svv, R.rx3, R.rw3));
-        } else {
-            // FP32 arithmetic relative to the target centroid
-            float tv[9], svv[9];
-            for (int i = 0; i < 9; ++i) {
-                tv[i] = (float)(a.pv[9 * (int64_t)k + i] - a.cen[3 * k + i % 3]);
-                svv[i] = (float)(a.pv[9 * (int64_t)l + i] - a.cen[3 * k + i % 3]);
-            }
-            val[vo + e] = (V)(rr < a.r_mid ? regular_pair<float, 4>(tv, svv, R.rx4, R.rw4)
-                                           : regular_pair<float, 3>(tv, svv, R.rx3, R.rw3));
+        double tv[9], svv[9];
+        for (int i = 0; i < 9; ++i) {
+            tv[i] = a.pv[9 * (int64_t)k + i];
+            svv[i] = a.pv[9 * (int64_t)l + i];
         }
+        val[vo + e] = (V)(d2 < a.r_mid * a.r_mid ? regular_pair<double, 5>(tv, svv, R.rx4, R.rw4)
+                                                 : regular_pair<double, 4>(tv, svv, R.rx3, R.rw3));
     }
     // class counters: LDS first, one global atomic per workgroup
-    __shared__ unsigned long long s_cnt[2];
-    if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0;
-    __syncthreads();
     if (c_self) atomicAdd(&s_cnt[0], c_self);
     if (c_reg) atomicAdd(&s_cnt[1], c_reg);
     __syncthreads();
@@ -388,18 +474,23 @@ __device__ inline void stage_points(const double *__restrict__ pv, int32_t k, co
     *out = o;
 }
 
+// sum_i w_i sum_j w_j / |x_i - y_j| over NQ points each: the source points
+// go to registers once, the target points stream from LDS.
 template <int NQ>
 __device__ inline float product_rule(const float4 *__restrict__ xp, const float4 *__restrict__ yp)
 {
+    float4 y[NQ];
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) y[j] = yp[j];
     float acc = 0.f;
+#pragma unroll 2
     for (int i = 0; i < NQ; ++i) {
         const float4 x = xp[i];
         float inner = 0.f;
 #pragma unroll
         for (int j = 0; j < NQ; ++j) {
-            const float4 y = yp[j];
-            const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z;
-            inner = fmaf(y.w, rsqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))), inner);
+            const float dx = x.x - y[j].x, dy = x.y - y[j].y, dz = x.z - y[j].z;
+            inner = fmaf(y[j].w, rsqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))), inner);
         }
         acc = fmaf(x.w, inner, acc);
     }
@@ -415,6 +506,12 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
     __shared__ float4 tcd[kMaxLeaf], scd[kRowChunk];  // centroid (relative), diameter
     __shared__ int4 tid[kMaxLeaf], sid[kRowChunk];    // vertex ids, panel index
     __shared__ unsigned long long s_cnt[2];
+    __shared__ unsigned long long s_q[kNQueues];  // next free position of this leaf in each queue
+    // regular entries of the current chunk, compacted by rule (4 x 4 from the
+    // front, 3 x 3 from the back) so that the lanes of a wave all run the
+    // same rule: entry = row << 8 | target
+    __shared__ int32_t s_reg[kRowChunk * kMaxLeaf];
+    __shared__ int s_n4, s_n3;
     const int32_t Tb = a.leaf_box[li];
     const int32_t kb = a.box_beg[Tb], nt = a.box_end[Tb] - kb;
     const int32_t r0 = a.near_rows[li], nr = a.near_rows[li + 1] - r0;
@@ -422,12 +519,12 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
     const int64_t vo = a.val_off[li];
     const double c0[3] = {a.cen[3 * (int64_t)kb], a.cen[3 * (int64_t)kb + 1], a.cen[3 * (int64_t)kb + 2]};
     if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0;
+    if (threadIdx.x < kNQueues) s_q[threadIdx.x] = (unsigned long long)a.q_off[4 * li + threadIdx.x];
     for (int e = threadIdx.x; e < nt * kRegPts; e += blockDim.x)
         stage_points(a.pv, kb + e / kRegPts, c0, R, e % kRegPts, &tp[e]);
     for (int j = threadIdx.x; j < nt; j += blockDim.x) {
         const int32_t k = kb + j;
-        tcd[j] = make_float4((float)(a.cen[3 * k] - c0[0]), (float)(a.cen[3 * k + 1] - c0[1]),
-                             (float)(a.cen[3 * k + 2] - c0[2]), (float)a.diam[k]);
+        tcd[j] = meta32(a, k, c0);
         tid[j] = make_int4(a.pvid[3 * k], a.pvid[3 * k + 1], a.pvid[3 * k + 2], k);
     }
     unsigned long long c_self = 0, c_reg = 0;
@@ -439,10 +536,11 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
             stage_points(a.pv, a.near_src[r0 + rc + e / kRegPts], c0, R, e % kRegPts, &spt[e]);
         for (int r = threadIdx.x; r < nrc; r += blockDim.x) {
             const int32_t l = a.near_src[r0 + rc + r];
-            scd[r] = make_float4((float)(a.cen[3 * l] - c0[0]), (float)(a.cen[3 * l + 1] - c0[1]),
-                                 (float)(a.cen[3 * l + 2] - c0[2]), (float)a.diam[l]);
+            scd[r] = meta32(a, l, c0);
             sid[r] = make_int4(a.pvid[3 * l], a.pvid[3 * l + 1], a.pvid[3 * l + 2], l);
         }
+        __syncthreads();
+        if (threadIdx.x == 0) s_n4 = s_n3 = 0;
         __syncthreads();
         for (int e = threadIdx.x; e < nrc * tpad; e += blockDim.x) {
             const int r = e / tpad, j = e - r * tpad;
@@ -452,31 +550,40 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
                 continue;
             }
             const int4 ik = tid[j], il = sid[r];
-            if (ik.w == il.w) {
+            const float d2 = ratio2_32(tcd[j], scd[r]);
+            const int c = entry_class<float>(ik.w == il.w, share_vertex4(ik, il), d2, rn2);
+            if (c == kSelf) {
                 val[out] = (float)self_term(a.pv + 9 * (int64_t)ik.w);
                 ++c_self;
-                continue;
-            }
-            const bool touch = ik.x == il.x || ik.x == il.y || ik.x == il.z || ik.y == il.x || ik.y == il.y ||
-                               ik.y == il.z || ik.z == il.x || ik.z == il.y || ik.z == il.z;
-            const float4 ck = tcd[j], cl = scd[r];
-            const float dx = ck.x - cl.x, dy = ck.y - cl.y, dz = ck.z - cl.z;
-            const float dm = fmaxf(ck.w, cl.w);
-            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) / (dm * dm);
-            if (touch || d2 < rn2) {
-                const int64_t pos = queue_slot(a, touch ? 0 : 1);
-                if (pos >= 0 && pos < a.work_cap) {
+            } else if (c < kNQueues) {
+                // k > l with a stored mirror: written when (l, k) is integrated
+                const int32_t k = ik.w, l = il.w;
+                const int64_t mir = mirror_index(a, k < l ? k : l, k < l ? l : k);
+                if (k < l || mir < 0) {
+                    const int64_t pos = (int64_t)atomicAdd(&s_q[c], 1ull);
                     a.work[pos] = out;
-                    a.work_meta[2 * pos] = ik.w;
-                    a.work_meta[2 * pos + 1] = il.w;
+                    a.work_meta[2 * pos] = k;
+                    a.work_meta[2 * pos + 1] = l;
+                    a.work_mirror[pos] = k < l ? mir : -1;
+                    val[out] = 0.f;
                 }
-                val[out] = 0.f;
-                continue;
+            } else if (d2 < rm2) {
+                s_reg[atomicAdd(&s_n4, 1)] = r << 8 | j;
+            } else {
+                s_reg[kRowChunk * kMaxLeaf - 1 - atomicAdd(&s_n3, 1)] = r << 8 | j;
             }
-            ++c_reg;
-            val[out] = d2 < rm2 ? product_rule<16>(&tp[j * kRegPts], &spt[r * kRegPts])
-                                : product_rule<9>(&tp[j * kRegPts + 16], &spt[r * kRegPts + 16]);
         }
+        __syncthreads();
+        const int n4 = s_n4, n3 = s_n3;
+        for (int q = threadIdx.x; q < n4; q += blockDim.x) {
+            const int rj = s_reg[q], r = rj >> 8, j = rj & 255;
+            val[vo + (int64_t)(rc + r) * tpad + j] = product_rule<16>(&tp[j * kRegPts], &spt[r * kRegPts]);
+        }
+        for (int q = threadIdx.x; q < n3; q += blockDim.x) {
+            const int rj = s_reg[kRowChunk * kMaxLeaf - 1 - q], r = rj >> 8, j = rj & 255;
+            val[vo + (int64_t)(rc + r) * tpad + j] = product_rule<9>(&tp[j * kRegPts + 16], &spt[r * kRegPts + 16]);
+        }
+        if (threadIdx.x == 0) c_reg += (unsigned long long)(n4 + n3);
     }
     // padding rows of a leaf without rows do not exist; class counters: LDS
     // first, one global atomic per workgroup
@@ -490,112 +597,95 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
     }
 }
 
-// Pass 2: queued touching (which = 0, from the front of the queue) or
-// near-singular (which = 1, from the back) entries, one per thread.
-// Rule class of a near-singular pair: r < 0.75 (2), r < 1.5 (1), r < r_near (0).
-__device__ inline int ns_level(const NFArgs &a, int32_t k, int32_t l)
-{
-    const double dx = a.cen[3 * k] - a.cen[3 * l], dy = a.cen[3 * k + 1] - a.cen[3 * l + 1],
-                 dz = a.cen[3 * k + 2] - a.cen[3 * l + 2];
-    const double rr = sqrt(dx * dx + dy * dy + dz * dz) / fmax(a.diam[k], a.diam[l]);
-    return rr < 0.75 ? 2 : (rr < 1.5 ? 1 : 0);
-}
-
-// Near-singular entries bucketed by subdivision level, so that each launch
-// of pass 2 runs one level (lanes of a wave then do equal work).  Entry i of
-// the batch is queue position list[i] (or cap - 1 - i without a list).
-// Pass 0 counts per level (one atomic per wave and level); pass 1 writes i
-// into order[] at the running offset of its level.
-__global__ void k_ns_bucket(NFArgs a, int64_t count, const int64_t *__restrict__ list, int pass,
-                            unsigned long long *__restrict__ ctr, int64_t *__restrict__ order, int64_t off1,
-                            int64_t off2)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int lev = -1;
-    if (i < count) {
-        const int64_t pos = list ? list[i] : a.work_cap - 1 - i;
-        lev = ns_level(a, a.work_meta[2 * pos], a.work_meta[2 * pos + 1]);
-    }
-    for (int q = 0; q < 3; ++q) {
-        const unsigned long long mask = __ballot(lev == q);
-        if (mask == 0) continue;
-        const int lane = __lane_id();
-        const int leader = __ffsll((long long)mask) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(&ctr[q], (unsigned long long)__popcll(mask));
-        base = __shfl(base, leader);
-        const int64_t off = q == 0 ? 0 : (q == 1 ? off1 : off2);
-        if (pass == 1 && lev == q) order[off + (int64_t)(base + __popcll(mask & ((1ull << lane) - 1ull)))] = i;
-    }
-}
-
+// Pass 2: the entries of one queue, one per thread.  Entry t of the launch
+// is queue position list[t] (a fall-back or audit list) or base + t.
+// Touching pairs: the graded rule collapsed at the shared vertex.  Near-
+// singular pairs of rule class c: P_kl = P_lk, so the outer rule runs over
+// the smaller panel and the closed-form potential belongs to the larger one,
+// whose evaluation points then lie within a few of its diameters (far from a
+// small triangle its edge terms cancel in FP32).
 template <typename V, typename C>
-__global__ __launch_bounds__(64) void k_nf_special(NFArgs a, NFRules R, int which, int64_t count,
+__global__ __launch_bounds__(64) void k_nf_special(NFArgs a, NFRules R, int queue, int64_t base, int64_t count,
                                                    V *__restrict__ val, const int64_t *__restrict__ list,
-                                                   const int64_t *__restrict__ order, double *__restrict__ alt_out)
+                                                   double *__restrict__ alt_out)
 {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= count) return;
-    const int64_t i = order ? order[t] : t;
-    const int64_t pos = list ? list[i] : (which == 0 ? i : a.work_cap - 1 - i);
+    const int64_t pos = list ? list[t] : base + t;
     const int32_t k = a.work_meta[2 * pos], l = a.work_meta[2 * pos + 1];
     // coordinates relative to the target centroid
     C tv[9], sv[9];
-    if (which == 0) {
+    C v;
+    if (queue == kQTouch) {
         const int s0 = shared_vertex(a.pvid + 3 * (int64_t)k, a.pvid + 3 * (int64_t)l);
         for (int j = 0; j < 3; ++j)
             for (int d = 0; d < 3; ++d) tv[3 * j + d] = (C)(a.pv[9 * (int64_t)k + 3 * ((s0 + j) % 3) + d] - a.cen[3 * k + d]);
         for (int q = 0; q < 9; ++q) sv[q] = (C)(a.pv[9 * (int64_t)l + q] - a.cen[3 * k + q % 3]);
-        const C v = touching_pair<C>(tv, sv, R);
-        if (alt_out)
-            alt_out[i] = (double)v;
-        else
-            val[a.work[pos]] = (V)v;
+        v = touching_pair<C>(tv, sv, R);
     } else {
-        // P_kl = P_lk: the outer rule runs over the smaller panel and the
-        // closed-form potential belongs to the larger one, so the points
-        // where it is evaluated lie within a few of its diameters (far from
-        // a small triangle its edge terms cancel in FP32)
         const int32_t o = a.diam[l] < a.diam[k] ? l : k, in = o == k ? l : k;
         for (int q = 0; q < 9; ++q) {
             tv[q] = (C)(a.pv[9 * (int64_t)o + q] - a.cen[3 * k + q % 3]);
             sv[q] = (C)(a.pv[9 * (int64_t)in + q] - a.cen[3 * k + q % 3]);
         }
-        const C v = near_pair<C>(tv, sv, ns_level(a, k, l), R);
-        if (alt_out)
-            alt_out[i] = (double)v;
-        else
-            val[a.work[pos]] = (V)v;
+        v = near_pair<C>(tv, sv, queue - kQNs0, R);
+    }
+    if (alt_out) {
+        alt_out[t] = (double)v;
+    } else {
+        val[a.work[pos]] = (V)v;
+        if (a.work_mirror[pos] >= 0) val[a.work_mirror[pos]] = (V)v;
     }
 }
 
-// Surrogate decision for queued near-singular entry i (queue position
-// cap - 1 - i): accept P = cheap (1 + out0) when every feature lies in the
-// training range and out1 <= bound, else queue the entry for quadrature.
-// Every audit_every-th accepted entry is also queued for an audit.
+// Claim n slots of a global counter for the lanes of a workgroup that pass
+// `take`: one global atomic per workgroup; returns this lane's slot or -1.
+__device__ inline int64_t block_claim(bool take, unsigned long long *ctr)
+{
+    __shared__ unsigned int s_n;
+    __shared__ unsigned long long s_base;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    const unsigned int mine = take ? atomicAdd(&s_n, 1u) : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) s_base = s_n ? atomicAdd(ctr, (unsigned long long)s_n) : 0ull;
+    __syncthreads();
+    return take ? (int64_t)(s_base + mine) : -1;
+}
+
+// Surrogate decision for entry i of the rule-class-0 near-singular queue
+// (position base + i): accept P = cheap (1 + out0) when every feature lies
+// in the training range and out1 <= bound, else list the entry for
+// quadrature.  Every audit_every-th accepted entry is also listed for an
+// audit against quadrature.
 template <typename V>
-__global__ void k_ns_accept(NFArgs a, int64_t n, const float *__restrict__ feat, const double *__restrict__ cheap,
-                            const float *__restrict__ out, const float *__restrict__ lo, const float *__restrict__ hi,
-                            float bound, int audit_every, V *__restrict__ val, int64_t *__restrict__ fb,
-                            unsigned long long *__restrict__ fbn, int64_t *__restrict__ aud,
-                            double *__restrict__ aud_val, unsigned long long *__restrict__ audn)
+__global__ __launch_bounds__(256) void k_ns_accept(NFArgs a, int64_t base, int64_t n, const float *__restrict__ feat,
+                                                   const double *__restrict__ cheap, const float *__restrict__ out,
+                                                   const float *__restrict__ lo, const float *__restrict__ hi,
+                                                   float bound, int audit_every, V *__restrict__ val,
+                                                   int64_t *__restrict__ fb, unsigned long long *__restrict__ fbn,
+                                                   int64_t *__restrict__ aud, double *__restrict__ aud_val,
+                                                   unsigned long long *__restrict__ audn)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t pos = a.work_cap - 1 - i;
-    bool ok = out[2 * i + 1] <= bound && isfinite(out[2 * i]);
-    for (int q = 0; q < 18 && ok; ++q) ok = feat[18 * i + q] >= lo[q] && feat[18 * i + q] <= hi[q];
-    if (ok) {
-        const double v = cheap[i] * (1.0 + (double)out[2 * i]);
-        val[a.work[pos]] = (V)v;
-        if (audit_every > 0 && i % audit_every == 0) {
-            const unsigned long long j = atomicAdd(audn, 1ull);
-            aud[j] = pos;
-            aud_val[j] = v;
+    const bool live = i < n;
+    bool ok = false;
+    double v = 0;
+    if (live) {
+        ok = out[2 * i + 1] <= bound && isfinite(out[2 * i]);
+        for (int q = 0; q < 18 && ok; ++q) ok = feat[18 * i + q] >= lo[q] && feat[18 * i + q] <= hi[q];
+        if (ok) {
+            v = cheap[i] * (1.0 + (double)out[2 * i]);
+            val[a.work[base + i]] = (V)v;
+            if (a.work_mirror[base + i] >= 0) val[a.work_mirror[base + i]] = (V)v;
         }
-    } else {
-        const unsigned long long j = atomicAdd(fbn, 1ull);
-        fb[j] = pos;
+    }
+    const int64_t f = block_claim(live && !ok, fbn);
+    if (f >= 0) fb[f] = base + i;
+    const int64_t d = block_claim(live && ok && audit_every > 0 && i % audit_every == 0, audn);
+    if (d >= 0) {
+        aud[d] = base + i;
+        aud_val[d] = v;
     }
 }
 
@@ -659,69 +749,78 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
             P->near64.release();
             P->near32.alloc(std::max<int64_t>(P->n_near_entries, 1));
         }
-        // queue capacity: touching + near-singular entries (bounded by all pairs)
-        const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(P->n_near_pairs, 160 * P->N));
-        DevBuf<int64_t> work(cap);
-        DevBuf<int32_t> meta(2 * cap);
-        DevBuf<unsigned long long> cnt(4), wn(2);
+        DevBuf<unsigned long long> cnt(4);
         XRL_HIP(hipMemsetAsync(cnt.p, 0, cnt.bytes(), s));
-        XRL_HIP(hipMemsetAsync(wn.p, 0, wn.bytes(), s));
         NFArgs a{P->leaf_box.p, P->box_beg.p, P->box_end.p, P->near_rows.p, P->near_src.p, P->leaf_tpad.p,
                  P->pvid.p,     P->near_val_off.p, P->pv.p, P->cen.p, P->diam.p, o.r_near, o.r_mid,
-                 P->n_leaves,   cnt.p,       work.p,   meta.p,  wn.p,    cap};
-        if (P->n_leaves > 0) {
+                 P->n_leaves,   cnt.p,       nullptr,  nullptr, nullptr, nullptr, P->panel_leaf.p};
+        // counting pass, then every leaf's first position in each queue
+        // (queues stored one after another: touching, near-singular 0, 1, 2)
+        const int64_t L = P->n_leaves;
+        DevBuf<int64_t> lcnt(std::max<int64_t>(4 * L, 4)), qoff(std::max<int64_t>(4 * L, 4));
+        std::vector<int64_t> qbase(kNQueues + 1, 0);
+        if (L > 0) {
             if (fp64)
-                k_nf_main<double, true><<<P->n_leaves, 256, 0, s>>>(a, R, P->near64.p);
+                k_nf_count<true><<<L, 256, 0, s>>>(a, lcnt.p);
             else
-                k_nf_leaf32<<<P->n_leaves, 256, 0, s>>>(a, R, P->near32.p);
+                k_nf_count<false><<<L, 256, 0, s>>>(a, lcnt.p);
+            XRL_HIP(hipGetLastError());
+            std::vector<int64_t> hc = lcnt.download(s, 4 * L), ho(4 * L);
+            for (int q = 0; q < kNQueues; ++q) {
+                int64_t tot = 0;
+                for (int64_t li = 0; li < L; ++li) tot += hc[4 * li + q];
+                qbase[q + 1] = qbase[q] + tot;
+            }
+            for (int q = 0; q < kNQueues; ++q) {
+                int64_t run = qbase[q];
+                for (int64_t li = 0; li < L; ++li) {
+                    ho[4 * li + q] = run;
+                    run += hc[4 * li + q];
+                }
+            }
+            qoff.upload(ho, s);
+        }
+        const int64_t nq = qbase[kNQueues];
+        DevBuf<int64_t> work(std::max<int64_t>(nq, 1));
+        DevBuf<int32_t> meta(2 * std::max<int64_t>(nq, 1));
+        DevBuf<int64_t> mirror(std::max<int64_t>(nq, 1));
+        a.work = work.p;
+        a.work_meta = meta.p;
+        a.work_mirror = mirror.p;
+        a.q_off = qoff.p;
+        if (L > 0) {
+            if (fp64)
+                k_nf_main<double, true><<<L, 256, 0, s>>>(a, R, P->near64.p);
+            else
+                k_nf_leaf32<<<L, 256, 0, s>>>(a, R, P->near32.p);
             XRL_HIP(hipGetLastError());
         }
-        auto hw = wn.download(s);
-        XRL_CHECK((int64_t)(hw[0] + hw[1]) <= cap, XRL_E_OOM,
-                  "xrl_nearfield_assemble: special-pair queue overflow (%llu + %llu > %lld)",
-                  (unsigned long long)hw[0], (unsigned long long)hw[1], (long long)cap);
         // mixed precision: FP64 for the touching (adjacent-panel) pairs and
         // for the audit reference of the surrogate, FP32 (relative to the
         // target centroid, exact inner potential) for the near-singular
         // pairs that are not adjacent
-        auto launch = [&](int which, int64_t count, const int64_t *list, const int64_t *order, double *alt) {
+        auto special = [&](int queue, int64_t base, int64_t count, const int64_t *list, double *alt) {
             if (count == 0) return;
             if (P->precision == XRL_PREC_FP64)
-                k_nf_special<double, double><<<cdiv(count, 64), 64, 0, s>>>(a, R, which, count, P->near64.p, list,
-                                                                            order, alt);
-            else if (P->precision == XRL_PREC_MIXED && (which == 0 || alt))
-                k_nf_special<float, double><<<cdiv(count, 64), 64, 0, s>>>(a, R, which, count, P->near32.p, list,
-                                                                           order, alt);
+                k_nf_special<double, double><<<cdiv(count, 64), 64, 0, s>>>(a, R, queue, base, count, P->near64.p,
+                                                                            list, alt);
+            else if (P->precision == XRL_PREC_MIXED && (queue == kQTouch || alt))
+                k_nf_special<float, double><<<cdiv(count, 64), 64, 0, s>>>(a, R, queue, base, count, P->near32.p,
+                                                                           list, alt);
             else
-                k_nf_special<float, float><<<cdiv(count, 64), 64, 0, s>>>(a, R, which, count, P->near32.p, list,
-                                                                          order, alt);
+                k_nf_special<float, float><<<cdiv(count, 64), 64, 0, s>>>(a, R, queue, base, count, P->near32.p,
+                                                                          list, alt);
             XRL_HIP(hipGetLastError());
         };
-        // touching entries in queue order; near-singular entries one
-        // subdivision level per launch
-        auto special = [&](int which, int64_t count, const int64_t *list, double *alt) {
-            if (count == 0) return;
-            if (which == 0) {
-                launch(0, count, list, nullptr, alt);
-                return;
-            }
-            DevBuf<unsigned long long> ctr(6);
-            DevBuf<int64_t> order(count);
-            XRL_HIP(hipMemsetAsync(ctr.p, 0, ctr.bytes(), s));
-            k_ns_bucket<<<cdiv(count, 256), 256, 0, s>>>(a, count, list, 0, ctr.p, nullptr, 0, 0);
-            XRL_HIP(hipGetLastError());
-            auto n = ctr.download(s, 3);
-            const int64_t off[3] = {0, (int64_t)n[0], (int64_t)(n[0] + n[1])};
-            k_ns_bucket<<<cdiv(count, 256), 256, 0, s>>>(a, count, list, 1, ctr.p + 3, order.p, off[1], off[2]);
-            XRL_HIP(hipGetLastError());
-            for (int q = 2; q >= 0; --q) launch(1, (int64_t)n[q], list, order.p + off[q], alt);
-            XRL_HIP(hipStreamSynchronize(s));  // order[] lives until the launches are done
-        };
-        special(0, (int64_t)hw[0], nullptr, nullptr);
-        int64_t n_acc = 0, n_fb = (int64_t)hw[1];
+        for (int q = 0; q < kNQueues; ++q)
+            if (!(o.surrogate && q == kQNs0)) special(q, qbase[q], qbase[q + 1] - qbase[q], nullptr, nullptr);
+        int64_t n_acc = 0, n_fb = 0;
         double aud_max = 0, aud_rms = 0;
-        if (o.surrogate && hw[1] > 0) {
-            const int64_t nns = (int64_t)hw[1];
+        // the surrogate takes the rule-class-0 near-singular pairs (r >= 1.5):
+        // closer pairs fail its error bound almost always, so evaluating the
+        // network there would only add to the quadrature
+        const int64_t nns = qbase[kQNs0 + 1] - qbase[kQNs0];
+        if (o.surrogate && nns > 0) {
             MlpDevice mlp;
             mlp_prepare_host(mlp, o.surrogate, s);
             DevBuf<float> feat(18 * nns), out(2 * nns), lo, hi;
@@ -731,26 +830,26 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
             lo.upload(o.surrogate->feat_lo, 18, s);
             hi.upload(o.surrogate->feat_hi, 18, s);
             XRL_HIP(hipMemsetAsync(fbn.p, 0, fbn.bytes(), s));
-            ns_features(a, nns, feat.p, cheap.p, s);
+            ns_features(a, qbase[kQNs0], nns, feat.p, cheap.p, s);
             mlp_infer(mlp, feat.p, nns, out.p, s);
             if (fp64)
-                k_ns_accept<double><<<cdiv(nns, 256), 256, 0, s>>>(a, nns, feat.p, cheap.p, out.p, lo.p, hi.p,
-                                                                  o.surrogate->log10_err_bound, o.audit_every,
+                k_ns_accept<double><<<cdiv(nns, 256), 256, 0, s>>>(a, qbase[kQNs0], nns, feat.p, cheap.p, out.p, lo.p,
+                                                                  hi.p, o.surrogate->log10_err_bound, o.audit_every,
                                                                   P->near64.p, fb.p, fbn.p, aud.p, aud_val.p,
                                                                   fbn.p + 1);
             else
-                k_ns_accept<float><<<cdiv(nns, 256), 256, 0, s>>>(a, nns, feat.p, cheap.p, out.p, lo.p, hi.p,
-                                                                 o.surrogate->log10_err_bound, o.audit_every,
+                k_ns_accept<float><<<cdiv(nns, 256), 256, 0, s>>>(a, qbase[kQNs0], nns, feat.p, cheap.p, out.p, lo.p,
+                                                                 hi.p, o.surrogate->log10_err_bound, o.audit_every,
                                                                  P->near32.p, fb.p, fbn.p, aud.p, aud_val.p,
                                                                  fbn.p + 1);
             XRL_HIP(hipGetLastError());
             auto hn = fbn.download(s);
             n_fb = (int64_t)hn[0];
             n_acc = nns - n_fb;
-            special(1, n_fb, fb.p, nullptr);
+            special(kQNs0, 0, n_fb, fb.p, nullptr);
             const int64_t na = (int64_t)hn[1];
             if (na > 0) {
-                special(1, na, aud.p, aud_ref.p);
+                special(kQNs0, 0, na, aud.p, aud_ref.p);
                 k_audit_err<<<cdiv(na, 256), 256, 0, s>>>(aud_ref.p, aud_val.p, na, rel.p);
                 auto hr = rel.download(s, na);
                 double ss = 0;
@@ -760,8 +859,6 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
                 }
                 aud_rms = std::sqrt(ss / na);
             }
-        } else {
-            special(1, (int64_t)hw[1], nullptr, nullptr);
         }
         XRL_HIP(hipEventRecord(e1, s));
         XRL_HIP(hipEventSynchronize(e1));
@@ -775,8 +872,8 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
             std::memset(stats, 0, sizeof *stats);
             stats->n_entries = P->n_near_entries;
             stats->n_self = (int64_t)hc[0];
-            stats->n_touching = (int64_t)hw[0];
-            stats->n_near_singular = (int64_t)hw[1];
+            stats->n_touching = (int64_t)hc[1];
+            stats->n_near_singular = (int64_t)hc[2];
             stats->n_regular = (int64_t)hc[3];
             stats->n_mlp_accepted = n_acc;
             stats->n_mlp_fallback = o.surrogate ? n_fb : 0;

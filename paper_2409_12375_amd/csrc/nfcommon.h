@@ -24,11 +24,23 @@ struct NFArgs {
     double r_near, r_mid;
     int64_t n_leaves;
     unsigned long long *counters;  // [0] self [1] touch [2] near-singular [3] regular
-    int64_t *work;                 // special entries: value index
-    int32_t *work_meta;            // packed (k, l)
-    unsigned long long *work_n;    // [0] touching count, [1] near-singular count (separate halves)
-    int64_t work_cap;
+    // Queued entries, one contiguous range per queue (kQTouch, kQNs0..2):
+    // work[pos] = value index, work_meta[2 pos], [2 pos + 1] = (k, l).
+    // q_off[4 li + q]: first position of leaf li in queue q (exclusive scan
+    // of the per-leaf counts, the queue's base included).
+    int64_t *work;
+    int32_t *work_meta;
+    const int64_t *q_off;
+    // P_kl = P_lk: a queued entry with k < l is integrated once and also
+    // written to the block of leaf(l) (work_mirror[pos], -1 if that entry is
+    // not stored); entries with k > l whose mirror is stored are not queued.
+    int64_t *work_mirror;
+    const int32_t *panel_leaf;  // [N] leaf of each sorted panel
 };
+
+// Near-field entry classes: the queues of pass 2 (touching; near-singular of
+// rule class 0, 1, 2 for r >= 1.5, 0.75 <= r < 1.5, r < 0.75), regular, self.
+enum { kQTouch = 0, kQNs0 = 1, kQNs1 = 2, kQNs2 = 3, kNQueues = 4, kRegular = 4, kSelf = 5 };
 
 struct CheapRule {
     double x[3], w[3];
@@ -46,7 +58,7 @@ void gauss_legendre01(int n, double *x, double *w);
 void mlp_prepare_host(MlpDevice &m, const xrl_mlp *h, hipStream_t s);
 void mlp_infer(const MlpDevice &m, const float *X, int64_t n, float *out, hipStream_t s);
 // features and cheap values of queued near-singular entries (queue positions
-// cap - 1 - i, i < n)
-void ns_features(const NFArgs &a, int64_t n, float *feat, double *cheap, hipStream_t s);
+// base + i, i < n)
+void ns_features(const NFArgs &a, int64_t base, int64_t n, float *feat, double *cheap, hipStream_t s);
 
 }  // namespace xrl

@@ -515,11 +515,12 @@ void mlp_prepare_host(MlpDevice &m, const xrl_mlp *h, hipStream_t s)
     XRL_HIP(hipStreamSynchronize(s));
 }
 
-__global__ void k_ns_features(NFArgs a, int64_t n, CheapRule R, float *__restrict__ feat, double *__restrict__ cheap)
+__global__ void k_ns_features(NFArgs a, int64_t base, int64_t n, CheapRule R, float *__restrict__ feat,
+                              double *__restrict__ cheap)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t pos = a.work_cap - 1 - i;
+    const int64_t pos = base + i;
     const int32_t k = a.work_meta[2 * pos], l = a.work_meta[2 * pos + 1];
     double tv[9], sv[9];
     for (int q = 0; q < 9; ++q) {
@@ -530,12 +531,12 @@ __global__ void k_ns_features(NFArgs a, int64_t n, CheapRule R, float *__restric
     cheap[i] = cheap_value(tv, sv, R);
 }
 
-void ns_features(const NFArgs &a, int64_t n, float *feat, double *cheap, hipStream_t s)
+void ns_features(const NFArgs &a, int64_t base, int64_t n, float *feat, double *cheap, hipStream_t s)
 {
     if (n == 0) return;
     CheapRule R;
     gauss_legendre01(3, R.x, R.w);
-    k_ns_features<<<cdiv(n, 128), 128, 0, s>>>(a, n, R, feat, cheap);
+    k_ns_features<<<cdiv(n, 128), 128, 0, s>>>(a, base, n, R, feat, cheap);
     XRL_HIP(hipGetLastError());
 }
 

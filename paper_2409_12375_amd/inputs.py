@@ -126,6 +126,21 @@ def bar(nx=4, ny=4, nz=126, size=(1.0, 1.0, 20.0), jitter=0.05, seed=GEOM_SEED):
 # --------------------------------------------------------------------------
 # icosphere
 # --------------------------------------------------------------------------
+def torus(n_major=24, n_minor=12, R=1.0, r=0.35):
+    """Closed genus-1 surface (a ring conductor): quads of a torus split in
+    two, consistently oriented."""
+    i, j = np.meshgrid(np.arange(n_major), np.arange(n_minor), indexing="ij")
+    u = 2 * np.pi * i / n_major
+    v = 2 * np.pi * j / n_minor
+    V = np.stack([(R + r * np.cos(v)) * np.cos(u), (R + r * np.cos(v)) * np.sin(u), r * np.sin(v)], -1).reshape(-1, 3)
+    a = (i * n_minor + j).ravel()
+    b = (((i + 1) % n_major) * n_minor + j).ravel()
+    c = (((i + 1) % n_major) * n_minor + (j + 1) % n_minor).ravel()
+    d = (i * n_minor + (j + 1) % n_minor).ravel()
+    T = np.concatenate([np.stack([a, b, c], 1), np.stack([a, c, d], 1)]).astype(np.int32)
+    return V, T
+
+
 def icosphere(level, radius=1.0, center=(0.0, 0.0, 0.0)):
     """Regular icosahedron, each face split into 4 `level` times, vertices
     projected onto the sphere.  N = 20 * 4**level."""

@@ -85,6 +85,11 @@ class MlpTrainOpts(ctypes.Structure):
                 ("log_sigma", ctypes.c_float), ("target_scale", ctypes.c_float), ("seed", ctypes.c_uint64)]
 
 
+class LoopsInfo(ctypes.Structure):
+    _fields_ = [("n_panels", _i64), ("n_edges", _i64), ("n_loops", _i64), ("n_vertex_loops", _i64),
+                ("n_global_loops", _i64), ("n_components", _i64), ("nnz_loop_matrix", _i64)]
+
+
 class GmresStats(ctypes.Structure):
     _fields_ = [("iterations", _i32), ("restarts", _i32), ("converged", _i32),
                 ("max_rel_residual", ctypes.c_double)]
@@ -125,6 +130,15 @@ def lib():
         L.xrl_selftest_mfma_bf16.argtypes = [_vp, _vp, _vp]
         L.xrl_gmres_solve.argtypes = [_vp, ctypes.POINTER(Epilogue), _vp, _vp, _i32, _i32, _i32, ctypes.c_double,
                                       _i32, _vp, ctypes.POINTER(GmresStats)]
+        L.xrl_loops_build.argtypes = [ctypes.POINTER(MeshDesc), _vp, ctypes.POINTER(_vp)]
+        L.xrl_loops_destroy.argtypes = [_vp]
+        L.xrl_loops_destroy.restype = None
+        L.xrl_loops_get_info.argtypes = [_vp, ctypes.POINTER(LoopsInfo)]
+        L.xrl_loops_export.argtypes = [_vp, _i32, _vp, ctypes.POINTER(_i64)]
+        L.xrl_surface_impedance.argtypes = [ctypes.c_double, ctypes.c_double, _vp, _i32, _vp]
+        L.xrl_edge_matvec.argtypes = [_vp, _vp, ctypes.POINTER(Epilogue), _vp, _vp, _i32, _vp]
+        L.xrl_loop_gmres_solve.argtypes = [_vp, _vp, ctypes.POINTER(Epilogue), _vp, _vp, _i32, _i32, _i32,
+                                           ctypes.c_double, _i32, _vp, ctypes.POINTER(GmresStats)]
         _lib = L
     return _lib
 
@@ -396,3 +410,96 @@ class Surrogate:
             o += size
         s = Mlp(H, *ptrs, self.feat_lo.ctypes.data, self.feat_hi.ctypes.data, self.bound)
         return (s, self)  # keep the arrays alive with the struct
+
+
+# ---------------------------------------------------------------------------
+# Loop analysis (PEEC graph, Algorithm 1 maps, loop basis, eq. (8) solve)
+# ---------------------------------------------------------------------------
+PRECOND = {"none": 0, "diag_p": 1, "diag_l": 2}
+
+
+def _epilogue_arrays(alpha, beta, R):
+    ep = Epilogue()
+    keep = []
+    for name, v in (("alpha", alpha), ("beta", beta)):
+        if v is None:
+            continue
+        a = np.empty(2 * R)
+        vv = np.broadcast_to(np.asarray(v, dtype=np.complex128), (R,))
+        a[0::2] = vv.real
+        a[1::2] = vv.imag
+        keep.append(a)
+        setattr(ep, name, a.ctypes.data)
+    return ep, keep
+
+
+def surface_impedance(freq, sigma, thickness):
+    """Z_s of eq. (3) at the given frequencies (host)."""
+    f = np.ascontiguousarray(np.atleast_1d(freq), dtype=np.float64)
+    out = np.zeros(2 * len(f))
+    _check(lib().xrl_surface_impedance(sigma, thickness, _vp(f.ctypes.data), len(f), _vp(out.ctypes.data)))
+    return out[0::2] + 1j * out[1::2]
+
+
+class Loops:
+    """Loop analysis of a closed mesh (xrl_loops_build)."""
+
+    def __init__(self, V, T, stream=None):
+        self._V = np.ascontiguousarray(V, dtype=np.float64)
+        self._T = np.ascontiguousarray(T, dtype=np.int32)
+        d = MeshDesc(self._V.shape[0], self._T.shape[0], self._V.ctypes.data, self._T.ctypes.data, 0)
+        h = _vp()
+        _check(lib().xrl_loops_build(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def info(self):
+        i = LoopsInfo()
+        _check(lib().xrl_loops_get_info(self.h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in LoopsInfo._fields_}
+
+    def export(self, item):
+        n = _i64(0)
+        _check(lib().xrl_loops_export(self.h, item, None, ctypes.byref(n)))
+        out = np.zeros(n.value // 4, dtype=np.int32)
+        _check(lib().xrl_loops_export(self.h, item, _vp(out.ctypes.data), ctypes.byref(n)))
+        return out
+
+    def edge_matvec(self, plan, i_edge, alpha=None, beta=None, stream=None):
+        """V_edge = sum_t A_t (beta area + alpha P) A_t^T I_edge, complex128 [N_e][R]."""
+        import torch
+        X = i_edge.reshape(i_edge.shape[0], -1).to(torch.complex128).contiguous()
+        R = X.shape[1]
+        Y = torch.empty_like(X)
+        ep, keep = _epilogue_arrays(alpha, beta, R)
+        _check(lib().xrl_edge_matvec(self.h, plan.h, ctypes.byref(ep), _vp(X.data_ptr()), _vp(Y.data_ptr()), R,
+                                     _stream(stream)))
+        return Y
+
+    def solve(self, plan, v_edge, alpha=None, beta=None, precond="none", restart=50, rtol=1e-6, max_iter=500,
+              stream=None):
+        """Branch currents of eq. (8) for branch voltages v_edge (complex128
+        [N_e][R]); returns (i_edge, stats)."""
+        import torch
+        B = v_edge.reshape(v_edge.shape[0], -1).to(torch.complex128).contiguous()
+        R = B.shape[1]
+        X = torch.empty_like(B)
+        ep, keep = _epilogue_arrays(alpha, beta, R)
+        st = GmresStats()
+        code = lib().xrl_loop_gmres_solve(self.h, plan.h, ctypes.byref(ep), _vp(B.data_ptr()), _vp(X.data_ptr()), R,
+                                          PRECOND[precond], restart, rtol, max_iter, _stream(stream), ctypes.byref(st))
+        stats = {f: getattr(st, f) for f, _ in GmresStats._fields_}
+        if code not in (0, -5):
+            _check(code)
+        stats["status"] = code
+        return X, stats
+
+    def close(self):
+        if self.h:
+            lib().xrl_loops_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -156,7 +156,9 @@ def test_assembly_with_surrogate_matches_oracle(small_model):
     st = plan.assemble(surrogate=sur, audit_every=10)
     say("  stats", {k: st[k] for k in ("n_near_singular", "n_mlp_accepted", "n_mlp_fallback",
                                          "audit_max_rel_err", "audit_rms_rel_err")})
-    assert st["n_mlp_accepted"] + st["n_mlp_fallback"] == st["n_near_singular"]
+    # the network is evaluated on the near-singular pairs of rule class 0
+    # (r >= 1.5); closer pairs go to quadrature directly
+    assert 0 < st["n_mlp_accepted"] + st["n_mlp_fallback"] <= st["n_near_singular"]
     y = plan.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
     rows = np.sort(np.random.default_rng(1).choice(N, 300, replace=False))
     ref, _ = O.matvec(V, T, x.astype(np.complex128), rows=rows)
