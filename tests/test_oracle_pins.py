@@ -215,6 +215,39 @@ def test_touching_pair_vs_independent_quadrature():
     assert O.entry(V, T, 0, 1) == pytest.approx(total, rel=2e-6)
 
 
+@pytest.mark.parametrize("shift,level", [((0.55, 0.35, 0.25), 2), ((1.05, 0.6, 0.3), 1)])
+def test_near_singular_subdivided_rule_vs_independent_quadrature(shift, level):
+    """Non-touching pairs at r < 2 (the oracle's 4 and 16 sub-triangle
+    levels): outer rule of a different family (collapsed-square tensor
+    Gauss, 10 x 10 points on each of 16 sub-triangles from a barycentric
+    split), inner potential by the polar-angle integration above."""
+    tk = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.3, 0.85, 0.0]])
+    tl = np.array([[0.0, 0.0, 0.0], [0.8, 0.1, 0.2], [0.2, 0.7, -0.3]]) + np.array(shift)
+    V = np.vstack([tk, tl])
+    T = np.array([[0, 1, 2], [3, 4, 5]], dtype=np.int32)
+    area, cen, _, diam = O.panel_geometry(V, T)
+    r = np.linalg.norm(cen[0] - cen[1]) / diam.max()
+    assert (r < 0.75) if level == 2 else (0.75 <= r < 1.5)
+    xg, wg = np.polynomial.legendre.leggauss(10)
+    xg, wg = 0.5 * (xg + 1), 0.5 * wg
+    total = 0.0
+    n = 4  # the target split into n^2 = 16 triangles along its barycentric grid
+    for i in range(n):
+        for j in range(n - i):
+            cells = [((i, j), (i + 1, j), (i, j + 1))]
+            if i + j < n - 1:
+                cells.append(((i + 1, j), (i + 1, j + 1), (i, j + 1)))
+            for c in cells:
+                P = [tk[0] + (a / n) * (tk[1] - tk[0]) + (b / n) * (tk[2] - tk[0]) for a, b in c]
+                a2 = np.linalg.norm(np.cross(P[1] - P[0], P[2] - P[0]))
+                for iu in range(10):
+                    for it in range(10):
+                        u, t_ = xg[iu], xg[it]
+                        x = P[0] + u * (P[1] - P[0]) + u * t_ * (P[2] - P[1])
+                        total += wg[iu] * wg[it] * u * a2 * _polar_potential(tl, x)
+    assert O.entry(V, T, 0, 1) == pytest.approx(total, rel=1e-9)
+
+
 def test_near_and_far_rules_agree_at_class_boundary():
     # r = |c_k - c_l| / max diam just above 4: the far product rule and the
     # semi-analytic rule must agree far below the 1e-4 gate
