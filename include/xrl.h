@@ -25,8 +25,9 @@
  *    Work is enqueued on it; functions that must read results back to the host
  *    synchronise that stream before returning.
  *  - Handles are opaque and owned by the library; each create has a matching
- *    destroy.  Device memory for handles is allocated with hipMalloc by the
- *    library.  Caller buffers (x, y, b) are never freed by the library.
+ *    destroy.  Device memory for handles and temporaries comes from the
+ *    allocator installed with xrl_set_allocator (hipMalloc/hipFree when none
+ *    is).  Caller buffers (x, y, b) are never freed by the library.
  *  - On error the outputs are unspecified and the handles stay valid.
  *    Asynchronous kernel faults surface as XRL_E_HIP at the next call that
  *    synchronises.
@@ -34,6 +35,7 @@
 #ifndef XRL_H
 #define XRL_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -49,6 +51,26 @@ typedef int32_t xrl_status;
 #define XRL_E_NOT_CONVERGED (-5)    /* GMRES stopped before reaching rtol */
 #define XRL_E_UNSUPPORTED (-6)      /* option combination not implemented */
 #define XRL_E_STATE (-7)            /* call out of order (e.g. matvec before assemble) */
+
+/* Device-memory hand-off.  alloc returns `bytes` of device memory on the
+ * current device (256-byte aligned), or NULL when it cannot; `stream` is the
+ * stream of the library call that needs the memory (the buffer is first used
+ * in stream order on it).  free releases a pointer alloc returned; the library
+ * waits for the device to finish every use of the buffer before it calls free.
+ * ctx is passed through.  The hooks may be called from any library entry point
+ * except xrl_fmm_matvec_noalloc, which allocates nothing. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} xrl_allocator;
+
+/* Install `a` (copied) for every later device allocation of the library, in
+ * every thread; NULL restores hipMalloc/hipFree.  A buffer is always released
+ * through the allocator that made it, also after the allocator is changed, so
+ * the hooks and ctx must stay valid until every handle created while they
+ * were installed is destroyed.  Errors: XRL_E_INVALID_ARG (one hook NULL). */
+xrl_status xrl_set_allocator(const xrl_allocator *a);
 
 /* Data types of densities and potentials (complex, interleaved re/im). */
 #define XRL_C64 1  /* complex64: pairs of float  */

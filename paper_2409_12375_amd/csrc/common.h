@@ -55,22 +55,47 @@ xrl_status guarded(F &&body)
     }
 }
 
+// Device allocation: through the installed xrl_allocator if any (the
+// stream of the current entry point is passed on), else hipMalloc/hipFree.
+// A buffer remembers the allocator that made it and is released through it,
+// after the device has finished with it (hipFree waits the same way).
+struct AllocSrc {
+    void (*free)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+void *dev_alloc(size_t bytes, AllocSrc &src);
+void dev_free(void *p, const AllocSrc &src);
+
+// The stream handed to the allocator for allocations made in this thread
+// while an entry point runs (set for the entry point's duration).
+struct AllocStream {
+    hipStream_t prev;
+    explicit AllocStream(hipStream_t s);
+    ~AllocStream();
+};
+
 // Owning device buffer.
 template <class T>
 struct DevBuf {
     T *p = nullptr;
     size_t n = 0;
+    AllocSrc src;
     DevBuf() = default;
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n), src(o.src)
+    {
+        o.p = nullptr;
+        o.n = 0;
+    }
     DevBuf &operator=(DevBuf &&o) noexcept
     {
         if (this != &o) {
             release();
             p = o.p;
             n = o.n;
+            src = o.src;
             o.p = nullptr;
             o.n = 0;
         }
@@ -80,12 +105,12 @@ struct DevBuf {
     void alloc(size_t count)
     {
         release();
+        if (count) p = (T *)dev_alloc(count * sizeof(T), src);
         n = count;
-        if (count) XRL_HIP(hipMalloc((void **)&p, count * sizeof(T)));
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) dev_free(p, src);
         p = nullptr;
         n = 0;
     }

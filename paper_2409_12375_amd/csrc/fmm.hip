@@ -2422,6 +2422,7 @@ extern "C" xrl_status xrl_fmm_matvec(const xrl_plan *P, const void *x, int64_t l
         XRL_CHECK(dtype == XRL_C64 || dtype == XRL_C128, XRL_E_INVALID_ARG, "xrl_fmm_matvec: bad dtype %d", dtype);
         XRL_CHECK(x != y, XRL_E_INVALID_ARG, "xrl_fmm_matvec: x and y must not alias");
         hipStream_t s = (hipStream_t)stream;
+        const AllocStream alloc_scope(s);
         xrl_plan *Pm = const_cast<xrl_plan *>(P);
         if (Pm->profiling) {
             auto &ring = Pm->prof_ev;
@@ -2552,6 +2553,7 @@ xrl_status xrl_matvec_eager(const xrl_plan *P, const void *x, int64_t ldx, int32
         XRL_CHECK(P && x && y && P->assembled && n_cols >= 1 && n_cols <= P->max_cols, XRL_E_INVALID_ARG,
                   "gmres matvec: bad arguments");
         hipStream_t s = (hipStream_t)stream;
+        const AllocStream alloc_scope(s);
         const double *al = ep ? ep->alpha : nullptr, *be = ep ? ep->beta : nullptr;
         upload_epilogue(P, n_cols, al, be, s);
         enqueue_matvec(P, x, ldx, n_cols, dtype, y, ldy, al != nullptr, be != nullptr, s, false);
@@ -2582,6 +2584,7 @@ extern "C" xrl_status xrl_plan_autotune(xrl_plan *P, const void *x, int64_t ldx,
                       (dtype == XRL_C64 || dtype == XRL_C128) && x != y,
                   XRL_E_INVALID_ARG, "xrl_plan_autotune: bad matvec arguments");
         hipStream_t s = (hipStream_t)stream;
+        const AllocStream alloc_scope(s);
         *res = xrl_tune_result{};
         struct Cand {
             int engine, ts_kernel;

@@ -283,6 +283,7 @@ extern "C" xrl_status xrl_gmres_solve(const xrl_plan *P, const xrl_epilogue *op,
         XRL_CHECK(n_rhs <= P->max_cols, XRL_E_INVALID_ARG, "xrl_gmres_solve: n_rhs > plan max_cols");
         XRL_CHECK(P->assembled, XRL_E_STATE, "xrl_gmres_solve: call xrl_nearfield_assemble first");
         hipStream_t s = (hipStream_t)stream;
+        const AllocStream alloc_scope(s);
         const int64_t N = P->N, R = n_rhs, NR2 = 2 * N * R;
         const xrl_epilogue ep = op ? *op : xrl_epilogue{nullptr, nullptr};
         // complex64 right-hand sides and solutions are widened to complex128

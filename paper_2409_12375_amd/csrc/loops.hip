@@ -501,6 +501,7 @@ extern "C" xrl_status xrl_loops_build(const xrl_mesh_desc *mesh, void *stream, x
                   XRL_E_INVALID_ARG, "xrl_loops_build: bad sizes");
         *out = nullptr;
         hipStream_t s = (hipStream_t)stream;
+        const AllocStream alloc_scope(s);
         auto L = std::make_unique<xrl_loops>();
         L->Np = mesh->n_panels;
         L->nv = mesh->n_vertices;
@@ -687,6 +688,7 @@ extern "C" xrl_status xrl_edge_matvec(const xrl_loops *L, const xrl_plan *P, con
     return guarded([&] {
         check_pair(L, P, n_cols, "xrl_edge_matvec");
         XRL_CHECK(i_edge && v_edge && i_edge != v_edge, XRL_E_INVALID_ARG, "xrl_edge_matvec: bad buffers");
+        const AllocStream alloc_scope((hipStream_t)stream);
         EdgeOp E{L, P, n_cols, (hipStream_t)stream};
         E.init(op);
         E.apply((const double *)i_edge, (double *)v_edge);
@@ -706,6 +708,7 @@ extern "C" xrl_status xrl_loop_gmres_solve(const xrl_loops *L, const xrl_plan *P
                       precond <= 2,
                   XRL_E_INVALID_ARG, "xrl_loop_gmres_solve: bad arguments");
         hipStream_t s = (hipStream_t)stream;
+        const AllocStream alloc_scope(s);
         const int R = n_rhs;
         const int64_t Nl = L->Nl, Ne = L->Ne;
         EdgeOp E{L, P, R, s};

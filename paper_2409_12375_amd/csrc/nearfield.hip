@@ -706,6 +706,7 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
     return guarded([&] {
         XRL_CHECK(P, XRL_E_INVALID_ARG, "xrl_nearfield_assemble: null plan");
         hipStream_t s = (hipStream_t)stream;
+        const AllocStream alloc_scope(s);
         xrl_nf_opts o{2.0, 6.0, nullptr, 0};
         if (opts) o = *opts;
         XRL_CHECK(o.r_near > 0 && o.r_mid >= o.r_near, XRL_E_INVALID_ARG,

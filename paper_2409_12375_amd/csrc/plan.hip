@@ -847,6 +847,7 @@ extern "C" xrl_status xrl_fmm_plan(xrl_tree *const *trees, int32_t n_trees, cons
         P->max_cols = opts->max_cols;
         P->theta = opts->theta == 0.0 ? XRL_DEFAULT_THETA : opts->theta;
         P->trees.assign(trees, trees + n_trees);
+        const AllocStream alloc_scope((hipStream_t)stream);
         build_plan(P.get(), (hipStream_t)stream);
         *out = P.release();
     });

@@ -367,17 +367,21 @@ template <int H>
 __global__ __launch_bounds__(256) void k_mlp_infer(MlpBf16 w, const float *__restrict__ X, int64_t n,
                                                    float *__restrict__ out)
 {
+    // LDS rows padded so that the 16 rows a wave reads at once start in
+    // different banks: W1 rows 40 shorts (20 words apart), W2, W3 and the
+    // hidden layer H + 8 shorts (H/2 + 4 words apart)
+    constexpr int S1 = 40, SH = H + 8;
     extern __shared__ unsigned char smem_raw[];
-    short *sw1 = reinterpret_cast<short *>(smem_raw);  // [H][32]
-    short *sw2 = sw1 + H * 32;                          // [H][H]
-    short *sw3 = sw2 + H * H;                           // [16][H]
-    short *sh = sw3 + 16 * H;                           // per wave [16][H]
-    for (int i = threadIdx.x; i < H * 32; i += 256) sw1[i] = w.w1[i];
-    for (int i = threadIdx.x; i < H * H; i += 256) sw2[i] = w.w2[i];
-    for (int i = threadIdx.x; i < 16 * H; i += 256) sw3[i] = w.w3[i];
+    short *sw1 = reinterpret_cast<short *>(smem_raw);  // [H][S1]
+    short *sw2 = sw1 + H * S1;                          // [H][SH]
+    short *sw3 = sw2 + H * SH;                          // [16][SH]
+    short *sh = sw3 + 16 * SH;                          // per wave [16][SH]
+    for (int i = threadIdx.x; i < H * 32; i += 256) sw1[(i / 32) * S1 + i % 32] = w.w1[i];
+    for (int i = threadIdx.x; i < H * H; i += 256) sw2[(i / H) * SH + i % H] = w.w2[i];
+    for (int i = threadIdx.x; i < 16 * H; i += 256) sw3[(i / H) * SH + i % H] = w.w3[i];
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, kq = lane >> 4;
-    short *hbuf = sh + wave * 16 * H;
+    short *hbuf = sh + wave * 16 * SH;
     const int64_t nchunks = (n + 15) / 16;
     // SiLU on the hardware exponential and reciprocal: its result is rounded
     // to BF16 at once, far coarser than their error
@@ -401,12 +405,12 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpBf16 w, const float *__res
         for (int ct = 0; ct < H / 16; ++ct) {
             f32x4 d = {0, 0, 0, 0};
             for (int ks = 0; ks < 2; ++ks) {
-                const s16x4 b = *reinterpret_cast<const s16x4 *>(sw1 + (16 * ct + li) * 32 + 16 * ks + 4 * kq);
+                const s16x4 b = *reinterpret_cast<const s16x4 *>(sw1 + (16 * ct + li) * S1 + 16 * ks + 4 * kq);
                 d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ax[ks], b, d, 0, 0, 0);
             }
             for (int e = 0; e < 4; ++e) {
                 const int r = 4 * kq + e, c = 16 * ct + li;
-                hbuf[r * H + c] = silu_bf(d[e] + w.b1[c]);
+                hbuf[r * SH + c] = silu_bf(d[e] + w.b1[c]);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -416,9 +420,9 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpBf16 w, const float *__res
         f32x4 d2[H / 16];
         for (int ct = 0; ct < H / 16; ++ct) d2[ct] = f32x4{0, 0, 0, 0};
         for (int ks = 0; ks < H / 16; ++ks) {
-            const s16x4 a = *reinterpret_cast<const s16x4 *>(hbuf + li * H + 16 * ks + 4 * kq);
+            const s16x4 a = *reinterpret_cast<const s16x4 *>(hbuf + li * SH + 16 * ks + 4 * kq);
             for (int ct = 0; ct < H / 16; ++ct) {
-                const s16x4 b = *reinterpret_cast<const s16x4 *>(sw2 + (16 * ct + li) * H + 16 * ks + 4 * kq);
+                const s16x4 b = *reinterpret_cast<const s16x4 *>(sw2 + (16 * ct + li) * SH + 16 * ks + 4 * kq);
                 d2[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, d2[ct], 0, 0, 0);
             }
         }
@@ -428,7 +432,7 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpBf16 w, const float *__res
         for (int ct = 0; ct < H / 16; ++ct)
             for (int e = 0; e < 4; ++e) {
                 const int r = 4 * kq + e, c = 16 * ct + li;
-                hbuf[r * H + c] = silu_bf(d2[ct][e] + w.b2[c]);
+                hbuf[r * SH + c] = silu_bf(d2[ct][e] + w.b2[c]);
             }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -436,8 +440,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpBf16 w, const float *__res
         // layer 3 (2 outputs, rows of W3 padded to 16)
         f32x4 d3 = {0, 0, 0, 0};
         for (int ks = 0; ks < H / 16; ++ks) {
-            const s16x4 a = *reinterpret_cast<const s16x4 *>(hbuf + li * H + 16 * ks + 4 * kq);
-            const s16x4 b = *reinterpret_cast<const s16x4 *>(sw3 + li * H + 16 * ks + 4 * kq);
+            const s16x4 a = *reinterpret_cast<const s16x4 *>(hbuf + li * SH + 16 * ks + 4 * kq);
+            const s16x4 b = *reinterpret_cast<const s16x4 *>(sw3 + li * SH + 16 * ks + 4 * kq);
             d3 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, d3, 0, 0, 0);
         }
         if (active && li < 2)
@@ -485,7 +489,7 @@ void mlp_infer(const MlpDevice &m, const float *X, int64_t n, float *out, hipStr
 {
     XRL_CHECK(m.H == 128 || m.H == 64, XRL_E_UNSUPPORTED, "surrogate: hidden width must be 64 or 128");
     if (n == 0) return;
-    const size_t sm = (size_t)(m.H * 32 + m.H * m.H + 16 * m.H + 4 * 16 * m.H) * sizeof(short);
+    const size_t sm = (size_t)(m.H * 40 + (m.H + 16 + 4 * 16) * (m.H + 8)) * sizeof(short);
     const unsigned grid = (unsigned)std::min<int64_t>(cdiv(cdiv(n, 16), 4), 4096);
     if (m.H == 128)
         k_mlp_infer<128><<<grid, 256, sm, s>>>(bf16_view(m), X, n, out);
@@ -591,6 +595,7 @@ extern "C" xrl_status xrl_mlp_loss_grad(const float *w, int32_t hidden, const fl
         XRL_CHECK(w && X && t && n >= 1 && hidden >= 1 && loss_args && loss && grad, XRL_E_INVALID_ARG,
                   "xrl_mlp_loss_grad: bad arguments");
         hipStream_t s = (hipStream_t)stream;
+        const AllocStream alloc_scope(s);
         MlpWork k;
         k.ensure(n, hidden);
         MlpView wv = mlp_view(const_cast<float *>(w), hidden), gv = mlp_view(grad, hidden);
@@ -614,6 +619,7 @@ extern "C" xrl_status xrl_mlp_forward(const float *w, int32_t hidden, const floa
     return guarded([&] {
         XRL_CHECK(w && X && out && n >= 0 && hidden >= 1, XRL_E_INVALID_ARG, "xrl_mlp_forward: bad arguments");
         hipStream_t s = (hipStream_t)stream;
+        const AllocStream alloc_scope(s);
         if (n == 0) return;
         if (bf16) {
             MlpDevice m;
@@ -638,6 +644,7 @@ extern "C" xrl_status xrl_mlp_train(const float *X, const float *t, int64_t n, c
         XRL_CHECK(X && t && o && w && n >= 1 && o->hidden >= 1 && o->batch >= 1 && o->epochs >= 1, XRL_E_INVALID_ARG,
                   "xrl_mlp_train: bad arguments");
         hipStream_t s = (hipStream_t)stream;
+        const AllocStream alloc_scope(s);
         const int H = o->hidden;
         const int64_t B = std::min<int64_t>(o->batch, n);
         const int64_t P = mlp_size(H);

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstring>
 #include <memory>
+#include <mutex>
 
 #include "common.h"
 
@@ -33,6 +34,48 @@ void fail(xrl_status code, const char *fmt, ...)
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     throw Error{code, std::string(buf)};
+}
+
+// ------------------------------------------------------------------ device memory
+static std::mutex g_alloc_mu;
+static xrl_allocator g_alloc{};  // hooks NULL: hipMalloc / hipFree
+static thread_local hipStream_t t_alloc_stream = nullptr;
+
+AllocStream::AllocStream(hipStream_t s) : prev(t_alloc_stream) { t_alloc_stream = s; }
+AllocStream::~AllocStream() { t_alloc_stream = prev; }
+
+void *dev_alloc(size_t bytes, AllocSrc &src)
+{
+    xrl_allocator a;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        a = g_alloc;
+    }
+    void *p = nullptr;
+    if (a.alloc) {
+        p = a.alloc(bytes, (void *)t_alloc_stream, a.ctx);
+        XRL_CHECK(p, XRL_E_OOM, "device allocation of %zu bytes refused by the installed allocator", bytes);
+        XRL_CHECK(((uintptr_t)p & 255) == 0, XRL_E_INVALID_ARG,
+                  "the installed allocator returned a pointer not aligned to 256 bytes");
+        src.free = a.free;
+        src.ctx = a.ctx;
+    } else {
+        XRL_HIP(hipMalloc(&p, bytes));
+        src = AllocSrc{};
+    }
+    return p;
+}
+
+void dev_free(void *p, const AllocSrc &src)
+{
+    if (src.free) {
+        // every use of the buffer is enqueued before its release; wait for
+        // them, as hipFree does, before the allocator may hand it out again
+        (void)hipDeviceSynchronize();
+        src.free(p, src.ctx);
+    } else {
+        (void)hipFree(p);
+    }
 }
 
 // Per panel (input order): vertices, centroid, area, longest edge; error
@@ -214,6 +257,7 @@ extern "C" xrl_status xrl_tree_build(const xrl_mesh_desc *mesh, int32_t max_leaf
         XRL_CHECK(max_depth >= 1 && max_depth <= kMaxDepth, XRL_E_INVALID_ARG,
                   "xrl_tree_build: max_depth must be in 1..21 (got %d)", max_depth);
         hipStream_t s = (hipStream_t)stream;
+        const AllocStream alloc_scope(s);
         const int64_t N = mesh->n_panels, nv = mesh->n_vertices;
         auto t = std::make_unique<xrl_tree>();
         t->N = N;
@@ -365,5 +409,14 @@ extern "C" xrl_status xrl_tree_get_info(const xrl_tree *t, xrl_tree_info *info)
         info->n_overfull_leaves = t->n_overfull;
         for (int d = 0; d < 3; ++d) info->root_center[d] = t->root_c[d];
         info->root_size = t->root_size;
+    });
+}
+
+extern "C" xrl_status xrl_set_allocator(const xrl_allocator *a)
+{
+    return xrl::guarded([&] {
+        if (a) XRL_CHECK(a->alloc && a->free, XRL_E_INVALID_ARG, "xrl_set_allocator: both hooks are required");
+        std::lock_guard<std::mutex> lk(xrl::g_alloc_mu);
+        xrl::g_alloc = a ? *a : xrl_allocator{};
     });
 }

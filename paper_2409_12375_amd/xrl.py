@@ -90,6 +90,14 @@ class LoopsInfo(ctypes.Structure):
                 ("n_global_loops", _i64), ("n_components", _i64), ("nnz_loop_matrix", _i64)]
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(_vp, ctypes.c_size_t, _vp, _vp)
+_FREE_FN = ctypes.CFUNCTYPE(None, _vp, _vp)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", _vp)]
+
+
 class GmresStats(ctypes.Structure):
     _fields_ = [("iterations", _i32), ("restarts", _i32), ("converged", _i32),
                 ("max_rel_residual", ctypes.c_double)]
@@ -116,6 +124,7 @@ def lib():
         L.xrl_nearfield_assemble.argtypes = [_vp, ctypes.POINTER(NfOpts), _vp, ctypes.POINTER(NfStats)]
         L.xrl_fmm_matvec.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _i64, ctypes.POINTER(Epilogue), _vp]
         L.xrl_fmm_matvec_noalloc.argtypes = [_vp, _vp, _i64, _i32, _i32, _vp, _i64, ctypes.POINTER(Epilogue), _vp]
+        L.xrl_set_allocator.argtypes = [ctypes.POINTER(Allocator)]
         L.xrl_plan_set_profiling.argtypes = [_vp, _i32]
         L.xrl_plan_get_phase_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
         L.xrl_plan_set_tuning.argtypes = [_vp, _i32, _i32]
@@ -155,6 +164,38 @@ def _stream(stream):
     if isinstance(stream, int):
         return _vp(stream)
     return _vp(stream.cuda_stream)
+
+
+_allocator = None  # the installed hooks (kept alive while installed)
+
+
+def use_torch_allocator(on=True):
+    """Route every device allocation of the library through torch's caching
+    allocator (xrl_set_allocator), on the stream of the library call that
+    allocates; on=False restores hipMalloc/hipFree for later allocations.
+    Buffers made while torch's hooks were installed are still released
+    through them, so the hooks stay referenced here for the process."""
+    global _allocator
+    if not on:
+        _check(lib().xrl_set_allocator(None))
+        return
+    if _allocator is None:
+        import torch
+
+        def _alloc(nbytes, stream, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+            except Exception:  # reported by the library as XRL_E_OOM
+                return None
+
+        def _free(ptr, ctx):
+            try:
+                torch.cuda.caching_allocator_delete(int(ptr))
+            except Exception:  # interpreter shutdown: the caching allocator is gone
+                pass
+
+        _allocator = Allocator(_ALLOC_FN(_alloc), _FREE_FN(_free), None)
+    _check(lib().xrl_set_allocator(ctypes.byref(_allocator)))
 
 
 class Tree:

@@ -54,6 +54,18 @@ def test_argument_errors_need_no_gpu(lib):
                                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                                            ctypes.c_void_p]
     assert lib.xrl_fmm_matvec(None, None, 1, 1, 1, None, 1, None, None) == -1
+    # the allocator hand-off: both hooks or none
+    alloc_t = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+    free_t = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+    class Allocator(ctypes.Structure):
+        _fields_ = [("alloc", alloc_t), ("free", free_t), ("ctx", ctypes.c_void_p)]
+
+    lib.xrl_set_allocator.argtypes = [ctypes.POINTER(Allocator)]
+    half = Allocator(alloc_t(lambda n, s, c: None), free_t(), None)
+    assert lib.xrl_set_allocator(ctypes.byref(half)) == -1
+    assert b"hooks" in lib.xrl_last_error()
+    assert lib.xrl_set_allocator(None) == 0
 
 
 def _reflection_signs(p):
