@@ -20,6 +20,10 @@ What it computes, from the paper (arXiv 2409.12375):
     basis M spans the null space of D: here M is replaced by an orthonormal
     basis Q of that null space (numpy SVD), so the reference needs no loop
     search of its own.
+Panels are triangles ([N][3]) or, on hybrid meshes (Sec. II-A, Fig. 1),
+triangles and four-sided panels ([N][4], a negative fourth index marks a
+triangle); Algorithm 1 is the same for both, with c_p the area centroid of
+panel p and one branch per side.
 Dense numpy, small meshes only.
 """
 import numpy as np
@@ -34,9 +38,10 @@ def mesh_edges(T):
     edge belongs to exactly two panels."""
     T = np.asarray(T)
     owner = {}
-    for p, tri in enumerate(T.tolist()):
-        for a in range(3):
-            u, v = tri[a], tri[(a + 1) % 3]
+    for p, poly in enumerate(T.tolist()):
+        poly = [v for v in poly if v >= 0]
+        for a in range(len(poly)):
+            u, v = poly[a], poly[(a + 1) % len(poly)]
             owner.setdefault((min(u, v), max(u, v)), []).append(p)
     keys = sorted(owner)
     pairs, verts = [], []
@@ -49,11 +54,31 @@ def mesh_edges(T):
     return np.array(pairs, dtype=np.int64), np.array(verts, dtype=np.int64)
 
 
+def centroids(V, T):
+    """Area centroid of every panel: the vertex mean of a triangle; for a
+    four-sided panel (a, b, c, d) the area-weighted mean of the centroids of
+    its triangles (a, b, c) and (a, c, d)."""
+    V = np.asarray(V, dtype=np.float64)
+    T = np.asarray(T)
+    if T.shape[1] == 3:
+        return V[T].mean(axis=1)
+    c = np.empty((len(T), 3))
+    for p, q in enumerate(T.tolist()):
+        if q[3] < 0:
+            c[p] = V[q[:3]].mean(axis=0)
+            continue
+        t1, t2 = V[[q[0], q[1], q[2]]], V[[q[0], q[2], q[3]]]
+        a1 = 0.5 * np.linalg.norm(np.cross(t1[1] - t1[0], t1[2] - t1[0]))
+        a2 = 0.5 * np.linalg.norm(np.cross(t2[1] - t2[0], t2[2] - t2[0]))
+        c[p] = (a1 * t1.mean(axis=0) + a2 * t2.mean(axis=0)) / (a1 + a2)
+    return c
+
+
 def cm_maps(V, T, pairs, verts):
     """A_1, A_2, A_3 of Algorithm 1 as dense [3][N_e][N_p] arrays."""
     V = np.asarray(V, dtype=np.float64)
     T = np.asarray(T)
-    c = V[T].mean(axis=1)
+    c = centroids(V, T)
     m = 0.5 * (V[verts[:, 0]] + V[verts[:, 1]])
     Ne, Np = len(pairs), len(T)
     A = np.zeros((3, Ne, Np))

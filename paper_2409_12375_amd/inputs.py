@@ -58,6 +58,15 @@ def _grid_tris(idx, flip=False):
     return np.concatenate([t1, t2])
 
 
+def _grid_quads(idx, flip=False):
+    """Every cell of an index grid idx[i][j] as one four-sided panel."""
+    a = idx[:-1, :-1].ravel()
+    b = idx[1:, :-1].ravel()
+    c = idx[1:, 1:].ravel()
+    d = idx[:-1, 1:].ravel()
+    return np.stack([a, d, c, b] if flip else [a, b, c, d], 1)
+
+
 def densities(n_panels, n_cols, dtype=np.complex128, seed=DENS_SEED):
     """iid N(0,1) real and imaginary parts, shape [N][n_cols] (panel-major)."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -69,7 +78,7 @@ def densities(n_panels, n_cols, dtype=np.complex128, seed=DENS_SEED):
 # --------------------------------------------------------------------------
 # straight bar
 # --------------------------------------------------------------------------
-def bar(nx=4, ny=4, nz=126, size=(1.0, 1.0, 20.0), jitter=0.05, seed=GEOM_SEED):
+def bar(nx=4, ny=4, nz=126, size=(1.0, 1.0, 20.0), jitter=0.05, seed=GEOM_SEED, hybrid=False):
     """Surface of the box [0,sx]x[0,sy]x[0,sz] with nx*ny*nz surface cells per
     direction, every quad split in two.  N = 4*(nx*nz + ny*nz + nx*ny).
     Defaults: 1 x 1 x 20 bar, 4096 triangles.
@@ -77,7 +86,12 @@ def bar(nx=4, ny=4, nz=126, size=(1.0, 1.0, 20.0), jitter=0.05, seed=GEOM_SEED):
     Vertex jitter is uniform in +-jitter of the local cell size, only along
     the directions in which the vertex is free to move without leaving its
     face (vertices on bar edges slide along the edge, corners stay fixed), so
-    the mesh stays flat and conforming."""
+    the mesh stays flat and conforming.
+
+    hybrid=True: the four long faces keep their cells as four-sided panels
+    (rectangles without jitter, planar quadrilaterals with it) and the end
+    caps are split into triangles; T is then [N][4] with -1 as the fourth
+    index of a triangle, N = 2*(nx*nz + ny*nz) + 4*nx*ny."""
     rng = np.random.Generator(np.random.PCG64(seed))
     sx, sy, sz = size
     n = (nx, ny, nz)
@@ -114,7 +128,11 @@ def bar(nx=4, ny=4, nz=126, size=(1.0, 1.0, 20.0), jitter=0.05, seed=GEOM_SEED):
         # outward normal: e_a1 x e_a2 = +e_axis for (axis,a1,a2) cyclic
         cyc = (a1 - axis) % 3 == 1
         flip = (side == 0) == cyc
-        tris.append(_grid_tris(idx, flip=flip))
+        if hybrid and axis != 2:
+            tris.append(_grid_quads(idx, flip=flip))
+        else:
+            t = _grid_tris(idx, flip=flip)
+            tris.append(np.concatenate([t, np.full((len(t), 1), -1)], 1) if hybrid else t)
 
     for axis in range(3):
         for side in (0, 1):

@@ -19,6 +19,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from oracle import hybrid as H
 from oracle import loops as LO
 from paper_2409_12375_amd import inputs as I
 
@@ -42,23 +43,31 @@ def torus(n_major=16, n_minor=8, R=1.0, r=0.35):
     return np.array(V), np.array(T, dtype=np.int32)
 
 
-def test_cm_maps_reproduce_uniform_current():
+@pytest.mark.parametrize("hybrid", [False, True])
+def test_cm_maps_reproduce_uniform_current(hybrid):
     """For every panel p and a constant tangential density J on it, edge
     currents equal to the outward fluxes J . nu_e l_e give
-    (A_t^T I_edge)[p] = J_t * area_p."""
-    V, T = I.bar(2, 2, 6, size=(1.0, 1.0, 3.0))
+    (A_t^T I_edge)[p] = J_t * area_p (the edge midpoint rule integrates the
+    flux of (x - c)_t J exactly on any straight-sided panel, triangle or
+    quadrilateral, with c its area centroid)."""
+    V, T = I.bar(2, 2, 6, size=(1.0, 1.0, 3.0), jitter=0.1 if hybrid else 0.05, hybrid=hybrid)
     pairs, verts = LO.mesh_edges(T)
     A = LO.cm_maps(V, T, pairs, verts)
-    area, cen, nrm, _ = O.panel_geometry(V, T)
+    if hybrid:
+        area, cen = H.panel_geometry(V, T)
+        Tt, owner = H.split(T)
+        nrm = O.panel_geometry(V, Tt)[2][np.searchsorted(owner, np.arange(len(T)))]
+    else:
+        area, cen, nrm, _ = O.panel_geometry(V, T)
     rng = np.random.default_rng(0)
     edge_of = {tuple(vv): e for e, vv in enumerate(verts.tolist())}
     for p in rng.choice(len(T), 40, replace=False):
         J = rng.standard_normal(3)
         J -= nrm[p] * (J @ nrm[p])  # tangential to panel p
         I_edge = np.zeros(len(pairs))
-        tri = T[p]
-        for a in range(3):
-            u, w = tri[a], tri[(a + 1) % 3]
+        tri = [v for v in T[p] if v >= 0]
+        for a in range(len(tri)):
+            u, w = tri[a], tri[(a + 1) % len(tri)]
             e = edge_of[(min(u, w), max(u, w))]
             ev = V[w] - V[u]
             nu = np.cross(ev, nrm[p])
@@ -69,25 +78,30 @@ def test_cm_maps_reproduce_uniform_current():
             I_edge[e] = flux if pairs[e][0] == p else -flux  # global direction i -> j
         got = np.array([A[t].T @ I_edge for t in range(3)])[:, p]
         assert np.allclose(got, J * area[p], rtol=1e-12, atol=1e-12 * np.abs(J).max() * area[p])
-    # a panel's rho vectors sum to zero (the midpoints average to the centroid)
+    # a panel's rho vectors sum to n (vertex mean - c): zero on a triangle
+    # (the midpoints average to the centroid), not on a general quadrilateral
     for p in range(len(T)):
         col = A[:, :, p]
         sgn = np.where(pairs[:, 0] == p, 1.0, np.where(pairs[:, 1] == p, -1.0, 0.0))
-        assert np.allclose((col * sgn[None, :]).sum(axis=1), 0.0, atol=1e-12)
+        tri = [v for v in T[p] if v >= 0]
+        expect = len(tri) * (V[tri].mean(axis=0) - cen[p])
+        assert np.allclose((col * sgn[None, :]).sum(axis=1), expect, atol=1e-12)
 
 
-@pytest.mark.parametrize("mesh,genus", [("sphere", 0), ("bar", 0), ("torus", 1)])
+@pytest.mark.parametrize("mesh,genus", [("sphere", 0), ("bar", 0), ("hybrid bar", 0), ("torus", 1)])
 def test_cycle_space_dimension_is_euler(mesh, genus):
     if mesh == "sphere":
         V, T = I.icosphere(2)
     elif mesh == "bar":
         V, T = I.bar(2, 2, 5, size=(1.0, 1.0, 3.0))
+    elif mesh == "hybrid bar":
+        V, T = I.bar(2, 2, 5, size=(1.0, 1.0, 3.0), hybrid=True)
     else:
         V, T = torus()
     pairs, verts = LO.mesh_edges(T)
     D = LO.incidence(pairs, len(T))
     Q = LO.cycle_space(D)
-    nv = len(np.unique(T))
+    nv = len(np.unique(T[T >= 0]))
     assert Q.shape[1] == nv - 1 + 2 * genus
     assert np.abs(D @ Q).max() < 1e-12
 
