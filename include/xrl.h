@@ -101,17 +101,26 @@ const char *xrl_version(void);
 /* ------------------------------------------------------------------ */
 /* Mesh and tree                                                       */
 /* ------------------------------------------------------------------ */
-/* An indexed triangle mesh.  vertices: [n_vertices][3] float64;
- * tris: [n_panels][3] int32 vertex indices (0-based).  Both arrays live on
- * the host (on_device = 0) or on the current HIP device (on_device = 1); they
- * are copied during xrl_tree_build and not referenced afterwards.
- * Vertex order only fixes the sign of the panel normal, which P does not use. */
+/* An indexed surface mesh of flat panels (Sec. II-A: triangles, or the
+ * hybrid mesh of triangles and rectangles of Fig. 1).
+ * vertices: [n_vertices][3] float64.
+ * tris: vertex indices (0-based), [n_panels][3] int32 when verts_per_panel is
+ *   3 (or 0); [n_panels][4] when it is 4, a row (a, b, c, d) being the
+ *   four-sided panel whose surface is the union of the triangles (a, b, c)
+ *   and (a, c, d) (a rectangle, or any planar quadrilateral), and a row with
+ *   d < 0 a triangle (a, b, c).  One pulse function per panel (eq. (4)): a
+ *   four-sided panel is one unknown, integrated over both of its triangles.
+ * Both arrays live on the host (on_device = 0) or on the current HIP device
+ * (on_device = 1); they are copied during xrl_tree_build and not referenced
+ * afterwards.  Vertex order only fixes the sign of the panel normal, which P
+ * does not use. */
 typedef struct {
     int64_t n_vertices;
     int64_t n_panels;
     const double *vertices;
     const int32_t *tris;
     int32_t on_device;
+    int32_t verts_per_panel; /* 3 (0 reads as 3) or 4 */
 } xrl_mesh_desc;
 
 typedef struct xrl_tree xrl_tree;
@@ -121,7 +130,13 @@ typedef struct xrl_plan xrl_plan;
  * centroids, 63-bit Morton codes of the centroids, a radix sort and a
  * level-by-level split of every box holding more than max_leaf centroids,
  * all on the device (the octree of the FMM of Sec. II-C, built on panel
- * centroids).  A panel belongs to the box that holds its centroid.
+ * centroids).  A panel belongs to the box that holds its centroid.  On a
+ * hybrid mesh the tree sorts elements: every triangle, and both triangles of
+ * every four-sided panel, each by its own centroid; the FMM, the near field
+ * and the leaf sizes count elements, and the matvec gathers each panel's
+ * density to its elements and sums their potentials back (P = S P_tri S^T,
+ * S the panel-element membership; the integral over a panel is the sum over
+ * its triangles).
  *   max_leaf  : 1..128; near-field blocks are padded to 16, 32, 64 or 128
  *               targets.  Larger leaves move work from the translations to
  *               the near field (fewer M2L pairs, more stored values).
@@ -141,9 +156,11 @@ typedef struct {
     int64_t n_boxes;
     int64_t n_leaves;
     int32_t depth;             /* deepest level present (root = 0) */
-    int32_t n_overfull_leaves; /* leaves at max_depth with more than max_leaf panels */
+    int32_t n_overfull_leaves; /* leaves at max_depth with more than max_leaf elements */
     double root_center[3];
     double root_size;          /* side of the root cube */
+    int64_t n_elements;        /* triangles the tree sorts: n_panels plus one per
+                                  four-sided panel */
 } xrl_tree_info;
 xrl_status xrl_tree_get_info(const xrl_tree *tree, xrl_tree_info *info);
 
@@ -193,6 +210,7 @@ typedef struct {
     int64_t n_demoted_pairs; /* V-list candidates whose panel-inclusive radii do not
                                 separate them; applied directly as near field */
     double theta;            /* separation criterion in use (xrl_plan_opts.theta) */
+    int64_t n_elements;      /* triangles the FMM and the near field work on */
 } xrl_plan_info;
 xrl_status xrl_plan_get_info(const xrl_plan *plan, xrl_plan_info *info);
 
@@ -413,11 +431,12 @@ xrl_status xrl_plan_autotune(xrl_plan *plan, const void *x, int64_t ldx, int32_t
                              int64_t ldy, int32_t reps, void *stream, xrl_tune_result *result);
 
 /* Debug export of plan internals to host memory (tests):
- *   item 0: perm        int32 [n_panels]   sorted position -> global panel
- *   item 1: box_range   int32 [n_boxes][2] panel range [begin, end) per box
+ *   item 0: perm        int32 [n_elements] sorted position -> global panel
+ *                       (both elements of a four-sided panel name the panel)
+ *   item 1: box_range   int32 [n_boxes][2] element range [begin, end) per box
  *   item 2: box_level   int32 [n_boxes]
  *   item 3: near_rows   int32 [n_leaves+1] CSR over leaves into item 4
- *   item 4: near_src    int32 [n_near_rows] sorted source panel per row
+ *   item 4: near_src    int32 [n_near_rows] sorted source element per row
  *   item 5: m2l_pairs   int32 [n_m2l_pairs][2] (target box, source box)
  *   item 6: leaf_box    int32 [n_leaves]   box index of each leaf
  *   item 7: box_parent  int32 [n_boxes]

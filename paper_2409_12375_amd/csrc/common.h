@@ -170,7 +170,9 @@ constexpr int kMaxLeaf = 128;
 // Tree: one mesh, panels sorted in Morton order of their centroids.
 // --------------------------------------------------------------------------
 struct xrl_tree {
-    int64_t N = 0, nv = 0;
+    int64_t N = 0, nv = 0;  // elements (triangles), vertices
+    int64_t Np = 0;         // user panels (N unless four-sided panels were split)
+    xrl::DevBuf<int32_t> elem_panel;  // [N] element (input order) -> user panel; empty: identity
     int max_leaf = 64, max_depth = 21;
     double root_c[3] = {0, 0, 0};
     double root_size = 0;
@@ -223,8 +225,10 @@ struct xrl_plan {
     int m2l_engine = XRL_M2L_MFMA;
     int max_cols = 1;  // complex columns
     std::vector<xrl_tree *> trees;
-    std::vector<int64_t> panel_off;  // [ntrees+1] global panel offsets (user order == sorted blocks)
-    int64_t N = 0;
+    std::vector<int64_t> panel_off;  // [ntrees+1] global element offsets (sorted blocks)
+    std::vector<int64_t> user_off;   // [ntrees+1] global user panel offsets
+    int64_t N = 0;                   // elements (the FMM's and the near field's points)
+    int64_t Nu = 0;                  // user panels (rows of x and y)
     // global boxes (level-major across trees)
     int64_t B = 0;
     int depth = 0;
@@ -239,8 +243,9 @@ struct xrl_plan {
     xrl::DevBuf<int32_t> leaf_box;   // [n_leaves]
     int64_t n_leaves = 0;
     // global sorted panels
-    xrl::DevBuf<int32_t> perm;   // global sorted pos -> global user panel index
-    xrl::DevBuf<int32_t> iperm;  // user -> sorted
+    xrl::DevBuf<int32_t> perm;    // global sorted element -> global user panel index
+    xrl::DevBuf<int32_t> iperm;   // [Nu] user panel -> sorted position of its (first) element
+    xrl::DevBuf<int32_t> iperm2;  // [Nu] second element of a four-sided panel, -1 (empty: none)
     xrl::DevBuf<double> pv;      // [N][9]
     xrl::DevBuf<int32_t> pvid;   // [N][3] (vertex ids offset per tree)
     xrl::DevBuf<double> cen, area, diam;

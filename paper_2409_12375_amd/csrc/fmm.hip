@@ -51,18 +51,30 @@ __global__ void k_gather_x(int64_t N, const int32_t *__restrict__ perm, const TI
     }
 }
 
+// One thread per (user panel, column): the potential of the panel's element
+// (or the sum over the two elements of a four-sided panel, iperm2 >= 0),
+// then the epilogue with the panel's area.
 template <typename TO, typename TW>
-__global__ void k_scatter_y(int64_t N, const int32_t *__restrict__ perm, const TW *__restrict__ ys,
-                            const double *__restrict__ area, const TO *__restrict__ x, int64_t ldx,
-                            TO *__restrict__ y, int64_t ldy, int ncols, const double *__restrict__ alpha,
+__global__ void k_scatter_y(int64_t Nu, const int32_t *__restrict__ iperm, const int32_t *__restrict__ iperm2,
+                            const TW *__restrict__ ys, const double *__restrict__ area, const TO *__restrict__ x,
+                            int64_t ldx, TO *__restrict__ y, int64_t ldy, int ncols, const double *__restrict__ alpha,
                             const double *__restrict__ beta)
 {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N * ncols;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Nu * ncols;
          e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / ncols;
-    const int c = (int)(e - i * ncols);
-    const int64_t u = perm[i];
-    const double pr = (double)ys[i * 2 * ncols + 2 * c], pi = (double)ys[i * 2 * ncols + 2 * c + 1];
+    const int64_t u = e / ncols;
+    const int c = (int)(e - u * ncols);
+    const int64_t i = iperm[u];
+    double pr = (double)ys[i * 2 * ncols + 2 * c], pi = (double)ys[i * 2 * ncols + 2 * c + 1];
+    double A = area[i];
+    if (iperm2) {
+        const int64_t i2 = iperm2[u];
+        if (i2 >= 0) {
+            pr += (double)ys[i2 * 2 * ncols + 2 * c];
+            pi += (double)ys[i2 * 2 * ncols + 2 * c + 1];
+            A += area[i2];
+        }
+    }
     double ar = 1, ai = 0, br = 0, bi = 0;
     if (alpha) {
         ar = alpha[2 * c];
@@ -73,7 +85,6 @@ __global__ void k_scatter_y(int64_t N, const int32_t *__restrict__ perm, const T
         br = beta[2 * c];
         bi = beta[2 * c + 1];
         const double xr = (double)x[2 * (u * ldx + c)], xi = (double)x[2 * (u * ldx + c) + 1];
-        const double A = area[i];
         yr += A * (br * xr - bi * xi);
         yi += A * (br * xi + bi * xr);
     }
@@ -2285,13 +2296,13 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
     }
     mark(7);
     const double *da = wk.alpha, *db = wk.beta;
-    const unsigned gy = (unsigned)std::min<int64_t>(cdiv(N * ncols, bs), 1 << 20);
+    const unsigned gy = (unsigned)std::min<int64_t>(cdiv(P->Nu * ncols, bs), 1 << 20);
     if (dtype == XRL_C64)
-        k_scatter_y<float, T><<<gy, bs, 0, s>>>(N, P->perm.p, wk.ys, P->area.p, (const float *)x, ldx, (float *)y, ldy,
-                                                ncols, da, db);
+        k_scatter_y<float, T><<<gy, bs, 0, s>>>(P->Nu, P->iperm.p, P->iperm2.p, wk.ys, P->area.p, (const float *)x,
+                                                ldx, (float *)y, ldy, ncols, da, db);
     else
-        k_scatter_y<double, T><<<gy, bs, 0, s>>>(N, P->perm.p, wk.ys, P->area.p, (const double *)x, ldx, (double *)y,
-                                                 ldy, ncols, da, db);
+        k_scatter_y<double, T><<<gy, bs, 0, s>>>(P->Nu, P->iperm.p, P->iperm2.p, wk.ys, P->area.p,
+                                                 (const double *)x, ldx, (double *)y, ldy, ncols, da, db);
     XRL_HIP(hipGetLastError());
     mark(8);
     if (prof) ++P->prof_count;

@@ -284,7 +284,7 @@ extern "C" xrl_status xrl_gmres_solve(const xrl_plan *P, const xrl_epilogue *op,
         XRL_CHECK(P->assembled, XRL_E_STATE, "xrl_gmres_solve: call xrl_nearfield_assemble first");
         hipStream_t s = (hipStream_t)stream;
         const AllocStream alloc_scope(s);
-        const int64_t N = P->N, R = n_rhs, NR2 = 2 * N * R;
+        const int64_t N = P->Nu, R = n_rhs, NR2 = 2 * N * R;
         const xrl_epilogue ep = op ? *op : xrl_epilogue{nullptr, nullptr};
         // complex64 right-hand sides and solutions are widened to complex128
         // for the iteration and the solution narrowed back at the end

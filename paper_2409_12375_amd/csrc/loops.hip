@@ -39,8 +39,8 @@ struct xrl_loops {
     std::vector<double> h_rho;     // [Ne][6] rho_i, rho_j
     std::vector<int32_t> h_mptr, h_midx;  // M, CSR over loops
     std::vector<int8_t> h_msgn;
-    std::vector<int32_t> h_pedge;  // [Np][3] branch of each side of a panel
-    std::vector<double> h_pcoef;   // [Np][3][3] A_t(e, p) of each side
+    std::vector<int32_t> h_pedge;  // [Np][4] branch of each side of a panel (-1: no fourth side)
+    std::vector<double> h_pcoef;   // [Np][4][3] A_t(e, p) of each side
     std::vector<double> h_area;    // [Np]
     xrl::DevBuf<int32_t> pairs, pedge, mptr, midx, mtptr, mtidx;
     xrl::DevBuf<int8_t> msgn, mtsgn;
@@ -52,6 +52,8 @@ xrl_status xrl_matvec_eager(const xrl_plan *P, const void *x, int64_t ldx, int32
                             int64_t ldy, const xrl_epilogue *ep, void *stream);
 
 namespace xrl {
+
+constexpr int kSides = 4;  // sides of a panel, at most (triangles leave the fourth empty)
 
 int gmres_core(const std::function<void(const double *, double *)> &apply, int64_t N, int R, const double *Bv,
                double *X, int restart, double rtol, int max_iter, hipStream_t stream, xrl_gmres_stats *stats);
@@ -77,8 +79,8 @@ __global__ void k_signed_csr(int64_t nrows, const int32_t *__restrict__ ptr, con
     out[2 * e + 1] = im;
 }
 
-// Panel currents I_p[p][3 c + t] = sum over the panel's three sides k of
-// A_t(e_k, p) I_edge[e_k][c]  (A_t^T applied, complex128).
+// Panel currents I_p[p][3 c + t] = sum over the panel's sides k (three or
+// four) of A_t(e_k, p) I_edge[e_k][c]  (A_t^T applied, complex128).
 __global__ void k_edge_to_panel(int64_t Np, const int32_t *__restrict__ pedge, const double *__restrict__ pcoef,
                                 const double *__restrict__ ie, int R, double *__restrict__ ip)
 {
@@ -87,12 +89,12 @@ __global__ void k_edge_to_panel(int64_t Np, const int32_t *__restrict__ pedge, c
     const int64_t p = e / R;
     const int c = (int)(e - p * R);
     double acc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-    for (int k = 0; k < 3; ++k) {
-        const int32_t b = pedge[3 * p + k];
+    for (int k = 0; k < kSides; ++k) {
+        const int32_t b = pedge[kSides * p + k];
         if (b < 0) continue;
         const double re = ie[2 * ((int64_t)b * R + c)], im = ie[2 * ((int64_t)b * R + c) + 1];
         for (int t = 0; t < 3; ++t) {
-            const double a = pcoef[9 * p + 3 * k + t];
+            const double a = pcoef[3 * (kSides * p + k) + t];
             acc[t][0] += a * re;
             acc[t][1] += a * im;
         }
@@ -123,46 +125,65 @@ __global__ void k_panel_to_edge(int64_t Ne, const int32_t *__restrict__ pairs, c
     ve[2 * e + 1] = im;
 }
 
-// Plan near-field entry P_kl for user panels (k, l) that are near neighbours
-// (l in the near list of k's leaf): the block row of l, column of k.
+// Stored near-field entry of sorted elements (sk, sl): the block row of sl
+// in the near list of sk's leaf, column of sk; NaN if it is not stored.
+struct NearTable {
+    const int32_t *panel_leaf, *leaf_box, *box_beg, *near_rows, *near_src, *leaf_tpad;
+    const int64_t *val_off;
+    const float *v32;
+    const double *v64;
+    __device__ double operator()(int32_t sk, int32_t sl) const
+    {
+        const int32_t li = panel_leaf[sk];
+        int32_t lo = near_rows[li], hi = near_rows[li + 1];
+        while (lo < hi) {
+            const int32_t mid = lo + (hi - lo) / 2;
+            if (near_src[mid] < sl)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        if (lo >= near_rows[li + 1] || near_src[lo] != sl) return NAN;
+        const int64_t at = val_off[li] + (int64_t)(lo - near_rows[li]) * leaf_tpad[li] + (sk - box_beg[leaf_box[li]]);
+        return v64 ? v64[at] : (double)v32[at];
+    }
+};
+
+// P_kl for user panels (k, l) that are near neighbours: the sum over the
+// elements of both panels (one each for triangles, two for a four-sided
+// panel, iperm2 >= 0).
 __global__ void k_near_lookup(int64_t n, const int32_t *__restrict__ qk, const int32_t *__restrict__ ql,
-                              const int32_t *__restrict__ iperm, const int32_t *__restrict__ panel_leaf,
-                              const int32_t *__restrict__ leaf_box, const int32_t *__restrict__ box_beg,
-                              const int32_t *__restrict__ near_rows, const int32_t *__restrict__ near_src,
-                              const int32_t *__restrict__ leaf_tpad, const int64_t *__restrict__ val_off,
-                              const float *__restrict__ v32, const double *__restrict__ v64, double *__restrict__ out)
+                              const int32_t *__restrict__ iperm, const int32_t *__restrict__ iperm2, NearTable tab,
+                              double *__restrict__ out)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int32_t sk = iperm[qk[i]], sl = iperm[ql[i]];
-    const int32_t li = panel_leaf[sk];
-    int32_t lo = near_rows[li], hi = near_rows[li + 1];
-    while (lo < hi) {
-        const int32_t mid = lo + (hi - lo) / 2;
-        if (near_src[mid] < sl)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    if (lo >= near_rows[li + 1] || near_src[lo] != sl) {
-        out[i] = NAN;
-        return;
-    }
-    const int64_t at = val_off[li] + (int64_t)(lo - near_rows[li]) * leaf_tpad[li] + (sk - box_beg[leaf_box[li]]);
-    out[i] = v64 ? v64[at] : (double)v32[at];
+    const int32_t k[2] = {iperm[qk[i]], iperm2 ? iperm2[qk[i]] : -1};
+    const int32_t l[2] = {iperm[ql[i]], iperm2 ? iperm2[ql[i]] : -1};
+    double v = 0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            if (k[a] >= 0 && l[b] >= 0) v += tab(k[a], l[b]);
+    out[i] = v;
 }
 
 // ------------------------------------------------------------------ loop search
-static void build_edges(const int32_t *T, int64_t Np, int64_t nv, xrl_loops &L)
+// Panels as [Np][4] vertex indices, -1 as the fourth of a triangle.
+static inline int sides(const int32_t *Q, int64_t p) { return Q[kSides * p + 3] >= 0 ? 4 : 3; }
+
+static void build_edges(const int32_t *Q, int64_t Np, int64_t nv, xrl_loops &L)
 {
-    std::vector<std::pair<uint64_t, int32_t>> key(3 * Np);
-    for (int64_t p = 0; p < Np; ++p)
-        for (int a = 0; a < 3; ++a) {
-            const uint32_t u = (uint32_t)T[3 * p + a], w = (uint32_t)T[3 * p + (a + 1) % 3];
-            key[3 * p + a] = {((uint64_t)std::min(u, w) << 32) | std::max(u, w), (int32_t)(3 * p + a)};
+    std::vector<std::pair<uint64_t, int32_t>> key;
+    key.reserve(kSides * Np);
+    for (int64_t p = 0; p < Np; ++p) {
+        const int ns = sides(Q, p);
+        for (int a = 0; a < ns; ++a) {
+            const uint32_t u = (uint32_t)Q[kSides * p + a], w = (uint32_t)Q[kSides * p + (a + 1) % ns];
+            key.push_back({((uint64_t)std::min(u, w) << 32) | std::max(u, w), (int32_t)(kSides * p + a)});
         }
+    }
     std::sort(key.begin(), key.end());
-    L.h_pedge.assign(3 * Np, -1);
+    L.h_pedge.assign(kSides * Np, -1);
     for (size_t q = 0; q < key.size();) {
         size_t r = q;
         while (r < key.size() && key[r].first == key[q].first) ++r;
@@ -170,7 +191,7 @@ static void build_edges(const int32_t *T, int64_t Np, int64_t nv, xrl_loops &L)
                   "xrl_loops_build: an edge belongs to %d panels (loop analysis needs a closed conforming mesh)",
                   (int)(r - q));
         const int32_t s0 = key[q].second, s1 = key[q + 1].second;
-        const int32_t p0 = s0 / 3, p1 = s1 / 3;
+        const int32_t p0 = s0 / kSides, p1 = s1 / kSides;
         XRL_CHECK(p0 != p1, XRL_E_DEGENERATE_PANEL, "xrl_loops_build: panel %d repeats an edge", p0);
         const int32_t e = (int32_t)(L.h_pairs.size() / 2);
         L.h_pairs.push_back(std::min(p0, p1));
@@ -188,7 +209,7 @@ static void build_edges(const int32_t *T, int64_t Np, int64_t nv, xrl_loops &L)
 // step the edge at v not crossed last; sign +1 where the walk follows the
 // branch's global direction.
 static bool vertex_fan(int32_t v, const std::vector<int32_t> &vp_ptr, const std::vector<int32_t> &vp,
-                       const int32_t *T, const xrl_loops &L, std::vector<std::pair<int32_t, int8_t>> &loop)
+                       const int32_t *Q, const xrl_loops &L, std::vector<std::pair<int32_t, int8_t>> &loop)
 {
     loop.clear();
     const int32_t n = vp_ptr[v + 1] - vp_ptr[v];
@@ -197,10 +218,11 @@ static bool vertex_fan(int32_t v, const std::vector<int32_t> &vp_ptr, const std:
     int32_t cur = start, came = -1;
     for (int step = 0; step < n; ++step) {
         int32_t next_e = -1;
-        for (int a = 0; a < 3 && next_e < 0; ++a) {
-            const int32_t u = T[3 * cur + a], w = T[3 * cur + (a + 1) % 3];
+        const int ns = sides(Q, cur);
+        for (int a = 0; a < ns && next_e < 0; ++a) {
+            const int32_t u = Q[kSides * cur + a], w = Q[kSides * cur + (a + 1) % ns];
             if (u != v && w != v) continue;
-            const int32_t e = L.h_pedge[3 * cur + a];
+            const int32_t e = L.h_pedge[kSides * cur + a];
             if (e != came) next_e = e;
         }
         if (next_e < 0) return false;
@@ -214,17 +236,19 @@ static bool vertex_fan(int32_t v, const std::vector<int32_t> &vp_ptr, const std:
     return false;
 }
 
-static void build_loops(const int32_t *T, xrl_loops &L)
+static void build_loops(const int32_t *Q, xrl_loops &L)
 {
     const int64_t Np = L.Np, Ne = L.Ne, nv = L.nv;
     // panels around each vertex
-    std::vector<int32_t> vp_ptr(nv + 1, 0), vp(3 * Np);
-    for (int64_t q = 0; q < 3 * Np; ++q) ++vp_ptr[T[q] + 1];
+    std::vector<int32_t> vp_ptr(nv + 1, 0);
+    for (int64_t q = 0; q < kSides * Np; ++q)
+        if (Q[q] >= 0) ++vp_ptr[Q[q] + 1];
     for (int64_t v = 0; v < nv; ++v) vp_ptr[v + 1] += vp_ptr[v];
+    std::vector<int32_t> vp(vp_ptr[nv]);
     {
         std::vector<int32_t> fill(vp_ptr.begin(), vp_ptr.end() - 1);
         for (int64_t p = 0; p < Np; ++p)
-            for (int a = 0; a < 3; ++a) vp[fill[T[3 * p + a]]++] = (int32_t)p;
+            for (int a = 0; a < sides(Q, p); ++a) vp[fill[Q[kSides * p + a]]++] = (int32_t)p;
     }
     // connected surfaces (BFS over branches)
     std::vector<std::vector<int32_t>> adj_e(Np);
@@ -265,7 +289,7 @@ static void build_loops(const int32_t *T, xrl_loops &L)
     for (int64_t v = 0; v < nv; ++v) {
         if (vp_ptr[v + 1] == vp_ptr[v]) continue;
         if (last_v[comp[vp[vp_ptr[v]]]] == v) continue;
-        XRL_CHECK(vertex_fan((int32_t)v, vp_ptr, vp, T, L, loop), XRL_E_UNSUPPORTED,
+        XRL_CHECK(vertex_fan((int32_t)v, vp_ptr, vp, Q, L, loop), XRL_E_UNSUPPORTED,
                   "xrl_loops_build: the panels around vertex %lld do not form one fan (non-manifold mesh)",
                   (long long)v);
         add(loop);
@@ -502,24 +526,43 @@ extern "C" xrl_status xrl_loops_build(const xrl_mesh_desc *mesh, void *stream, x
         *out = nullptr;
         hipStream_t s = (hipStream_t)stream;
         const AllocStream alloc_scope(s);
+        const int vpp = mesh->verts_per_panel == 0 ? 3 : mesh->verts_per_panel;
+        XRL_CHECK(vpp == 3 || vpp == 4, XRL_E_INVALID_ARG, "xrl_loops_build: verts_per_panel must be 3 or 4");
         auto L = std::make_unique<xrl_loops>();
         L->Np = mesh->n_panels;
         L->nv = mesh->n_vertices;
-        const int32_t *T = mesh->tris;
         const double *V = mesh->vertices;
-        for (int64_t q = 0; q < 3 * L->Np; ++q)
-            XRL_CHECK(T[q] >= 0 && T[q] < L->nv, XRL_E_INVALID_ARG, "xrl_loops_build: vertex index out of range");
-        build_edges(T, L->Np, L->nv, *L);
-        // rho vectors (Algorithm 1) and the per-panel side coefficients
-        std::vector<double> c(3 * L->Np);
-        L->h_area.resize(L->Np);
-        for (int64_t p = 0; p < L->Np; ++p) {
-            const double *a = V + 3 * T[3 * p], *b = V + 3 * T[3 * p + 1], *d = V + 3 * T[3 * p + 2];
-            for (int k = 0; k < 3; ++k) c[3 * p + k] = (a[k] + b[k] + d[k]) / 3.0;
+        // panels as [Np][4], -1 as the fourth index of a triangle
+        std::vector<int32_t> Qv(kSides * L->Np, -1);
+        for (int64_t p = 0; p < L->Np; ++p)
+            for (int a = 0; a < vpp; ++a) Qv[kSides * p + a] = mesh->tris[vpp * p + a];
+        const int32_t *Q = Qv.data();
+        for (int64_t p = 0; p < L->Np; ++p)
+            for (int a = 0; a < sides(Q, p); ++a)
+                XRL_CHECK(Q[kSides * p + a] >= 0 && Q[kSides * p + a] < L->nv, XRL_E_INVALID_ARG,
+                          "xrl_loops_build: vertex index out of range");
+        build_edges(Q, L->Np, L->nv, *L);
+        // area centroids (a four-sided panel: the triangles (a, b, c) and
+        // (a, c, d) weighted by area), rho vectors of Algorithm 1 and the
+        // per-panel side coefficients
+        std::vector<double> c(3 * L->Np, 0.0);
+        L->h_area.assign(L->Np, 0.0);
+        auto tri_area = [&](const double *a, const double *b, const double *d) {
             const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {d[0] - a[0], d[1] - a[1], d[2] - a[2]};
             const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
                          cz = e1[0] * e2[1] - e1[1] * e2[0];
-            L->h_area[p] = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+            return 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+        };
+        for (int64_t p = 0; p < L->Np; ++p) {
+            const int nt = sides(Q, p) - 2;
+            for (int t = 0; t < nt; ++t) {
+                const double *a = V + 3 * Q[kSides * p], *b = V + 3 * Q[kSides * p + 1 + t],
+                             *d = V + 3 * Q[kSides * p + 2 + t];
+                const double ar = tri_area(a, b, d);
+                L->h_area[p] += ar;
+                for (int k = 0; k < 3; ++k) c[3 * p + k] += ar * (a[k] + b[k] + d[k]) / 3.0;
+            }
+            for (int k = 0; k < 3; ++k) c[3 * p + k] /= L->h_area[p];
         }
         L->h_rho.resize(6 * L->Ne);
         for (int64_t e = 0; e < L->Ne; ++e) {
@@ -529,15 +572,15 @@ extern "C" xrl_status xrl_loops_build(const xrl_mesh_desc *mesh, void *stream, x
                 for (int k = 0; k < 3; ++k) L->h_rho[6 * e + 3 * side + k] = 0.5 * (u[k] + w[k]) - c[3 * p + k];
             }
         }
-        L->h_pcoef.assign(9 * L->Np, 0.0);
+        L->h_pcoef.assign(3 * kSides * L->Np, 0.0);
         for (int64_t p = 0; p < L->Np; ++p)
-            for (int k = 0; k < 3; ++k) {
-                const int32_t e = L->h_pedge[3 * p + k];
+            for (int k = 0; k < sides(Q, p); ++k) {
+                const int32_t e = L->h_pedge[kSides * p + k];
                 const bool is_i = L->h_pairs[2 * e] == p;
                 for (int t = 0; t < 3; ++t)
-                    L->h_pcoef[9 * p + 3 * k + t] = is_i ? L->h_rho[6 * e + t] : -L->h_rho[6 * e + 3 + t];
+                    L->h_pcoef[3 * (kSides * p + k) + t] = is_i ? L->h_rho[6 * e + t] : -L->h_rho[6 * e + 3 + t];
             }
-        build_loops(T, *L);
+        build_loops(Q, *L);
         // M^T (CSR over branches)
         std::vector<int32_t> mtptr(L->Ne + 1, 0), mtidx(L->h_midx.size());
         std::vector<int8_t> mtsgn(L->h_midx.size());
@@ -674,7 +717,7 @@ void check_pair(const xrl_loops *L, const xrl_plan *P, int R, const char *who)
 {
     XRL_CHECK(L && P, XRL_E_INVALID_ARG, "%s: null handle", who);
     XRL_CHECK(P->assembled, XRL_E_STATE, "%s: call xrl_nearfield_assemble first", who);
-    XRL_CHECK(P->N == L->Np, XRL_E_INVALID_ARG, "%s: plan has %lld panels, loops %lld", who, (long long)P->N,
+    XRL_CHECK(P->Nu == L->Np, XRL_E_INVALID_ARG, "%s: plan has %lld panels, loops %lld", who, (long long)P->Nu,
               (long long)L->Np);
     XRL_CHECK(R >= 1 && 3 * R <= P->max_cols, XRL_E_INVALID_ARG,
               "%s: 3 x n_cols (%d) must not exceed the plan's max_cols (%d)", who, 3 * R, P->max_cols);
@@ -750,9 +793,10 @@ extern "C" xrl_status xrl_loop_gmres_solve(const xrl_loops *L, const xrl_plan *P
             dk.upload(qk, s);
             dl.upload(ql, s);
             DevBuf<double> dv(qk.size());
-            k_near_lookup<<<cdiv((int64_t)qk.size(), 256), 256, 0, s>>>(
-                (int64_t)qk.size(), dk.p, dl.p, P->iperm.p, P->panel_leaf.p, P->leaf_box.p, P->box_beg.p,
-                P->near_rows.p, P->near_src.p, P->leaf_tpad.p, P->near_val_off.p, P->near32.p, P->near64.p, dv.p);
+            const NearTable tab{P->panel_leaf.p, P->leaf_box.p, P->box_beg.p, P->near_rows.p, P->near_src.p,
+                                P->leaf_tpad.p, P->near_val_off.p, P->near32.p, P->near64.p};
+            k_near_lookup<<<cdiv((int64_t)qk.size(), 256), 256, 0, s>>>((int64_t)qk.size(), dk.p, dl.p, P->iperm.p,
+                                                                        P->iperm2.p, tab, dv.p);
             XRL_HIP(hipGetLastError());
             std::vector<double> pv = dv.download(s);
             for (double v : pv) XRL_CHECK(std::isfinite(v), XRL_E_STATE, "preconditioner: near entry missing");
@@ -769,12 +813,14 @@ extern "C" xrl_status xrl_loop_gmres_solve(const xrl_loops *L, const xrl_plan *P
                 };
                 for (int64_t p = 0; p < Np; ++p) {
                     const cplx w = be * L->h_area[p] + (precond == 1 ? al * pv[p] : cplx(0));
-                    for (int k = 0; k < 3; ++k)
-                        for (int m = 0; m < 3; ++m) {
+                    for (int k = 0; k < kSides; ++k)
+                        for (int m = 0; m < kSides; ++m) {
+                            const int32_t ek = L->h_pedge[kSides * p + k], em = L->h_pedge[kSides * p + m];
+                            if (ek < 0 || em < 0) continue;
                             double dot = 0;
                             for (int t = 0; t < 3; ++t)
-                                dot += L->h_pcoef[9 * p + 3 * k + t] * L->h_pcoef[9 * p + 3 * m + t];
-                            addB(L->h_pedge[3 * p + k], L->h_pedge[3 * p + m], w * dot);
+                                dot += L->h_pcoef[3 * (kSides * p + k) + t] * L->h_pcoef[3 * (kSides * p + m) + t];
+                            addB(ek, em, w * dot);
                         }
                 }
                 if (precond == 2)

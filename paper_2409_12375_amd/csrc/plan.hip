@@ -284,20 +284,41 @@ __global__ void k_moments(int64_t N, const double *__restrict__ pv, const int32_
     }
 }
 
+__global__ void k_fill(int32_t *__restrict__ p, int64_t n, int32_t v)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// elem_panel_t (NULL for a tree of triangles): element -> panel of the tree;
+// the two elements of a four-sided panel are consecutive in input order, the
+// first goes to iperm, the second to iperm2.
 __global__ void k_concat_panels(int64_t n, int64_t off, int32_t user_off, int32_t vid_off,
-                                const int32_t *__restrict__ perm_t, const double *__restrict__ pv_t,
-                                const int32_t *__restrict__ pvid_t, const double *__restrict__ cen_t,
-                                const double *__restrict__ area_t, const double *__restrict__ diam_t,
-                                int32_t *__restrict__ perm, int32_t *__restrict__ iperm, double *__restrict__ pv,
+                                const int32_t *__restrict__ perm_t, const int32_t *__restrict__ elem_panel_t,
+                                const double *__restrict__ pv_t, const int32_t *__restrict__ pvid_t,
+                                const double *__restrict__ cen_t, const double *__restrict__ area_t,
+                                const double *__restrict__ diam_t, int32_t *__restrict__ perm,
+                                int32_t *__restrict__ iperm, int32_t *__restrict__ iperm2, double *__restrict__ pv,
                                 int32_t *__restrict__ pvid, double *__restrict__ cen, double *__restrict__ area,
                                 double *__restrict__ diam)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t g = off + i;
-    const int32_t u = user_off + perm_t[i];
-    perm[g] = u;
-    iperm[u] = (int32_t)g;
+    const int32_t oe = perm_t[i];
+    if (elem_panel_t) {
+        const int32_t up = elem_panel_t[oe];
+        const int32_t u = user_off + up;
+        perm[g] = u;
+        if (oe > 0 && elem_panel_t[oe - 1] == up)
+            iperm2[u] = (int32_t)g;
+        else
+            iperm[u] = (int32_t)g;
+    } else {
+        const int32_t u = user_off + oe;
+        perm[g] = u;
+        iperm[u] = (int32_t)g;
+    }
     for (int j = 0; j < 9; ++j) pv[9 * g + j] = pv_t[9 * i + j];
     for (int j = 0; j < 3; ++j) {
         pvid[3 * g + j] = vid_off + pvid_t[3 * i + j];
@@ -413,16 +434,28 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     const int ntrees = (int)P->trees.size();
     // ---------------- global panels
     P->panel_off.assign(ntrees + 1, 0);
+    P->user_off.assign(ntrees + 1, 0);
     std::vector<int64_t> vid_off(ntrees + 1, 0);
+    bool hybrid = false;
     for (int t = 0; t < ntrees; ++t) {
         P->panel_off[t + 1] = P->panel_off[t] + P->trees[t]->N;
+        P->user_off[t + 1] = P->user_off[t] + P->trees[t]->Np;
         vid_off[t + 1] = vid_off[t] + P->trees[t]->nv;
+        hybrid |= P->trees[t]->elem_panel.p != nullptr;
     }
     XRL_CHECK(P->panel_off[ntrees] < (int64_t(1) << 31) && vid_off[ntrees] < (int64_t(1) << 31), XRL_E_UNSUPPORTED,
               "xrl_fmm_plan: more than 2^31 panels or vertices in one plan");
     const int64_t N = P->N = P->panel_off[ntrees];
+    const int64_t Nu = P->Nu = P->user_off[ntrees];
     P->perm.alloc(N);
-    P->iperm.alloc(N);
+    P->iperm.alloc(Nu);
+    if (hybrid) {
+        P->iperm2.alloc(Nu);
+        k_fill<<<cdiv(Nu, 256), 256, 0, s>>>(P->iperm2.p, Nu, -1);
+        XRL_HIP(hipGetLastError());
+    } else {
+        P->iperm2.release();
+    }
     P->pv.alloc(9 * N);
     P->pvid.alloc(3 * N);
     P->cen.alloc(3 * N);
@@ -430,10 +463,11 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     P->diam.alloc(N);
     for (int t = 0; t < ntrees; ++t) {
         const xrl_tree *T = P->trees[t];
-        k_concat_panels<<<cdiv(T->N, 256), 256, 0, s>>>(T->N, P->panel_off[t], (int32_t)P->panel_off[t],
-                                                        (int32_t)vid_off[t], T->perm.p, T->pv.p, T->pvid.p, T->cen.p,
-                                                        T->area.p, T->diam.p, P->perm.p, P->iperm.p, P->pv.p,
-                                                        P->pvid.p, P->cen.p, P->area.p, P->diam.p);
+        k_concat_panels<<<cdiv(T->N, 256), 256, 0, s>>>(T->N, P->panel_off[t], (int32_t)P->user_off[t],
+                                                        (int32_t)vid_off[t], T->perm.p, T->elem_panel.p, T->pv.p,
+                                                        T->pvid.p, T->cen.p, T->area.p, T->diam.p, P->perm.p,
+                                                        P->iperm.p, P->iperm2.p, P->pv.p, P->pvid.p, P->cen.p,
+                                                        P->area.p, P->diam.p);
         XRL_HIP(hipGetLastError());
     }
     // ---------------- global boxes, level-major across trees
@@ -867,7 +901,8 @@ extern "C" xrl_status xrl_plan_get_info(const xrl_plan *P, xrl_plan_info *info)
 {
     return guarded([&] {
         XRL_CHECK(P && info, XRL_E_INVALID_ARG, "xrl_plan_get_info: null argument");
-        info->n_panels = P->N;
+        info->n_panels = P->Nu;
+        info->n_elements = P->N;
         info->n_boxes = P->B;
         info->n_leaves = P->n_leaves;
         info->n_m2l_pairs = P->n_m2l;

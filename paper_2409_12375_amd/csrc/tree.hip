@@ -11,6 +11,7 @@
 #include <mutex>
 
 #include "common.h"
+#include "scan.h"
 
 namespace xrl {
 
@@ -234,6 +235,33 @@ __global__ void k_child_bounds(const uint64_t *__restrict__ code, const int32_t 
     bounds[9 * b + 8] = end[b];
 }
 
+// Hybrid meshes: one element per triangle row, two per four-sided panel
+// (a, b, c, d) -> (a, b, c), (a, c, d).
+__global__ void k_elem_count(const int32_t *__restrict__ Q, int64_t N, int32_t *__restrict__ cnt)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < N) cnt[p] = Q[4 * p + 3] >= 0 ? 2 : 1;
+}
+
+__global__ void k_split_panels(const int32_t *__restrict__ Q, int64_t N, const int64_t *__restrict__ off,
+                               int32_t *__restrict__ T, int32_t *__restrict__ elem_panel)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int32_t a = Q[4 * p], b = Q[4 * p + 1], c = Q[4 * p + 2], d = Q[4 * p + 3];
+    const int64_t e = off[p];
+    T[3 * e] = a;
+    T[3 * e + 1] = b;
+    T[3 * e + 2] = c;
+    elem_panel[e] = (int32_t)p;
+    if (d >= 0) {
+        T[3 * e + 3] = a;
+        T[3 * e + 4] = c;
+        T[3 * e + 5] = d;
+        elem_panel[e + 1] = (int32_t)p;
+    }
+}
+
 }  // namespace xrl
 
 using namespace xrl;
@@ -256,19 +284,41 @@ extern "C" xrl_status xrl_tree_build(const xrl_mesh_desc *mesh, int32_t max_leaf
                   "xrl_tree_build: max_leaf must be in 1..%d (got %d)", kMaxLeaf, max_leaf);
         XRL_CHECK(max_depth >= 1 && max_depth <= kMaxDepth, XRL_E_INVALID_ARG,
                   "xrl_tree_build: max_depth must be in 1..21 (got %d)", max_depth);
+        const int vpp = mesh->verts_per_panel == 0 ? 3 : mesh->verts_per_panel;
+        XRL_CHECK(vpp == 3 || vpp == 4, XRL_E_INVALID_ARG, "xrl_tree_build: verts_per_panel must be 3 or 4 (got %d)",
+                  mesh->verts_per_panel);
         hipStream_t s = (hipStream_t)stream;
         const AllocStream alloc_scope(s);
-        const int64_t N = mesh->n_panels, nv = mesh->n_vertices;
+        const int64_t Np = mesh->n_panels, nv = mesh->n_vertices;
         auto t = std::make_unique<xrl_tree>();
-        t->N = N;
+        t->Np = Np;
         t->nv = nv;
         t->max_leaf = max_leaf;
         t->max_depth = max_depth;
         DevBuf<double> V(3 * nv);
-        DevBuf<int32_t> T(3 * N);
         hipMemcpyKind kind = mesh->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
         XRL_HIP(hipMemcpyAsync(V.p, mesh->vertices, V.bytes(), kind, s));
-        XRL_HIP(hipMemcpyAsync(T.p, mesh->tris, T.bytes(), kind, s));
+        DevBuf<int32_t> T;
+        int64_t N = Np;
+        if (vpp == 3) {
+            T.alloc(3 * Np);
+            XRL_HIP(hipMemcpyAsync(T.p, mesh->tris, T.bytes(), kind, s));
+        } else {
+            // elements: the triangles of every panel, in panel order
+            DevBuf<int32_t> Q(4 * Np), cnt(Np);
+            DevBuf<int64_t> off(Np), tot(1);
+            XRL_HIP(hipMemcpyAsync(Q.p, mesh->tris, Q.bytes(), kind, s));
+            k_elem_count<<<cdiv(Np, 256), 256, 0, s>>>(Q.p, Np, cnt.p);
+            XRL_HIP(hipGetLastError());
+            exclusive_scan<int32_t, int64_t>(cnt.p, Np, off.p, tot.p, s);
+            N = tot.download(s)[0];
+            XRL_CHECK(N < (int64_t(1) << 31), XRL_E_INVALID_ARG, "xrl_tree_build: more than 2^31 elements");
+            T.alloc(3 * N);
+            t->elem_panel.alloc(N);
+            k_split_panels<<<cdiv(Np, 256), 256, 0, s>>>(Q.p, Np, off.p, T.p, t->elem_panel.p);
+            XRL_HIP(hipGetLastError());
+        }
+        t->N = N;
         DevBuf<double> cen0(3 * N), area0(N), diam0(N);
         DevBuf<int> flags(1);
         XRL_HIP(hipMemsetAsync(flags.p, 0, sizeof(int), s));
@@ -400,7 +450,8 @@ extern "C" xrl_status xrl_tree_get_info(const xrl_tree *t, xrl_tree_info *info)
 {
     return guarded([&] {
         XRL_CHECK(t && info, XRL_E_INVALID_ARG, "xrl_tree_get_info: null argument");
-        info->n_panels = t->N;
+        info->n_panels = t->Np;
+        info->n_elements = t->N;
         info->n_boxes = (int64_t)t->box_key.size();
         int64_t nl = 0;
         for (size_t b = 0; b < t->box_nchild.size(); ++b) nl += t->box_nchild[b] == 0;

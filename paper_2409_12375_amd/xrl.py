@@ -31,12 +31,14 @@ class XrlError(RuntimeError):
 
 
 class MeshDesc(ctypes.Structure):
-    _fields_ = [("n_vertices", _i64), ("n_panels", _i64), ("vertices", _vp), ("tris", _vp), ("on_device", _i32)]
+    _fields_ = [("n_vertices", _i64), ("n_panels", _i64), ("vertices", _vp), ("tris", _vp), ("on_device", _i32),
+                ("verts_per_panel", _i32)]
 
 
 class TreeInfo(ctypes.Structure):
     _fields_ = [("n_panels", _i64), ("n_boxes", _i64), ("n_leaves", _i64), ("depth", _i32),
-                ("n_overfull_leaves", _i32), ("root_center", ctypes.c_double * 3), ("root_size", ctypes.c_double)]
+                ("n_overfull_leaves", _i32), ("root_center", ctypes.c_double * 3), ("root_size", ctypes.c_double),
+                ("n_elements", _i64)]
 
 
 class TuneResult(ctypes.Structure):
@@ -54,7 +56,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("n_panels", _i64), ("n_boxes", _i64), ("n_leaves", _i64), ("n_m2l_pairs", _i64),
                 ("n_near_rows", _i64), ("n_near_entries", _i64), ("n_near_pairs", _i64), ("order", _i32),
                 ("precision", _i32), ("max_sep_ratio", ctypes.c_double), ("n_demoted_pairs", _i64),
-                ("theta", ctypes.c_double)]
+                ("theta", ctypes.c_double), ("n_elements", _i64)]
 
 
 class Mlp(ctypes.Structure):
@@ -202,9 +204,12 @@ class Tree:
     """Octree over one mesh (xrl_tree_build)."""
 
     def __init__(self, V, T, max_leaf=64, max_depth=21, stream=None):
+        """T: [N][3] triangles, or [N][4] panels of a hybrid mesh (-1 as the
+        fourth index of a triangle)."""
         self._V = np.ascontiguousarray(V, dtype=np.float64)
         self._T = np.ascontiguousarray(T, dtype=np.int32)
-        d = MeshDesc(self._V.shape[0], self._T.shape[0], self._V.ctypes.data, self._T.ctypes.data, 0)
+        d = MeshDesc(self._V.shape[0], self._T.shape[0], self._V.ctypes.data, self._T.ctypes.data, 0,
+                     self._T.shape[1])
         h = _vp()
         _check(lib().xrl_tree_build(ctypes.byref(d), max_leaf, max_depth, _stream(stream), ctypes.byref(h)))
         self.h = h
@@ -488,7 +493,8 @@ class Loops:
     def __init__(self, V, T, stream=None):
         self._V = np.ascontiguousarray(V, dtype=np.float64)
         self._T = np.ascontiguousarray(T, dtype=np.int32)
-        d = MeshDesc(self._V.shape[0], self._T.shape[0], self._V.ctypes.data, self._T.ctypes.data, 0)
+        d = MeshDesc(self._V.shape[0], self._T.shape[0], self._V.ctypes.data, self._T.ctypes.data, 0,
+                     self._T.shape[1])
         h = _vp()
         _check(lib().xrl_loops_build(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
         self.h = h
