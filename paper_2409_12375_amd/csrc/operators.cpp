@@ -40,6 +40,31 @@ static double snm(int n, int m)
     return std::sqrt(fact(n + m) * fact(n - m));
 }
 
+// s_nm for every (n, m) up to degree P, index n*n + n + m.
+static std::vector<double> snm_table(int P)
+{
+    std::vector<double> t((P + 1) * (P + 1));
+    for (int n = 0; n <= P; ++n)
+        for (int m = -n; m <= n; ++m) t[n * n + n + m] = snm(n, m);
+    return t;
+}
+
+// Nonzero coefficients (n, m, value) of an expansion, in (n, m) order: a
+// real unit vector has at most two, so the operators built by probing cost
+// O(K) per column instead of O(K^2).
+struct Term {
+    int n, m;
+    cd v;
+};
+static std::vector<Term> nonzeros(const std::vector<cd> &c, int p)
+{
+    std::vector<Term> t;
+    for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m)
+            if (c[n * n + n + m] != cd(0.0)) t.push_back({n, m, c[n * n + n + m]});
+    return t;
+}
+
 // Associated Legendre P_n^m(c), m >= 0, with the Condon-Shortley phase.
 static void legendre(int P, double c, std::vector<double> &out)
 {
@@ -109,12 +134,6 @@ static void to_real(int p, const std::vector<cd> &c, double *x)
         }
     }
 }
-static cd get(const std::vector<cd> &c, int p, int n, int m)
-{
-    if (n < 0 || n > p || std::abs(m) > n) return 0.0;
-    return c[n * n + n + m];
-}
-
 // Dense real operator: out = A in, A[K][K] row-major (row = output index),
 // built by applying `apply` to the K real unit vectors.
 template <class F>
@@ -146,17 +165,19 @@ void build_m2m(int p, double *out /* [8][K][K] */)
         double u[3];
         octant_shift(d, u);
         Harm R = harmonics(p, u, false);
+        const std::vector<double> sn = snm_table(p);
         probe(
             p,
             [&](const std::vector<cd> &M) {
                 std::vector<cd> O((p + 1) * (p + 1), 0.0);
+                const std::vector<Term> nz = nonzeros(M, p);
                 for (int n = 0; n <= p; ++n)
                     for (int m = -n; m <= n; ++m) {
                         cd acc = 0;
-                        for (int j = 0; j <= n; ++j)
-                            for (int k = -j; k <= j; ++k)
-                                acc += snm(n, m) / snm(j, k) * std::conj(R(n - j, m - k)) * std::pow(0.5, j) *
-                                       get(M, p, j, k);
+                        for (const Term &t : nz)
+                            if (t.n <= n)
+                                acc += sn[n * n + n + m] / sn[t.n * t.n + t.n + t.m] * std::conj(R(n - t.n, m - t.m)) *
+                                       std::pow(0.5, t.n) * t.v;
                         O[n * n + n + m] = acc;
                     }
                 return O;
@@ -172,17 +193,19 @@ void build_l2l(int p, double *out /* [8][K][K] */)
         double u[3];
         octant_shift(d, u);
         Harm R = harmonics(p, u, false);
+        const std::vector<double> sn = snm_table(p);
         probe(
             p,
             [&](const std::vector<cd> &L) {
                 std::vector<cd> O((p + 1) * (p + 1), 0.0);
+                const std::vector<Term> nz = nonzeros(L, p);
                 for (int j = 0; j <= p; ++j)
                     for (int k = -j; k <= j; ++k) {
                         cd acc = 0;
-                        for (int n = j; n <= p; ++n)
-                            for (int m = -n; m <= n; ++m)
-                                acc += snm(n, m) / snm(j, k) * R(n - j, m - k) * std::pow(0.5, j + 1) *
-                                       get(L, p, n, m);
+                        for (const Term &t : nz)
+                            if (t.n >= j)
+                                acc += sn[t.n * t.n + t.n + t.m] / sn[j * j + j + k] * R(t.n - j, t.m - k) *
+                                       std::pow(0.5, j + 1) * t.v;
                         O[j * j + j + k] = acc;
                     }
                 return O;
@@ -196,16 +219,17 @@ void build_m2l(int p, int ox, int oy, int oz, double *out /* [K][K] */)
 {
     double u[3] = {(double)ox, (double)oy, (double)oz};
     Harm I = harmonics(2 * p, u, true);
+    const std::vector<double> sn = snm_table(p);
     probe(
         p,
         [&](const std::vector<cd> &M) {
             std::vector<cd> O((p + 1) * (p + 1), 0.0);
+            const std::vector<Term> nz = nonzeros(M, p);
             for (int j = 0; j <= p; ++j)
                 for (int k = -j; k <= j; ++k) {
                     cd acc = 0;
-                    for (int n = 0; n <= p; ++n)
-                        for (int m = -n; m <= n; ++m)
-                            acc += get(M, p, n, m) * I(n + j, m - k) / (snm(j, k) * snm(n, m));
+                    for (const Term &t : nz)
+                        acc += t.v * I(t.n + j, t.m - k) / (sn[j * j + j + k] * sn[t.n * t.n + t.n + t.m]);
                     O[j * j + j + k] = (((j + k) & 1) ? -1.0 : 1.0) * acc;
                 }
             return O;

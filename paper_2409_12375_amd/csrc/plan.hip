@@ -13,7 +13,6 @@
 //         leaf below B
 // so the near field of a target leaf is U(T), W(T) and X of T and of all its
 // ancestors, each given as a contiguous range of Morton-sorted panels.
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <array>
@@ -23,6 +22,7 @@
 #include <numeric>
 
 #include "common.h"
+#include "scan.h"
 #include "harmonics.h"
 
 namespace xrl {
@@ -216,6 +216,77 @@ __global__ void k_nearlist(BoxView bv, const int32_t *__restrict__ leaves, int64
     if (!out) cnt[li] = n;
 }
 
+// Source boxes of each leaf's near field: its U, W and X boxes (nbox) and
+// the sources of the pairs demoted to the near field at the leaf or at any
+// of its ancestors (every leaf below a demoted target takes the source's
+// panels), sorted by their first panel so the rows come in Morton order.
+// Count pass (soff NULL), then fill pass.
+__global__ void k_leaf_sources(const int32_t *__restrict__ leaves, int64_t nleaf, const int32_t *__restrict__ parent,
+                               const int64_t *__restrict__ noff, const int32_t *__restrict__ nbox,
+                               const int64_t *__restrict__ doff, const int32_t *__restrict__ dsrc,
+                               const int32_t *__restrict__ beg, const int32_t *__restrict__ end,
+                               const int64_t *__restrict__ soff, int32_t *__restrict__ cnt,
+                               int32_t *__restrict__ nrow, int32_t *__restrict__ sbox)
+{
+    const int64_t li = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (li >= nleaf) return;
+    const int32_t T = leaves[li];
+    if (!soff) {
+        int64_t n = noff[li + 1] - noff[li], r = 0;
+        for (int64_t j = noff[li]; j < noff[li + 1]; ++j) r += end[nbox[j]] - beg[nbox[j]];
+        for (int32_t A = T; A >= 0; A = parent[A]) {
+            n += doff[A + 1] - doff[A];
+            for (int64_t j = doff[A]; j < doff[A + 1]; ++j) r += end[dsrc[j]] - beg[dsrc[j]];
+        }
+        cnt[li] = (int32_t)n;
+        nrow[li] = (int32_t)min(r, (int64_t)INT32_MAX);
+        return;
+    }
+    int32_t *out = sbox + soff[li];
+    int n = 0;
+    auto put = [&](int32_t b) {
+        // insertion by first panel (lists hold tens of boxes)
+        int i = n++;
+        while (i > 0 && beg[out[i - 1]] > beg[b]) {
+            out[i] = out[i - 1];
+            --i;
+        }
+        out[i] = b;
+    };
+    for (int64_t j = noff[li]; j < noff[li + 1]; ++j) put(nbox[j]);
+    for (int32_t A = T; A >= 0; A = parent[A])
+        for (int64_t j = doff[A]; j < doff[A + 1]; ++j) put(dsrc[j]);
+}
+
+// Rows of each leaf's block: the panels of its source boxes in order
+// (one workgroup per leaf).
+__global__ void k_leaf_rows(int64_t nleaf, const int64_t *__restrict__ soff, const int32_t *__restrict__ sbox,
+                            const int32_t *__restrict__ beg, const int32_t *__restrict__ end,
+                            const int32_t *__restrict__ rows_ptr, int32_t *__restrict__ src)
+{
+    const int64_t li = blockIdx.x;
+    if (li >= nleaf) return;
+    int32_t at = rows_ptr[li];
+    for (int64_t j = soff[li]; j < soff[li + 1]; ++j) {
+        const int32_t b0 = beg[sbox[j]], nb = end[sbox[j]] - b0;
+        for (int32_t k = threadIdx.x; k < nb; k += blockDim.x) src[at + k] = b0 + k;
+        at += nb;
+    }
+}
+
+// Per leaf: block padding (targets rounded up to 16) and its value count.
+__global__ void k_leaf_blocks(int64_t nleaf, const int32_t *__restrict__ leaves, const int32_t *__restrict__ beg,
+                              const int32_t *__restrict__ end, const int32_t *__restrict__ nrow,
+                              int32_t *__restrict__ tpad, int64_t *__restrict__ nval, int64_t *__restrict__ npair)
+{
+    const int64_t li = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (li >= nleaf) return;
+    const int32_t nt = end[leaves[li]] - beg[leaves[li]];
+    tpad[li] = 16 * ((nt + 15) / 16);
+    nval[li] = (int64_t)nrow[li] * tpad[li];
+    npair[li] = (int64_t)nrow[li] * nt;
+}
+
 // Panel-inclusive radius of every box about its centre.
 __global__ void k_box_radius(int64_t B, const int32_t *__restrict__ beg, const int32_t *__restrict__ end,
                              const double *__restrict__ center, const double *__restrict__ pv,
@@ -282,6 +353,70 @@ __global__ void k_moments(int64_t N, const double *__restrict__ pv, const int32_
         mom64[(size_t)k * K + i] = acc[i];
         mom32[(size_t)k * K + i] = (float)acc[i];
     }
+}
+
+// Operator layouts, from the padded FP64 tables pad[op][KP][KK] (row =
+// output coefficient) on the device; one thread per output element.
+//   fragment order (16x16x4 MFMA A operand): [op][rt][ks][lane],
+//     lane = row % 16 + 16 (k % 4), row = 16 rt + lane % 16, k = 4 ks + lane / 16
+//   k-major (vector ALU): [op][k][row]
+//   vector fragment order: [op][rt][ks / vec][lane][ks % vec], zero past the
+//     last k step
+//   last row (K - 1) by k lane group: [op][kq][ks] padded to a multiple of vec
+template <typename TO>
+__global__ void k_lay_frag(const double *__restrict__ pad, int64_t n, int KP, int KK, TO *__restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int nks = KK / 4, nrt = KP / 16;
+    const int lane = (int)(i & 63);
+    const int64_t q = i >> 6;
+    const int ks = (int)(q % nks), rt = (int)((q / nks) % nrt);
+    const int64_t c = q / ((int64_t)nks * nrt);
+    out[i] = (TO)pad[(c * KP + rt * 16 + (lane & 15)) * KK + 4 * ks + (lane >> 4)];
+}
+
+template <typename TO>
+__global__ void k_lay_kmaj(const double *__restrict__ pad, int64_t n, int KP, int KK, TO *__restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int r = (int)(i % KP), k = (int)((i / KP) % KK);
+    const int64_t c = i / ((int64_t)KP * KK);
+    out[i] = (TO)pad[(c * KP + r) * KK + k];
+}
+
+template <typename TO>
+__global__ void k_lay_vec(const double *__restrict__ pad, int64_t n, int KP, int KK, int vec, TO *__restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int nks = KK / 4, nrt = KP / 16, nkv = (nks + vec - 1) / vec;
+    const int e = (int)(i % vec);
+    const int lane = (int)((i / vec) & 63);
+    const int64_t q = i / vec / 64;
+    const int kv = (int)(q % nkv), rt = (int)((q / nkv) % nrt);
+    const int64_t c = q / ((int64_t)nkv * nrt);
+    const int ks = kv * vec + e;
+    out[i] = ks < nks ? (TO)pad[(c * KP + rt * 16 + (lane & 15)) * KK + 4 * ks + (lane >> 4)] : TO(0);
+}
+
+template <typename TO>
+__global__ void k_lay_last(const double *__restrict__ pad, int64_t n, int KP, int KK, int K, int vec,
+                           TO *__restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int nks = KK / 4, w = ((nks + vec - 1) / vec) * vec;
+    const int ks = (int)(i % w), kq = (int)((i / w) % 4);
+    const int64_t c = i / ((int64_t)w * 4);
+    out[i] = ks < nks ? (TO)pad[(c * KP + K - 1) * KK + 4 * ks + kq] : TO(0);
+}
+
+__global__ void k_to_f32(const double *__restrict__ in, int64_t n, float *__restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
 }
 
 __global__ void k_fill(int32_t *__restrict__ p, int64_t n, int32_t v)
@@ -354,14 +489,31 @@ static int32_t m2l_reflected_code(int32_t slot)
 // itself, no reflection.  That kernel visits the pairs of a target sorted by
 // reflection bits (then in input order), so its accumulator changes frame
 // at most seven times per target.
+// Stable counting sort of idx[0..n) by key(idx) in [0, nkey): O(n + nkey).
+template <class Key>
+static void counting_sort(int32_t *idx, int64_t n, int nkey, Key key, std::vector<int64_t> &cnt,
+                          std::vector<int32_t> &tmp)
+{
+    cnt.assign(nkey + 1, 0);
+    for (int64_t j = 0; j < n; ++j) ++cnt[key(idx[j]) + 1];
+    for (int k = 0; k < nkey; ++k) cnt[k + 1] += cnt[k];
+    tmp.resize(n);
+    for (int64_t j = 0; j < n; ++j) tmp[cnt[key(idx[j])]++] = idx[j];
+    std::copy(tmp.begin(), tmp.begin() + n, idx);
+}
+
 static void build_pass(TransPass &T, const std::vector<int32_t> &tgt, const std::vector<int32_t> &src,
                        const std::vector<int32_t> &code, hipStream_t s, const std::vector<int32_t> &ts_code = {})
 {
     const int64_t n = (int64_t)tgt.size();
     T.n_pairs = n;
+    std::vector<int64_t> cnt;
+    std::vector<int32_t> tmp;
     std::vector<int32_t> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+    int ncode = 1;
+    for (int32_t c : code) ncode = std::max(ncode, c + 1);
+    counting_sort(ord.data(), n, ncode, [&](int32_t a) { return code[a]; }, cnt, tmp);
     std::vector<int32_t> osrc(n), slot(n), goff, gbeg;
     for (int64_t j = 0; j < n; ++j) {
         osrc[j] = src[ord[j]];
@@ -394,8 +546,7 @@ static void build_pass(TransPass &T, const std::vector<int32_t> &tgt, const std:
     for (int64_t j = 0; j < n; ++j) c8[j] = ts_code.empty() ? code[j] << 3 : ts_code[j];
     std::iota(tord.begin(), tord.end(), 0);
     for (size_t i = 0; i + 1 < rp.size(); ++i)
-        std::stable_sort(tord.begin() + rp[i], tord.begin() + rp[i + 1],
-                         [&](int32_t a, int32_t b) { return (c8[a] & 7) < (c8[b] & 7); });
+        counting_sort(tord.data() + rp[i], rp[i + 1] - rp[i], 8, [&](int32_t a) { return c8[a] & 7; }, cnt, tmp);
     std::vector<int32_t> tcode(n);
     for (int64_t j = 0; j < n; ++j) {
         tsrc[j] = src[tord[j]];
@@ -414,10 +565,13 @@ static void build_pass(TransPass &T, const std::vector<int32_t> &tgt, const std:
     T.n_ps = n > 0 ? (int64_t)psb.size() - 1 : 0;
     T.ts_tgt.upload(ttgt, s);
     T.ps_beg.upload(psb, s);
+    // targets with the most pairs first (ties in target order)
     std::vector<int32_t> heavy(rt.size());
     std::iota(heavy.begin(), heavy.end(), 0);
-    std::stable_sort(heavy.begin(), heavy.end(),
-                     [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+    int32_t maxc = 0;
+    for (size_t i = 0; i + 1 < rp.size(); ++i) maxc = std::max(maxc, rp[i + 1] - rp[i]);
+    counting_sort(heavy.data(), (int64_t)heavy.size(), maxc + 1,
+                  [&](int32_t a) { return maxc - (rp[a + 1] - rp[a]); }, cnt, tmp);
     T.ts_order.upload(heavy, s);
     if (!ts_code.empty()) {
         for (int64_t j = 0; j < n; ++j) tcode[j] = code[tord[j]] << 3;
@@ -586,75 +740,63 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     XRL_HIP(hipGetLastError());
     auto hsrc = vsrc.download(s, nV);
     auto hcode = vcode.download(s, nV);
-    auto hdsrc = dsrc.download(s, doff[B]);
-    // demoted pairs (t, s): every leaf below t gets the panels of s as near sources
-    std::vector<int32_t> leaf_of_panel(N, -1);
-    for (size_t li = 0; li < leaves.size(); ++li)
-        for (int32_t k = beg[leaves[li]]; k < end[leaves[li]]; ++k) leaf_of_panel[k] = (int32_t)li;
-    std::vector<std::vector<int32_t>> extra(leaves.size());
-    for (int64_t b = 0; b < B; ++b)
-        for (int64_t j = doff[b]; j < doff[b + 1]; ++j)
-            for (int32_t k = beg[b]; k < end[b];) {
-                const int32_t li = leaf_of_panel[k];
-                extra[li].push_back(hdsrc[j]);
-                k = end[leaves[li]];
-            }
-    // ---------------- near lists (source boxes), then rows
-    DevBuf<int32_t> ncnt(P->n_leaves);
-    k_nearlist<<<cdiv(P->n_leaves, 64), 64, 0, s>>>(bv, P->leaf_box.p, P->n_leaves, coll.p, ncnt.p, nullptr,
-                                                     nullptr);
-    XRL_HIP(hipGetLastError());
-    auto hn = ncnt.download(s);
-    std::vector<int64_t> noff(P->n_leaves + 1, 0);
-    for (int64_t i = 0; i < P->n_leaves; ++i) noff[i + 1] = noff[i] + hn[i];
-    DevBuf<int64_t> dnoff;
-    dnoff.upload(noff, s);
-    DevBuf<int32_t> nbox(std::max<int64_t>(noff.back(), 1));
-    k_nearlist<<<cdiv(P->n_leaves, 64), 64, 0, s>>>(bv, P->leaf_box.p, P->n_leaves, coll.p, ncnt.p, dnoff.p,
-                                                     nbox.p);
-    XRL_HIP(hipGetLastError());
-    auto hnbox = nbox.download(s, noff.back());
-    // rows
-    std::vector<int32_t> rows_ptr(P->n_leaves + 1, 0), src_rows;
-    std::vector<int64_t> val_off(P->n_leaves + 1, 0);
-    std::vector<int32_t> tpad(P->n_leaves);
-    int64_t pairs = 0;
-    for (int64_t li = 0; li < P->n_leaves; ++li) {
-        const int32_t T = leaves[li];
-        const int nt = end[T] - beg[T];
-        // the near-field block of a leaf holds at most 64 targets; a leaf can
-        // exceed that only at the maximum depth (centroids closer than the
-        // root size / 2^21), which is refused rather than mis-stored
-        XRL_CHECK(nt <= kMaxLeaf, XRL_E_UNSUPPORTED,
+    // ---------------- near lists (source boxes), then rows, all on the device
+    const int64_t nl = P->n_leaves;
+    for (int64_t li = 0; li < nl; ++li)
+        XRL_CHECK(end[leaves[li]] - beg[leaves[li]] <= kMaxLeaf, XRL_E_UNSUPPORTED,
                   "xrl_fmm_plan: a leaf at the maximum depth holds %d panels (more than %d); "
                   "the mesh has (nearly) coincident panel centroids",
-                  nt, kMaxLeaf);
-        // block rows padded to the next multiple of 16 targets (one MFMA tile)
-        tpad[li] = 16 * (int32_t)cdiv(nt, 16);
-        // sort source boxes by their panel range so the rows are in Morton order
-        std::vector<std::pair<int32_t, int32_t>> rg;
-        for (int64_t j = noff[li]; j < noff[li + 1]; ++j) rg.push_back({beg[hnbox[j]], end[hnbox[j]]});
-        for (int32_t sb : extra[li]) rg.push_back({beg[sb], end[sb]});
-        std::sort(rg.begin(), rg.end());
-        int64_t nrow = 0;
-        for (auto &r : rg) {
-            for (int32_t k = r.first; k < r.second; ++k) src_rows.push_back(k);
-            nrow += r.second - r.first;
-        }
-        XRL_CHECK((int64_t)src_rows.size() < (int64_t(1) << 31), XRL_E_UNSUPPORTED,
-                  "xrl_fmm_plan: near-field row count overflows int32");
-        rows_ptr[li + 1] = (int32_t)src_rows.size();
-        val_off[li + 1] = val_off[li] + nrow * tpad[li];
-        pairs += nrow * nt;
-    }
-    P->h_near_rows = rows_ptr;
-    P->n_near_rows = (int64_t)src_rows.size();
-    P->n_near_entries = val_off.back();
-    P->n_near_pairs = pairs;
+                  end[leaves[li]] - beg[leaves[li]], kMaxLeaf);
+    DevBuf<int32_t> ncnt(std::max<int64_t>(nl, 1));
+    k_nearlist<<<cdiv(nl, 64), 64, 0, s>>>(bv, P->leaf_box.p, nl, coll.p, ncnt.p, nullptr, nullptr);
+    XRL_HIP(hipGetLastError());
+    DevBuf<int64_t> dnoff(nl + 1), tot(1);
+    exclusive_scan<int32_t, int64_t>(ncnt.p, nl, dnoff.p, tot.p, s);
+    XRL_HIP(hipMemcpyAsync(dnoff.p + nl, tot.p, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    const int64_t n_nbox = tot.download(s)[0];
+    DevBuf<int32_t> nbox(std::max<int64_t>(n_nbox, 1));
+    k_nearlist<<<cdiv(nl, 64), 64, 0, s>>>(bv, P->leaf_box.p, nl, coll.p, ncnt.p, dnoff.p, nbox.p);
+    XRL_HIP(hipGetLastError());
+    // with the demoted pairs: boxes and rows per leaf
+    DevBuf<int32_t> scnt(std::max<int64_t>(nl, 1)), nrow(std::max<int64_t>(nl, 1));
+    k_leaf_sources<<<cdiv(nl, 64), 64, 0, s>>>(P->leaf_box.p, nl, P->box_parent.p, dnoff.p, nbox.p, ddoff.p, dsrc.p,
+                                                P->box_beg.p, P->box_end.p, nullptr, scnt.p, nrow.p, nullptr);
+    XRL_HIP(hipGetLastError());
+    DevBuf<int64_t> soff(nl + 1), rows64(nl + 1);
+    exclusive_scan<int32_t, int64_t>(scnt.p, nl, soff.p, tot.p, s);
+    XRL_HIP(hipMemcpyAsync(soff.p + nl, tot.p, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    const int64_t n_sbox = tot.download(s)[0];
+    DevBuf<int32_t> sbox(std::max<int64_t>(n_sbox, 1));
+    k_leaf_sources<<<cdiv(nl, 64), 64, 0, s>>>(P->leaf_box.p, nl, P->box_parent.p, dnoff.p, nbox.p, ddoff.p, dsrc.p,
+                                                P->box_beg.p, P->box_end.p, soff.p, scnt.p, nrow.p, sbox.p);
+    XRL_HIP(hipGetLastError());
+    exclusive_scan<int32_t, int64_t>(nrow.p, nl, rows64.p, tot.p, s);
+    const int64_t n_rows = tot.download(s)[0];
+    XRL_CHECK(n_rows < (int64_t(1) << 31), XRL_E_UNSUPPORTED, "xrl_fmm_plan: near-field row count overflows int32");
+    std::vector<int64_t> h_rows64 = rows64.download(s, nl);
+    std::vector<int32_t> rows_ptr(nl + 1);
+    for (int64_t li = 0; li < nl; ++li) rows_ptr[li] = (int32_t)h_rows64[li];
+    rows_ptr[nl] = (int32_t)n_rows;
     P->near_rows.upload(rows_ptr, s);
-    P->near_src.upload(src_rows, s);
-    P->near_val_off.upload(val_off, s);
-    P->leaf_tpad.upload(tpad, s);
+    P->near_src.alloc(std::max<int64_t>(n_rows, 1));
+    k_leaf_rows<<<(unsigned)std::max<int64_t>(nl, 1), 256, 0, s>>>(nl, soff.p, sbox.p, P->box_beg.p, P->box_end.p,
+                                                                    P->near_rows.p, P->near_src.p);
+    XRL_HIP(hipGetLastError());
+    // block padding and value offsets
+    P->leaf_tpad.alloc(std::max<int64_t>(nl, 1));
+    DevBuf<int64_t> nval(std::max<int64_t>(nl, 1)), npair(std::max<int64_t>(nl, 1)), tot2(1);
+    k_leaf_blocks<<<cdiv(nl, 256), 256, 0, s>>>(nl, P->leaf_box.p, P->box_beg.p, P->box_end.p, nrow.p,
+                                                P->leaf_tpad.p, nval.p, npair.p);
+    XRL_HIP(hipGetLastError());
+    P->near_val_off.alloc(nl + 1);
+    exclusive_scan<int64_t, int64_t>(nval.p, nl, P->near_val_off.p, tot.p, s);
+    XRL_HIP(hipMemcpyAsync(P->near_val_off.p + nl, tot.p, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    DevBuf<int64_t> pscan(std::max<int64_t>(nl, 1));
+    exclusive_scan<int64_t, int64_t>(npair.p, nl, pscan.p, tot2.p, s);
+    P->h_near_rows = rows_ptr;
+    P->n_near_rows = n_rows;
+    P->n_near_entries = tot.download(s)[0];
+    P->n_near_pairs = tot2.download(s)[0];
     // ---------------- translation passes: M2L (all levels), M2M and L2L per level
     {
         std::vector<int32_t> tg, sr, cd, rc;
@@ -737,55 +879,42 @@ static void build_plan(xrl_plan *P, hipStream_t s)
         for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
         return f;
     };
-    // fragment order for the 16x16x4 MFMA A operand (lane = row % 16 + 16 (k % 4))
-    // and k-major order for the vector-ALU GEMM, from padded [n_op][KP][KK]
     const int nrt = P->KP / 16, nks = P->KK / 4;
-    auto layouts = [&](const std::vector<double> &pad, int nop, DevBuf<double> &f64, DevBuf<float> &f32,
-                       DevBuf<double> &k64, DevBuf<float> &k32) {
-        std::vector<double> frag(pad.size(), 0.0), kmaj(pad.size(), 0.0);
-        for (int c = 0; c < nop; ++c) {
-            for (int rt = 0; rt < nrt; ++rt)
-                for (int ks = 0; ks < nks; ++ks)
-                    for (int lane = 0; lane < 64; ++lane)
-                        frag[(((size_t)c * nrt + rt) * nks + ks) * 64 + lane] =
-                            pad[((size_t)c * P->KP + rt * 16 + (lane & 15)) * P->KK + 4 * ks + (lane >> 4)];
-            for (int r = 0; r < P->KP; ++r)
-                for (int k = 0; k < P->KK; ++k)
-                    kmaj[((size_t)c * P->KK + k) * P->KP + r] = pad[((size_t)c * P->KP + r) * P->KK + k];
-        }
-        f64.upload(frag, s);
-        f32.upload(to32(frag), s);
-        k64.upload(kmaj, s);
-        k32.upload(to32(kmaj), s);
+    auto grid = [](int64_t n) { return (unsigned)cdiv(n, 256); };
+    // fragment order and k-major order, FP64 and FP32, from a padded table
+    // already on the device
+    auto layouts = [&](const double *pad, int nop, DevBuf<double> &f64, DevBuf<float> &f32, DevBuf<double> &k64,
+                       DevBuf<float> &k32) {
+        const int64_t n = (int64_t)nop * P->KP * P->KK;
+        f64.alloc(n);
+        f32.alloc(n);
+        k64.alloc(n);
+        k32.alloc(n);
+        k_lay_frag<double><<<grid(n), 256, 0, s>>>(pad, n, P->KP, P->KK, f64.p);
+        k_lay_frag<float><<<grid(n), 256, 0, s>>>(pad, n, P->KP, P->KK, f32.p);
+        k_lay_kmaj<double><<<grid(n), 256, 0, s>>>(pad, n, P->KP, P->KK, k64.p);
+        k_lay_kmaj<float><<<grid(n), 256, 0, s>>>(pad, n, P->KP, P->KK, k32.p);
+        XRL_HIP(hipGetLastError());
     };
-    // vector fragment order: element e of the 16-byte vector kv of a lane is
-    // the A operand of k step VEC kv + e (zero past the last step)
-    auto vec_layouts = [&](const std::vector<double> &pad, int nop, DevBuf<double> &v64, DevBuf<float> &v32,
-                           DevBuf<double> *t64 = nullptr, DevBuf<float> *t32 = nullptr) {
+    // vector fragment order (pairs of k steps in FP64, quads in FP32) and the
+    // last-row tables
+    auto vec_layouts = [&](const double *pad, int nop, DevBuf<double> &v64, DevBuf<float> &v32, DevBuf<double> &t64,
+                           DevBuf<float> &t32) {
         for (int vec : {2, 4}) {
             const int nkv = (nks + vec - 1) / vec;
-            if (t64) {
-                std::vector<double> t((size_t)nop * 4 * nkv * vec, 0.0);
-                for (int c = 0; c < nop; ++c)
-                    for (int kq = 0; kq < 4; ++kq)
-                        for (int ks = 0; ks < nks; ++ks)
-                            t[((size_t)c * 4 + kq) * nkv * vec + ks] = pad[((size_t)c * P->KP + K - 1) * P->KK + 4 * ks + kq];
-                if (vec == 2)
-                    t64->upload(t, s);
-                else
-                    t32->upload(to32(t), s);
+            const int64_t nt = (int64_t)nop * 4 * nkv * vec, nv = (int64_t)nop * nrt * nkv * 64 * vec;
+            if (vec == 2) {
+                t64.alloc(nt);
+                v64.alloc(nv);
+                k_lay_last<double><<<grid(nt), 256, 0, s>>>(pad, nt, P->KP, P->KK, K, vec, t64.p);
+                k_lay_vec<double><<<grid(nv), 256, 0, s>>>(pad, nv, P->KP, P->KK, vec, v64.p);
+            } else {
+                t32.alloc(nt);
+                v32.alloc(nv);
+                k_lay_last<float><<<grid(nt), 256, 0, s>>>(pad, nt, P->KP, P->KK, K, vec, t32.p);
+                k_lay_vec<float><<<grid(nv), 256, 0, s>>>(pad, nv, P->KP, P->KK, vec, v32.p);
             }
-            std::vector<double> v((size_t)nop * nrt * nkv * 64 * vec, 0.0);
-            for (int c = 0; c < nop; ++c)
-                for (int rt = 0; rt < nrt; ++rt)
-                    for (int ks = 0; ks < nks; ++ks)
-                        for (int lane = 0; lane < 64; ++lane)
-                            v[((((size_t)c * nrt + rt) * nkv + ks / vec) * 64 + lane) * vec + ks % vec] =
-                                pad[((size_t)c * P->KP + rt * 16 + (lane & 15)) * P->KK + 4 * ks + (lane >> 4)];
-            if (vec == 2)
-                v64.upload(v, s);
-            else
-                v32.upload(to32(v), s);
+            XRL_HIP(hipGetLastError());
         }
     };
     auto padded = [&](const std::vector<double> &dense, int nop) {
@@ -796,7 +925,15 @@ static void build_plan(xrl_plan *P, hipStream_t s)
                     out[((size_t)c * P->KP + r) * P->KK + k] = dense[((size_t)c * K + r) * K + k];
         return out;
     };
-    layouts(m2l, 343, P->op_m2l64f, P->op_m2l32f, P->op_m2l64k, P->op_m2l32k);
+    P->op_m2m64.upload(m2m, s);
+    P->op_l2l64.upload(l2l, s);
+    P->op_m2l64.upload(m2l, s);  // padded [343][KP][KK]
+    P->op_m2m32.upload(to32(m2m), s);
+    P->op_l2l32.upload(to32(l2l), s);
+    P->op_m2l32.alloc(P->op_m2l64.n);
+    k_to_f32<<<grid((int64_t)P->op_m2l64.n), 256, 0, s>>>(P->op_m2l64.p, (int64_t)P->op_m2l64.n, P->op_m2l32.p);
+    XRL_HIP(hipGetLastError());
+    layouts(P->op_m2l64.p, 343, P->op_m2l64f, P->op_m2l32f, P->op_m2l64k, P->op_m2l32k);
     {
         // the non-negative offsets that some used offset reflects onto
         std::vector<double> m2lc(64 * (size_t)P->KP * P->KK, 0.0);
@@ -808,19 +945,19 @@ static void build_plan(xrl_plan *P, hipStream_t s)
             for (int r = 0; r < K; ++r)
                 for (int k = 0; k < K; ++k) m2lc[((size_t)c * P->KP + r) * P->KK + k] = tmp[(size_t)r * K + k];
         }
-        vec_layouts(m2lc, 64, P->op_m2lc64v, P->op_m2lc32v, &P->op_m2lc64t, &P->op_m2lc32t);
-        vec_layouts(m2l, 343, P->op_m2l64v, P->op_m2l32v, &P->op_m2l64t, &P->op_m2l32t);
+        DevBuf<double> dm2lc;
+        dm2lc.upload(m2lc, s);
+        vec_layouts(dm2lc.p, 64, P->op_m2lc64v, P->op_m2lc32v, P->op_m2lc64t, P->op_m2lc32t);
+        vec_layouts(P->op_m2l64.p, 343, P->op_m2l64v, P->op_m2l32v, P->op_m2l64t, P->op_m2l32t);
+        DevBuf<double> pm2m, pl2l;
+        pm2m.upload(padded(m2m, 8), s);
+        pl2l.upload(padded(l2l, 8), s);
+        vec_layouts(pm2m.p, 8, P->op_m2m64v, P->op_m2m32v, P->op_m2m64t, P->op_m2m32t);
+        vec_layouts(pl2l.p, 8, P->op_l2l64v, P->op_l2l32v, P->op_l2l64t, P->op_l2l32t);
+        layouts(pm2m.p, 8, P->op_m2m64f, P->op_m2m32f, P->op_m2m64k, P->op_m2m32k);
+        layouts(pl2l.p, 8, P->op_l2l64f, P->op_l2l32f, P->op_l2l64k, P->op_l2l32k);
+        XRL_HIP(hipStreamSynchronize(s));  // the padded staging tables are released here
     }
-    vec_layouts(padded(m2m, 8), 8, P->op_m2m64v, P->op_m2m32v, &P->op_m2m64t, &P->op_m2m32t);
-    vec_layouts(padded(l2l, 8), 8, P->op_l2l64v, P->op_l2l32v, &P->op_l2l64t, &P->op_l2l32t);
-    layouts(padded(m2m, 8), 8, P->op_m2m64f, P->op_m2m32f, P->op_m2m64k, P->op_m2m32k);
-    layouts(padded(l2l, 8), 8, P->op_l2l64f, P->op_l2l32f, P->op_l2l64k, P->op_l2l32k);
-    P->op_m2m64.upload(m2m, s);
-    P->op_l2l64.upload(l2l, s);
-    P->op_m2l64.upload(m2l, s);
-    P->op_m2m32.upload(to32(m2m), s);
-    P->op_l2l32.upload(to32(l2l), s);
-    P->op_m2l32.upload(to32(m2l), s);
     // ---------------- moments
     const int nq = (p + 3) / 2;  // 2 nq - 2 >= p
     std::vector<double> gx(nq), gw(nq);

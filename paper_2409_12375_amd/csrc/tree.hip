@@ -1,7 +1,6 @@
 // Octree on panel centroids (the FMM of Sec. II-C runs on panel centroids):
-// panel geometry, Morton codes, radix sort and level-by-level splitting, on
-// the device.
-#include <hipcub/hipcub.hpp>
+// panel geometry, Morton codes, radix sort (our own, sort.h) and
+// level-by-level splitting, on the device.
 
 #include <algorithm>
 #include <cmath>
@@ -11,7 +10,7 @@
 #include <mutex>
 
 #include "common.h"
-#include "scan.h"
+#include "sort.h"
 
 namespace xrl {
 
@@ -349,19 +348,15 @@ extern "C" xrl_status xrl_tree_build(const xrl_mesh_desc *mesh, int32_t max_leaf
         for (int d = 0; d < 3; ++d) t->root_c[d] = 0.5 * (mn[d] + mx[d]);
         t->root_size = side;
         // Morton codes and sort
-        DevBuf<uint64_t> code_in(N), code(N);
-        DevBuf<int32_t> idx_in(N);
+        DevBuf<uint64_t> code(N), code_tmp(N);
+        DevBuf<int32_t> idx_tmp(N);
         t->perm.alloc(N);
         const double inv_h = double(1 << kMaxDepth) / side;
         k_morton<<<cdiv(N, bs), bs, 0, s>>>(cen0.p, N, t->root_c[0] - 0.5 * side, t->root_c[1] - 0.5 * side,
-                                            t->root_c[2] - 0.5 * side, inv_h, code_in.p, idx_in.p);
+                                            t->root_c[2] - 0.5 * side, inv_h, code.p, t->perm.p);
         XRL_HIP(hipGetLastError());
-        size_t tmp_bytes = 0;
-        XRL_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, code_in.p, code.p, idx_in.p, t->perm.p,
-                                                   (int)N, 0, 63, s));
-        DevBuf<char> tmp(tmp_bytes);
-        XRL_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp_bytes, code_in.p, code.p, idx_in.p, t->perm.p,
-                                                   (int)N, 0, 63, s));
+        // stable: equal codes keep their input order
+        radix_sort_pairs(code.p, t->perm.p, code_tmp.p, idx_tmp.p, N, 63, s);
         t->pv.alloc(9 * N);
         t->pvid.alloc(3 * N);
         t->cen.alloc(3 * N);
