@@ -260,7 +260,7 @@ def main():
     else:
         mfma = R["precision"] != "fp32"
         roof = {"bound": "mfma" if mfma else "alu",
-                "kernel": "M2L (%s)" % ("k_trans_ts, FP32 MFMA" if mfma else "k_m2l_os_valu, FP32 vector ALU"),
+                "kernel": "M2L (%s)" % ("k_trans_ts, FP32 MFMA" if mfma else "k_m2l_os_col + k_pass_reduce, FP32 vector ALU"),
                 "achieved": R["m2l_tflops"], "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                 "traffic": recorded_traffic() if (args.workload == "bga" and mfma) else None}
     roof["frac"] = roof["achieved"] / roof["peak"]

@@ -387,6 +387,11 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
  *       (C = 16 n + 1 .. 16 n + 4, e.g. 18 complex columns): those columns
  *       on 4x4x1 MFMA blocks beside the n 16x16x4 tiles (1) or in a further,
  *       mostly padded 16x16x4 tile (0).
+ *   XRL_TUNE_VALU_FORM   (0/1, default 1): the vector-ALU offset-stationary
+ *       translations in FP32 up to order 8: one column per thread with all
+ *       (p+1)^2 output rows in registers and the operator read from LDS as
+ *       broadcasts (1), or 16 x 4 register tiles of 6 rows by 4 columns over
+ *       64-column blocks (0).
  * Errors: XRL_E_INVALID_ARG (null plan, unknown key, bad value). */
 #define XRL_TUNE_TS_KERNEL 0
 #define XRL_TUNE_TS_MIN_COLS 1
@@ -396,6 +401,7 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
 #define XRL_TUNE_L2L_FORM 5
 #define XRL_TUNE_M2M_FORM 6
 #define XRL_TUNE_LEAF_FORM 7
+#define XRL_TUNE_VALU_FORM 8
 xrl_status xrl_plan_set_tuning(xrl_plan *plan, int32_t key, int32_t value);
 
 /* Graph mode (on != 0): the first xrl_fmm_matvec with a new argument set

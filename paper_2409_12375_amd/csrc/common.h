@@ -287,6 +287,7 @@ struct xrl_plan {
     int ts_min_cols = 16;  // MFMA engine: target-stationary from this many real columns on
     int p2p_form = 0;  // P2P above 16 FP32 columns: 0 MFMA, 1 scalar densities, 2 LDS-staged (XRL_TUNE_P2P_FORM)
     int leaf_mfma = 1;       // P2M and L2P above 16 FP32 columns on MFMA (1) or the vector ALU (0)
+    int valu_col = 1;        // vector-ALU offset-stationary form (XRL_TUNE_VALU_FORM)
     int tr_m2m = 2;          // <= 8 pairs per target: one wave per row tile (1), per target (0), by level size (2)
     int ps_l2l = 1;          // passes with one source per target: source-stationary (1) or lean (0)
     int ts_order = 1;        // target-stationary launch order: 1 most pairs first, 0 target order

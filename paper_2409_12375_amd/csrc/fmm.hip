@@ -978,6 +978,65 @@ __global__ __launch_bounds__(256) void k_m2l_os_valu(const int32_t *__restrict__
     }
 }
 
+// Offset-stationary translation on the vector ALU, one column per thread
+// (FP32): the group's operator, k-major, in LDS and read as broadcasts (every
+// lane of a wave reads the same address), all K output rows of the thread's
+// column in registers, its multipole column streamed from memory one chunk
+// of p + 1 coefficients ahead (K = (p + 1)^2 is a whole number of chunks).
+// Per coefficient: K FMAs for about K / 4 broadcast reads.
+template <int ORD>
+__global__ __launch_bounds__(256) void k_m2l_os_col(const int32_t *__restrict__ items,
+                                                    const int32_t *__restrict__ gbeg, const int32_t *__restrict__ goff,
+                                                    const int32_t *__restrict__ src, const float *__restrict__ op_k,
+                                                    const float *__restrict__ M, int C, int c0, int Cc,
+                                                    float *__restrict__ tmp)
+{
+    using D = M2LDims<ORD>;
+    constexpr int K = D::K, KC = ORD + 1, NCH = ORD + 1;
+    __shared__ float4 sA4[K * D::KP / 4];
+    const float *sA = reinterpret_cast<const float *>(sA4);
+    const int g = items[3 * blockIdx.x], n0 = items[3 * blockIdx.x + 1], n1 = items[3 * blockIdx.x + 2];
+    const int pb = gbeg[g];
+    const float4 *Ao = reinterpret_cast<const float4 *>(op_k + (int64_t)goff[g] * D::KK * D::KP);
+    for (int i = threadIdx.x; i < K * D::KP / 4; i += 256) sA4[i] = Ao[i];
+    const int n = n0 + (int)threadIdx.x;
+    const bool active = n < n1;
+    int p = 0, c = 0;
+    const float *mcol = M;
+    if (active) {
+        p = n / Cc;
+        c = n - p * Cc;
+        mcol = M + (int64_t)src[pb + p] * K * C + c0 + c;
+    }
+    float acc[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) acc[r] = 0.f;
+    float bcur[KC], bnext[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) bcur[j] = active ? mcol[(int64_t)j * C] : 0.f;
+    __syncthreads();
+    for (int ch = 0; ch < NCH; ++ch) {
+        if (ch + 1 < NCH) {
+#pragma unroll
+            for (int j = 0; j < KC; ++j) bnext[j] = active ? mcol[(int64_t)((ch + 1) * KC + j) * C] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            const float *a = sA + (ch * KC + j) * D::KP;
+            const float b = bcur[j];
+#pragma unroll
+            for (int r = 0; r < K; ++r) acc[r] = fmaf(a[r], b, acc[r]);
+        }
+#pragma unroll
+        for (int j = 0; j < KC; ++j) bcur[j] = bnext[j];
+    }
+    if (active) {
+        float *out = tmp + ((int64_t)(pb + p) * Cc + c) * D::KP;
+#pragma unroll
+        for (int r = 0; r < K; ++r) out[r] = acc[r];
+    }
+}
+
 // Target-stationary translation for wide column blocks: one wave per item
 // (target, WT consecutive 16-column tiles).  The wave visits the pairs of its
 // target in their list order and accumulates T_o M_s in registers, so there
@@ -1821,9 +1880,9 @@ __global__ __launch_bounds__(256) void k_pass_reduce(const int32_t *__restrict__
 }
 
 // Work items of one column chunk width Cc (cached per engine and width).
-static const int32_t *pass_items(const TransPass &T, bool mfma, int Cc, int *n_items, hipStream_t s)
+static const int32_t *pass_items(const TransPass &T, bool mfma, int Cc, int *n_items, hipStream_t s, int width = 64)
 {
-    const int64_t key = (mfma ? 1000000 : 0) + Cc;
+    const int64_t key = (mfma ? 1000000 : 0) + (int64_t)width * 10000000 + Cc;
     for (auto &kv : T.item_cache)
         if (kv.first == key) {
             *n_items = (int)(kv.second.n / 3);
@@ -1836,7 +1895,8 @@ static const int32_t *pass_items(const TransPass &T, bool mfma, int Cc, int *n_i
             const int64_t nct = cdiv(ncols, 16), WT = 8;
             for (int64_t c = 0; c < nct; c += WT) it.insert(it.end(), {(int32_t)g, (int32_t)c, (int32_t)std::min(nct, c + WT)});
         } else {
-            for (int64_t c = 0; c < ncols; c += 64) it.insert(it.end(), {(int32_t)g, (int32_t)c, (int32_t)std::min(ncols, c + 64)});
+            for (int64_t c = 0; c < ncols; c += width)
+                it.insert(it.end(), {(int32_t)g, (int32_t)c, (int32_t)std::min(ncols, c + width)});
         }
     }
     T.item_cache.emplace_back(key, DevBuf<int32_t>());
@@ -1956,13 +2016,23 @@ static void pass_launch(const xrl_plan *P, const TransPass &TP, const T *op_frag
     for (int c0 = 0; c0 < C; c0 += Cc) {
         const int cc = std::min(Cc, C - c0);
         int n_items = 0;
-        const int32_t *items = pass_items(TP, mfma, cc, &n_items, s);
+        // the column-per-thread vector-ALU kernel: FP32, K = (p+1)^2 registers
+        constexpr bool col = sizeof(T) == 4 && ORD <= 8;
+        const int32_t *items = pass_items(TP, mfma, cc, &n_items, s, !mfma && col && P->valu_col ? 256 : 64);
         if (mfma) {
             k_m2l_os_mfma<T, ORD><<<(unsigned)cdiv(n_items, 4), 256, 0, s>>>(
                 items, n_items, TP.gbeg.p, TP.goff.p, TP.src.p, op_frag, in, C, c0, cc, tmp->p);
         } else {
             // the LDS-staged operator of the vector-ALU kernel fits up to order 8
-            if constexpr (ORD <= 8 && (sizeof(T) == 4 || ORD <= 6))
+            if constexpr (col) {
+                if (P->valu_col)
+                    k_m2l_os_col<ORD><<<(unsigned)n_items, 256, 0, s>>>(items, TP.gbeg.p, TP.goff.p, TP.src.p,
+                                                                         (const float *)op_k, (const float *)in, C, c0,
+                                                                         cc, (float *)tmp->p);
+                else
+                    k_m2l_os_valu<T, ORD><<<(unsigned)n_items, 256, 0, s>>>(items, TP.gbeg.p, TP.goff.p, TP.src.p,
+                                                                            op_k, in, C, c0, cc, tmp->p);
+            } else if constexpr (ORD <= 8 && (sizeof(T) == 4 || ORD <= 6))
                 k_m2l_os_valu<T, ORD><<<(unsigned)n_items, 256, 0, s>>>(items, TP.gbeg.p, TP.goff.p, TP.src.p, op_k,
                                                                         in, C, c0, cc, tmp->p);
             else
@@ -2775,6 +2845,10 @@ extern "C" xrl_status xrl_plan_set_tuning(xrl_plan *P, int32_t key, int32_t valu
             case XRL_TUNE_LEAF_FORM:
                 XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: leaf form must be 0 or 1");
                 P->leaf_mfma = value;
+                break;
+            case XRL_TUNE_VALU_FORM:
+                XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: vector-ALU form must be 0 or 1");
+                P->valu_col = value;
                 break;
             case XRL_TUNE_M2M_FORM:
                 XRL_CHECK(value >= 0 && value <= 2, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: M2M form must be 0..2");

@@ -133,9 +133,11 @@ def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
     x = I.densities(N, 18, np.complex64)
     tree = xrl.Tree(V, T)
     ys = {}
-    for eng in ("mfma", "mfma_os", "refl", "lean", "p2p_scalar", "p2p_lds", "padded", "refl_padded", "l2l_ts", "m2m_ts", "m2m_tiles", "valu_leaf"):
-        plan = xrl.Plan(tree, order=8, precision="mixed", engine="mfma_os" if eng == "mfma_os" else "mfma",
-                        max_cols=18)
+    forms = ("mfma", "mfma_os", "refl", "lean", "p2p_scalar", "p2p_lds", "padded", "refl_padded", "l2l_ts", "m2m_ts",
+             "m2m_tiles", "valu_leaf", "valu", "valu_tiles")
+    for eng in forms:
+        engine = eng if eng in ("mfma_os", "valu") else ("valu" if eng == "valu_tiles" else "mfma")
+        plan = xrl.Plan(tree, order=8, precision="mixed", engine=engine, max_cols=18)
         plan.assemble()
         if eng in ("padded", "refl_padded"):  # the last four columns in a padded 16-column tile
             plan.set_tuning("ts_narrow_cols", 0)
@@ -153,6 +155,8 @@ def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
             plan.set_tuning("m2m_form", 0)
         if eng == "m2m_tiles":  # M2M one wave per row tile on every level
             plan.set_tuning("m2m_form", 1)
+        if eng == "valu_tiles":  # vector-ALU translations as 6 x 4 register tiles
+            plan.set_tuning("valu_form", 0)
         if eng == "valu_leaf":  # P2P, P2M and L2P on the vector ALU
             plan.set_tuning("leaf_form", 0)
             plan.set_tuning("p2p_form", 2)
@@ -166,7 +170,7 @@ def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
     d = np.linalg.norm(ys["mfma"] - ys["mfma_os"], axis=0) / np.linalg.norm(ys["mfma_os"], axis=0)
     say("  target- vs offset-stationary", d.max())
     assert d.max() < 1e-6
-    for v in ("refl", "lean", "p2p_scalar", "p2p_lds", "padded", "refl_padded", "l2l_ts", "m2m_ts", "m2m_tiles", "valu_leaf"):
+    for v in forms[2:]:
         d = np.linalg.norm(ys["mfma"] - ys[v], axis=0) / np.linalg.norm(ys[v], axis=0)
         say("  kernel form %s vs default" % v, d.max())
         assert d.max() < 1e-6
