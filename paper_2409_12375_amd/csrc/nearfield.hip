@@ -289,11 +289,13 @@ __device__ inline float ratio2_32(float4 ck, float4 cl)
     return fmaf(dx, dx, fmaf(dy, dy, dz * dz)) / (dm * dm);
 }
 
-// Centroid relative to the leaf's reference point, and diameter, in FP32.
-__device__ inline float4 meta32(const NFArgs &a, int32_t k, const double *c0)
+// Centroid relative to the plan's reference point, and diameter, in FP32:
+// the same four floats for a panel in every leaf, so the FP32 class of
+// (k, l) and of (l, k) is the same.
+__device__ inline float4 meta32(const NFArgs &a, int32_t k)
 {
-    return make_float4((float)(a.cen[3 * k] - c0[0]), (float)(a.cen[3 * k + 1] - c0[1]),
-                       (float)(a.cen[3 * k + 2] - c0[2]), (float)a.diam[k]);
+    return make_float4((float)(a.cen[3 * k] - a.cref[0]), (float)(a.cen[3 * k + 1] - a.cref[1]),
+                       (float)(a.cen[3 * k + 2] - a.cref[2]), (float)a.diam[k]);
 }
 
 __device__ inline bool share_vertex4(int4 ik, int4 il)
@@ -321,7 +323,7 @@ __device__ inline int64_t mirror_index(const NFArgs &a, int32_t k, int32_t l)
 
 // Counting pass: per leaf, the number of entries of each queue (touching,
 // near-singular classes 0..2), cnt[4 li + q].  FP32 classifies as the FP32
-// filling pass does (centroids relative to the leaf's first centroid),
+// filling pass does (centroids relative to the plan's reference point),
 // FP64 as the FP64 one.
 template <bool FP64>
 __global__ __launch_bounds__(256) void k_nf_count(NFArgs a, int64_t *__restrict__ cnt)
@@ -333,7 +335,6 @@ __global__ __launch_bounds__(256) void k_nf_count(NFArgs a, int64_t *__restrict_
     const int32_t Tb = a.leaf_box[li];
     const int32_t kb = a.box_beg[Tb], nt = a.box_end[Tb] - kb;
     const int32_t r0 = a.near_rows[li], nr = a.near_rows[li + 1] - r0;
-    const double c0[3] = {a.cen[3 * (int64_t)kb], a.cen[3 * (int64_t)kb + 1], a.cen[3 * (int64_t)kb + 2]};
     if (threadIdx.x < kNQueues) s_cnt[threadIdx.x] = 0;
     if (threadIdx.x < 2) s_all[threadIdx.x] = 0;
     __syncthreads();
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(256) void k_nf_count(NFArgs a, int64_t *__restrict_
         if (FP64)
             c = entry_class<double>(k == l, share_vertex4(ik, il), ratio2_64(a, k, l), a.r_near * a.r_near);
         else
-            c = entry_class<float>(k == l, share_vertex4(ik, il), ratio2_32(meta32(a, k, c0), meta32(a, l, c0)),
+            c = entry_class<float>(k == l, share_vertex4(ik, il), ratio2_32(meta32(a, k), meta32(a, l)),
                                    rn2f);
         if (c < kNQueues) {
             ++all[c == kQTouch ? 0 : 1];
@@ -524,7 +525,7 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
         stage_points(a.pv, kb + e / kRegPts, c0, R, e % kRegPts, &tp[e]);
     for (int j = threadIdx.x; j < nt; j += blockDim.x) {
         const int32_t k = kb + j;
-        tcd[j] = meta32(a, k, c0);
+        tcd[j] = meta32(a, k);
         tid[j] = make_int4(a.pvid[3 * k], a.pvid[3 * k + 1], a.pvid[3 * k + 2], k);
     }
     unsigned long long c_self = 0, c_reg = 0;
@@ -536,7 +537,7 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
             stage_points(a.pv, a.near_src[r0 + rc + e / kRegPts], c0, R, e % kRegPts, &spt[e]);
         for (int r = threadIdx.x; r < nrc; r += blockDim.x) {
             const int32_t l = a.near_src[r0 + rc + r];
-            scd[r] = meta32(a, l, c0);
+            scd[r] = meta32(a, l);
             sid[r] = make_int4(a.pvid[3 * l], a.pvid[3 * l + 1], a.pvid[3 * l + 2], l);
         }
         __syncthreads();
@@ -754,7 +755,8 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
         XRL_HIP(hipMemsetAsync(cnt.p, 0, cnt.bytes(), s));
         NFArgs a{P->leaf_box.p, P->box_beg.p, P->box_end.p, P->near_rows.p, P->near_src.p, P->leaf_tpad.p,
                  P->pvid.p,     P->near_val_off.p, P->pv.p, P->cen.p, P->diam.p, o.r_near, o.r_mid,
-                 P->n_leaves,   cnt.p,       nullptr,  nullptr, nullptr, nullptr, P->panel_leaf.p};
+                 P->n_leaves,   cnt.p,       nullptr,  nullptr, nullptr, nullptr, P->panel_leaf.p,
+                 {P->trees[0]->root_c[0], P->trees[0]->root_c[1], P->trees[0]->root_c[2]}};
         // counting pass, then every leaf's first position in each queue
         // (queues stored one after another: touching, near-singular 0, 1, 2)
         const int64_t L = P->n_leaves;

@@ -36,6 +36,11 @@ struct NFArgs {
     // not stored); entries with k > l whose mirror is stored are not queued.
     int64_t *work_mirror;
     const int32_t *panel_leaf;  // [N] leaf of each sorted panel
+    // Reference point of the FP32 classification: every leaf classifies its
+    // entries from centroids relative to this one point, so (k, l) and
+    // (l, k) get the same class bit for bit in any two leaves (the mirror of
+    // an entry skipped above is then always integrated and written).
+    double cref[3];
 };
 
 // Near-field entry classes: the queues of pass 2 (touching; near-singular of

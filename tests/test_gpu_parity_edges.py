@@ -7,6 +7,7 @@ Reference values come from the FP64 oracle (oracle/), the closed form of the
 point-charge potential, or numpy's dense solve; nothing here is computed by
 the GPU path and then compared with itself, except where the GPU result is
 compared under a change that must not alter it (a permutation)."""
+import os
 import sys
 
 import numpy as np
@@ -18,6 +19,9 @@ pytestmark = pytest.mark.gpu
 import oracle as O  # noqa: E402
 from paper_2409_12375_amd import inputs as I  # noqa: E402
 from paper_2409_12375_amd import xrl  # noqa: E402
+
+
+SURROGATE = os.path.join(os.path.dirname(__file__), "golden", "surrogate_mlp.npz")
 
 
 def say(*a):
@@ -113,6 +117,41 @@ def _leaf_rows(plan, n_leaves, seed):
     return np.concatenate([perm[rng_[leaf_box[i]][0]:rng_[leaf_box[i]][1]] for i in pick])
 
 
+@pytest.mark.parametrize("precision,jitter", [("mixed", 0.0), ("mixed", 0.05), ("fp64", 0.0)])
+def test_stored_near_field_is_symmetric(precision, jitter):
+    """P_kl = P_lk: the assembly integrates a touching or near-singular pair
+    once and writes both stored entries; a regular pair is integrated by
+    each of the two leaves, in its own summation order.  So every stored
+    entry equals its stored mirror to rounding.  A regular grid (no jitter)
+    puts many pairs exactly on the class boundaries, where the two leaves
+    holding (k, l) and (l, k) must still classify the pair alike (otherwise
+    one entry is skipped as a mirror that the other leaf never writes)."""
+    say("case: stored near field symmetric, bar jitter %.2f, %s" % (jitter, precision))
+    V, T = I.bar(4, 4, 60, size=(1.0, 1.0, 15.0), jitter=jitter)
+    N = len(T)
+    tree = xrl.Tree(V, T, max_leaf=32)
+    plan = xrl.Plan(tree, order=8, precision=precision, max_cols=1)
+    plan.assemble()
+    k, l, v = block_entries(plan)
+    key = k.astype(np.int64) * N + l
+    order = np.argsort(key)
+    mkey = l.astype(np.int64) * N + k
+    pos = np.clip(np.searchsorted(key[order], mkey), 0, len(key) - 1)
+    found = key[order][pos] == mkey
+    vm = v[order][pos]
+    say("  %d entries, %d with a stored mirror" % (len(v), found.sum()))
+    assert found.sum() > len(v) // 2
+    assert np.all(np.isfinite(v))
+    rel = np.where(found, np.abs(v - vm) / np.abs(v), 0.0)
+    say("  largest relative difference from the mirror %.3e" % rel.max())
+    bad = rel > (1e-5 if precision != "fp64" else 1e-12)
+    assert not bad.any(), "entries differ from their mirror: %s" % list(zip(k[bad][:5], l[bad][:5], rel[bad][:5]))
+    # and they are the oracle's (a sample)
+    idx = np.random.default_rng(2).choice(len(v), 2000, replace=False)
+    ref = O.pairs(V, T, k[idx], l[idx])
+    assert np.abs(v[idx] - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("precision", ["fp32", "mixed"])
 def test_coils_200k_matches_oracle(precision):
     """The two-coil workload at its full size (199,952 panels, 3 complex
@@ -133,6 +172,60 @@ def test_coils_200k_matches_oracle(precision):
     err = relerr_cols(y[rows], ref)
     say("  %d rows, rel L2 per column" % len(rows), err)
     assert err.max() <= 1e-4
+
+
+def test_stack_2m_matches_oracle():
+    """The package-on-package-like stack at its full size (2,146,880 panels,
+    24 complex columns), surrogate + mixed precision as the benchmark runs it,
+    on 256 random rows plus every panel of two random leaves."""
+    say("case: stack 2.1M, 24 columns, surrogate + mixed")
+    V, T = I.pop()
+    N = len(T)
+    x = I.densities(N, 24, np.complex64)
+    tree = xrl.Tree(V, T, max_leaf=128)
+    plan = xrl.Plan(tree, order=8, precision="mixed", max_cols=24)
+    plan.assemble(surrogate=xrl.Surrogate.load(SURROGATE), audit_every=100)
+    y = plan.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    rows = np.unique(np.concatenate([np.random.default_rng(11).choice(N, 256, replace=False),
+                                     _leaf_rows(plan, 2, 12)]))
+    ref, _ = O.matvec(V, T, x.astype(np.complex128), rows=rows)
+    err = relerr_cols(y[rows], ref)
+    say("  %d rows, rel L2 per column: max %.3e" % (len(rows), err.max()))
+    assert err.max() <= 1e-4
+
+
+def test_batch_of_32_meshes_matches_oracle():
+    """The batched workload at its full size: 32 meshes of 10k-500k panels in
+    one plan, 384 complex columns per mesh (768 real: several column items
+    per target), autotuned kernel forms and HIP-graph replay as the benchmark
+    runs it; 32 random rows of the smallest, the median and the largest mesh
+    against the oracle, each against all of its own sources."""
+    say("case: batch of 32 meshes, 384 columns, mixed, autotuned, graph")
+    meshes = [(V, T) for _, V, T in I.batch_meshes()]
+    Ns = [len(T) for _, T in meshes]
+    offs = np.concatenate([[0], np.cumsum(Ns)])
+    g = torch.Generator(device="cuda")
+    g.manual_seed(I.DENS_SEED)
+    x = torch.view_as_complex(torch.randn(int(offs[-1]), 384, 2, generator=g, device="cuda"))
+    trees = [xrl.Tree(V, T, max_leaf=128) for V, T in meshes]
+    plan = xrl.Plan(trees, order=8, precision="mixed", max_cols=384)
+    plan.assemble()
+    y = torch.empty_like(x)
+    plan.autotune(x, y)
+    plan.set_graph(True)
+    for _ in range(2):  # captured, then replayed
+        plan.matvec(x, y)
+    torch.cuda.synchronize()
+    pick = sorted({int(np.argmin(Ns)), int(np.argsort(Ns)[len(Ns) // 2]), int(np.argmax(Ns))})
+    for i in pick:
+        V, T = meshes[i]
+        rows = np.sort(np.random.default_rng(20 + i).choice(Ns[i], 32, replace=False))
+        xi = x[offs[i]:offs[i + 1]].cpu().numpy().astype(np.complex128)
+        ref, _ = O.matvec(V, T, xi, rows=rows)
+        yi = y[offs[i]:offs[i + 1]][torch.from_numpy(rows).cuda()].cpu().numpy()
+        err = relerr_cols(yi, ref)
+        say("  mesh %d (%d panels): rel L2 per column max %.3e" % (i, Ns[i], err.max()))
+        assert err.max() <= 1e-4
 
 
 def worst_ratio_rows(plan, n_pairs=12, per_target=1, seed=0):
