@@ -13,8 +13,8 @@
 //   near-singular r < r_near: outer conical Gauss rule on 1, 4 or 16
 //                 sub-triangles of S_k, inner integral exact.  Optionally the
 //                 learned surrogate with quadrature fall-back.
-//   regular       product of two conical Gauss rules (4x4 or 3x3 points per
-//                 triangle in FP32; 5x5 or 4x4 in FP64).
+//   regular       product of two conical Gauss rules (4x4 below r_mid, 3x3
+//                 above, points per triangle, in FP32; 5x5 or 4x4 in FP64).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -708,7 +708,7 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
         XRL_CHECK(P, XRL_E_INVALID_ARG, "xrl_nearfield_assemble: null plan");
         hipStream_t s = (hipStream_t)stream;
         const AllocStream alloc_scope(s);
-        xrl_nf_opts o{2.0, 6.0, nullptr, 0};
+        xrl_nf_opts o{2.0, 4.0, nullptr, 0};
         if (opts) o = *opts;
         XRL_CHECK(o.r_near > 0 && o.r_mid >= o.r_near, XRL_E_INVALID_ARG,
                   "xrl_nearfield_assemble: need 0 < r_near <= r_mid");

@@ -252,7 +252,7 @@ class Plan:
         _check(lib().xrl_plan_get_info(self.h, ctypes.byref(i)))
         return {f: getattr(i, f) for f, _ in PlanInfo._fields_}
 
-    def assemble(self, r_near=2.0, r_mid=6.0, surrogate=None, audit_every=0, stream=None):
+    def assemble(self, r_near=2.0, r_mid=4.0, surrogate=None, audit_every=0, stream=None):
         o = NfOpts(r_near, r_mid, None, audit_every)
         keep = None
         if surrogate is not None:
