@@ -236,9 +236,11 @@ typedef struct {
 typedef struct {
     double r_near;      /* non-touching pairs with |c_k-c_l|/max(diam) < r_near use the
                            semi-analytic rule (default 2.0) */
-    double r_mid;       /* regular pairs below r_mid use 4x4 product Gauss, above 3x3
-                           (5x5 and 4x4 in FP64 mode); default 4.0, where the 3x3
-                           rule is within 2.3e-7 of the exact entry */
+    double r_mid;       /* regular pairs below r_mid use the finer product rule (FP32
+                           storage: 12-point symmetric triangle rules, FP64: 5x5
+                           conical Gauss), above it the coarser (6-point; 4x4);
+                           default 4.0, where the coarser rule is within 2e-7 of
+                           the exact entry */
     const xrl_mlp *surrogate; /* NULL: quadrature everywhere */
     int32_t audit_every;      /* with a surrogate: every k-th accepted pair is also
                                  integrated by quadrature for the error report (0: off) */

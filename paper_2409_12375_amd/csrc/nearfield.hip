@@ -13,8 +13,10 @@
 //   near-singular r < r_near: outer conical Gauss rule on 1, 4 or 16
 //                 sub-triangles of S_k, inner integral exact.  Optionally the
 //                 learned surrogate with quadrature fall-back.
-//   regular       product of two conical Gauss rules (4x4 below r_mid, 3x3
-//                 above, points per triangle, in FP32; 5x5 or 4x4 in FP64).
+//   regular       product of two triangle rules: in FP32 the symmetric rules
+//                 of Dunavant (1985), 12 points (degree 6) below r_mid and
+//                 6 points (degree 4) above; in FP64 conical Gauss rules,
+//                 5x5 or 4x4 points.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -438,14 +440,15 @@ __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restr
 }
 
 // Pass 1 in FP32 (plain FP32 and mixed modes): one workgroup per target leaf.
-// The quadrature points of both product rules (4 x 4 and 3 x 3 conical Gauss
-// points per triangle, weights times twice the area) of the leaf's targets
+// The quadrature points of both product rules (the 12- and 6-point symmetric
+// triangle rules, weights times the area) of the leaf's targets
 // and of a chunk of source rows are staged in LDS, in FP32 relative to the
 // leaf's first centroid; every lane takes one (row, target) entry of the
 // chunk at a time: the self entry in FP64 by the closed form, touching and
 // near-singular entries queued for pass 2, regular entries by the product
 // rule (sum of w_i w_j / |x_i - y_j|), padding entries set to zero.
-constexpr int kRegPts = 16 + 9;  // points per panel: the 4 x 4 rule, then the 3 x 3 rule
+constexpr int kRegHi = 12, kRegLo = 6;
+constexpr int kRegPts = kRegHi + kRegLo;  // points per panel: the 12-point rule, then the 6-point rule
 constexpr int kRowChunk = 16;
 
 __device__ inline void stage_points(const double *__restrict__ pv, int32_t k, const double *c0, const NFRules &R,
@@ -456,22 +459,13 @@ __device__ inline void stage_points(const double *__restrict__ pv, int32_t k, co
     const double e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
     const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
                  cz = e1[0] * e2[1] - e1[1] * e2[0];
-    const double A2 = sqrt(cx * cx + cy * cy + cz * cz);
-    double s, t, w;
-    if (q < 16) {
-        s = R.rx4[q / 4];
-        t = R.rx4[q % 4];
-        w = R.rw4[q / 4] * R.rw4[q % 4] * s * A2;
-    } else {
-        s = R.rx3[(q - 16) / 3];
-        t = R.rx3[(q - 16) % 3];
-        w = R.rw3[(q - 16) / 3] * R.rw3[(q - 16) % 3] * s * A2;
-    }
+    const double area = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+    const double *b = R.sym_b[q];
     float4 o;
-    o.x = (float)(v[0] + s * (v[3] - v[0]) + s * t * (v[6] - v[3]) - c0[0]);
-    o.y = (float)(v[1] + s * (v[4] - v[1]) + s * t * (v[7] - v[4]) - c0[1]);
-    o.z = (float)(v[2] + s * (v[5] - v[2]) + s * t * (v[8] - v[5]) - c0[2]);
-    o.w = (float)w;
+    o.x = (float)(b[0] * v[0] + b[1] * v[3] + b[2] * v[6] - c0[0]);
+    o.y = (float)(b[0] * v[1] + b[1] * v[4] + b[2] * v[7] - c0[1]);
+    o.z = (float)(b[0] * v[2] + b[1] * v[5] + b[2] * v[8] - c0[2]);
+    o.w = (float)(R.sym_w[q] * area);
     *out = o;
 }
 
@@ -578,11 +572,12 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
         const int n4 = s_n4, n3 = s_n3;
         for (int q = threadIdx.x; q < n4; q += blockDim.x) {
             const int rj = s_reg[q], r = rj >> 8, j = rj & 255;
-            val[vo + (int64_t)(rc + r) * tpad + j] = product_rule<16>(&tp[j * kRegPts], &spt[r * kRegPts]);
+            val[vo + (int64_t)(rc + r) * tpad + j] = product_rule<kRegHi>(&tp[j * kRegPts], &spt[r * kRegPts]);
         }
         for (int q = threadIdx.x; q < n3; q += blockDim.x) {
             const int rj = s_reg[kRowChunk * kMaxLeaf - 1 - q], r = rj >> 8, j = rj & 255;
-            val[vo + (int64_t)(rc + r) * tpad + j] = product_rule<9>(&tp[j * kRegPts + 16], &spt[r * kRegPts + 16]);
+            val[vo + (int64_t)(rc + r) * tpad + j] =
+                product_rule<kRegLo>(&tp[j * kRegPts + kRegHi], &spt[r * kRegPts + kRegHi]);
         }
         if (threadIdx.x == 0) c_reg += (unsigned long long)(n4 + n3);
     }
@@ -741,6 +736,33 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
             const double u = R.gx[i], u3 = u * u * u, v3 = (1 - u) * (1 - u) * (1 - u);
             R.tx[i] = u3 / (u3 + v3);
             R.tw[i] = R.gw[i] * 3.0 * u * u * (1 - u) * (1 - u) / ((u3 + v3) * (u3 + v3));
+        }
+        // symmetric rules for the triangle (Dunavant 1985): orbits of the
+        // barycentric point (a, a, 1 - 2a) (3 points) and (a, b, 1 - a - b)
+        // (6 points); degree 6 with 12 points, degree 4 with 6 points
+        {
+            int q = 0;
+            auto orbit3 = [&](double a, double w) {
+                const double c = 1.0 - 2.0 * a;
+                const double p[3][3] = {{a, a, c}, {a, c, a}, {c, a, a}};
+                for (auto &b : p) {
+                    for (int d = 0; d < 3; ++d) R.sym_b[q][d] = b[d];
+                    R.sym_w[q++] = w;
+                }
+            };
+            auto orbit6 = [&](double a, double b, double w) {
+                const double c = 1.0 - a - b;
+                const double p[6][3] = {{a, b, c}, {a, c, b}, {b, a, c}, {b, c, a}, {c, a, b}, {c, b, a}};
+                for (auto &t : p) {
+                    for (int d = 0; d < 3; ++d) R.sym_b[q][d] = t[d];
+                    R.sym_w[q++] = w;
+                }
+            };
+            orbit3(0.063089014491502228, 0.050844906370206817);
+            orbit3(0.24928674517091042, 0.11678627572637937);
+            orbit6(0.053145049844816947, 0.31035245103378440, 0.082851075618373575);
+            orbit3(0.44594849091596489, 0.22338158967801147);
+            orbit3(0.091576213509770743, 0.10995174365532187);
         }
         gauss_legendre01(R.n_hi, R.rx4, R.rw4);
         gauss_legendre01(R.n_lo, R.rx3, R.rw3);

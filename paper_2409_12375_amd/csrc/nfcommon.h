@@ -15,6 +15,10 @@ struct NFRules {
     double rx4[8], rw4[8];  // regular, n_hi points
     double rx3[8], rw3[8];  // regular, n_lo points
     int n_touch, n_hi, n_lo;
+    // regular pairs in the FP32 pass: symmetric triangle rules, barycentric
+    // points and weights summing to one: 12 points (exact to degree 6)
+    // below r_mid, 6 points (degree 4) above
+    double sym_b[18][3], sym_w[18];
 };
 
 struct NFArgs {
