@@ -12,6 +12,10 @@ struct NFRules {
     // an ns_n[c] x ns_n[c] conical rule on 4^ns_lev[c] sub-triangles
     double nx[3][8], nw[3][8];
     int ns_n[3], ns_lev[3];
+    // ns_sym[c]: class c takes the 16-point symmetric triangle rule (exact to
+    // degree 8) on each sub-triangle instead of the conical rule
+    int ns_sym[3];
+    double ns16_b[16][3], ns16_w[16];
     double rx4[8], rw4[8];  // regular, n_hi points
     double rx3[8], rw3[8];  // regular, n_lo points
     int n_touch, n_hi, n_lo;
