@@ -142,14 +142,32 @@ __device__ inline T tri_area2(const T *v)
     return sqrt(cx * cx + cy * cy + cz * cz);
 }
 
-// Touching pair: target vertices reordered so that tv[0] is a shared vertex.
+// Touching pair: target vertices reordered so that tv[0] is a shared vertex
+// and, when the panels share an edge (edge), tv[1] is its other end, so
+// that the shared side is t = 0 of the collapsed coordinates.
 template <typename T>
-__device__ T touching_pair(const T *tv, const T *sv, const NFRules &R)
+__device__ T touching_pair(const T *tv, const T *sv, const NFRules &R, bool edge)
 {
     TriPot<T> pot;
     pot.init(sv);
     const T A2 = tri_area2(tv);
     T acc = 0;
+    if (R.touch_graded) {
+        const int ns = edge ? R.n_gse : R.n_gs;
+        const double *sx = edge ? R.gse_x : R.gs_x, *sw = edge ? R.gse_w : R.gs_w;
+        for (int i = 0; i < ns; ++i) {
+            const T s = (T)sx[i];
+            T inner = 0;
+            for (int j = 0; j < R.n_gt; ++j) {
+                const T t = (T)R.gt_x[j];
+                T x[3];
+                for (int d = 0; d < 3; ++d) x[d] = tv[d] + s * (tv[3 + d] - tv[d]) + s * t * (tv[6 + d] - tv[3 + d]);
+                inner += (T)R.gt_w[j] * pot(x);
+            }
+            acc += (T)sw[i] * s * inner;
+        }
+        return acc * A2;
+    }
     for (int i = 0; i < R.n_touch; ++i) {
         const T s = (T)R.tx[i];
         T inner = 0;
@@ -623,11 +641,20 @@ __global__ __launch_bounds__(64) void k_nf_special(NFArgs a, NFRules R, int queu
     C tv[9], sv[9];
     C v;
     if (queue == kQTouch) {
-        const int s0 = shared_vertex(a.pvid + 3 * (int64_t)k, a.pvid + 3 * (int64_t)l);
+        const int32_t *ik = a.pvid + 3 * (int64_t)k, *il = a.pvid + 3 * (int64_t)l;
+        const int s0 = shared_vertex(ik, il);
+        // a second shared vertex (the panels share an edge) goes second
+        int ord[3] = {s0, (s0 + 1) % 3, (s0 + 2) % 3};
+        const auto shared = [&](int i) { return ik[i] == il[0] || ik[i] == il[1] || ik[i] == il[2]; };
+        const bool edge = shared(ord[1]) || shared(ord[2]);
+        if (!shared(ord[1]) && shared(ord[2])) {
+            ord[1] = (s0 + 2) % 3;
+            ord[2] = (s0 + 1) % 3;
+        }
         for (int j = 0; j < 3; ++j)
-            for (int d = 0; d < 3; ++d) tv[3 * j + d] = (C)(a.pv[9 * (int64_t)k + 3 * ((s0 + j) % 3) + d] - a.cen[3 * k + d]);
+            for (int d = 0; d < 3; ++d) tv[3 * j + d] = (C)(a.pv[9 * (int64_t)k + 3 * ord[j] + d] - a.cen[3 * k + d]);
         for (int q = 0; q < 9; ++q) sv[q] = (C)(a.pv[9 * (int64_t)l + q] - a.cen[3 * k + q % 3]);
-        v = touching_pair<C>(tv, sv, R);
+        v = touching_pair<C>(tv, sv, R, edge);
     } else {
         const int32_t o = a.diam[l] < a.diam[k] ? l : k, in = o == k ? l : k;
         for (int q = 0; q < 9; ++q) {
@@ -771,6 +798,23 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
         R.n_hi = fp64 ? 5 : 4;
         R.n_lo = fp64 ? 4 : 3;
         gauss_legendre01(R.n_touch, R.gx, R.gw);
+        // graded touching rules of the FP32 storage modes: Gauss-Legendre
+        // nodes u through u -> u^2 (weights times 2u)
+        R.touch_graded = !fp64;
+        R.n_gs = 12;
+        R.n_gse = 16;
+        R.n_gt = 12;
+        auto graded = [](int n, double *x, double *w) {
+            double u[16], gw[16];
+            gauss_legendre01(n, u, gw);
+            for (int i = 0; i < n; ++i) {
+                x[i] = u[i] * u[i];
+                w[i] = gw[i] * 2.0 * u[i];
+            }
+        };
+        graded(R.n_gs, R.gs_x, R.gs_w);
+        graded(R.n_gse, R.gse_x, R.gse_w);
+        graded(R.n_gt, R.gt_x, R.gt_w);
         for (int i = 0; i < R.n_touch; ++i) {
             // sigmoidal map s(u) = u^3 / (u^3 + (1-u)^3), clustering the nodes
             // at both ends of each collapsed coordinate

@@ -8,6 +8,12 @@ namespace xrl {
 struct NFRules {
     double gx[40], gw[40];  // Gauss-Legendre on [0,1], n_touch points
     double tx[40], tw[40];  // the same nodes through the sigmoidal map u^3/(u^3+(1-u)^3), weights times its derivative
+    // touching pairs in the FP32 storage modes (touch_graded): one-sided
+    // grading u -> u^2 toward the shared vertex (s = 0; n_gs points, n_gse
+    // when the panels share an edge) and toward the shared side (t = 0;
+    // n_gt points)
+    int touch_graded, n_gs, n_gse, n_gt;
+    double gs_x[16], gs_w[16], gse_x[16], gse_w[16], gt_x[16], gt_w[16];
     // near-singular pairs, by class c (r >= 1.5, 0.75 <= r < 1.5, r < 0.75):
     // an ns_n[c] x ns_n[c] conical rule on 4^ns_lev[c] sub-triangles
     double nx[3][8], nw[3][8];
