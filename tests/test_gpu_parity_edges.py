@@ -67,11 +67,12 @@ def block_entries(plan):
 
 
 # Bounds per class: self, the closed form (FP64: rounding; stored in FP32:
-# two FP32 roundings); touching, the 24 x 24 graded rule of the FP32 storage
-# modes, whose own error reaches 1.4e-6 on the needle cells of the package's
-# hole rings (measured against the oracle; 32 x 32 in FP64 mode); other, the
-# FP32 product and conical rules with the closed-form potential of the larger
-# panel (a few 1e-6 at r ~ 2, where the product rule's own error is 1e-7).
+# two FP32 roundings); touching, the one-sided graded rules of the FP32
+# storage modes (12 x 12 or 16 x 12 points), whose own error stays below 3e-7
+# on the package's cells (measured against the oracle), plus FP32 arithmetic
+# in plain FP32 (32 x 32 sigmoidal rule in FP64 mode); other, the FP32
+# product rules and the symmetric rules with the closed-form potential of
+# the larger panel (a few 1e-6 at r ~ 2, where the rules' own error is 1e-7).
 @pytest.mark.parametrize("precision,tol", [
     ("fp64", {"self": 1e-8, "touch": 1e-8, "other": 1e-8}),
     ("mixed", {"self": 3e-7, "touch": 2e-6, "other": 1e-5}),
