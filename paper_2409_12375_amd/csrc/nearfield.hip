@@ -371,20 +371,46 @@ __global__ __launch_bounds__(256) void k_nf_count(NFArgs a, int64_t *__restrict_
     int my[kNQueues] = {0, 0, 0, 0};
     unsigned long long all[2] = {0, 0};
     const float rn2f = (float)(a.r_near * a.r_near);
-    for (int64_t e = threadIdx.x; e < (int64_t)nr * nt; e += blockDim.x) {
-        const int32_t r = (int32_t)(e / nt), j = (int32_t)(e - (int64_t)r * nt);
-        const int32_t k = kb + j, l = a.near_src[r0 + r];
-        const int4 ik = make_int4(a.pvid[3 * k], a.pvid[3 * k + 1], a.pvid[3 * k + 2], k);
-        const int4 il = make_int4(a.pvid[3 * l], a.pvid[3 * l + 1], a.pvid[3 * l + 2], l);
-        int c;
-        if (FP64)
-            c = entry_class<double>(k == l, share_vertex4(ik, il), ratio2_64(a, k, l), a.r_near * a.r_near);
-        else
-            c = entry_class<float>(k == l, share_vertex4(ik, il), ratio2_32(meta32(a, k), meta32(a, l)),
-                                   rn2f);
+    auto tally = [&](int c, int32_t k, int32_t l) {
         if (c < kNQueues) {
             ++all[c == kQTouch ? 0 : 1];
-            if (k < l || mirror_index(a, l, k) < 0) ++my[c];
+            if (k < l || mirror_index(a, k, l) < 0) ++my[c];
+        }
+    };
+    if constexpr (FP64) {
+        for (int64_t e = threadIdx.x; e < (int64_t)nr * nt; e += blockDim.x) {
+            const int32_t r = (int32_t)(e / nt), j = (int32_t)(e - (int64_t)r * nt);
+            const int32_t k = kb + j, l = a.near_src[r0 + r];
+            const int4 ik = make_int4(a.pvid[3 * k], a.pvid[3 * k + 1], a.pvid[3 * k + 2], k);
+            const int4 il = make_int4(a.pvid[3 * l], a.pvid[3 * l + 1], a.pvid[3 * l + 2], l);
+            tally(entry_class<double>(k == l, share_vertex4(ik, il), ratio2_64(a, k, l), a.r_near * a.r_near), k,
+                  l);
+        }
+    } else {
+        // the leaf's targets and each chunk of source rows staged in LDS, as
+        // in the FP32 filling pass
+        __shared__ float4 tcd[kMaxLeaf], scd[256];
+        __shared__ int4 tid[kMaxLeaf], sid[256];
+        for (int j = threadIdx.x; j < nt; j += blockDim.x) {
+            const int32_t k = kb + j;
+            tcd[j] = meta32(a, k);
+            tid[j] = make_int4(a.pvid[3 * k], a.pvid[3 * k + 1], a.pvid[3 * k + 2], k);
+        }
+        for (int rc = 0; rc < nr; rc += 256) {
+            const int nrc = min(256, nr - rc);
+            __syncthreads();  // the previous chunk is no longer read
+            for (int r = threadIdx.x; r < nrc; r += blockDim.x) {
+                const int32_t l = a.near_src[r0 + rc + r];
+                scd[r] = meta32(a, l);
+                sid[r] = make_int4(a.pvid[3 * l], a.pvid[3 * l + 1], a.pvid[3 * l + 2], l);
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < nrc * nt; e += blockDim.x) {
+                const int r = e / nt, j = e - r * nt;
+                const int4 ik = tid[j], il = sid[r];
+                tally(entry_class<float>(ik.w == il.w, share_vertex4(ik, il), ratio2_32(tcd[j], scd[r]), rn2f), ik.w,
+                      il.w);
+            }
         }
     }
     for (int q = 0; q < kNQueues; ++q)
@@ -436,8 +462,9 @@ __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restr
             continue;
         }
         if (c < kNQueues) {
-            // k > l with a stored mirror: written when (l, k) is integrated
-            const int64_t mir = mirror_index(a, k < l ? k : l, k < l ? l : k);
+            // the mirror entry (target l, source k); with k > l and the
+            // mirror stored, this entry is written when (l, k) is integrated
+            const int64_t mir = mirror_index(a, k, l);
             if (k < l || mir < 0) {
                 const int64_t pos = (int64_t)atomicAdd(&s_q[c], 1ull);
                 a.work[pos] = vo + e;
@@ -579,9 +606,10 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
                 val[out] = (float)self_term(a.pv + 9 * (int64_t)ik.w);
                 ++c_self;
             } else if (c < kNQueues) {
-                // k > l with a stored mirror: written when (l, k) is integrated
+                // the mirror entry (target l, source k); with k > l and the
+                // mirror stored, this entry is written when (l, k) is integrated
                 const int32_t k = ik.w, l = il.w;
-                const int64_t mir = mirror_index(a, k < l ? k : l, k < l ? l : k);
+                const int64_t mir = mirror_index(a, k, l);
                 if (k < l || mir < 0) {
                     const int64_t pos = (int64_t)atomicAdd(&s_q[c], 1ull);
                     a.work[pos] = out;
