@@ -496,53 +496,71 @@ __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restr
 
 // Pass 1 in FP32 (plain FP32 and mixed modes): one workgroup per target leaf.
 // The quadrature points of both product rules (the 12- and 6-point symmetric
-// triangle rules, weights times the area) of the leaf's targets
-// and of a chunk of source rows are staged in LDS, in FP32 relative to the
-// leaf's first centroid; every lane takes one (row, target) entry of the
+// triangle rules) and the areas of the leaf's targets and of a chunk of
+// source rows are staged in LDS, in FP32 relative to the leaf's first
+// centroid; every lane takes one (row, target) entry of the
 // chunk at a time: the self entry in FP64 by the closed form, touching and
 // near-singular entries queued for pass 2, regular entries by the product
 // rule (sum of w_i w_j / |x_i - y_j|), padding entries set to zero.
 constexpr int kRegHi = 12, kRegLo = 6;
 constexpr int kRegPts = kRegHi + kRegLo;  // points per panel: the 12-point rule, then the 6-point rule
 constexpr int kRowChunk = 16;
+static_assert(kRowChunk <= 256 && kMaxLeaf <= 256, "a regular entry is packed as row << 8 | target in 16 bits");
 
-__device__ inline void stage_points(const double *__restrict__ pv, int32_t k, const double *c0, const NFRules &R,
-                                    int q, float4 *__restrict__ out)
+// A quadrature point in FP32 relative to the leaf's first centroid; the
+// weight of point q of panel k is the rule weight times the panel's area, so
+// the points carry positions only and each panel one area.
+struct P3 {
+    float x, y, z;
+};
+
+__device__ inline void stage_point(const double *__restrict__ pv, int32_t k, const double *c0, const NFRules &R, int q,
+                                   P3 *__restrict__ out)
+{
+    const double *v = pv + 9 * (int64_t)k;
+    const double *b = R.sym_b[q];
+    P3 o;
+    o.x = (float)(b[0] * v[0] + b[1] * v[3] + b[2] * v[6] - c0[0]);
+    o.y = (float)(b[0] * v[1] + b[1] * v[4] + b[2] * v[7] - c0[1]);
+    o.z = (float)(b[0] * v[2] + b[1] * v[5] + b[2] * v[8] - c0[2]);
+    *out = o;
+}
+
+__device__ inline float area32(const double *__restrict__ pv, int32_t k)
 {
     const double *v = pv + 9 * (int64_t)k;
     const double e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
     const double e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
     const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
                  cz = e1[0] * e2[1] - e1[1] * e2[0];
-    const double area = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
-    const double *b = R.sym_b[q];
-    float4 o;
-    o.x = (float)(b[0] * v[0] + b[1] * v[3] + b[2] * v[6] - c0[0]);
-    o.y = (float)(b[0] * v[1] + b[1] * v[4] + b[2] * v[7] - c0[1]);
-    o.z = (float)(b[0] * v[2] + b[1] * v[5] + b[2] * v[8] - c0[2]);
-    o.w = (float)(R.sym_w[q] * area);
-    *out = o;
+    return (float)(0.5 * sqrt(cx * cx + cy * cy + cz * cz));
 }
 
-// sum_i w_i sum_j w_j / |x_i - y_j| over NQ points each: the source points
-// go to registers once, the target points stream from LDS.
+// sum_i w_i sum_j w_j / |x_i - y_j| over the NQ points of one rule (weights
+// R.sym_w[off ..], summing to one; the caller multiplies by both areas): the
+// source points and weights go to registers once, the target points stream
+// from LDS.
 template <int NQ>
-__device__ inline float product_rule(const float4 *__restrict__ xp, const float4 *__restrict__ yp)
+__device__ inline float product_rule(const P3 *__restrict__ xp, const P3 *__restrict__ yp, const NFRules &R, int off)
 {
-    float4 y[NQ];
+    P3 y[NQ];
+    float w[NQ];
 #pragma unroll
-    for (int j = 0; j < NQ; ++j) y[j] = yp[j];
+    for (int j = 0; j < NQ; ++j) {
+        y[j] = yp[j];
+        w[j] = (float)R.sym_w[off + j];
+    }
     float acc = 0.f;
 #pragma unroll 2
     for (int i = 0; i < NQ; ++i) {
-        const float4 x = xp[i];
+        const P3 x = xp[i];
         float inner = 0.f;
 #pragma unroll
         for (int j = 0; j < NQ; ++j) {
             const float dx = x.x - y[j].x, dy = x.y - y[j].y, dz = x.z - y[j].z;
-            inner = fmaf(y[j].w, rsqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))), inner);
+            inner = fmaf(w[j], rsqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))), inner);
         }
-        acc = fmaf(x.w, inner, acc);
+        acc = fmaf((float)R.sym_w[off + i], inner, acc);
     }
     return acc;
 }
@@ -551,8 +569,9 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
 {
     const int64_t li = blockIdx.x;
     if (li >= a.n_leaves) return;
-    __shared__ float4 tp[kMaxLeaf * kRegPts];
-    __shared__ float4 spt[kRowChunk * kRegPts];
+    __shared__ P3 tp[kMaxLeaf * kRegPts];
+    __shared__ P3 spt[kRowChunk * kRegPts];
+    __shared__ float tar[kMaxLeaf], sar[kRowChunk];  // panel areas
     __shared__ float4 tcd[kMaxLeaf], scd[kRowChunk];  // centroid (relative), diameter
     __shared__ int4 tid[kMaxLeaf], sid[kRowChunk];    // vertex ids, panel index
     __shared__ unsigned long long s_cnt[2];
@@ -560,7 +579,7 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
     // regular entries of the current chunk, compacted by rule (4 x 4 from the
     // front, 3 x 3 from the back) so that the lanes of a wave all run the
     // same rule: entry = row << 8 | target
-    __shared__ int32_t s_reg[kRowChunk * kMaxLeaf];
+    __shared__ uint16_t s_reg[kRowChunk * kMaxLeaf];
     __shared__ int s_n4, s_n3;
     const int32_t Tb = a.leaf_box[li];
     const int32_t kb = a.box_beg[Tb], nt = a.box_end[Tb] - kb;
@@ -571,9 +590,10 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
     if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0;
     if (threadIdx.x < kNQueues) s_q[threadIdx.x] = (unsigned long long)a.q_off[4 * li + threadIdx.x];
     for (int e = threadIdx.x; e < nt * kRegPts; e += blockDim.x)
-        stage_points(a.pv, kb + e / kRegPts, c0, R, e % kRegPts, &tp[e]);
+        stage_point(a.pv, kb + e / kRegPts, c0, R, e % kRegPts, &tp[e]);
     for (int j = threadIdx.x; j < nt; j += blockDim.x) {
         const int32_t k = kb + j;
+        tar[j] = area32(a.pv, k);
         tcd[j] = meta32(a, k);
         tid[j] = make_int4(a.pvid[3 * k], a.pvid[3 * k + 1], a.pvid[3 * k + 2], k);
     }
@@ -583,9 +603,10 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
         const int nrc = min(kRowChunk, nr - rc);
         __syncthreads();  // the previous chunk's points are no longer read
         for (int e = threadIdx.x; e < nrc * kRegPts; e += blockDim.x)
-            stage_points(a.pv, a.near_src[r0 + rc + e / kRegPts], c0, R, e % kRegPts, &spt[e]);
+            stage_point(a.pv, a.near_src[r0 + rc + e / kRegPts], c0, R, e % kRegPts, &spt[e]);
         for (int r = threadIdx.x; r < nrc; r += blockDim.x) {
             const int32_t l = a.near_src[r0 + rc + r];
+            sar[r] = area32(a.pv, l);
             scd[r] = meta32(a, l);
             sid[r] = make_int4(a.pvid[3 * l], a.pvid[3 * l + 1], a.pvid[3 * l + 2], l);
         }
@@ -628,12 +649,13 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
         const int n4 = s_n4, n3 = s_n3;
         for (int q = threadIdx.x; q < n4; q += blockDim.x) {
             const int rj = s_reg[q], r = rj >> 8, j = rj & 255;
-            val[vo + (int64_t)(rc + r) * tpad + j] = product_rule<kRegHi>(&tp[j * kRegPts], &spt[r * kRegPts]);
+            val[vo + (int64_t)(rc + r) * tpad + j] =
+                tar[j] * sar[r] * product_rule<kRegHi>(&tp[j * kRegPts], &spt[r * kRegPts], R, 0);
         }
         for (int q = threadIdx.x; q < n3; q += blockDim.x) {
             const int rj = s_reg[kRowChunk * kMaxLeaf - 1 - q], r = rj >> 8, j = rj & 255;
             val[vo + (int64_t)(rc + r) * tpad + j] =
-                product_rule<kRegLo>(&tp[j * kRegPts + kRegHi], &spt[r * kRegPts + kRegHi]);
+                tar[j] * sar[r] * product_rule<kRegLo>(&tp[j * kRegPts + kRegHi], &spt[r * kRegPts + kRegHi], R, kRegHi);
         }
         if (threadIdx.x == 0) c_reg += (unsigned long long)(n4 + n3);
     }
