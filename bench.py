@@ -237,7 +237,7 @@ def main():
             "m2l_flops": m2l_flops, "m2l_tflops": m2l_flops / (ph["m2l"] * 1e-3) / 1e12,
             "p2p_gbps": near_bytes / (ph["p2p"] * 1e-3) / 1e9,
             "nearfield": {k: st[k] for k in ("n_self", "n_touching", "n_near_singular", "n_regular",
-                                             "n_mlp_accepted", "n_mlp_fallback", "audit_max_rel_err",
+                                             "n_regular_fine", "n_mlp_accepted", "n_mlp_fallback", "audit_max_rel_err",
                                              "audit_rms_rel_err", "ms")},
         }
         if tune is not None:

@@ -252,6 +252,7 @@ typedef struct {
     int64_t n_mlp_accepted, n_mlp_fallback;
     double audit_max_rel_err, audit_rms_rel_err; /* surrogate audit, if any */
     double ms;             /* wall time of the assembly */
+    int64_t n_regular_fine; /* regular pairs below r_mid (the finer product rule) */
 } xrl_nf_stats;
 
 /* Fill the near-field panel-panel entries P_kl (frequency independent, done

@@ -334,27 +334,45 @@ __device__ inline bool share_vertex4(int4 ik, int4 il)
            ik.z == il.x || ik.z == il.y || ik.z == il.z;
 }
 
-// Value index of the stored entry (target l, source k) in the block of
-// leaf(l), or -1 when k is not among that leaf's source rows.
-__device__ inline int64_t mirror_index(const NFArgs &a, int32_t k, int32_t l)
+// Mirror of a source row.  The source rows of a leaf are a sorted union of
+// whole boxes and a leaf's panels are one range of panels, so the panels of
+// leaf T (kb .. kb + nt - 1) are either all source rows of leaf(l), on
+// consecutive rows, or none of them is.  Returns the value index of the
+// entry (target l, source kb) in the block of leaf(l), with that block's row
+// stride (its tpad, at most 128) in bits 48..55, or -1 when T's panels are
+// not source rows of leaf(l).
+constexpr int64_t kMirMask = (1ll << 48) - 1;
+
+__device__ inline int64_t row_mirror(const NFArgs &a, int32_t kb, int32_t nt, int32_t l)
 {
     const int32_t li = a.panel_leaf[l];
-    int32_t lo = a.near_rows[li], hi = a.near_rows[li + 1];
+    const int32_t end = a.near_rows[li + 1];
+    int32_t lo = a.near_rows[li], hi = end;
     while (lo < hi) {
         const int32_t mid = lo + (hi - lo) / 2;
-        if (a.near_src[mid] < k)
+        if (a.near_src[mid] < kb)
             lo = mid + 1;
         else
             hi = mid;
     }
-    if (lo >= a.near_rows[li + 1] || a.near_src[lo] != k) return -1;
-    return a.val_off[li] + (int64_t)(lo - a.near_rows[li]) * a.leaf_tpad[li] + (l - a.box_beg[a.leaf_box[li]]);
+    if (lo + nt > end || a.near_src[lo] != kb || a.near_src[lo + nt - 1] != kb + nt - 1) return -1;
+    const int64_t tp = a.leaf_tpad[li];
+    return (tp << 48) | (a.val_off[li] + (int64_t)(lo - a.near_rows[li]) * tp + (l - a.box_beg[a.leaf_box[li]]));
+}
+
+// Value index of the entry (target l, source kb + j) from the row's mirror,
+// or -1.
+__device__ inline int64_t mirror_of(int64_t rm, int32_t j)
+{
+    return rm < 0 ? -1 : (rm & kMirMask) + (int64_t)j * (rm >> 48);
 }
 
 // Counting pass: per leaf, the number of entries of each queue (touching,
-// near-singular classes 0..2), cnt[4 li + q].  FP32 classifies as the FP32
+// near-singular classes 0..2), cnt[4 li + q]; also the mirror of every source
+// row (a.row_mir) for the filling passes.  FP32 classifies as the FP32
 // filling pass does (centroids relative to the plan's reference point),
-// FP64 as the FP64 one.
+// FP64 as the FP64 one.  A pair (k, l) with k > l whose mirror is stored is
+// not queued here: it is integrated as (l, k) and written to both blocks.
 template <bool FP64>
 __global__ __launch_bounds__(256) void k_nf_count(NFArgs a, int64_t *__restrict__ cnt)
 {
@@ -362,57 +380,62 @@ __global__ __launch_bounds__(256) void k_nf_count(NFArgs a, int64_t *__restrict_
     if (li >= a.n_leaves) return;
     __shared__ int s_cnt[kNQueues];
     __shared__ unsigned long long s_all[2];
+    // each chunk of source rows: centroid (relative), diameter; vertex ids,
+    // panel index; the row's mirror
+    __shared__ float4 tcd[kMaxLeaf], scd[256];
+    __shared__ int4 tid[kMaxLeaf], sid[256];
+    __shared__ int64_t smir[256];
     const int32_t Tb = a.leaf_box[li];
     const int32_t kb = a.box_beg[Tb], nt = a.box_end[Tb] - kb;
     const int32_t r0 = a.near_rows[li], nr = a.near_rows[li + 1] - r0;
     if (threadIdx.x < kNQueues) s_cnt[threadIdx.x] = 0;
     if (threadIdx.x < 2) s_all[threadIdx.x] = 0;
-    __syncthreads();
     int my[kNQueues] = {0, 0, 0, 0};
     unsigned long long all[2] = {0, 0};
     const float rn2f = (float)(a.r_near * a.r_near);
-    auto tally = [&](int c, int32_t k, int32_t l) {
+    auto tally = [&](int c, int32_t k, int32_t l, int64_t rm) {
         if (c < kNQueues) {
             ++all[c == kQTouch ? 0 : 1];
-            if (k < l || mirror_index(a, k, l) < 0) ++my[c];
+            if (k < l || rm < 0) ++my[c];
         }
     };
-    if constexpr (FP64) {
-        for (int64_t e = threadIdx.x; e < (int64_t)nr * nt; e += blockDim.x) {
-            const int32_t r = (int32_t)(e / nt), j = (int32_t)(e - (int64_t)r * nt);
-            const int32_t k = kb + j, l = a.near_src[r0 + r];
-            const int4 ik = make_int4(a.pvid[3 * k], a.pvid[3 * k + 1], a.pvid[3 * k + 2], k);
-            const int4 il = make_int4(a.pvid[3 * l], a.pvid[3 * l + 1], a.pvid[3 * l + 2], l);
-            tally(entry_class<double>(k == l, share_vertex4(ik, il), ratio2_64(a, k, l), a.r_near * a.r_near), k,
-                  l);
-        }
-    } else {
-        // the leaf's targets and each chunk of source rows staged in LDS, as
-        // in the FP32 filling pass
-        __shared__ float4 tcd[kMaxLeaf], scd[256];
-        __shared__ int4 tid[kMaxLeaf], sid[256];
+    if constexpr (!FP64) {
         for (int j = threadIdx.x; j < nt; j += blockDim.x) {
             const int32_t k = kb + j;
             tcd[j] = meta32(a, k);
             tid[j] = make_int4(a.pvid[3 * k], a.pvid[3 * k + 1], a.pvid[3 * k + 2], k);
         }
-        for (int rc = 0; rc < nr; rc += 256) {
-            const int nrc = min(256, nr - rc);
-            __syncthreads();  // the previous chunk is no longer read
-            for (int r = threadIdx.x; r < nrc; r += blockDim.x) {
-                const int32_t l = a.near_src[r0 + rc + r];
+    }
+    for (int rc = 0; rc < nr; rc += 256) {
+        const int nrc = min(256, nr - rc);
+        __syncthreads();  // the previous chunk is no longer read
+        for (int r = threadIdx.x; r < nrc; r += blockDim.x) {
+            const int32_t l = a.near_src[r0 + rc + r];
+            const int64_t rm = row_mirror(a, kb, nt, l);
+            smir[r] = rm;
+            a.row_mir[r0 + rc + r] = rm;
+            if constexpr (!FP64) {
                 scd[r] = meta32(a, l);
                 sid[r] = make_int4(a.pvid[3 * l], a.pvid[3 * l + 1], a.pvid[3 * l + 2], l);
             }
-            __syncthreads();
-            for (int e = threadIdx.x; e < nrc * nt; e += blockDim.x) {
-                const int r = e / nt, j = e - r * nt;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nrc * nt; e += blockDim.x) {
+            const int r = e / nt, j = e - r * nt;
+            if constexpr (FP64) {
+                const int32_t k = kb + j, l = a.near_src[r0 + rc + r];
+                const int4 ik = make_int4(a.pvid[3 * k], a.pvid[3 * k + 1], a.pvid[3 * k + 2], k);
+                const int4 il = make_int4(a.pvid[3 * l], a.pvid[3 * l + 1], a.pvid[3 * l + 2], l);
+                tally(entry_class<double>(k == l, share_vertex4(ik, il), ratio2_64(a, k, l), a.r_near * a.r_near), k,
+                      l, smir[r]);
+            } else {
                 const int4 ik = tid[j], il = sid[r];
                 tally(entry_class<float>(ik.w == il.w, share_vertex4(ik, il), ratio2_32(tcd[j], scd[r]), rn2f), ik.w,
-                      il.w);
+                      il.w, smir[r]);
             }
         }
     }
+    __syncthreads();
     for (int q = 0; q < kNQueues; ++q)
         if (my[q]) atomicAdd(&s_cnt[q], my[q]);
     if (all[0]) atomicAdd(&s_all[0], all[0]);
@@ -428,23 +451,25 @@ __global__ __launch_bounds__(256) void k_nf_count(NFArgs a, int64_t *__restrict_
 
 // Pass 1 in FP64: one workgroup per target leaf; self and regular entries
 // computed, the others written to their queue at the leaf's offset (slots
-// within a leaf from LDS counters).
+// within a leaf from LDS counters).  P_kl = P_lk: an entry with k < l whose
+// mirror is stored is computed once and written to both blocks, the entry
+// with k > l is left to the leaf that holds (l, k).
 template <typename V, bool FP64>
 __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restrict__ val)
 {
     const int64_t li = blockIdx.x;
     if (li >= a.n_leaves) return;
-    __shared__ unsigned long long s_cnt[2];
+    __shared__ unsigned long long s_cnt[3];
     __shared__ unsigned long long s_q[kNQueues];
     const int32_t T = a.leaf_box[li];
     const int32_t kb = a.box_beg[T], nt = a.box_end[T] - kb;
     const int32_t r0 = a.near_rows[li], nr = a.near_rows[li + 1] - r0;
     const int tpad = a.leaf_tpad[li];
     const int64_t vo = a.val_off[li];
-    if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0;
+    if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = s_cnt[2] = 0;
     if (threadIdx.x < kNQueues) s_q[threadIdx.x] = (unsigned long long)a.q_off[4 * li + threadIdx.x];
     __syncthreads();
-    unsigned long long c_self = 0, c_reg = 0;
+    unsigned long long c_self = 0, c_reg = 0, c_fine = 0;
     for (int64_t e = threadIdx.x; e < (int64_t)nr * tpad; e += blockDim.x) {
         const int32_t r = (int32_t)(e / tpad), j = (int32_t)(e - (int64_t)r * tpad);
         if (j >= nt) {
@@ -461,10 +486,10 @@ __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restr
             ++c_self;
             continue;
         }
+        // the mirror entry (target l, source k); with k > l and the mirror
+        // stored, this entry is written when (l, k) is computed
+        const int64_t mir = mirror_of(a.row_mir[r0 + r], j);
         if (c < kNQueues) {
-            // the mirror entry (target l, source k); with k > l and the
-            // mirror stored, this entry is written when (l, k) is integrated
-            const int64_t mir = mirror_index(a, k, l);
             if (k < l || mir < 0) {
                 const int64_t pos = (int64_t)atomicAdd(&s_q[c], 1ull);
                 a.work[pos] = vo + e;
@@ -476,21 +501,28 @@ __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restr
             continue;
         }
         ++c_reg;
+        const bool fine = d2 < a.r_mid * a.r_mid;
+        c_fine += fine;
+        if (k > l && mir >= 0) continue;
         double tv[9], svv[9];
         for (int i = 0; i < 9; ++i) {
             tv[i] = a.pv[9 * (int64_t)k + i];
             svv[i] = a.pv[9 * (int64_t)l + i];
         }
-        val[vo + e] = (V)(d2 < a.r_mid * a.r_mid ? regular_pair<double, 5>(tv, svv, R.rx4, R.rw4)
-                                                 : regular_pair<double, 4>(tv, svv, R.rx3, R.rw3));
+        const V v = (V)(fine ? regular_pair<double, 5>(tv, svv, R.rx4, R.rw4)
+                             : regular_pair<double, 4>(tv, svv, R.rx3, R.rw3));
+        val[vo + e] = v;
+        if (mir >= 0) val[mir] = v;
     }
     // class counters: LDS first, one global atomic per workgroup
     if (c_self) atomicAdd(&s_cnt[0], c_self);
     if (c_reg) atomicAdd(&s_cnt[1], c_reg);
+    if (c_fine) atomicAdd(&s_cnt[2], c_fine);
     __syncthreads();
     if (threadIdx.x == 0) {
         atomicAdd(&a.counters[0], s_cnt[0]);
         atomicAdd(&a.counters[3], s_cnt[1]);
+        atomicAdd(&a.counters[4], s_cnt[2]);
     }
 }
 
@@ -502,6 +534,9 @@ __global__ __launch_bounds__(256) void k_nf_main(NFArgs a, NFRules R, V *__restr
 // chunk at a time: the self entry in FP64 by the closed form, touching and
 // near-singular entries queued for pass 2, regular entries by the product
 // rule (sum of w_i w_j / |x_i - y_j|), padding entries set to zero.
+// P_kl = P_lk: a regular entry with k < l whose mirror is stored is computed
+// once and written to both blocks (the classification is bitwise the same
+// in both leaves, see meta32); the entry with k > l is left to leaf(l).
 constexpr int kRegHi = 12, kRegLo = 6;
 constexpr int kRegPts = kRegHi + kRegLo;  // points per panel: the 12-point rule, then the 6-point rule
 constexpr int kRowChunk = 16;
@@ -574,7 +609,8 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
     __shared__ float tar[kMaxLeaf], sar[kRowChunk];  // panel areas
     __shared__ float4 tcd[kMaxLeaf], scd[kRowChunk];  // centroid (relative), diameter
     __shared__ int4 tid[kMaxLeaf], sid[kRowChunk];    // vertex ids, panel index
-    __shared__ unsigned long long s_cnt[2];
+    __shared__ int64_t smir[kRowChunk];               // mirror of each row of the chunk
+    __shared__ unsigned long long s_cnt[3];
     __shared__ unsigned long long s_q[kNQueues];  // next free position of this leaf in each queue
     // regular entries of the current chunk, compacted by rule (4 x 4 from the
     // front, 3 x 3 from the back) so that the lanes of a wave all run the
@@ -587,7 +623,7 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
     const int tpad = a.leaf_tpad[li];
     const int64_t vo = a.val_off[li];
     const double c0[3] = {a.cen[3 * (int64_t)kb], a.cen[3 * (int64_t)kb + 1], a.cen[3 * (int64_t)kb + 2]};
-    if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = 0;
+    if (threadIdx.x == 0) s_cnt[0] = s_cnt[1] = s_cnt[2] = 0;
     if (threadIdx.x < kNQueues) s_q[threadIdx.x] = (unsigned long long)a.q_off[4 * li + threadIdx.x];
     for (int e = threadIdx.x; e < nt * kRegPts; e += blockDim.x)
         stage_point(a.pv, kb + e / kRegPts, c0, R, e % kRegPts, &tp[e]);
@@ -597,7 +633,7 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
         tcd[j] = meta32(a, k);
         tid[j] = make_int4(a.pvid[3 * k], a.pvid[3 * k + 1], a.pvid[3 * k + 2], k);
     }
-    unsigned long long c_self = 0, c_reg = 0;
+    unsigned long long c_self = 0, c_reg = 0, c_fine = 0;
     const float rn2 = (float)(a.r_near * a.r_near), rm2 = (float)(a.r_mid * a.r_mid);
     for (int rc = 0; rc < nr; rc += kRowChunk) {
         const int nrc = min(kRowChunk, nr - rc);
@@ -609,6 +645,7 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
             sar[r] = area32(a.pv, l);
             scd[r] = meta32(a, l);
             sid[r] = make_int4(a.pvid[3 * l], a.pvid[3 * l + 1], a.pvid[3 * l + 2], l);
+            smir[r] = a.row_mir[r0 + rc + r];
         }
         __syncthreads();
         if (threadIdx.x == 0) s_n4 = s_n3 = 0;
@@ -626,11 +663,13 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
             if (c == kSelf) {
                 val[out] = (float)self_term(a.pv + 9 * (int64_t)ik.w);
                 ++c_self;
-            } else if (c < kNQueues) {
-                // the mirror entry (target l, source k); with k > l and the
-                // mirror stored, this entry is written when (l, k) is integrated
-                const int32_t k = ik.w, l = il.w;
-                const int64_t mir = mirror_index(a, k, l);
+                continue;
+            }
+            // the mirror entry (target l, source k); with k > l and the
+            // mirror stored, this entry is written when (l, k) is computed
+            const int32_t k = ik.w, l = il.w;
+            const int64_t mir = mirror_of(smir[r], j);
+            if (c < kNQueues) {
                 if (k < l || mir < 0) {
                     const int64_t pos = (int64_t)atomicAdd(&s_q[c], 1ull);
                     a.work[pos] = out;
@@ -639,35 +678,47 @@ __global__ __launch_bounds__(256) void k_nf_leaf32(NFArgs a, NFRules R, float *_
                     a.work_mirror[pos] = k < l ? mir : -1;
                     val[out] = 0.f;
                 }
-            } else if (d2 < rm2) {
-                s_reg[atomicAdd(&s_n4, 1)] = r << 8 | j;
-            } else {
-                s_reg[kRowChunk * kMaxLeaf - 1 - atomicAdd(&s_n3, 1)] = r << 8 | j;
+                continue;
             }
+            const bool fine = d2 < rm2;
+            ++c_reg;
+            c_fine += fine;
+            if (k > l && mir >= 0) continue;
+            if (fine)
+                s_reg[atomicAdd(&s_n4, 1)] = r << 8 | j;
+            else
+                s_reg[kRowChunk * kMaxLeaf - 1 - atomicAdd(&s_n3, 1)] = r << 8 | j;
         }
         __syncthreads();
         const int n4 = s_n4, n3 = s_n3;
+        // the value, and its mirror where stored (then k < l)
+        auto store = [&](int r, int j, float v) {
+            val[vo + (int64_t)(rc + r) * tpad + j] = v;
+            const int64_t mir = mirror_of(smir[r], j);
+            if (mir >= 0) val[mir] = v;
+        };
         for (int q = threadIdx.x; q < n4; q += blockDim.x) {
             const int rj = s_reg[q], r = rj >> 8, j = rj & 255;
-            val[vo + (int64_t)(rc + r) * tpad + j] =
-                tar[j] * sar[r] * product_rule<kRegHi>(&tp[j * kRegPts], &spt[r * kRegPts], R, 0);
+            store(r, j, tar[j] * sar[r] * product_rule<kRegHi>(&tp[j * kRegPts], &spt[r * kRegPts], R, 0));
         }
         for (int q = threadIdx.x; q < n3; q += blockDim.x) {
             const int rj = s_reg[kRowChunk * kMaxLeaf - 1 - q], r = rj >> 8, j = rj & 255;
-            val[vo + (int64_t)(rc + r) * tpad + j] =
-                tar[j] * sar[r] * product_rule<kRegLo>(&tp[j * kRegPts + kRegHi], &spt[r * kRegPts + kRegHi], R, kRegHi);
+            store(r, j,
+                  tar[j] * sar[r] *
+                      product_rule<kRegLo>(&tp[j * kRegPts + kRegHi], &spt[r * kRegPts + kRegHi], R, kRegHi));
         }
-        if (threadIdx.x == 0) c_reg += (unsigned long long)(n4 + n3);
     }
     // padding rows of a leaf without rows do not exist; class counters: LDS
     // first, one global atomic per workgroup
     __syncthreads();
     if (c_self) atomicAdd(&s_cnt[0], c_self);
     if (c_reg) atomicAdd(&s_cnt[1], c_reg);
+    if (c_fine) atomicAdd(&s_cnt[2], c_fine);
     __syncthreads();
     if (threadIdx.x == 0) {
         atomicAdd(&a.counters[0], s_cnt[0]);
         atomicAdd(&a.counters[3], s_cnt[1]);
+        atomicAdd(&a.counters[4], s_cnt[2]);
     }
 }
 
@@ -908,12 +959,14 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
             P->near64.release();
             P->near32.alloc(std::max<int64_t>(P->n_near_entries, 1));
         }
-        DevBuf<unsigned long long> cnt(4);
+        DevBuf<unsigned long long> cnt(5);
         XRL_HIP(hipMemsetAsync(cnt.p, 0, cnt.bytes(), s));
         NFArgs a{P->leaf_box.p, P->box_beg.p, P->box_end.p, P->near_rows.p, P->near_src.p, P->leaf_tpad.p,
                  P->pvid.p,     P->near_val_off.p, P->pv.p, P->cen.p, P->diam.p, o.r_near, o.r_mid,
-                 P->n_leaves,   cnt.p,       nullptr,  nullptr, nullptr, nullptr, P->panel_leaf.p,
+                 P->n_leaves,   cnt.p,       nullptr,  nullptr, nullptr, nullptr, nullptr, P->panel_leaf.p,
                  {P->trees[0]->root_c[0], P->trees[0]->root_c[1], P->trees[0]->root_c[2]}};
+        DevBuf<int64_t> rowmir(std::max<int64_t>(P->n_near_rows, 1));
+        a.row_mir = rowmir.p;
         // counting pass, then every leaf's first position in each queue
         // (queues stored one after another: touching, near-singular 0, 1, 2)
         const int64_t L = P->n_leaves;
@@ -1035,6 +1088,7 @@ extern "C" xrl_status xrl_nearfield_assemble(xrl_plan *P, const xrl_nf_opts *opt
             stats->n_touching = (int64_t)hc[1];
             stats->n_near_singular = (int64_t)hc[2];
             stats->n_regular = (int64_t)hc[3];
+            stats->n_regular_fine = (int64_t)hc[4];
             stats->n_mlp_accepted = n_acc;
             stats->n_mlp_fallback = o.surrogate ? n_fb : 0;
             stats->audit_max_rel_err = aud_max;

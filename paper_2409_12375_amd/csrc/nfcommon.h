@@ -37,7 +37,7 @@ struct NFArgs {
     const double *pv, *cen, *diam;
     double r_near, r_mid;
     int64_t n_leaves;
-    unsigned long long *counters;  // [0] self [1] touch [2] near-singular [3] regular
+    unsigned long long *counters;  // [0] self [1] touch [2] near-singular [3] regular [4] regular below r_mid
     // Queued entries, one contiguous range per queue (kQTouch, kQNs0..2):
     // work[pos] = value index, work_meta[2 pos], [2 pos + 1] = (k, l).
     // q_off[4 li + q]: first position of leaf li in queue q (exclusive scan
@@ -49,6 +49,9 @@ struct NFArgs {
     // written to the block of leaf(l) (work_mirror[pos], -1 if that entry is
     // not stored); entries with k > l whose mirror is stored are not queued.
     int64_t *work_mirror;
+    // [n_near_rows]: the mirror of every source row (row_mirror), written by
+    // the counting pass and read by the filling passes
+    int64_t *row_mir;
     const int32_t *panel_leaf;  // [N] leaf of each sorted panel
     // Reference point of the FP32 classification: every leaf classifies its
     // entries from centroids relative to this one point, so (k, l) and

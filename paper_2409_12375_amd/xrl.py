@@ -73,7 +73,7 @@ class NfStats(ctypes.Structure):
     _fields_ = [("n_entries", _i64), ("n_self", _i64), ("n_touching", _i64), ("n_near_singular", _i64),
                 ("n_regular", _i64), ("n_mlp_accepted", _i64), ("n_mlp_fallback", _i64),
                 ("audit_max_rel_err", ctypes.c_double), ("audit_rms_rel_err", ctypes.c_double),
-                ("ms", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("n_regular_fine", _i64)]
 
 
 class Epilogue(ctypes.Structure):
@@ -112,6 +112,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libxrl.so is not built (run paper_2409_12375_amd/build.py or "
                                "__graft_entry__.build()); there is no CPU fallback")
+        # Device pointers and streams pass between torch and the library, so
+        # both must use one HIP runtime.  torch ships its own libamdhip64.so.7
+        # (same soname as the system one): loading torch first makes the
+        # library bind to that copy instead of a second runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         L.xrl_last_error.restype = ctypes.c_char_p
         L.xrl_version.restype = ctypes.c_char_p

@@ -116,6 +116,10 @@ def test_bar_matvec_matches_oracle(precision, engine, dtype, tol):
     x = I.densities(N, 3, dtype)
     plan, y, st = _run(V, T, x, precision, engine=engine)
     assert st["n_self"] == N
+    # every unpadded near pair falls in exactly one class; the finer
+    # regular rule takes the pairs below r_mid
+    assert st["n_self"] + st["n_touching"] + st["n_near_singular"] + st["n_regular"] == plan.info()["n_near_pairs"]
+    assert 0 < st["n_regular_fine"] < st["n_regular"]
     rows = sample_rows(N, 384)
     ref, _ = O.matvec(V, T, x.astype(np.complex128), rows=rows)
     err = relerr_cols(y[rows], ref)
