@@ -253,8 +253,8 @@ struct xrl_plan {
     // translation passes
     int64_t n_m2l = 0;
     int64_t n_demoted = 0;  // V candidates applied directly (radii do not separate)
-    std::vector<int32_t> h_m2l_pairs;  // [n][2] (t, s), per-target order, for export
-    std::vector<double> h_m2l_ratio;   // [n] (r_t + r_s) / |c_t - c_s| of each pair, same order
+    xrl::DevBuf<int32_t> m2l_pair_t, m2l_pair_s;  // [n] target and source box of each pair, per-target order
+    xrl::DevBuf<double> m2l_ratio;                // [n] (r_t + r_s) / |c_t - c_s| of each pair, same order
     double theta = XRL_DEFAULT_THETA;  // separation criterion of the V-list pairs
     TransPass m2l;
     std::vector<TransPass> m2m, l2l;   // per level

@@ -16,13 +16,18 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <memory>
+#include <mutex>
 #include <numeric>
+#include <thread>
 
 #include "common.h"
 #include "scan.h"
+#include "sort.h"
 #include "harmonics.h"
 
 namespace xrl {
@@ -482,106 +487,282 @@ static int32_t m2l_reflected_code(int32_t slot)
     return canon << 3 | (ox < 0 ? 1 : 0) | (oy < 0 ? 2 : 0) | (oz < 0 ? 4 : 0);
 }
 
-// Sort the (target, source, operator) triples of one pass by operator; the
-// input is grouped by target (targets ascending, pairs of a target
-// contiguous).  ts_code: operator code of each pair for the
-// target-stationary kernel (input order); empty = the operator index
-// itself, no reflection.  That kernel visits the pairs of a target sorted by
-// reflection bits (then in input order), so its accumulator changes frame
-// at most seven times per target.
-// Stable counting sort of idx[0..n) by key(idx) in [0, nkey): O(n + nkey).
-template <class Key>
-static void counting_sort(int32_t *idx, int64_t n, int nkey, Key key, std::vector<int64_t> &cnt,
-                          std::vector<int32_t> &tmp)
+// ---------------------------------------------------------------- passes
+// A translation pass from its (target, source, operator) triples, grouped
+// by target (targets ascending, the pairs of a target contiguous), built on
+// the device:
+//   operator order (offset-stationary kernels): the triples stably sorted by
+//     operator, the groups of one operator, and each pair's sorted position;
+//   target order (target-stationary kernels): the runs of one target, the
+//     pairs of each run stably sorted by reflection bits (so the
+//     accumulator of a reflected table changes frame at most seven times
+//     per target), the runs of one source in that order, and the targets
+//     with the most pairs first (ties in target order).
+
+// flag[j] = 1 where a[j] starts a run of equal values
+__global__ void k_run_flags(int64_t n, const int32_t *__restrict__ a, int32_t *__restrict__ flag)
 {
-    cnt.assign(nkey + 1, 0);
-    for (int64_t j = 0; j < n; ++j) ++cnt[key(idx[j]) + 1];
-    for (int k = 0; k < nkey; ++k) cnt[k + 1] += cnt[k];
-    tmp.resize(n);
-    for (int64_t j = 0; j < n; ++j) tmp[cnt[key(idx[j])]++] = idx[j];
-    std::copy(tmp.begin(), tmp.begin() + n, idx);
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j < n) flag[j] = (j == 0 || a[j] != a[j - 1]) ? 1 : 0;
 }
 
-static void build_pass(TransPass &T, const std::vector<int32_t> &tgt, const std::vector<int32_t> &src,
-                       const std::vector<int32_t> &code, hipStream_t s, const std::vector<int32_t> &ts_code = {})
+// beg[pos[j]] = j for every run start j, and beg[runs] = n
+__global__ void k_run_starts(int64_t n, const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
+                             int32_t *__restrict__ beg)
 {
-    const int64_t n = (int64_t)tgt.size();
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    if (flag[j]) beg[pos[j]] = (int32_t)j;
+    if (j == n - 1) beg[pos[j] + flag[j]] = (int32_t)n;
+}
+
+// out[i] = a[idx[i]]
+__global__ void k_gather_i32(int64_t n, const int32_t *__restrict__ idx, const int32_t *__restrict__ a,
+                             int32_t *__restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[idx[i]];
+}
+
+__global__ void k_code_keys(int64_t n, const int32_t *__restrict__ code, uint64_t *__restrict__ key,
+                            int32_t *__restrict__ idx)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    key[j] = (uint64_t)code[j];
+    idx[j] = (int32_t)j;
+}
+
+// operator order: sorted source, operator and position of every pair
+__global__ void k_pass_osort(int64_t n, const int32_t *__restrict__ ord, const int32_t *__restrict__ src,
+                             const int32_t *__restrict__ code, int32_t *__restrict__ osrc,
+                             int32_t *__restrict__ ocode, int32_t *__restrict__ slot)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int32_t o = ord[j];
+    osrc[j] = src[o];
+    ocode[j] = code[o];
+    slot[o] = (int32_t)j;
+}
+
+// target order: one thread per target run [rp[i], rp[i+1]), its pairs by
+// reflection bits (eight stable passes over the run)
+__global__ void k_pass_tsort(int64_t nrun, const int32_t *__restrict__ rp, const int32_t *__restrict__ rt,
+                             const int32_t *__restrict__ src, const int32_t *__restrict__ code,
+                             const int32_t *__restrict__ ts_code, int32_t *__restrict__ tsrc,
+                             int32_t *__restrict__ tcode, int32_t *__restrict__ ttgt,
+                             int32_t *__restrict__ tfull)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nrun) return;
+    const int32_t a = rp[i], b = rp[i + 1], t = rt[i];
+    int32_t p = a;
+    for (int f = 0; f < 8; ++f)
+        for (int32_t j = a; j < b; ++j) {
+            const int32_t c8 = ts_code ? ts_code[j] : code[j] << 3;
+            if ((c8 & 7) != f) continue;
+            tsrc[p] = src[j];
+            tcode[p] = c8;
+            ttgt[p] = t;
+            if (tfull) tfull[p] = code[j] << 3;
+            ++p;
+        }
+}
+
+// pairs per run and their maximum
+__global__ void k_run_counts(int64_t nrun, const int32_t *__restrict__ rp, int32_t *__restrict__ cnt,
+                             int32_t *__restrict__ maxc)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nrun) return;
+    const int32_t c = rp[i + 1] - rp[i];
+    cnt[i] = c;
+    atomicMax(maxc, c);
+}
+
+__global__ void k_heavy_keys(int64_t nrun, const int32_t *__restrict__ cnt, const int32_t *__restrict__ maxc,
+                             uint64_t *__restrict__ key, int32_t *__restrict__ idx)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nrun) return;
+    key[i] = (uint64_t)(*maxc - cnt[i]);
+    idx[i] = (int32_t)i;
+}
+
+static int bit_width(uint64_t v)
+{
+    int b = 0;
+    while (v >> b) ++b;
+    return std::max(b, 1);
+}
+
+// Starts of the runs of equal values of a[0..n) into beg (n + 1 entries,
+// the first runs + 1 used); returns the number of runs.
+static int64_t run_starts(const int32_t *a, int64_t n, DevBuf<int32_t> &beg, hipStream_t s)
+{
+    DevBuf<int32_t> flag(n), pos(n), tot(1);
+    k_run_flags<<<(unsigned)cdiv(n, 256), 256, 0, s>>>(n, a, flag.p);
+    XRL_HIP(hipGetLastError());
+    exclusive_scan<int32_t, int32_t>(flag.p, n, pos.p, tot.p, s);
+    beg.alloc(n + 1);
+    k_run_starts<<<(unsigned)cdiv(n, 256), 256, 0, s>>>(n, flag.p, pos.p, beg.p);
+    XRL_HIP(hipGetLastError());
+    return tot.download(s)[0];
+}
+
+// The pass of n triples (device arrays tgt, src, code; ts_code: operator
+// code of each pair for the target-stationary kernel, or null for code << 3,
+// no reflection); ncode bounds the codes.
+static void build_pass(TransPass &T, int64_t n, const int32_t *tgt, const int32_t *src, const int32_t *code,
+                       int ncode, hipStream_t s, const int32_t *ts_code = nullptr)
+{
     T.n_pairs = n;
-    std::vector<int64_t> cnt;
-    std::vector<int32_t> tmp;
-    std::vector<int32_t> ord(n);
-    std::iota(ord.begin(), ord.end(), 0);
-    int ncode = 1;
-    for (int32_t c : code) ncode = std::max(ncode, c + 1);
-    counting_sort(ord.data(), n, ncode, [&](int32_t a) { return code[a]; }, cnt, tmp);
-    std::vector<int32_t> osrc(n), slot(n), goff, gbeg;
-    for (int64_t j = 0; j < n; ++j) {
-        osrc[j] = src[ord[j]];
-        slot[ord[j]] = (int32_t)j;
-        if (j == 0 || code[ord[j]] != code[ord[j - 1]]) {
-            goff.push_back(code[ord[j]]);
-            gbeg.push_back((int32_t)j);
+    T.n_groups = T.n_red = T.n_ps = 0;
+    T.h_gbeg.assign(1, 0);
+    if (n == 0) return;
+    XRL_CHECK(n < (int64_t(1) << 31), XRL_E_UNSUPPORTED, "xrl_fmm_plan: a translation pass of %lld pairs",
+              (long long)n);
+    const unsigned g = (unsigned)cdiv(n, 256);
+    // operator order
+    {
+        DevBuf<uint64_t> key(n), ktmp(n);
+        DevBuf<int32_t> ord(n), otmp(n), ocode(n);
+        k_code_keys<<<g, 256, 0, s>>>(n, code, key.p, ord.p);
+        XRL_HIP(hipGetLastError());
+        radix_sort_pairs(key.p, ord.p, ktmp.p, otmp.p, n, bit_width((uint64_t)ncode), s);
+        T.src.alloc(n);
+        T.red_slot.alloc(n);
+        k_pass_osort<<<g, 256, 0, s>>>(n, ord.p, src, code, T.src.p, ocode.p, T.red_slot.p);
+        XRL_HIP(hipGetLastError());
+        T.n_groups = run_starts(ocode.p, n, T.gbeg, s);
+        T.goff.alloc(T.n_groups);
+        k_gather_i32<<<(unsigned)cdiv(T.n_groups, 256), 256, 0, s>>>(T.n_groups, T.gbeg.p, ocode.p, T.goff.p);
+        XRL_HIP(hipGetLastError());
+        T.h_gbeg = T.gbeg.download(s, T.n_groups + 1);
+    }
+    // target order
+    T.n_red = run_starts(tgt, n, T.red_ptr, s);
+    const int64_t nr = T.n_red;
+    const unsigned gr = (unsigned)cdiv(nr, 256);
+    T.red_tgt.alloc(nr);
+    k_gather_i32<<<gr, 256, 0, s>>>(nr, T.red_ptr.p, tgt, T.red_tgt.p);
+    XRL_HIP(hipGetLastError());
+    T.ts_src.alloc(n);
+    T.ts_op.alloc(n);
+    T.ts_tgt.alloc(n);
+    if (ts_code)
+        T.ts_op_full.alloc(n);
+    else
+        T.ts_op_full.release();
+    k_pass_tsort<<<gr, 256, 0, s>>>(nr, T.red_ptr.p, T.red_tgt.p, src, code, ts_code, T.ts_src.p, T.ts_op.p,
+                                    T.ts_tgt.p, ts_code ? T.ts_op_full.p : nullptr);
+    XRL_HIP(hipGetLastError());
+    T.n_ps = run_starts(T.ts_src.p, n, T.ps_beg, s);
+    // targets with the most pairs first, ties in target order
+    DevBuf<int32_t> cnt(nr), maxc(1), hidx(nr), htmp(nr);
+    DevBuf<uint64_t> hkey(nr), hktmp(nr);
+    XRL_HIP(hipMemsetAsync(maxc.p, 0, sizeof(int32_t), s));
+    k_run_counts<<<gr, 256, 0, s>>>(nr, T.red_ptr.p, cnt.p, maxc.p);
+    XRL_HIP(hipGetLastError());
+    const int32_t mc = maxc.download(s)[0];
+    k_heavy_keys<<<gr, 256, 0, s>>>(nr, cnt.p, maxc.p, hkey.p, hidx.p);
+    XRL_HIP(hipGetLastError());
+    radix_sort_pairs(hkey.p, hidx.p, hktmp.p, htmp.p, nr, bit_width((uint64_t)mc), s);
+    T.ts_order = std::move(hidx);
+}
+
+// M2L offset slot (ox+3) + 7 (oy+3) + 49 (oz+3) of every V-list pair -> the
+// code of the target-stationary kernel: index of the offset (|ox|, |oy|,
+// |oz|) in the 64-entry table of non-negative offsets, shifted left by 3,
+// with the reflection bits (1: x, 2: y, 4: z) of the signs.
+__global__ void k_m2l_pairs(int64_t B, const int64_t *__restrict__ voff, const int32_t *__restrict__ vsrc,
+                            const int32_t *__restrict__ vcode, const double *__restrict__ center,
+                            const double *__restrict__ rad, int32_t *__restrict__ tgt, int32_t *__restrict__ rcode,
+                            double *__restrict__ ratio, unsigned long long *__restrict__ max_ratio_bits)
+{
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double mx = 0;
+    for (int64_t j = voff[b]; j < voff[b + 1]; ++j) {
+        tgt[j] = (int32_t)b;
+        const int32_t slot = vcode[j];
+        const int ox = slot % 7 - 3, oy = (slot / 7) % 7 - 3, oz = slot / 49 - 3;
+        const int canon = abs(ox) + 4 * abs(oy) + 16 * abs(oz);
+        rcode[j] = canon << 3 | (ox < 0 ? 1 : 0) | (oy < 0 ? 2 : 0) | (oz < 0 ? 4 : 0);
+        const int32_t sb = vsrc[j];
+        double d2 = 0;
+        for (int d = 0; d < 3; ++d) {
+            const double dd = center[3 * b + d] - center[3 * (int64_t)sb + d];
+            d2 += dd * dd;
         }
+        const double r = (rad[b] + rad[sb]) / sqrt(d2);
+        ratio[j] = r;
+        mx = fmax(mx, r);
     }
-    gbeg.push_back((int32_t)n);
-    std::vector<int32_t> rt, rp{0};
-    for (int64_t q = 0; q < n; ++q) {
-        if (q == 0 || tgt[q] != tgt[q - 1]) {
-            if (q > 0) rp.push_back((int32_t)q);
-            rt.push_back(tgt[q]);
-        }
+    // non-negative doubles order as their bit patterns
+    if (mx > 0) atomicMax(max_ratio_bits, (unsigned long long)__double_as_longlong(mx));
+}
+
+// M2M pairs of one level (parent b <- child, operator: the child's octant),
+// from each parent's first position pos[b - lo]
+__global__ void k_m2m_pairs(int32_t lo, int32_t nb, const int32_t *__restrict__ child0,
+                            const int32_t *__restrict__ nchild, const int32_t *__restrict__ octant,
+                            const int32_t *__restrict__ pos, int32_t *__restrict__ tgt, int32_t *__restrict__ src,
+                            int32_t *__restrict__ code)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int32_t b = lo + i;
+    for (int32_t c = 0; c < nchild[b]; ++c) {
+        const int32_t ch = child0[b] + c;
+        tgt[pos[i] + c] = b;
+        src[pos[i] + c] = ch;
+        code[pos[i] + c] = octant[ch];
     }
-    if (n > 0) rp.push_back((int32_t)n);
-    T.n_groups = (int64_t)goff.size();
-    T.n_red = (int64_t)rt.size();
-    T.h_gbeg = gbeg;
-    T.src.upload(osrc, s);
-    T.goff.upload(goff, s);
-    T.gbeg.upload(gbeg, s);
-    T.red_tgt.upload(rt, s);
-    T.red_ptr.upload(rp, s);
-    T.red_slot.upload(slot, s);
-    // target order: source and operator code of every pair
-    std::vector<int32_t> c8(n), tsrc(n), tord(n);
-    for (int64_t j = 0; j < n; ++j) c8[j] = ts_code.empty() ? code[j] << 3 : ts_code[j];
-    std::iota(tord.begin(), tord.end(), 0);
-    for (size_t i = 0; i + 1 < rp.size(); ++i)
-        counting_sort(tord.data() + rp[i], rp[i + 1] - rp[i], 8, [&](int32_t a) { return c8[a] & 7; }, cnt, tmp);
-    std::vector<int32_t> tcode(n);
-    for (int64_t j = 0; j < n; ++j) {
-        tsrc[j] = src[tord[j]];
-        tcode[j] = c8[tord[j]];
-    }
-    T.ts_src.upload(tsrc, s);
-    T.ts_op.upload(tcode, s);
-    // target of every pair, and the runs of pairs with one source (the
-    // children of one parent in an L2L pass)
-    std::vector<int32_t> ttgt(n), psb;
-    for (size_t i = 0; i + 1 < rp.size(); ++i)
-        for (int32_t j = rp[i]; j < rp[i + 1]; ++j) ttgt[j] = rt[i];
-    for (int64_t j = 0; j < n; ++j)
-        if (j == 0 || tsrc[j] != tsrc[j - 1]) psb.push_back((int32_t)j);
-    psb.push_back((int32_t)n);
-    T.n_ps = n > 0 ? (int64_t)psb.size() - 1 : 0;
-    T.ts_tgt.upload(ttgt, s);
-    T.ps_beg.upload(psb, s);
-    // targets with the most pairs first (ties in target order)
-    std::vector<int32_t> heavy(rt.size());
-    std::iota(heavy.begin(), heavy.end(), 0);
-    int32_t maxc = 0;
-    for (size_t i = 0; i + 1 < rp.size(); ++i) maxc = std::max(maxc, rp[i + 1] - rp[i]);
-    counting_sort(heavy.data(), (int64_t)heavy.size(), maxc + 1,
-                  [&](int32_t a) { return maxc - (rp[a + 1] - rp[a]); }, cnt, tmp);
-    T.ts_order.upload(heavy, s);
-    if (!ts_code.empty()) {
-        for (int64_t j = 0; j < n; ++j) tcode[j] = code[tord[j]] << 3;
-        T.ts_op_full.upload(tcode, s);
-    }
+}
+
+// L2L pairs of one level (child b <- its parent, operator: the octant of b)
+__global__ void k_l2l_pairs(int32_t lo, int32_t nb, const int32_t *__restrict__ parent,
+                            const int32_t *__restrict__ octant, int32_t *__restrict__ tgt, int32_t *__restrict__ src,
+                            int32_t *__restrict__ code)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    tgt[i] = lo + i;
+    src[i] = parent[lo + i];
+    code[i] = octant[lo + i];
 }
 
 }  // namespace xrl
 
 using namespace xrl;
+
+// fn(i, scratch) for i in [0, n) on up to 16 host threads, each with its own
+// scratch vector of `scratch` doubles; the calls are independent.
+template <class F>
+static void for_each_parallel(int n, F fn, size_t scratch)
+{
+    const int nt = std::max(1, std::min<int>({n, 16, (int)std::thread::hardware_concurrency()}));
+    std::atomic<int> next{0};
+    std::mutex mu;
+    std::exception_ptr err;  // the first failure, rethrown on the calling thread
+    auto work = [&] {
+        try {
+            std::vector<double> buf(scratch);
+            for (int i = next++; i < n; i = next++) fn(i, buf);
+        } catch (...) {
+            std::lock_guard<std::mutex> lk(mu);
+            if (!err) err = std::current_exception();
+            next = n;
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+    work();
+    for (auto &th : pool) th.join();
+    if (err) std::rethrow_exception(err);
+}
 
 static void build_plan(xrl_plan *P, hipStream_t s)
 {
@@ -720,26 +901,18 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     k_vlist<<<cdiv(B, 128), 128, 0, s>>>(bv, B, coll.p, P->box_center.p, P->box_rad.p, theta, vcnt.p, dcnt.p,
                                          nullptr, nullptr, nullptr, nullptr, nullptr);
     XRL_HIP(hipGetLastError());
-    auto hv = vcnt.download(s);
-    auto hd = dcnt.download(s);
-    std::vector<int64_t> voff(B + 1, 0), doff(B + 1, 0);
-    for (int64_t b = 0; b < B; ++b) {
-        voff[b + 1] = voff[b] + hv[b];
-        doff[b + 1] = doff[b] + hd[b];
-    }
-    const int64_t nV = voff[B];
+    DevBuf<int64_t> dvoff(B + 1), ddoff(B + 1), vtot(1), dtot(1);
+    exclusive_scan<int32_t, int64_t>(vcnt.p, B, dvoff.p, vtot.p, s);
+    exclusive_scan<int32_t, int64_t>(dcnt.p, B, ddoff.p, dtot.p, s);
+    XRL_HIP(hipMemcpyAsync(dvoff.p + B, vtot.p, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    XRL_HIP(hipMemcpyAsync(ddoff.p + B, dtot.p, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    const int64_t nV = vtot.download(s)[0], nD = dtot.download(s)[0];
     P->n_m2l = nV;
-    P->n_demoted = doff[B];
-    DevBuf<int64_t> dvoff, ddoff;
-    dvoff.upload(voff, s);
-    ddoff.upload(doff, s);
-    DevBuf<int32_t> vsrc(std::max<int64_t>(nV, 1)), vcode(std::max<int64_t>(nV, 1)),
-        dsrc(std::max<int64_t>(doff[B], 1));
+    P->n_demoted = nD;
+    DevBuf<int32_t> vsrc(std::max<int64_t>(nV, 1)), vcode(std::max<int64_t>(nV, 1)), dsrc(std::max<int64_t>(nD, 1));
     k_vlist<<<cdiv(B, 128), 128, 0, s>>>(bv, B, coll.p, P->box_center.p, P->box_rad.p, theta, vcnt.p, dcnt.p,
                                          dvoff.p, ddoff.p, vsrc.p, vcode.p, dsrc.p);
     XRL_HIP(hipGetLastError());
-    auto hsrc = vsrc.download(s, nV);
-    auto hcode = vcode.download(s, nV);
     // ---------------- near lists (source boxes), then rows, all on the device
     const int64_t nl = P->n_leaves;
     for (int64_t li = 0; li < nl; ++li)
@@ -797,66 +970,53 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     P->n_near_rows = n_rows;
     P->n_near_entries = tot.download(s)[0];
     P->n_near_pairs = tot2.download(s)[0];
-    // ---------------- translation passes: M2L (all levels), M2M and L2L per level
+    // ---------------- translation passes: M2L (all levels), M2M and L2L per
+    // level, on the device
     {
-        std::vector<int32_t> tg, sr, cd, rc;
-        for (int64_t b = 0; b < B; ++b)
-            for (int64_t j = voff[b]; j < voff[b + 1]; ++j) {
-                tg.push_back((int32_t)b);
-                sr.push_back(hsrc[j]);
-                cd.push_back(hcode[j]);
-                rc.push_back(m2l_reflected_code(hcode[j]));
-            }
-        build_pass(P->m2l, tg, sr, cd, s, rc);
+        DevBuf<int32_t> mtgt(std::max<int64_t>(nV, 1)), mrc(std::max<int64_t>(nV, 1));
+        DevBuf<unsigned long long> mx(1);
+        P->m2l_ratio.alloc(std::max<int64_t>(nV, 1));
+        XRL_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned long long), s));
+        k_m2l_pairs<<<cdiv(B, 128), 128, 0, s>>>(B, dvoff.p, vsrc.p, vcode.p, P->box_center.p, P->box_rad.p, mtgt.p,
+                                                 mrc.p, P->m2l_ratio.p, mx.p);
+        XRL_HIP(hipGetLastError());
+        build_pass(P->m2l, nV, mtgt.p, vsrc.p, vcode.p, 343, s, mrc.p);
+        const unsigned long long mb = mx.download(s)[0];
+        double maxsep;
+        std::memcpy(&maxsep, &mb, sizeof maxsep);
+        P->max_sep_ratio = maxsep;
+        // the pairs in per-target order, for export
+        P->m2l_pair_t = std::move(mtgt);
+        P->m2l_pair_s = std::move(vsrc);
         P->m2m.clear();
         P->l2l.clear();
         P->m2m.resize(depth + 1);
         P->l2l.resize(depth + 1);
         for (int l = 0; l <= depth; ++l) {
-            std::vector<int32_t> t1, s1, c1, t2, s2, c2;
-            for (int64_t b = P->level_off[l]; b < P->level_off[l + 1]; ++b) {
-                for (int i = 0; i < nchild[b]; ++i) {  // M2M: parent b <- child
-                    t1.push_back((int32_t)b);
-                    s1.push_back(child0[b] + i);
-                    c1.push_back(octant[child0[b] + i]);
-                }
-                if (l >= 3) {  // L2L: child b <- parent (locals are zero above level 2)
-                    t2.push_back((int32_t)b);
-                    s2.push_back(parent[b]);
-                    c2.push_back(octant[b]);
-                }
+            const int32_t lo = (int32_t)P->level_off[l], nb = (int32_t)(P->level_off[l + 1] - P->level_off[l]);
+            if (nb == 0) continue;
+            // M2M: parent b <- each child
+            DevBuf<int32_t> pos(nb), ptot(1);
+            exclusive_scan<int32_t, int32_t>(P->box_nchild.p + lo, nb, pos.p, ptot.p, s);
+            const int32_t n1 = ptot.download(s)[0];
+            if (n1 > 0) {
+                DevBuf<int32_t> t1(n1), s1(n1), c1(n1);
+                k_m2m_pairs<<<cdiv(nb, 128), 128, 0, s>>>(lo, nb, P->box_child0.p, P->box_nchild.p, P->box_octant.p,
+                                                          pos.p, t1.p, s1.p, c1.p);
+                XRL_HIP(hipGetLastError());
+                build_pass(P->m2m[l], n1, t1.p, s1.p, c1.p, 8, s);
             }
-            build_pass(P->m2m[l], t1, s1, c1, s);
-            build_pass(P->l2l[l], t2, s2, c2, s);
+            // L2L: child b <- its parent (locals are zero above level 2)
+            if (l >= 3) {
+                DevBuf<int32_t> t2(nb), s2(nb), c2(nb);
+                k_l2l_pairs<<<cdiv(nb, 128), 128, 0, s>>>(lo, nb, P->box_parent.p, P->box_octant.p, t2.p, s2.p, c2.p);
+                XRL_HIP(hipGetLastError());
+                build_pass(P->l2l[l], nb, t2.p, s2.p, c2.p, 8, s);
+            }
         }
     }
-    P->h_m2l_pairs.resize(2 * nV);
-    P->h_m2l_ratio.resize(nV);
-    std::vector<double> hrad = P->box_rad.download(s);
-    double maxsep = 0;
-    for (int64_t b = 0, q = 0; b < B; ++b)
-        for (int64_t j = voff[b]; j < voff[b + 1]; ++j, ++q) {
-            P->h_m2l_pairs[2 * q] = (int32_t)b;
-            P->h_m2l_pairs[2 * q + 1] = hsrc[j];
-            const int32_t sb = hsrc[j];
-            double d2 = 0;
-            for (int d = 0; d < 3; ++d) {
-                const double dd = center[3 * b + d] - center[3 * sb + d];
-                d2 += dd * dd;
-            }
-            P->h_m2l_ratio[q] = (hrad[b] + hrad[sb]) / std::sqrt(d2);
-            maxsep = std::max(maxsep, P->h_m2l_ratio[q]);
-        }
-    P->max_sep_ratio = maxsep;
     std::vector<int32_t> grp_off;
-    {
-        std::vector<char> seen(343, 0);
-        for (int64_t j = 0; j < nV; ++j)
-            if (!seen[hcode[j]]) {
-                seen[hcode[j]] = 1;
-                grp_off.push_back(hcode[j]);
-            }
-    }
+    if (P->m2l.n_groups > 0) grp_off = P->m2l.goff.download(s, P->m2l.n_groups);
     // ---------------- operators
     const int p = P->p, K = P->K;
     std::vector<double> m2m(8 * (size_t)K * K), l2l(8 * (size_t)K * K);
@@ -864,16 +1024,23 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     build_l2l(p, l2l.data());
     P->KP = (int)cdiv(K, 16) * 16;
     P->KK = (int)cdiv(K, 4) * 4;
-    std::vector<double> m2l(343 * (size_t)P->KP * P->KK, 0.0), tmp((size_t)K * K);
-    std::vector<char> used(343, 0);
-    for (int c : grp_off) used[c] = 1;
-    for (int c = 0; c < 343; ++c) {
-        if (!used[c]) continue;
-        const int ox = c % 7 - 3, oy = (c / 7) % 7 - 3, oz = c / 49 - 3;
-        build_m2l(p, ox, oy, oz, tmp.data());
-        for (int r = 0; r < K; ++r)
-            for (int k = 0; k < K; ++k) m2l[((size_t)c * P->KP + r) * P->KK + k] = tmp[(size_t)r * K + k];
+    std::vector<double> m2l(343 * (size_t)P->KP * P->KK, 0.0);
+    std::vector<int> used_codes;
+    {
+        std::vector<char> used(343, 0);
+        for (int c : grp_off) used[c] = 1;
+        for (int c = 0; c < 343; ++c)
+            if (used[c]) used_codes.push_back(c);
     }
+    // the operators of the offsets in use, each an independent FP64
+    // construction, on the host's cores
+    for_each_parallel((int)used_codes.size(), [&](int i, std::vector<double> &scratch) {
+        const int c = used_codes[i];
+        const int ox = c % 7 - 3, oy = (c / 7) % 7 - 3, oz = c / 49 - 3;
+        build_m2l(p, ox, oy, oz, scratch.data());
+        for (int r = 0; r < K; ++r)
+            for (int k = 0; k < K; ++k) m2l[((size_t)c * P->KP + r) * P->KK + k] = scratch[(size_t)r * K + k];
+    }, (size_t)K * K);
     auto to32 = [](const std::vector<double> &v) {
         std::vector<float> f(v.size());
         for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
@@ -939,12 +1106,15 @@ static void build_plan(xrl_plan *P, hipStream_t s)
         std::vector<double> m2lc(64 * (size_t)P->KP * P->KK, 0.0);
         std::vector<char> cu(64, 0);
         for (int c : grp_off) cu[m2l_reflected_code(c) >> 3] = 1;
-        for (int c = 0; c < 64; ++c) {
-            if (!cu[c]) continue;
-            build_m2l(p, c % 4, (c / 4) % 4, c / 16, tmp.data());
+        std::vector<int> canon;
+        for (int c = 0; c < 64; ++c)
+            if (cu[c]) canon.push_back(c);
+        for_each_parallel((int)canon.size(), [&](int i, std::vector<double> &scratch) {
+            const int c = canon[i];
+            build_m2l(p, c % 4, (c / 4) % 4, c / 16, scratch.data());
             for (int r = 0; r < K; ++r)
-                for (int k = 0; k < K; ++k) m2lc[((size_t)c * P->KP + r) * P->KK + k] = tmp[(size_t)r * K + k];
-        }
+                for (int k = 0; k < K; ++k) m2lc[((size_t)c * P->KP + r) * P->KK + k] = scratch[(size_t)r * K + k];
+        }, (size_t)K * K);
         DevBuf<double> dm2lc;
         dm2lc.upload(m2lc, s);
         vec_layouts(dm2lc.p, 64, P->op_m2lc64v, P->op_m2lc32v, P->op_m2lc64t, P->op_m2lc32t);
@@ -1071,7 +1241,15 @@ extern "C" xrl_status xrl_plan_export(const xrl_plan *P, int32_t item, void *buf
             case 2: v = P->h_box_level; break;
             case 3: v = P->h_near_rows; break;
             case 4: v = const_cast<xrl_plan *>(P)->near_src.download(0); break;
-            case 5: v = P->h_m2l_pairs; break;
+            case 5: {
+                const auto t = P->m2l_pair_t.download(0, P->n_m2l), src = P->m2l_pair_s.download(0, P->n_m2l);
+                v.resize(2 * P->n_m2l);
+                for (int64_t q = 0; q < P->n_m2l; ++q) {
+                    v[2 * q] = t[q];
+                    v[2 * q + 1] = src[q];
+                }
+                break;
+            }
             case 6: v = P->h_leaf_box; break;
             case 7: v = P->h_box_parent; break;
             case 9: v = const_cast<xrl_plan *>(P)->leaf_tpad.download(0); break;
@@ -1081,7 +1259,7 @@ extern "C" xrl_status xrl_plan_export(const xrl_plan *P, int32_t item, void *buf
                 // separation ratio of every M2L pair (order of item 5)
                 std::vector<double> d;
                 if (item == 10)
-                    d = P->h_m2l_ratio;
+                    d = P->m2l_ratio.download(0, P->n_m2l);
                 else if (P->near64.p)
                     d = const_cast<xrl_plan *>(P)->near64.download(0, P->n_near_entries);
                 else {

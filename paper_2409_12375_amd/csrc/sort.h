@@ -12,6 +12,8 @@
 //      ranked by matching the 8 digit bits with ballots, across the waves of
 //      a slot by per-wave counts in LDS, across slots by a running count per
 //      digit, so equal digits keep their input order.
+// The kernels have internal linkage: every source that sorts includes this
+// header.
 #pragma once
 
 #include "scan.h"
@@ -20,7 +22,7 @@ namespace xrl {
 
 constexpr int kSortThreads = 256, kSortSlots = 8, kSortTile = kSortThreads * kSortSlots, kSortWaves = 4;
 
-__global__ __launch_bounds__(kSortThreads) void k_digit_count(const uint64_t *__restrict__ key, int64_t n, int shift,
+static __global__ __launch_bounds__(kSortThreads) void k_digit_count(const uint64_t *__restrict__ key, int64_t n, int shift,
                                                               int64_t ntile, int32_t *__restrict__ count)
 {
     __shared__ int32_t h[256];
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(kSortThreads) void k_digit_count(const uint64_t *__
     count[(int64_t)threadIdx.x * ntile + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_digit_scatter(const uint64_t *__restrict__ key,
+static __global__ __launch_bounds__(kSortThreads) void k_digit_scatter(const uint64_t *__restrict__ key,
                                                                 const int32_t *__restrict__ val, int64_t n, int shift,
                                                                 int64_t ntile, const int64_t *__restrict__ first,
                                                                 uint64_t *__restrict__ key_out,
