@@ -210,28 +210,85 @@ __global__ void k_duplicates(const uint64_t *__restrict__ code, const int32_t *_
     }
 }
 
-// For every box of one level that must split: the 9 boundaries of its child
-// ranges in the sorted code array (lower bounds of the 8 child digits + end).
-__global__ void k_child_bounds(const uint64_t *__restrict__ code, const int32_t *__restrict__ beg,
-                               const int32_t *__restrict__ end, const uint64_t *__restrict__ key, int nbox,
-                               int level, int32_t *__restrict__ bounds)
+// Root box: every element, at level 0.
+__global__ void k_root_box(int32_t N, uint64_t *key, int32_t *level, int32_t *parent, int32_t *child0,
+                           int32_t *nchild, int32_t *beg, int32_t *end)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbox) return;
-    const int shift_child = 3 * (kMaxDepth - level - 1);
-    for (int d = 0; d < 8; ++d) {
-        int32_t lo = beg[b], hi = end[b];
-        const uint64_t target = ((key[b] << 3) | (uint64_t)d) << shift_child;
-        while (lo < hi) {
-            int32_t mid = lo + (hi - lo) / 2;
-            if (code[mid] < target)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        bounds[9 * b + d] = lo;
+    key[0] = 0;
+    level[0] = 0;
+    parent[0] = -1;
+    child0[0] = -1;
+    nchild[0] = 0;
+    beg[0] = 0;
+    end[0] = N;
+}
+
+// Boxes lo .. lo + n - 1 of one level: a box with more than max_leaf
+// elements splits (below the maximum depth; at it, it is counted in *over).
+// For a splitting box: the 9 boundaries of its child ranges in the sorted
+// code array (lower bounds of the 8 child digits, then its end) and the
+// number of nonempty children; 0 children for the others.
+__global__ void k_split_level(const uint64_t *__restrict__ code, int32_t lo, int32_t n, int level, bool can_split,
+                              int max_leaf, const uint64_t *__restrict__ key, const int32_t *__restrict__ beg,
+                              const int32_t *__restrict__ end, int32_t *__restrict__ bounds,
+                              int32_t *__restrict__ nch, int32_t *__restrict__ over)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = lo + i;
+    nch[i] = 0;
+    if (end[b] - beg[b] <= max_leaf) return;
+    if (!can_split) {
+        atomicAdd(over, 1);
+        return;
     }
-    bounds[9 * b + 8] = end[b];
+    const int shift_child = 3 * (kMaxDepth - level - 1);
+    int cnt = 0;
+    int32_t prev = beg[b];
+    for (int d = 0; d < 8; ++d) {
+        int32_t l = beg[b], h = end[b];
+        const uint64_t target = ((key[b] << 3) | (uint64_t)d) << shift_child;
+        while (l < h) {
+            const int32_t mid = l + (h - l) / 2;
+            if (code[mid] < target)
+                l = mid + 1;
+            else
+                h = mid;
+        }
+        bounds[9 * (int64_t)i + d] = l;
+        if (d > 0) cnt += l > prev;
+        prev = l;
+    }
+    bounds[9 * (int64_t)i + 8] = end[b];
+    cnt += end[b] > prev;
+    nch[i] = cnt;
+}
+
+// The children of the splitting boxes of one level, from position
+// first + coff[i] on (nonempty octants in order).
+__global__ void k_make_children(int32_t lo, int32_t n, int32_t first, int level, const int32_t *__restrict__ bounds,
+                                const int32_t *__restrict__ nch, const int32_t *__restrict__ coff, uint64_t *key,
+                                int32_t *blevel, int32_t *parent, int32_t *child0, int32_t *nchild, int32_t *beg,
+                                int32_t *end)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || nch[i] == 0) return;
+    const int32_t b = lo + i, c0 = first + coff[i];
+    child0[b] = c0;
+    nchild[b] = nch[i];
+    int k = 0;
+    for (int d = 0; d < 8; ++d) {
+        const int32_t cb = bounds[9 * (int64_t)i + d], ce = bounds[9 * (int64_t)i + d + 1];
+        if (ce <= cb) continue;
+        const int32_t c = c0 + k++;
+        key[c] = (key[b] << 3) | (uint64_t)d;
+        blevel[c] = level + 1;
+        parent[c] = b;
+        child0[c] = -1;
+        nchild[c] = 0;
+        beg[c] = cb;
+        end[c] = ce;
+    }
 }
 
 // Hybrid meshes: one element per triangle row, two per four-sided panel
@@ -369,68 +426,78 @@ extern "C" xrl_status xrl_tree_build(const xrl_mesh_desc *mesh, int32_t max_leaf
         XRL_HIP(hipGetLastError());
         XRL_CHECK(!(flags.download(s)[0] & 4), XRL_E_DEGENERATE_PANEL,
                   "xrl_tree_build: two panels share their three vertices (coincident panels)");
-        // level-by-level split
+        // level-by-level split, on the device: the boxes of one level that
+        // hold more than max_leaf elements split into their nonempty octant
+        // children, appended in parent order (then octant order) as the next
+        // level; the arrays grow by doubling
+        struct Boxes {
+            DevBuf<uint64_t> key;
+            DevBuf<int32_t> level, parent, child0, nchild, beg, end;
+        } bx, grow;
+        int64_t cap = 0, B = 1;
+        auto reserve = [&](int64_t need) {
+            if (need <= cap) return;
+            const int64_t nc = std::max<int64_t>({need, 2 * cap, 1024});
+            grow.key.alloc(nc);
+            grow.level.alloc(nc);
+            grow.parent.alloc(nc);
+            grow.child0.alloc(nc);
+            grow.nchild.alloc(nc);
+            grow.beg.alloc(nc);
+            grow.end.alloc(nc);
+            if (B > 0 && cap > 0) {
+                auto cp = [&](auto &dst, auto &src) {
+                    XRL_HIP(hipMemcpyAsync(dst.p, src.p, B * sizeof(*src.p), hipMemcpyDeviceToDevice, s));
+                };
+                cp(grow.key, bx.key);
+                cp(grow.level, bx.level);
+                cp(grow.parent, bx.parent);
+                cp(grow.child0, bx.child0);
+                cp(grow.nchild, bx.nchild);
+                cp(grow.beg, bx.beg);
+                cp(grow.end, bx.end);
+            }
+            std::swap(bx, grow);
+            cap = nc;
+        };
+        reserve(1);
+        k_root_box<<<1, 1, 0, s>>>((int32_t)N, bx.key.p, bx.level.p, bx.parent.p, bx.child0.p, bx.nchild.p, bx.beg.p,
+                                   bx.end.p);
+        XRL_HIP(hipGetLastError());
         t->level_off = {0};
-        t->box_key = {0};
-        t->box_level = {0};
-        t->box_parent = {-1};
-        t->box_beg = {0};
-        t->box_end = {(int32_t)N};
-        t->box_child0 = {-1};
-        t->box_nchild = {0};
-        int level = 0;
-        DevBuf<int32_t> dbeg, dend, dbounds;
-        DevBuf<uint64_t> dkey;
-        while (true) {
-            const int64_t lo = t->level_off.back();
-            const int64_t hi = (int64_t)t->box_key.size();
+        DevBuf<int32_t> over(1), nch, coff, ctot(1), bounds;
+        XRL_HIP(hipMemsetAsync(over.p, 0, sizeof(int32_t), s));
+        for (int level = 0;; ++level) {
+            const int64_t lo = t->level_off.back(), hi = B, n = hi - lo;
             t->level_off.push_back(hi);
-            // boxes of this level that split
-            std::vector<int32_t> sb, se, sidx;
-            std::vector<uint64_t> sk;
-            for (int64_t b = lo; b < hi; ++b) {
-                int32_t cnt = t->box_end[b] - t->box_beg[b];
-                if (cnt > max_leaf) {
-                    if (level < max_depth) {
-                        sb.push_back(t->box_beg[b]);
-                        se.push_back(t->box_end[b]);
-                        sk.push_back(t->box_key[b]);
-                        sidx.push_back((int32_t)b);
-                    } else {
-                        t->n_overfull++;
-                    }
-                }
-            }
-            if (sb.empty()) break;
-            const int ns = (int)sb.size();
-            dbeg.upload(sb, s);
-            dend.upload(se, s);
-            dkey.upload(sk, s);
-            dbounds.alloc(9 * (size_t)ns);
-            k_child_bounds<<<cdiv(ns, 128), 128, 0, s>>>(code.p, dbeg.p, dend.p, dkey.p, ns, level, dbounds.p);
+            nch.alloc(n);
+            coff.alloc(n);
+            bounds.alloc(9 * n);
+            k_split_level<<<(unsigned)cdiv(n, 128), 128, 0, s>>>(code.p, (int32_t)lo, (int32_t)n, level,
+                                                                level < max_depth, max_leaf, bx.key.p, bx.beg.p,
+                                                                bx.end.p, bounds.p, nch.p, over.p);
             XRL_HIP(hipGetLastError());
-            auto bd = dbounds.download(s);
-            for (int i = 0; i < ns; ++i) {
-                const int32_t b = sidx[i];
-                t->box_child0[b] = (int32_t)t->box_key.size();
-                int nch = 0;
-                for (int d = 0; d < 8; ++d) {
-                    int32_t cb = bd[9 * i + d], ce = bd[9 * i + d + 1];
-                    if (ce > cb) {
-                        t->box_key.push_back((sk[i] << 3) | (uint64_t)d);
-                        t->box_level.push_back(level + 1);
-                        t->box_parent.push_back(b);
-                        t->box_beg.push_back(cb);
-                        t->box_end.push_back(ce);
-                        t->box_child0.push_back(-1);
-                        t->box_nchild.push_back(0);
-                        ++nch;
-                    }
-                }
-                t->box_nchild[b] = nch;
-            }
-            ++level;
+            exclusive_scan<int32_t, int32_t>(nch.p, n, coff.p, ctot.p, s);
+            const int64_t nc = ctot.download(s)[0];
+            if (nc == 0) break;
+            XRL_CHECK(hi + nc < (int64_t(1) << 31), XRL_E_UNSUPPORTED, "xrl_tree_build: more than 2^31 boxes");
+            reserve(hi + nc);
+            k_make_children<<<(unsigned)cdiv(n, 128), 128, 0, s>>>((int32_t)lo, (int32_t)n, (int32_t)hi, level,
+                                                                   bounds.p, nch.p, coff.p, bx.key.p, bx.level.p,
+                                                                   bx.parent.p, bx.child0.p, bx.nchild.p, bx.beg.p,
+                                                                   bx.end.p);
+            XRL_HIP(hipGetLastError());
+            B = hi + nc;
         }
+        t->n_overfull = over.download(s)[0];
+        // host copies of the box arrays (the plan merges the boxes of its trees)
+        t->box_key = bx.key.download(s, B);
+        t->box_level = bx.level.download(s, B);
+        t->box_parent = bx.parent.download(s, B);
+        t->box_child0 = bx.child0.download(s, B);
+        t->box_nchild = bx.nchild.download(s, B);
+        t->box_beg = bx.beg.download(s, B);
+        t->box_end = bx.end.download(s, B);
         // level_off holds [depth + 2] entries: the start of every level and the total
         t->depth = (int)t->level_off.size() - 2;
         t->code = std::move(code);
