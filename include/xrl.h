@@ -396,6 +396,11 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
  *       (p+1)^2 output rows in registers and the operator read from LDS as
  *       broadcasts (1), or 16 x 4 register tiles of 6 rows by 4 columns over
  *       64-column blocks (0).
+ *   XRL_TUNE_LEAF_L2L    (0/1, default 1): FP32 plans whose P2M and L2P run
+ *       on MFMA (more than 16 real columns): L2P adds the parent's local
+ *       expansion through each leaf's L2L operator itself (a second
+ *       contraction with precomputed moment rows), and L2L translates into
+ *       the boxes with children only (1); or L2L into every box (0).
  * Errors: XRL_E_INVALID_ARG (null plan, unknown key, bad value). */
 #define XRL_TUNE_TS_KERNEL 0
 #define XRL_TUNE_TS_MIN_COLS 1
@@ -406,6 +411,7 @@ xrl_status xrl_plan_get_phase_ms(const xrl_plan *plan, double *ms /* [XRL_N_PHAS
 #define XRL_TUNE_M2M_FORM 6
 #define XRL_TUNE_LEAF_FORM 7
 #define XRL_TUNE_VALU_FORM 8
+#define XRL_TUNE_LEAF_L2L 9
 xrl_status xrl_plan_set_tuning(xrl_plan *plan, int32_t key, int32_t value);
 
 /* Graph mode (on != 0): the first xrl_fmm_matvec with a new argument set

@@ -258,6 +258,9 @@ struct xrl_plan {
     double theta = XRL_DEFAULT_THETA;  // separation criterion of the V-list pairs
     TransPass m2l;
     std::vector<TransPass> m2m, l2l;   // per level
+    // L2L per level without the leaf targets: the FP32 matrix-core L2P
+    // applies the parent's local to a leaf's panels itself (mom_l2l32)
+    std::vector<TransPass> l2l_inner;
     mutable xrl::DevBuf<float> os_tmp32;
     mutable xrl::DevBuf<double> os_tmp64;
     double max_sep_ratio = 0;
@@ -287,6 +290,7 @@ struct xrl_plan {
     int ts_min_cols = 16;  // MFMA engine: target-stationary from this many real columns on
     int p2p_form = 0;  // P2P above 16 FP32 columns: 0 MFMA, 1 scalar densities, 2 LDS-staged (XRL_TUNE_P2P_FORM)
     int leaf_mfma = 1;       // P2M and L2P above 16 FP32 columns on MFMA (1) or the vector ALU (0)
+    int leaf_l2l = 1;        // matrix-core L2P applies the leaves' L2L itself (XRL_TUNE_LEAF_L2L)
     int valu_col = 1;        // vector-ALU offset-stationary form (XRL_TUNE_VALU_FORM)
     int tr_m2m = 2;          // <= 8 pairs per target: one wave per row tile (1), per target (0), by level size (2)
     int ps_l2l = 1;          // passes with one source per target: source-stationary (1) or lean (0)
@@ -297,6 +301,10 @@ struct xrl_plan {
     // moment table per sorted panel, scaled to its leaf: [N][K]
     xrl::DevBuf<double> mom64;
     xrl::DevBuf<float> mom32;
+    // [N][K] per panel of a leaf at level >= 3: its weighted moment row
+    // through the L2L operator of its leaf's octant, (1/h) sum_i Q[i] w_i
+    // T[i][j], so that L2P takes the parent's local directly (FP32 plans)
+    xrl::DevBuf<float> mom_l2l32;
     // near field: per leaf a list of source rows; block [rows][tpad]
     std::vector<int32_t> h_near_rows;  // [n_leaves+1]
     xrl::DevBuf<int32_t> near_rows;    // [n_leaves+1]

@@ -712,12 +712,18 @@ __global__ __launch_bounds__(256) void k_l2p(const int32_t *__restrict__ leaf_bo
 // per item and reused for every 16-target tile; narrow columns (XC = 4) on
 // 4x4x1 blocks as in the translations.  Moment rows past the leaf read as
 // zeros (range-checked buffer loads).
-template <int ORD, int WT, int XC>
+// FUSE: the leaf's local holds its M2L part only (L2L skipped the leaves);
+// for a leaf at level >= 3 the wave adds sum_j Q'[t][j] L_parent[j][c], Q'
+// the moment rows through the leaf's L2L operator (momp), as a second
+// contraction with the parent's local as B.
+template <int ORD, int WT, int XC, bool FUSE>
 __global__ __launch_bounds__(64) void k_l2p_mfma(int items_per_leaf, const int32_t *__restrict__ leaf_box,
                                                  const int32_t *__restrict__ box_beg,
                                                  const int32_t *__restrict__ box_end,
                                                  const double *__restrict__ hbox, const float *__restrict__ mom,
-                                                 const float *__restrict__ L, float *__restrict__ ys, int C)
+                                                 const float *__restrict__ L, float *__restrict__ ys, int C,
+                                                 const float *__restrict__ momp, const int32_t *__restrict__ box_parent,
+                                                 const int32_t *__restrict__ box_level)
 {
     constexpr int K = (ORD + 1) * (ORD + 1), NKS = (K + 3) / 4;
     struct BV {
@@ -747,12 +753,31 @@ __global__ __launch_bounds__(64) void k_l2p_mfma(int items_per_leaf, const int32
         for (int ct = 0; ct < WT; ++ct) bl[ks][ct] = v.v[ct] * wk;
         if constexpr (XC > 0) bx[ks] = buf_load<float>(rl, (kc * C + cn + (li & 3)) * 4, 0) * wk;
     }
+    // the parent's local (unweighted: the weights are in Q')
+    const bool fz = FUSE && box_level[b] >= 3;
+    float bp[FUSE ? NKS : 1][WT], bpx[FUSE && XC ? NKS : 1];
+    if constexpr (FUSE) {
+        if (fz) {
+            const auto rp = buf_rsrc(L + (int64_t)box_parent[b] * K * C, (uint32_t)((K * C + 256) * 4));
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) {
+                const int k = NKS * kq + ks;
+                const int kc = k < K ? k : K - 1;
+                const BV v = buf_load<BV>(rp, (kc * C + cb + WT * li) * 4, 0);
+#pragma unroll
+                for (int ct = 0; ct < WT; ++ct) bp[ks][ct] = v.v[ct];
+                if constexpr (XC > 0) bpx[ks] = buf_load<float>(rp, (kc * C + cn + (li & 3)) * 4, 0);
+            }
+        }
+    }
     const auto rq = buf_rsrc(mom + (int64_t)kb * K, (uint32_t)(nt * K * 4));
+    const auto rq2 = buf_rsrc(FUSE ? momp + (int64_t)kb * K : mom, (uint32_t)(fz ? nt * K * 4 : 0));
     const int ntt = (nt + 15) / 16;
     // a 16-target tile's moments and the values it adds to, fetched one
     // tile ahead
     struct Tile {
         float a[NKS];
+        float a2[FUSE ? NKS : 1];
         float old[WT][4];
         float ox;
     };
@@ -760,6 +785,10 @@ __global__ __launch_bounds__(64) void k_l2p_mfma(int items_per_leaf, const int32
         const int qo = ((16 * tt + li) * K + NKS * kq) * 4;
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) T.a[ks] = buf_load<float>(rq, qo + 4 * ks, 0);
+        if constexpr (FUSE)
+            if (fz)
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks) T.a2[ks] = buf_load<float>(rq2, qo + 4 * ks, 0);
 #pragma unroll
         for (int ct = 0; ct < WT; ++ct)
 #pragma unroll
@@ -788,6 +817,18 @@ __global__ __launch_bounds__(64) void k_l2p_mfma(int items_per_leaf, const int32
 #pragma unroll
             for (int ct = 0; ct < WT; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks], bl[ks][ct], acc[ct], 0, 0, 0);
             if constexpr (XC > 0) accx = __builtin_amdgcn_mfma_f32_4x4x1f32(a[ks], bx[ks], accx, 0, 0, 0);
+        }
+        if constexpr (FUSE) {
+            if (fz) {
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks) {
+                    const float a2 = valid[ks] ? tc.a2[ks] : 0.f;
+#pragma unroll
+                    for (int ct = 0; ct < WT; ++ct)
+                        acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, bp[ks][ct], acc[ct], 0, 0, 0);
+                    if constexpr (XC > 0) accx = __builtin_amdgcn_mfma_f32_4x4x1f32(a2, bpx[ks], accx, 0, 0, 0);
+                }
+            }
         }
         // D[i][j] at lane j + 16 q, element i - 4 q: target 16 tt + i,
         // column cb + WT j + ct
@@ -2162,7 +2203,7 @@ struct Ops {
 
 template <typename T, int ORD>
 static void translations(const xrl_plan *P, const Ops<T> &op, T *M, T *L, DevBuf<T> *tmp, int C, hipStream_t s,
-                         bool force_ts, const std::function<void(int)> &mark)
+                         bool force_ts, const std::function<void(int)> &mark, bool leaf_l2l_in_l2p)
 {
     using D = M2LDims<ORD>;
     mark(3);
@@ -2178,9 +2219,10 @@ static void translations(const xrl_plan *P, const Ops<T> &op, T *M, T *L, DevBuf
     pass_launch<T, ORD>(P, P->m2l, op.m2l_f, op.m2l_k, op.m2l_v, op.m2l_t, true, M, L, 0, tmp, C, s, force_ts,
                         op.m2l_full, op.m2l_full_t);
     mark(5);
+    // (without the leaf targets when L2P applies the leaves' L2L itself)
+    const std::vector<TransPass> &l2l = leaf_l2l_in_l2p ? P->l2l_inner : P->l2l;
     for (int l = 3; l <= P->depth; ++l)
-        pass_launch<T, ORD>(P, P->l2l[l], op.l2l_f, op.l2l_k, op.l2l_v, op.l2l_t, false, L, L, 1, tmp, C, s,
-                            force_ts);
+        pass_launch<T, ORD>(P, l2l[l], op.l2l_f, op.l2l_k, op.l2l_v, op.l2l_t, false, L, L, 1, tmp, C, s, force_ts);
     mark(6);
 }
 
@@ -2246,6 +2288,9 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
             return fn(std::integral_constant<int, 48>());
         }
     };
+    // the FP32 matrix-core L2P applies the leaves' L2L itself (Q' table)
+    const bool fuse_l2l = sizeof(T) == 4 && P->n_leaves > 0 && C > 16 && P->leaf_mfma && P->leaf_l2l &&
+                          P->mom_l2l32.p != nullptr && (int)P->l2l_inner.size() == P->depth + 1;
     bool p2m_done = false;
     if constexpr (sizeof(T) == 4) {
         if (P->n_leaves > 0 && C > 16 && P->leaf_mfma) {
@@ -2299,12 +2344,12 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
         XRL_HIP(hipGetLastError());
     }
     switch (P->p) {
-        case 2: translations<T, 2>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark); break;
-        case 4: translations<T, 4>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark); break;
-        case 6: translations<T, 6>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark); break;
-        case 8: translations<T, 8>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark); break;
-        case 10: translations<T, 10>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark); break;
-        default: translations<T, 12>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark); break;
+        case 2: translations<T, 2>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark, fuse_l2l); break;
+        case 4: translations<T, 4>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark, fuse_l2l); break;
+        case 6: translations<T, 6>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark, fuse_l2l); break;
+        case 8: translations<T, 8>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark, fuse_l2l); break;
+        case 10: translations<T, 10>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark, fuse_l2l); break;
+        default: translations<T, 12>(P, op, wk.M, wk.L, wk.tmp, C, s, wk.force_ts, mark, fuse_l2l); break;
     }
     bool l2p_done = false;
     if constexpr (sizeof(T) == 4) {
@@ -2324,9 +2369,14 @@ static void run_matvec(const xrl_plan *P, const void *x, int64_t ldx, int ncols,
             XRL_CHECK(n_items < (int64_t(1) << 31), XRL_E_UNSUPPORTED, "xrl_fmm_matvec: too many L2P items");
             auto go = [&](auto ordc, auto wt, auto xcols) {
                 constexpr int O = decltype(ordc)::value, W = decltype(wt)::value, X = decltype(xcols)::value;
-                k_l2p_mfma<O, W, X><<<(unsigned)n_items, 64, 0, s>>>(ipl, P->leaf_box.p, P->box_beg.p, P->box_end.p,
-                                                                    P->box_h.p, (const float *)op.mom, (const float *)wk.L,
-                                                                    (float *)wk.ys, C);
+                if (fuse_l2l)
+                    k_l2p_mfma<O, W, X, true><<<(unsigned)n_items, 64, 0, s>>>(
+                        ipl, P->leaf_box.p, P->box_beg.p, P->box_end.p, P->box_h.p, (const float *)op.mom,
+                        (const float *)wk.L, (float *)wk.ys, C, P->mom_l2l32.p, P->box_parent.p, P->box_level.p);
+                else
+                    k_l2p_mfma<O, W, X, false><<<(unsigned)n_items, 64, 0, s>>>(
+                        ipl, P->leaf_box.p, P->box_beg.p, P->box_end.p, P->box_h.p, (const float *)op.mom,
+                        (const float *)wk.L, (float *)wk.ys, C, nullptr, nullptr, nullptr);
             };
             auto go_w = [&](auto ordc) {
                 auto gx = [&](auto wt) {
@@ -2849,6 +2899,10 @@ extern "C" xrl_status xrl_plan_set_tuning(xrl_plan *P, int32_t key, int32_t valu
             case XRL_TUNE_VALU_FORM:
                 XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: vector-ALU form must be 0 or 1");
                 P->valu_col = value;
+                break;
+            case XRL_TUNE_LEAF_L2L:
+                XRL_CHECK(value == 0 || value == 1, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: leaf L2L must be 0 or 1");
+                P->leaf_l2l = value;
                 break;
             case XRL_TUNE_M2M_FORM:
                 XRL_CHECK(value >= 0 && value <= 2, XRL_E_INVALID_ARG, "xrl_plan_set_tuning: M2M form must be 0..2");

@@ -722,6 +722,53 @@ __global__ void k_m2m_pairs(int32_t lo, int32_t nb, const int32_t *__restrict__ 
     }
 }
 
+// flag[i] = 1 for the boxes lo + i with children
+__global__ void k_inner_flags(int32_t lo, int32_t nb, const int32_t *__restrict__ nchild, int32_t *__restrict__ flag)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) flag[i] = nchild[lo + i] > 0 ? 1 : 0;
+}
+
+// L2L pairs of the boxes with children of one level, in box order
+__global__ void k_l2l_inner_pairs(int32_t lo, int32_t nb, const int32_t *__restrict__ flag,
+                                  const int32_t *__restrict__ pos, const int32_t *__restrict__ parent,
+                                  const int32_t *__restrict__ octant, int32_t *__restrict__ tgt,
+                                  int32_t *__restrict__ src, int32_t *__restrict__ code)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb || !flag[i]) return;
+    tgt[pos[i]] = lo + i;
+    src[pos[i]] = parent[lo + i];
+    code[pos[i]] = octant[lo + i];
+}
+
+// Moment rows through the L2L operator: out[t][j] = (1/h) sum_i Q[t][i] w_i
+// T_o[i][j] for the panels t of a leaf at level >= 3 (o: the leaf's
+// octant, w_i = 1 for the m = 0 coefficient of each degree, 2 otherwise),
+// zero for the others.  L2P of the leaf's panels then adds
+// sum_j out[t][j] L_parent[j], which is L2P of T_o L_parent.
+__global__ void k_mom_l2l(int64_t N, int K, const int32_t *__restrict__ panel_leaf,
+                          const int32_t *__restrict__ leaf_box, const int32_t *__restrict__ box_level,
+                          const int32_t *__restrict__ box_octant, const double *__restrict__ box_h,
+                          const double *__restrict__ mom, const double *__restrict__ l2l, float *__restrict__ out)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= N * K) return;
+    const int64_t t = e / K;
+    const int j = (int)(e - t * K);
+    const int32_t b = leaf_box[panel_leaf[t]];
+    if (box_level[b] < 3) {
+        out[e] = 0.f;
+        return;
+    }
+    const double *T = l2l + (int64_t)box_octant[b] * K * K;
+    const double *q = mom + t * K;
+    double acc = 0;
+    for (int n = 0, i = 0; i < K; ++n)
+        for (int m = 0; m <= 2 * n; ++m, ++i) acc += q[i] * (m == 0 ? 1.0 : 2.0) * T[(int64_t)i * K + j];
+    out[e] = (float)(acc / box_h[b]);
+}
+
 // L2L pairs of one level (child b <- its parent, operator: the octant of b)
 __global__ void k_l2l_pairs(int32_t lo, int32_t nb, const int32_t *__restrict__ parent,
                             const int32_t *__restrict__ octant, int32_t *__restrict__ tgt, int32_t *__restrict__ src,
@@ -990,8 +1037,10 @@ static void build_plan(xrl_plan *P, hipStream_t s)
         P->m2l_pair_s = std::move(vsrc);
         P->m2m.clear();
         P->l2l.clear();
+        P->l2l_inner.clear();
         P->m2m.resize(depth + 1);
         P->l2l.resize(depth + 1);
+        P->l2l_inner.resize(depth + 1);
         for (int l = 0; l <= depth; ++l) {
             const int32_t lo = (int32_t)P->level_off[l], nb = (int32_t)(P->level_off[l + 1] - P->level_off[l]);
             if (nb == 0) continue;
@@ -1006,12 +1055,25 @@ static void build_plan(xrl_plan *P, hipStream_t s)
                 XRL_HIP(hipGetLastError());
                 build_pass(P->m2m[l], n1, t1.p, s1.p, c1.p, 8, s);
             }
-            // L2L: child b <- its parent (locals are zero above level 2)
+            // L2L: child b <- its parent (locals are zero above level 2); and
+            // the same without the leaf targets
             if (l >= 3) {
                 DevBuf<int32_t> t2(nb), s2(nb), c2(nb);
                 k_l2l_pairs<<<cdiv(nb, 128), 128, 0, s>>>(lo, nb, P->box_parent.p, P->box_octant.p, t2.p, s2.p, c2.p);
                 XRL_HIP(hipGetLastError());
                 build_pass(P->l2l[l], nb, t2.p, s2.p, c2.p, 8, s);
+                DevBuf<int32_t> flag(nb), ipos(nb), itot(1);
+                k_inner_flags<<<cdiv(nb, 128), 128, 0, s>>>(lo, nb, P->box_nchild.p, flag.p);
+                XRL_HIP(hipGetLastError());
+                exclusive_scan<int32_t, int32_t>(flag.p, nb, ipos.p, itot.p, s);
+                const int32_t ni = itot.download(s)[0];
+                if (ni > 0) {
+                    DevBuf<int32_t> t3(ni), s3(ni), c3(ni);
+                    k_l2l_inner_pairs<<<cdiv(nb, 128), 128, 0, s>>>(lo, nb, flag.p, ipos.p, P->box_parent.p,
+                                                                    P->box_octant.p, t3.p, s3.p, c3.p);
+                    XRL_HIP(hipGetLastError());
+                    build_pass(P->l2l_inner[l], ni, t3.p, s3.p, c3.p, 8, s);
+                }
             }
         }
     }
@@ -1154,6 +1216,15 @@ static void build_plan(xrl_plan *P, hipStream_t s)
     }
 #undef XRL_MOM
     XRL_HIP(hipGetLastError());
+    if (P->precision != XRL_PREC_FP64 && N > 0) {
+        P->mom_l2l32.alloc((size_t)N * K);
+        k_mom_l2l<<<(unsigned)cdiv(N * K, 256), 256, 0, s>>>(N, K, P->panel_leaf.p, P->leaf_box.p, P->box_level.p,
+                                                             P->box_octant.p, P->box_h.p, P->mom64.p,
+                                                             P->op_l2l64.p, P->mom_l2l32.p);
+        XRL_HIP(hipGetLastError());
+    } else {
+        P->mom_l2l32.release();
+    }
     XRL_HIP(hipStreamSynchronize(s));
 }
 

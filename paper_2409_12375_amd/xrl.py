@@ -309,7 +309,7 @@ class Plan:
         _check(lib().xrl_plan_set_profiling(self.h, 1 if on else 0))
 
     TUNE = {"ts_kernel": 0, "ts_min_cols": 1, "p2p_form": 2, "ts_narrow_cols": 3, "ts_order": 4, "l2l_form": 5, "m2m_form": 6, "leaf_form": 7,
-            "valu_form": 8}
+            "valu_form": 8, "leaf_l2l": 9}
 
     def set_tuning(self, key, value):
         """Kernel-shape knob (see xrl_plan_set_tuning); results agree to rounding."""

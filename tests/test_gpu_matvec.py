@@ -138,7 +138,7 @@ def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
     tree = xrl.Tree(V, T)
     ys = {}
     forms = ("mfma", "mfma_os", "refl", "lean", "p2p_scalar", "p2p_lds", "padded", "refl_padded", "l2l_ts", "m2m_ts",
-             "m2m_tiles", "valu_leaf", "valu", "valu_tiles")
+             "m2m_tiles", "valu_leaf", "valu", "valu_tiles", "l2l_leaves")
     for eng in forms:
         engine = eng if eng in ("mfma_os", "valu") else ("valu" if eng == "valu_tiles" else "mfma")
         plan = xrl.Plan(tree, order=8, precision="mixed", engine=engine, max_cols=18)
@@ -161,6 +161,8 @@ def test_wide_columns_target_stationary_matches_oracle_and_offset_stationary():
             plan.set_tuning("m2m_form", 1)
         if eng == "valu_tiles":  # vector-ALU translations as 6 x 4 register tiles
             plan.set_tuning("valu_form", 0)
+        if eng == "l2l_leaves":  # L2L into the leaves too (L2P without the parent term)
+            plan.set_tuning("leaf_l2l", 0)
         if eng == "valu_leaf":  # P2P, P2M and L2P on the vector ALU
             plan.set_tuning("leaf_form", 0)
             plan.set_tuning("p2p_form", 2)
