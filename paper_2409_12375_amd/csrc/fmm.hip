@@ -635,16 +635,24 @@ __global__ __launch_bounds__(64) void k_p2m_mfma(int items_per_leaf, const int32
             if constexpr (XC > 0) accx[it] = __builtin_amdgcn_mfma_f32_4x4x1f32(st.a[it], st.x, accx[it], 0, 0, 0);
         }
     };
-    // two k steps per trip, the next one in flight; steps past the leaf read
-    // zeros (range-checked loads), so the trip count may round up
+    // a ring of four k steps in flight (one wave per leaf: the loads of the
+    // next steps cover each step's latency); steps past the leaf read zeros
+    // (range-checked loads) and are not computed
     const int nks = (nt + 3) / 4;
-    Step s0, s1;
+    Step s0, s1, s2, s3;
     load(0, s0);
-    for (int ks = 0; ks < nks; ks += 2) {
-        load(ks + 1, s1);
+    load(1, s1);
+    load(2, s2);
+    load(3, s3);
+    for (int ks = 0; ks < nks; ks += 4) {
         comp(s0);
-        load(ks + 2, s0);
-        comp(s1);
+        load(ks + 4, s0);
+        if (ks + 1 < nks) comp(s1);
+        load(ks + 5, s1);
+        if (ks + 2 < nks) comp(s2);
+        load(ks + 6, s2);
+        if (ks + 3 < nks) comp(s3);
+        load(ks + 7, s3);
     }
     float *Mb = M + (int64_t)b * K * C;
 #pragma unroll
