@@ -206,6 +206,7 @@ def main():
     t_tree = time.perf_counter() - t0
     sur_path = os.path.join(ROOT, "tests", "golden", "surrogate_mlp.npz")
     results, ys = {}, {}
+    x_diag = y_diag = None
     for name in variants.split(","):
         base, _, engine = name.partition("@")
         prec = "mixed" if base == "surrogate" else base
@@ -242,6 +243,18 @@ def main():
         }
         if tune is not None:
             results[name]["autotune"] = tune
+        if name == variants.split(",")[0] and args.workload != "batch":
+            # diagnostic columns of the headline variant (reported, not
+            # gated): x = 1 and a smooth density over the structure
+            V0, T0 = meshes[0]
+            Tv = np.asarray(T0)
+            cnt = (Tv >= 0).sum(axis=1, keepdims=True)
+            cen = (np.asarray(V0)[np.where(Tv >= 0, Tv, 0)] * (Tv >= 0)[..., None]).sum(axis=1) / cnt
+            lo, ext = cen.min(axis=0), np.maximum(np.ptp(cen, axis=0), 1e-12)
+            u = (cen - lo) / ext
+            smooth = np.cos(np.pi * u[:, 0]) * np.cos(np.pi * u[:, 1]) + np.cos(np.pi * u[:, 2])
+            x_diag = np.stack([np.ones(N), smooth], axis=1).astype(np.complex64)
+            y_diag = plan.matvec(torch.from_numpy(x_diag).cuda()).cpu().numpy()
         if args.workload == "batch":
             ys[name] = y  # stays on the device; sampled below
         else:
@@ -268,6 +281,7 @@ def main():
     # accuracy and CPU baseline: the FP64 oracle on a bounded row sample
     cpu = None
     acc = {}
+    diag = None
     if not args.no_cpu:
         import oracle as O
         if args.workload == "batch":
@@ -329,6 +343,11 @@ def main():
                 e = np.linalg.norm(yv[allrows] - ref, axis=0) / np.linalg.norm(ref, axis=0)
                 acc[v] = float(e.max())
                 results[v]["max_col_rel_l2"] = acc[v]
+            if x_diag is not None:
+                ref_d, _ = O.matvec(V, T, x_diag.astype(np.complex128), rows=allrows)
+                e_d = np.linalg.norm(y_diag[allrows] - ref_d, axis=0) / np.linalg.norm(ref_d, axis=0)
+                diag = {"ones_rel_l2": float(e_d[0]), "smooth_rel_l2": float(e_d[1]), "rows": int(m),
+                        "variant": main_v}
 
     line = {
         "metric": "panel-interactions/s per FMM matvec at 1e-4 rel L2; surrogate+MP vs plain FP32",
@@ -347,6 +366,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "max_col_rel_l2": acc.get(main_v),
+        "diagnostics": diag,
         "tree_build_s": t_tree,
         "variants": results,
     }
