@@ -132,12 +132,153 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_calibration_bytes": n * 4, "launches": 3}), flush=True)
 
 
+def run_loops(args, torch, I, xrl):
+    """The loop formulation around the FMM (Sec. II-A/B/D, eq. (8)) on a long
+    bar of about 50k panels, three frequencies: one application of the
+    branch operator sum_t A_t (beta area + alpha P) A_t^T (its FMM matvec
+    on 3 x 3 complex columns and the sparse maps around it), and the loop
+    GMRES with each preconditioner (the factorisation of the preconditioner
+    runs on the host).  Oracle leg: the branch operator on sampled branches
+    from the FP64 oracle's rows of P."""
+    MU0 = 4e-7 * np.pi
+    V, T = I.bar(24, 24, 250, size=(1.0, 1.0, 20.0))
+    N = len(T)
+    freqs = np.array([1e6, 1e8, 1e9])
+    R = len(freqs)
+    alpha = 1j * 2 * np.pi * freqs * MU0 / (4 * np.pi) * 1e-9
+    beta = xrl.surface_impedance(freqs, 5.96e7, 35e-6) * 1e-6
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tree = xrl.Tree(V, T, max_leaf=args.max_leaf)
+    plan = xrl.Plan(tree, order=8, precision="mixed", max_cols=3 * R)
+    st = plan.assemble()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    L = xrl.Loops(V, T)
+    torch.cuda.synchronize()
+    t_loops = time.perf_counter() - t0
+    info = L.info()
+    Ne = info["n_edges"]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(I.DENS_SEED)
+    ie = torch.view_as_complex(torch.randn(Ne, R, 2, generator=g, device="cuda", dtype=torch.float64))
+
+    def timed(fn, reps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    ve = L.edge_matvec(plan, ie, alpha=alpha, beta=beta)
+    t_edge = timed(lambda: L.edge_matvec(plan, ie, alpha=alpha, beta=beta), args.steps)
+    xp = torch.view_as_complex(torch.randn(N, 3 * R, 2, generator=g, device="cuda")).contiguous()
+    t_fmm = timed(lambda: plan.matvec(xp), args.steps)
+    solves = {}
+    for pc in ("none", "diag_p", "diag_l"):
+        # one iteration first: the preconditioner's set-up (its entries and
+        # factorisation) plus one step
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.solve(plan, ve, alpha=alpha, beta=beta, precond=pc, rtol=1e-6, max_iter=1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, gs = L.solve(plan, ve, alpha=alpha, beta=beta, precond=pc, rtol=1e-6, max_iter=600)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        it = max(gs["iterations"], 2)
+        solves[pc] = {"iterations": gs["iterations"], "converged": gs["status"] == 0, "s": ts,
+                      "setup_and_one_iteration_s": t1,
+                      "ms_per_iteration": 1e3 * (ts - t1) / (it - 1),
+                      "max_rel_residual": gs["max_rel_residual"]}
+        log("loop solve", pc, json.dumps(solves[pc]))
+    cpu = err = None
+    if not args.no_cpu:
+        import oracle as O
+        from oracle import loops as LO
+        # branches in the library's order; the maps of the sampled branches
+        pairs, verts = LO.mesh_edges(T)
+        key = {tuple(v): e for e, v in enumerate(verts.tolist())}
+        lib_verts = L.export(1).reshape(-1, 2)
+        perm = np.array([key[tuple(v)] for v in lib_verts.tolist()])
+        c = LO.centroids(V, T)
+        mid = 0.5 * (V[verts[:, 0]] + V[verts[:, 1]])
+        ih = ie.cpu().numpy()
+        # panel currents of each component: y_t = A_t^T I (every branch adds
+        # to its two panels)
+        y = np.zeros((3, N, R), dtype=np.complex128)
+        pi, pj = pairs[perm, 0], pairs[perm, 1]
+        for t in range(3):
+            np.add.at(y[t], pi, (mid[perm, t] - c[pi, t])[:, None] * ih)
+            np.add.at(y[t], pj, -(mid[perm, t] - c[pj, t])[:, None] * ih)
+        sample = np.sort(np.random.default_rng(11).choice(Ne, 32, replace=False))
+        rows = np.unique(np.concatenate([pairs[perm[s_]] for s_ in sample]))
+        t0 = time.perf_counter()
+        Y = np.concatenate([y[t] for t in range(3)], axis=1)  # [N][3R]
+        Py, used = O.matvec(V, T, Y, rows=rows)
+        t_cpu = time.perf_counter() - t0
+        area, _ = LO_area(V, T)
+        z = {}
+        for q, k in enumerate(rows):
+            for t in range(3):
+                z[(k, t)] = beta * area[k] * y[t, k, :] + alpha * Py[q, t * R:(t + 1) * R]
+        ref = np.zeros((len(sample), R), dtype=np.complex128)
+        for q, le in enumerate(sample):
+            e = perm[le]
+            i, j = pairs[e]
+            for t in range(3):
+                ref[q] += (mid[e][t] - c[i][t]) * z[(i, t)] - (mid[e][t] - c[j][t]) * z[(j, t)]
+        got = ve.cpu().numpy()[sample]
+        err = float((np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)).max())
+        cpu = {"value": 3 * R * float(len(rows)) * N / t_cpu, "unit": "panel-interactions/s", "cores": int(used),
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": "P rows of the %d panels of 32 random branches x all %d source panels x %d complex "
+                         "columns (3 components x %d frequencies), FP64 direct summation, %.1f s" % (
+                             len(rows), N, 3 * R, R, t_cpu)}
+    line = {
+        "metric": "panel-interactions/s per loop-operator application (branch operator of eq. (8), 3 "
+                  "components x 3 frequencies)",
+        "value": 3 * R * float(N) * N / t_edge,
+        "unit": "panel-interactions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_edge,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "1 x 1 x 20 bar, %d triangle panels, %d branches, %d loops, 3 frequencies "
+                               "(1 MHz, 100 MHz, 1 GHz), p=8, leaf<=%d, mixed precision" % (
+                                   N, Ne, info["n_loops"], args.max_leaf),
+                   "n_panels": N, "n_edges": Ne, "n_loops": info["n_loops"]},
+        "roofline": None,
+        "cpu_baseline": cpu,
+        "branch_operator_rel_l2": err,
+        "fmm_matvec_ms": 1e3 * t_fmm,
+        "maps_ms": 1e3 * (t_edge - t_fmm),
+        "setup_s": {"tree_plan_assembly": t_setup, "loops_build": t_loops},
+        "loop_gmres": solves,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def LO_area(V, T):
+    """Panel areas (host) for the loop workload's oracle leg."""
+    V = np.asarray(V, dtype=np.float64)
+    T = np.asarray(T)
+    e1 = V[T[:, 1]] - V[T[:, 0]]
+    e2 = V[T[:, 2]] - V[T[:, 0]]
+    return 0.5 * np.linalg.norm(np.cross(e1, e2), axis=1), None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="bga", choices=["bga", "coils", "pop", "batch"])
+    ap.add_argument("--workload", default="bga", choices=["bga", "coils", "pop", "batch", "loops"])
     ap.add_argument("--n", type=int, default=200_000, help="target panel count of the coil mesh")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
@@ -162,6 +303,9 @@ def main():
     from paper_2409_12375_amd import xrl
 
     torch.cuda.set_device(0)
+    if args.workload == "loops":
+        run_loops(args, torch, I, xrl)
+        return
     graph = autotune = False
     if args.workload == "coils":
         meshes = [I.coils(args.n)]

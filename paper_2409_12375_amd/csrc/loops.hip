@@ -22,9 +22,11 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <exception>
 #include <functional>
 #include <numeric>
 #include <memory>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -465,6 +467,31 @@ struct SparseLDL {
     }
 };
 
+// fn(c) for c in [0, n) on n host threads (the columns of the
+// preconditioner are independent); the first failure is rethrown here.
+template <class F>
+static void for_each_column(int n, F fn)
+{
+    std::vector<std::exception_ptr> err(n);
+    std::vector<std::thread> pool;
+    for (int c = 1; c < n; ++c)
+        pool.emplace_back([&, c] {
+            try {
+                fn(c);
+            } catch (...) {
+                err[c] = std::current_exception();
+            }
+        });
+    try {
+        if (n > 0) fn(0);
+    } catch (...) {
+        err[0] = std::current_exception();
+    }
+    for (auto &t : pool) t.join();
+    for (auto &e : err)
+        if (e) std::rethrow_exception(e);
+}
+
 // Q = M B M^T for an edge-space sparse B given per row (host).
 static std::vector<std::vector<std::pair<int64_t, cplx>>> loop_product(
     const xrl_loops &L, const std::vector<std::vector<std::pair<int64_t, cplx>>> &B)
@@ -800,7 +827,8 @@ extern "C" xrl_status xrl_loop_gmres_solve(const xrl_loops *L, const xrl_plan *P
             XRL_HIP(hipGetLastError());
             std::vector<double> pv = dv.download(s);
             for (double v : pv) XRL_CHECK(std::isfinite(v), XRL_E_STATE, "preconditioner: near entry missing");
-            for (int c = 0; c < R; ++c) {
+            Qf.resize(R);
+            for_each_column(R, [&](int c) {
                 const cplx al(E.alpha3[6 * c], E.alpha3[6 * c + 1]), be(E.beta3[6 * c], E.beta3[6 * c + 1]);
                 std::vector<std::vector<std::pair<int64_t, cplx>>> B(Ne);
                 auto addB = [&](int64_t e, int64_t f, cplx v) {
@@ -832,9 +860,8 @@ extern "C" xrl_status xrl_loop_gmres_solve(const xrl_loops *L, const xrl_plan *P
                         const double ij = ri[0] * rj[0] + ri[1] * rj[1] + ri[2] * rj[2];
                         addB(e, e, al * (ii * pv[i] + jj * pv[j] - 2.0 * ij * pv[Np + e]));
                     }
-                Qf.emplace_back();
-                Qf.back().factor(Nl, loop_product(*L, B));
-            }
+                Qf[c].factor(Nl, loop_product(*L, B));
+            });
         }
         // right preconditioning: GMRES on Z_loop Q^-1 u = V_l, I_l = Q^-1 u
         std::vector<cplx> hbuf;
@@ -842,12 +869,12 @@ extern "C" xrl_status xrl_loop_gmres_solve(const xrl_loops *L, const xrl_plan *P
             hbuf.resize((size_t)Nl * R);
             XRL_HIP(hipMemcpyAsync(hbuf.data(), x, hbuf.size() * sizeof(cplx), hipMemcpyDeviceToHost, s));
             XRL_HIP(hipStreamSynchronize(s));
-            std::vector<cplx> col(Nl);
-            for (int c = 0; c < R; ++c) {
+            for_each_column(R, [&](int c) {
+                std::vector<cplx> col(Nl);
                 for (int64_t l = 0; l < Nl; ++l) col[l] = hbuf[(size_t)l * R + c];
                 Qf[c].solve(col.data());
                 for (int64_t l = 0; l < Nl; ++l) hbuf[(size_t)l * R + c] = col[l];
-            }
+            });
             XRL_HIP(hipMemcpyAsync(y, hbuf.data(), hbuf.size() * sizeof(cplx), hipMemcpyHostToDevice, s));
             XRL_HIP(hipStreamSynchronize(s));
         };
