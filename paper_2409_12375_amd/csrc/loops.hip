@@ -379,10 +379,34 @@ static void build_loops(const int32_t *Q, xrl_loops &L)
 // Envelope factorisation after a reverse Cuthill-McKee ordering:
 // A = L D L^T without pivoting (A = R + jX with R, X symmetric positive
 // definite, as the preconditioners of eq. (10) are, has no zero pivot).
+static inline cplx zmulh(cplx a, cplx b)
+{
+    return cplx(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real());
+}
+
+// sum_{k in [k0, k1)} a[k] b[k] (complex), four independent partial sums so
+// that the multiply-adds pipeline
+static inline cplx zdot(const cplx *a, const cplx *b, int64_t k0, int64_t k1)
+{
+    double r[4] = {0, 0, 0, 0}, m[4] = {0, 0, 0, 0};
+    int64_t k = k0;
+    for (; k + 4 <= k1; k += 4)
+        for (int u = 0; u < 4; ++u) {
+            const cplx x = a[k + u], y = b[k + u];
+            r[u] += x.real() * y.real() - x.imag() * y.imag();
+            m[u] += x.real() * y.imag() + x.imag() * y.real();
+        }
+    for (; k < k1; ++k) {
+        r[0] += a[k].real() * b[k].real() - a[k].imag() * b[k].imag();
+        m[0] += a[k].real() * b[k].imag() + a[k].imag() * b[k].real();
+    }
+    return cplx((r[0] + r[1]) + (r[2] + r[3]), (m[0] + m[1]) + (m[2] + m[3]));
+}
+
 struct SparseLDL {
     int64_t n = 0;
     std::vector<int64_t> perm, first, off;  // permuted row i: columns first[i]..i-1 at env[off[i]..]
-    std::vector<cplx> env, d;
+    std::vector<cplx> env, d, rinv;         // rinv = 1 / d
 
     void factor(int64_t nn, const std::vector<std::vector<std::pair<int64_t, cplx>>> &rows)
     {
@@ -426,6 +450,7 @@ struct SparseLDL {
         for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + (i - first[i]);
         env.assign(off[n], cplx(0));
         d.assign(n, cplx(0));
+        rinv.assign(n, cplx(0));
         for (int64_t i = 0; i < n; ++i)
             for (auto &q : rows[order[i]]) {
                 const int64_t j = pos[q.first];
@@ -435,19 +460,28 @@ struct SparseLDL {
                     d[i] += q.second;
             }
         // row by row: L_ij = (A_ij - sum_k L_ik D_k L_jk) / D_j, D_i = A_ii - sum_k L_ik^2 D_k
+        // (complex products written out: the library's complex multiply
+        // handles infinities and NaNs through a slow call; the values here
+        // are finite); W_k = L_ik D_k of the current row, kept beside it
+        std::vector<cplx> w(n);
         for (int64_t i = 0; i < n; ++i) {
             cplx *li = env.data() + off[i];
-            for (int64_t j = first[i]; j < i; ++j) {
-                cplx acc = li[j - first[i]];
-                const int64_t k0 = std::max(first[i], first[j]);
-                const cplx *lj = env.data() + off[j];
-                for (int64_t k = k0; k < j; ++k) acc -= li[k - first[i]] * d[k] * lj[k - first[j]];
-                li[j - first[i]] = acc / d[j];
+            const int64_t fi = first[i];
+            for (int64_t j = fi; j < i; ++j) {
+                const int64_t k0 = std::max(fi, first[j]);
+                const cplx acc = li[j - fi] - zdot(w.data(), env.data() + off[j] - first[j], k0, j);
+                const double ar = acc.real(), ai = acc.imag();
+                const cplx r = rinv[j];
+                const cplx l(ar * r.real() - ai * r.imag(), ar * r.imag() + ai * r.real());
+                li[j - fi] = l;
+                w[j] = zmulh(l, d[j]);
             }
-            cplx dd = d[i];
-            for (int64_t k = first[i]; k < i; ++k) dd -= li[k - first[i]] * li[k - first[i]] * d[k];
+            const cplx dd = d[i] - zdot(w.data(), li - fi, fi, i);
+            const double dr = dd.real(), di = dd.imag();
             XRL_CHECK(std::abs(dd) > 0, XRL_E_UNSUPPORTED, "preconditioner: zero pivot");
             d[i] = dd;
+            const double q = dr * dr + di * di;
+            rinv[i] = cplx(dr / q, -di / q);
         }
     }
     // x = A^-1 b in place (original order)
@@ -455,14 +489,15 @@ struct SparseLDL {
     {
         std::vector<cplx> y(n);
         for (int64_t i = 0; i < n; ++i) y[i] = b[perm[i]];
-        for (int64_t i = 0; i < n; ++i) {
-            cplx acc = y[i];
-            for (int64_t k = first[i]; k < i; ++k) acc -= env[off[i] + (k - first[i])] * y[k];
-            y[i] = acc;
+        for (int64_t i = 0; i < n; ++i) y[i] -= zdot(env.data() + off[i] - first[i], y.data(), first[i], i);
+        for (int64_t i = 0; i < n; ++i) y[i] = zmulh(y[i], rinv[i]);
+        for (int64_t i = n - 1; i >= 0; --i) {
+            const double yr = y[i].real(), yi = y[i].imag();
+            const cplx *li = env.data() + off[i] - first[i];
+            for (int64_t k = first[i]; k < i; ++k)
+                y[k] = cplx(y[k].real() - (li[k].real() * yr - li[k].imag() * yi),
+                            y[k].imag() - (li[k].real() * yi + li[k].imag() * yr));
         }
-        for (int64_t i = 0; i < n; ++i) y[i] /= d[i];
-        for (int64_t i = n - 1; i >= 0; --i)
-            for (int64_t k = first[i]; k < i; ++k) y[k] -= env[off[i] + (k - first[i])] * y[i];
         for (int64_t i = 0; i < n; ++i) b[perm[i]] = y[i];
     }
 };
