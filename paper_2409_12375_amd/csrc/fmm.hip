@@ -725,7 +725,7 @@ __global__ __launch_bounds__(256) void k_l2p(const int32_t *__restrict__ leaf_bo
 // the moment rows through the leaf's L2L operator (momp), as a second
 // contraction with the parent's local as B.
 template <int ORD, int WT, int XC, bool FUSE>
-__global__ __launch_bounds__(64) void k_l2p_mfma(int items_per_leaf, const int32_t *__restrict__ leaf_box,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_l2p_mfma(int items_per_leaf, const int32_t *__restrict__ leaf_box,
                                                  const int32_t *__restrict__ box_beg,
                                                  const int32_t *__restrict__ box_end,
                                                  const double *__restrict__ hbox, const float *__restrict__ mom,
