@@ -168,7 +168,8 @@ xrl_status xrl_tree_get_info(const xrl_tree *tree, xrl_tree_info *info);
 /* Plan                                                                */
 /* ------------------------------------------------------------------ */
 typedef struct {
-    int32_t order;     /* expansion order p (1..12); (p+1)^2 real coefficients per column */
+    int32_t order;     /* expansion order p, even, 2..12 (other values: XRL_E_UNSUPPORTED);
+                          (p+1)^2 real coefficients per column */
     int32_t precision; /* XRL_PREC_* */
     int32_t m2l_engine;/* XRL_M2L_* */
     int32_t max_cols;  /* largest number of complex columns one matvec will carry */

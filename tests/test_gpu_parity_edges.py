@@ -450,7 +450,8 @@ def _mesh_call(V, T, max_leaf=64, max_depth=21):
 def test_rejected_inputs():
     """Degenerate, non-finite, coincident and out-of-range panels are refused
     with their status codes; a leaf over the block limit at the maximum depth
-    and a separation criterion out of range are refused by the plan."""
+    and a separation criterion or an expansion order out of range are
+    refused by the plan."""
     say("case: rejected inputs")
     V, T = I.bar(2, 2, 6, size=(1.0, 1.0, 3.0))
     # collinear vertices: zero area
@@ -480,6 +481,11 @@ def test_rejected_inputs():
         with pytest.raises(xrl.XrlError) as ei:
             xrl.Plan(tree, theta=th)
         assert ei.value.code == -1
+    # expansion orders: even, 2..12
+    for p in (0, 7, 14):
+        with pytest.raises(xrl.XrlError) as ei:
+            xrl.Plan(tree, order=p)
+        assert ei.value.code == -6, p
     # leaves of more than 128 panels at the maximum depth
     Vb, Tb = I.bar()
     tb = xrl.Tree(Vb, Tb, max_leaf=16, max_depth=2)
