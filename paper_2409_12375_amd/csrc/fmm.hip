@@ -148,7 +148,7 @@ __device__ inline V buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff)
 
 // ---------------------------------------------------------------- P2P
 // One workgroup per (target leaf, column tile).  The stored block of a leaf
-// is [rows][tpad] (tpad a multiple of 16); a thread owns VEC consecutive
+// is [rows][tpad] (tpad a multiple of 4); a thread owns VEC consecutive
 // targets of one row (one 16-byte load) and the tpad/VEC threads of a row
 // group stride over the rows (threads past the last whole group idle).
 // Source indices and the source densities of a chunk of 256 rows are staged
@@ -381,19 +381,21 @@ __global__ __launch_bounds__(64) void k_p2p_sx(const int32_t *__restrict__ leaf_
 // stored block as B (4 rows x 16 targets).  One wave per (leaf, item of WT
 // column tiles, plus XC = 4 narrow columns on 4x4x1 blocks as in the
 // target-stationary translation).  A lane (li, kq) takes row 4 ks + kq of
-// every k step: E = tpad / 16 consecutive targets E li .. E li + E - 1 of it
-// in one vector load (target E li + e goes to target tile e), and WT
-// consecutive densities (column cb + WT li + ct to column tile ct).  Rows
-// past the block read as zeros (range-checked buffer loads), and so do
-// their source indices, which then point at source 0: every product with
-// a missing row is zero.
+// every k step: targets li, 16 + li, ..., 16 (E - 1) + li of it, E =
+// ceil(G / 16) for the block width G (one word each; target 16 e + li goes
+// to target tile e), and WT consecutive densities (column cb + WT li + ct to
+// column tile ct).  Targets past G read the start of the next row and feed
+// only results that are not stored; rows past the block read as zeros
+// (range-checked buffer loads, one word each, so the check is exact), and
+// so do their source indices, which then point at source 0: every product
+// with a missing row is zero.
 template <int WT, int XC, int E>
-__device__ inline void p2p_mfma_leaf(int lane, int nr, const float *__restrict__ vb, const int32_t *__restrict__ srcs,
-                                     const float *__restrict__ xs, int C, int cb, float *__restrict__ ys, int64_t kb,
-                                     int nt)
+__device__ inline void p2p_mfma_leaf(int lane, int nr, int G, const float *__restrict__ vb,
+                                     const int32_t *__restrict__ srcs, const float *__restrict__ xs, int C, int cb,
+                                     float *__restrict__ ys, int64_t kb, int nt)
 {
-    constexpr int G = 16 * E, U = 4;  // block width; k steps per stage
-    using VE = Words<E>;  // E consecutive block values, one (or two) buffer loads
+    constexpr int U = 4;  // k steps per stage
+    using VE = Words<E>;  // a row's values of the lane's E targets
     struct BV {
         float v[WT];
     };
@@ -426,7 +428,8 @@ __device__ inline void p2p_mfma_leaf(int lane, int nr, const float *__restrict__
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int r = 4 * (ks0 + u) + kq;
-            st.v[u] = buf_load_words<E>(rv, (r * G + E * li) * 4, 0);
+#pragma unroll
+            for (int e = 0; e < E; ++e) st.v[u].w[e] = buf_load_words<1>(rv, (r * G + 16 * e + li) * 4, 0).w[0];
             const float *xr = xs + (int64_t)sr.r[u] * C;
             st.b[u] = *reinterpret_cast<const BV *>(xr + xo);
             if constexpr (XC > 0) st.xn[u] = xr[xno];
@@ -463,10 +466,10 @@ __device__ inline void p2p_mfma_leaf(int lane, int nr, const float *__restrict__
         comp(s1);
     }
     // D[i][j] of tile (e, ct) at lane j + 16 q, element i - 4 q: column
-    // cb + WT i + ct, target E j + e
+    // cb + WT i + ct, target 16 e + j
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int t = E * li + e;
+        const int t = 16 * e + li;
 #pragma unroll
         for (int ct = 0; ct < WT; ++ct)
 #pragma unroll
@@ -475,7 +478,7 @@ __device__ inline void p2p_mfma_leaf(int lane, int nr, const float *__restrict__
                 if (t < nt && col < C) ys[(kb + t) * C + col] = acc[e][ct][e4];
             }
         if constexpr (XC > 0) {
-            // block accumulators: lane (li, kq) holds target E li + e and
+            // block accumulators: lane (li, kq) holds target 16 e + li and
             // narrow columns 0..3 in elements 0..3 for its k-subset; after the
             // sum over the four k-subsets it stores column kq
             f32x4 v = accx[e];
@@ -509,15 +512,17 @@ __global__ __launch_bounds__(64) void k_p2p_mfma(int items_per_leaf, const int32
     const int32_t kb = box_beg[tb], nt = box_end[tb] - kb;
     const int32_t r0 = near_rows[li], nr = near_rows[li + 1] - r0;
     const float *vb = val + val_off[li];
-    switch (leaf_tpad[li]) {
-        case 16: p2p_mfma_leaf<WT, XC, 1>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
-        case 32: p2p_mfma_leaf<WT, XC, 2>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
-        case 48: p2p_mfma_leaf<WT, XC, 3>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
-        case 64: p2p_mfma_leaf<WT, XC, 4>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
-        case 80: p2p_mfma_leaf<WT, XC, 5>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
-        case 96: p2p_mfma_leaf<WT, XC, 6>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
-        case 112: p2p_mfma_leaf<WT, XC, 7>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
-        default: p2p_mfma_leaf<WT, XC, 8>(lane, nr, vb, near_src + r0, xs, C, cb, ys, kb, nt); break;
+    const int G = leaf_tpad[li];  // 4..128
+    const int32_t *sr = near_src + r0;
+    switch ((G + 15) >> 4) {
+        case 1: p2p_mfma_leaf<WT, XC, 1>(lane, nr, G, vb, sr, xs, C, cb, ys, kb, nt); break;
+        case 2: p2p_mfma_leaf<WT, XC, 2>(lane, nr, G, vb, sr, xs, C, cb, ys, kb, nt); break;
+        case 3: p2p_mfma_leaf<WT, XC, 3>(lane, nr, G, vb, sr, xs, C, cb, ys, kb, nt); break;
+        case 4: p2p_mfma_leaf<WT, XC, 4>(lane, nr, G, vb, sr, xs, C, cb, ys, kb, nt); break;
+        case 5: p2p_mfma_leaf<WT, XC, 5>(lane, nr, G, vb, sr, xs, C, cb, ys, kb, nt); break;
+        case 6: p2p_mfma_leaf<WT, XC, 6>(lane, nr, G, vb, sr, xs, C, cb, ys, kb, nt); break;
+        case 7: p2p_mfma_leaf<WT, XC, 7>(lane, nr, G, vb, sr, xs, C, cb, ys, kb, nt); break;
+        default: p2p_mfma_leaf<WT, XC, 8>(lane, nr, G, vb, sr, xs, C, cb, ys, kb, nt); break;
     }
 }
 

@@ -279,7 +279,9 @@ __global__ void k_leaf_rows(int64_t nleaf, const int64_t *__restrict__ soff, con
     }
 }
 
-// Per leaf: block padding (targets rounded up to 16) and its value count.
+// Per leaf: block padding (targets rounded up to 4, so that a row starts
+// on 16 bytes for the vector loads of the vector-ALU forms) and its value
+// count.
 __global__ void k_leaf_blocks(int64_t nleaf, const int32_t *__restrict__ leaves, const int32_t *__restrict__ beg,
                               const int32_t *__restrict__ end, const int32_t *__restrict__ nrow,
                               int32_t *__restrict__ tpad, int64_t *__restrict__ nval, int64_t *__restrict__ npair)
@@ -287,7 +289,7 @@ __global__ void k_leaf_blocks(int64_t nleaf, const int32_t *__restrict__ leaves,
     const int64_t li = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (li >= nleaf) return;
     const int32_t nt = end[leaves[li]] - beg[leaves[li]];
-    tpad[li] = 16 * ((nt + 15) / 16);
+    tpad[li] = 4 * ((nt + 3) / 4);
     nval[li] = (int64_t)nrow[li] * tpad[li];
     npair[li] = (int64_t)nrow[li] * nt;
 }

@@ -270,7 +270,8 @@ def test_leaves_of_128_panels(precision, ncomplex):
             plan.set_tuning("leaf_form", 0)
         ys[v] = plan.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
         plan.close()
-    assert tp.max() > 64 and np.all(tp % 16 == 0)
+    # blocks wider than 64 targets, and widths that end inside a 16-target tile
+    assert tp.max() > 64 and np.all(tp % 4 == 0) and np.any(tp % 16 != 0)
     first = next(iter(ys))
     for v in ys:
         if v != first:
