@@ -729,8 +729,19 @@ __global__ __launch_bounds__(256) void k_l2p(const int32_t *__restrict__ leaf_bo
 // for a leaf at level >= 3 the wave adds sum_j Q'[t][j] L_parent[j][c], Q'
 // the moment rows through the leaf's L2L operator (momp), as a second
 // contraction with the parent's local as B.
+//
+// Waves per SIMD asked of the compiler: two (at most 256 registers) where
+// that costs no spills (order <= 8, up to two column tiles; the fused form
+// at order 8 and two tiles needs 263 otherwise), else no bound: the wider
+// items would spill to scratch.
+template <int ORD, int WT>
+constexpr int l2p_min_waves()
+{
+    return ORD <= 8 && WT <= 2 ? 2 : 1;
+}
+
 template <int ORD, int WT, int XC, bool FUSE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_l2p_mfma(int items_per_leaf, const int32_t *__restrict__ leaf_box,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(l2p_min_waves<ORD, WT>()))) void k_l2p_mfma(int items_per_leaf, const int32_t *__restrict__ leaf_box,
                                                  const int32_t *__restrict__ box_beg,
                                                  const int32_t *__restrict__ box_end,
                                                  const double *__restrict__ hbox, const float *__restrict__ mom,
