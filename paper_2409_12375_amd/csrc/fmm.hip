@@ -494,8 +494,16 @@ __device__ inline void p2p_mfma_leaf(int lane, int nr, int G, const float *__res
     }
 }
 
+// three full column tiles (C = 48) fit three waves per SIMD (168 registers)
 template <int WT, int XC>
-__global__ __launch_bounds__(64) void k_p2p_mfma(int items_per_leaf, const int32_t *__restrict__ leaf_box,
+constexpr int p2p_min_waves()
+{
+    return WT == 3 && XC == 0 ? 3 : 1;
+}
+
+template <int WT, int XC>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(p2p_min_waves<WT, XC>()))) void k_p2p_mfma(
+    int items_per_leaf, const int32_t *__restrict__ leaf_box,
                                                  const int32_t *__restrict__ box_beg,
                                                  const int32_t *__restrict__ box_end,
                                                  const int32_t *__restrict__ near_rows,
@@ -731,17 +739,17 @@ __global__ __launch_bounds__(256) void k_l2p(const int32_t *__restrict__ leaf_bo
 // contraction with the parent's local as B.
 //
 // Waves per SIMD asked of the compiler: two (at most 256 registers) where
-// that costs no spills (order <= 8, up to two column tiles; the fused form
-// at order 8 and two tiles needs 263 otherwise), else no bound: the wider
-// items would spill to scratch.
-template <int ORD, int WT>
+// that costs no spills (below order 8; at order 8 the fused items of up to
+// 48 columns, e.g. 263 registers otherwise at two tiles and four narrow
+// columns), else no bound: the wider fused items would spill to scratch.
+template <int ORD, int WT, int XC, bool FUSE>
 constexpr int l2p_min_waves()
 {
-    return ORD <= 8 && WT <= 2 ? 2 : 1;
+    return ORD < 8 || (ORD == 8 && (!FUSE || 16 * WT + XC <= 48)) ? 2 : 1;
 }
 
 template <int ORD, int WT, int XC, bool FUSE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(l2p_min_waves<ORD, WT>()))) void k_l2p_mfma(int items_per_leaf, const int32_t *__restrict__ leaf_box,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(l2p_min_waves<ORD, WT, XC, FUSE>()))) void k_l2p_mfma(int items_per_leaf, const int32_t *__restrict__ leaf_box,
                                                  const int32_t *__restrict__ box_beg,
                                                  const int32_t *__restrict__ box_end,
                                                  const double *__restrict__ hbox, const float *__restrict__ mom,
