@@ -137,7 +137,7 @@ typedef struct xrl_plan xrl_plan;
  * density to its elements and sums their potentials back (P = S P_tri S^T,
  * S the panel-element membership; the integral over a panel is the sum over
  * its triangles).
- *   max_leaf  : 1..128; near-field blocks are padded to 16, 32, 64 or 128
+ *   max_leaf  : 1..128; near-field blocks are padded to a multiple of 4
  *               targets.  Larger leaves move work from the translations to
  *               the near field (fewer M2L pairs, more stored values).
  *   max_depth : 1..21; a box at max_depth is a leaf whatever its count
@@ -459,6 +459,7 @@ xrl_status xrl_plan_autotune(xrl_plan *plan, const void *x, int64_t ldx, int32_t
  *   item 7: box_parent  int32 [n_boxes]
  *   item 8: near_values float64 [n_near_entries] (per leaf [rows][tpad])
  *   item 9: leaf_tpad   int32 [n_leaves]   padded target count of each leaf block
+ *                                          (its targets rounded up to a multiple of 4)
  *   item 10: m2l_ratio  float64 [n_m2l_pairs] (r_t + r_s) / |c_t - c_s| of each
  *                       pair of item 5, in the same order
  * With buf == NULL only *nbytes is set. */
